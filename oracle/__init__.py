@@ -1,0 +1,259 @@
+"""Python access to the CPU oracle (``liboracle.so``, built from oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check and the
+benchmark's CPU-baseline leg are the only callers. The GPU library never
+imports, links or runs anything from here, and this module never touches the
+GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+FLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+         "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (IEEE FP64, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["g++", *FLAGS, _SRC, "-o", tmp], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_last_error.restype = ctypes.c_char_p
+        L.oracle_tree_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _chk(rc):
+    if rc != 0:
+        raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int64)
+
+
+def nm(p: int) -> int:
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()
+
+
+def morton_keys(pos, box=None):
+    pos = _f64(pos)
+    n = pos.shape[0]
+    keys = np.empty(n, np.uint64)
+    ls = np.empty(4)
+    b = None if box is None else _f64(box)
+    _chk(lib().oracle_morton_keys(ctypes.c_int64(n), _p(pos), _p(b), _p(ls), _p(keys)))
+    return keys, ls
+
+
+class Tree:
+    """O-T: the FP64 scalar treecode, step by step."""
+
+    def __init__(self, pos, n_leaf=16, n_group=64, box=None):
+        self._pos = _f64(pos)
+        self.n = self._pos.shape[0]
+        h = ctypes.c_void_p()
+        b = None if box is None else _f64(box)
+        _chk(lib().oracle_tree_build(ctypes.c_int64(self.n), _p(self._pos), n_leaf, n_group,
+                                     _p(b), ctypes.byref(h)))
+        self.h = h
+        self.p = None
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().oracle_tree_destroy(self.h)
+            self.h = None
+
+    def counts(self):
+        out = np.zeros(8, np.int64)
+        _chk(lib().oracle_tree_counts(self.h, _p(out)))
+        return dict(n=int(out[0]), n_cells=int(out[1]), n_groups=int(out[2]),
+                    n_leaves=int(out[3]), max_level=int(out[4]), n_p2p=int(out[5]),
+                    n_m2p=int(out[6]))
+
+    def root(self):
+        out = np.empty(4)
+        _chk(lib().oracle_tree_root(self.h, _p(out)))
+        return out
+
+    def keys(self):
+        k = np.empty(self.n, np.uint64)
+        perm = np.empty(self.n, np.int64)
+        _chk(lib().oracle_tree_get_keys(self.h, _p(k), _p(perm)))
+        return k, perm
+
+    def cells(self):
+        C = self.counts()["n_cells"]
+        out = dict(level=np.empty(C, np.int32), key=np.empty(C, np.uint64),
+                   first=np.empty(C, np.int64), count=np.empty(C, np.int64),
+                   parent=np.empty(C, np.int64), child_first=np.empty(C, np.int64),
+                   n_child=np.empty(C, np.int32), is_leaf=np.empty(C, np.int32),
+                   centre=np.empty((C, 3)), bmax=np.empty(C))
+        _chk(lib().oracle_tree_get_cells(
+            self.h, _p(out["level"]), _p(out["key"]), _p(out["first"]), _p(out["count"]),
+            _p(out["parent"]), _p(out["child_first"]), _p(out["n_child"]), _p(out["is_leaf"]),
+            _p(out["centre"]), _p(out["bmax"])))
+        return out
+
+    def groups(self):
+        G = self.counts()["n_groups"]
+        g = np.empty(G, np.int64)
+        _chk(lib().oracle_tree_get_groups(self.h, _p(g)))
+        return g
+
+    def build_lists(self, theta, direct_max=0):
+        _chk(lib().oracle_build_lists(self.h, ctypes.c_double(theta), int(direct_max)))
+
+    def lists(self):
+        c = self.counts()
+        G = c["n_groups"]
+        po = np.empty(G + 1, np.int64)
+        mo = np.empty(G + 1, np.int64)
+        pl = np.empty(c["n_p2p"], np.int32)
+        ml = np.empty(c["n_m2p"], np.int32)
+        _chk(lib().oracle_get_lists(self.h, _p(po), _p(pl), _p(mo), _p(ml)))
+        return po, pl, mo, ml
+
+    def compute_moments(self, pos, mass, p, cells=None):
+        pos = _f64(pos)
+        mass = _f64(mass)
+        sel = _i64(cells)
+        ns = 0 if sel is None else sel.shape[0]
+        _chk(lib().oracle_compute_moments(self.h, _p(pos), _p(mass), int(p),
+                                          ctypes.c_int64(ns), _p(sel)))
+        self.p = p
+
+    def moments(self):
+        C = self.counts()["n_cells"]
+        out = np.empty((C, nm(self.p)))
+        _chk(lib().oracle_get_moments(self.h, _p(out)))
+        return out
+
+    def eval(self, pos, mass, eps, sinks=None, with_pot=True):
+        pos = _f64(pos)
+        mass = _f64(mass)
+        s = _i64(sinks)
+        T = self.n if s is None else s.shape[0]
+        acc = np.empty((T, 3))
+        pot = np.empty(T) if with_pot else None
+        counts = np.zeros(2, np.int64)
+        _chk(lib().oracle_eval_tree(self.h, _p(pos), _p(mass), ctypes.c_double(eps),
+                                    ctypes.c_int64(0 if s is None else T), _p(s), _p(acc),
+                                    _p(pot), _p(counts)))
+        return acc, pot, counts
+
+    def vjp(self, pos, mass, eps, abar):
+        pos = _f64(pos)
+        mass = _f64(mass)
+        abar = _f64(abar)
+        xbar = np.empty_like(pos)
+        mbar = np.empty(self.n)
+        _chk(lib().oracle_tree_vjp(self.h, _p(pos), _p(mass), ctypes.c_double(eps), _p(abar),
+                                   _p(xbar), _p(mbar)))
+        return xbar, mbar
+
+
+def direct(pos, mass, eps, sinks=None):
+    """O-D: exact softened direct sum (compensated), sinks = caller indices."""
+    pos = _f64(pos)
+    mass = _f64(mass)
+    s = _i64(sinks)
+    n = pos.shape[0]
+    T = n if s is None else s.shape[0]
+    acc = np.empty((T, 3))
+    pot = np.empty(T)
+    _chk(lib().oracle_direct(ctypes.c_int64(n), _p(pos), _p(mass), ctypes.c_double(eps),
+                             ctypes.c_int64(0 if s is None else T), _p(s), _p(acc), _p(pot)))
+    return acc, pot
+
+
+def direct_vjp(pos, mass, eps, abar, rows=None):
+    pos = _f64(pos)
+    mass = _f64(mass)
+    abar = _f64(abar)
+    r = _i64(rows)
+    n = pos.shape[0]
+    T = n if r is None else r.shape[0]
+    xbar = np.empty((T, 3))
+    mbar = np.empty(T)
+    _chk(lib().oracle_direct_vjp(ctypes.c_int64(n), _p(pos), _p(mass), ctypes.c_double(eps),
+                                 _p(abar), ctypes.c_int64(0 if r is None else T), _p(r),
+                                 _p(xbar), _p(mbar)))
+    return xbar, mbar
+
+
+def m2p(p, M, R, eps):
+    M = _f64(M)
+    R = _f64(R)
+    out = np.empty(4)
+    _chk(lib().oracle_m2p(int(p), _p(M), _p(R), ctypes.c_double(eps), _p(out)))
+    return out[:3], out[3]
+
+
+def p2m(p, pos, mass, centre):
+    pos = _f64(pos)
+    mass = _f64(mass)
+    c = _f64(centre)
+    out = np.empty(nm(p))
+    _chk(lib().oracle_p2m(int(p), ctypes.c_int64(pos.shape[0]), _p(pos), _p(mass), _p(c),
+                          _p(out)))
+    return out
+
+
+def m2m(p, M, shift):
+    M = _f64(M)
+    s = _f64(shift)
+    out = np.empty(nm(p))
+    _chk(lib().oracle_m2m(int(p), _p(M), _p(s), _p(out)))
+    return out
+
+
+def derivs(order, R, eps):
+    R = _f64(R)
+    out = np.empty(nm(order))
+    _chk(lib().oracle_derivs(int(order), _p(R), ctypes.c_double(eps), _p(out)))
+    return out
+
+
+def multi_indices(p):
+    """(a, b, c) for every storage slot up to order p (order, then a desc, then b desc)."""
+    out = []
+    for n in range(p + 1):
+        for a in range(n, -1, -1):
+            for b in range(n - a, -1, -1):
+                out.append((a, b, n - a - b))
+    return out

@@ -1,0 +1,1002 @@
+// CPU oracle for the hashed oct-tree gravitational force evaluation.
+//
+// TEST INFRASTRUCTURE ONLY. Only the test suite, the package smoke check and
+// the CPU-baseline leg of the benchmark may load or call this library. It
+// shares no code, header, table or helper with the GPU library, and neither
+// one includes or links the other.
+//
+// Everything here is plain FP64 and follows the definitions directly:
+//   * O-D: direct summation of the softened Newtonian force (eq. "eom" of
+//     the Mathematical Approach section at a = 1, G = 1, with the Plummer
+//     smoothing of the "Force Smoothing" section), compensated sums.
+//   * O-T: a scalar treecode taking the method's steps in order -- integer
+//     Morton keys (Domain Decomposition section), a sort, an oct-tree of key
+//     prefixes (Tree Construction section), moments about geometric cell
+//     centres (Background Subtraction and Multipole Methods sections: the
+//     moment tensor definition), a multipole acceptance walk over the source
+//     tree for each sink cell (dual-tree traversal, m x n blocking of the
+//     Improving instruction-level parallelism section) and the Cartesian
+//     cell-body multipole expansion with Delta = 0 (Multipole Error Bounds
+//     section), evaluated with the softened Green's function.
+//   * The VJP (reverse derivative) of O-D and of O-T with the tree topology
+//     held fixed.
+//
+// Build flags: -O2 -ffp-contract=off, never fast-math, so that every FP64
+// expression below is evaluated exactly as written (IEEE, correctly rounded,
+// no fused multiply-add).
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(const char* msg) {
+  g_err = msg;
+  return -1;
+}
+
+constexpr int kBits = 21;  // bits per axis in a key; 63 key bits + placeholder
+
+// ---------------------------------------------------------------------------
+// Keys (Domain Decomposition section: coordinates are mapped to integer keys;
+// the format itself is deferred by the paper to its 1993 predecessor). Reading
+// used here: 21 bits per axis, octant digit 4x + 2y + z, most significant
+// digit first, a leading placeholder bit so that a level-L cell key is the
+// particle key shifted right by 3 (21 - L).
+// ---------------------------------------------------------------------------
+uint64_t interleave(uint32_t qx, uint32_t qy, uint32_t qz) {
+  uint64_t k = 0;
+  for (int b = kBits - 1; b >= 0; --b) {
+    uint64_t digit = (uint64_t)(((qx >> b) & 1u) * 4u + ((qy >> b) & 1u) * 2u + ((qz >> b) & 1u));
+    k = k * 8u + digit;
+  }
+  return k;
+}
+
+void deinterleave(uint64_t k, int ndigits, uint32_t* ix, uint32_t* iy, uint32_t* iz) {
+  uint32_t x = 0, y = 0, z = 0;
+  for (int d = ndigits - 1; d >= 0; --d) {
+    uint64_t digit = (k >> (3 * d)) & 7u;
+    x = x * 2u + (uint32_t)((digit >> 2) & 1u);
+    y = y * 2u + (uint32_t)((digit >> 1) & 1u);
+    z = z * 2u + (uint32_t)(digit & 1u);
+  }
+  *ix = x;
+  *iy = y;
+  *iz = z;
+}
+
+bool is_pow2(double s) {
+  if (!(s > 0) || !std::isfinite(s)) return false;
+  int e;
+  double m = std::frexp(s, &e);
+  return m == 0.5;
+}
+
+// Root cube: lo = per-axis minimum, side = the power of two at or above the
+// largest extent (1 if every point coincides).
+void root_cube(int64_t n, const double* pos, double lo[3], double* side) {
+  for (int d = 0; d < 3; ++d) {
+    double m = pos[d];
+    for (int64_t i = 1; i < n; ++i) m = std::min(m, pos[3 * i + d]);
+    lo[d] = m;
+  }
+  double ext = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double mx = pos[d];
+    for (int64_t i = 1; i < n; ++i) mx = std::max(mx, pos[3 * i + d]);
+    ext = std::max(ext, mx - lo[d]);
+  }
+  if (ext == 0.0) {
+    *side = 1.0;
+    return;
+  }
+  int e;
+  double m = std::frexp(ext, &e);  // ext = m 2^e, m in [0.5, 1)
+  *side = (m == 0.5) ? ext : std::ldexp(1.0, e);
+}
+
+uint32_t quantise(double x, double lo, double scale) {
+  double t = std::floor((x - lo) * scale);
+  const double qmax = (double)((1u << kBits) - 1u);
+  if (t > qmax) t = qmax;
+  if (t < 0) t = 0;
+  return (uint32_t)t;
+}
+
+// ---------------------------------------------------------------------------
+// Tree
+// ---------------------------------------------------------------------------
+struct Cell {
+  int level;
+  uint64_t key;  // prefix with placeholder bit
+  int64_t first, count;
+  int64_t parent;
+  int64_t child_first;
+  int n_child;
+  int is_leaf;
+  double centre[3];
+  double bmax;
+};
+
+struct Tree {
+  int64_t n = 0;
+  int n_leaf = 16, n_group = 64;
+  double lo[3] = {0, 0, 0};
+  double side = 1.0;
+  std::vector<uint64_t> key;   // sorted keys
+  std::vector<int64_t> perm;   // sorted position -> caller index
+  std::vector<Cell> cells;     // canonical order: (level, key)
+  std::vector<int64_t> groups; // cell ids, ordered by first particle
+  std::vector<int64_t> group_of;  // sorted position -> group ordinal
+  std::vector<int64_t> leaf_of;   // sorted position -> leaf cell id
+  int max_level = 0;
+  // interaction lists, CSR over groups
+  bool has_lists = false;
+  double theta = 0;
+  int direct_max = 0;
+  std::vector<int64_t> p2p_off, m2p_off;
+  std::vector<int32_t> p2p, m2p;
+  // moments
+  int p = -1;
+  std::vector<double> mom;        // n_cells x nm(p)
+  std::vector<char> mom_valid;
+};
+
+int nm(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Multi-index (a, b, c) <-> storage slot: by order n = a+b+c, then a
+// descending, then b descending.
+int mindex(int a, int b, int c) {
+  int n = a + b + c;
+  return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
+}
+
+std::vector<int> g_alpha;  // 3 entries per slot, filled up to order 12
+void ensure_alpha() {
+  if (!g_alpha.empty()) return;
+  const int pmax = 12;
+  g_alpha.resize(3 * nm(pmax));
+  for (int n = 0; n <= pmax; ++n)
+    for (int a = n; a >= 0; --a)
+      for (int b = n - a; b >= 0; --b) {
+        int c = n - a - b;
+        int s = mindex(a, b, c);
+        g_alpha[3 * s] = a;
+        g_alpha[3 * s + 1] = b;
+        g_alpha[3 * s + 2] = c;
+      }
+}
+
+double ipow(double x, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= x;
+  return r;
+}
+
+double factorial(int k) {
+  double r = 1.0;
+  for (int i = 2; i <= k; ++i) r *= i;
+  return r;
+}
+
+void cell_centre(const Tree& t, int level, uint64_t key, double c[3]) {
+  uint32_t ix, iy, iz;
+  deinterleave(key, level, &ix, &iy, &iz);  // the placeholder bit lies above the digits
+  double h = std::ldexp(t.side, -(level + 1));
+  uint32_t ic[3] = {ix, iy, iz};
+  for (int d = 0; d < 3; ++d) c[d] = t.lo[d] + (double)(2u * ic[d] + 1u) * h;
+}
+
+// b_max: largest distance from the geometric centre to a particle of the cell
+// (the source radius of the Multipole Error Bounds section's figure).
+double cell_bmax(const double* spos, const Cell& c) {
+  double m = 0.0;
+  for (int64_t j = c.first; j < c.first + c.count; ++j) {
+    double dx = spos[3 * j] - c.centre[0];
+    double dy = spos[3 * j + 1] - c.centre[1];
+    double dz = spos[3 * j + 2] - c.centre[2];
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    if (d2 > m) m = d2;
+  }
+  return std::sqrt(m);
+}
+
+int build_tree(Tree& t, int64_t n, const double* pos, const double* box) {
+  t.n = n;
+  if (box) {
+    for (int d = 0; d < 3; ++d) t.lo[d] = box[d];
+    t.side = box[3];
+  } else {
+    root_cube(n, pos, t.lo, &t.side);
+  }
+  int e;
+  std::frexp(t.side, &e);  // side = 2^(e-1)
+  double scale = std::ldexp(1.0, kBits - (e - 1));
+  std::vector<uint64_t> k0(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) q[d] = quantise(pos[3 * i + d], t.lo[d], scale);
+    k0[i] = (1ull << 63) | interleave(q[0], q[1], q[2]);
+  }
+  // Stable sort by key: equal keys keep caller order.
+  t.perm.resize(n);
+  for (int64_t i = 0; i < n; ++i) t.perm[i] = i;
+  std::stable_sort(t.perm.begin(), t.perm.end(),
+                   [&](int64_t a, int64_t b) { return k0[a] < k0[b]; });
+  t.key.resize(n);
+  for (int64_t i = 0; i < n; ++i) t.key[i] = k0[t.perm[i]];
+  std::vector<double> spos(3 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) spos[3 * i + d] = pos[3 * t.perm[i] + d];
+
+  // Cells level by level, children in octant order: a cell splits when it
+  // holds more than n_leaf particles and is above the deepest level.
+  t.cells.clear();
+  Cell root{};
+  root.level = 0;
+  root.key = 1;
+  root.first = 0;
+  root.count = n;
+  root.parent = -1;
+  t.cells.push_back(root);
+  size_t level_begin = 0;
+  for (int L = 0; L <= kBits; ++L) {
+    size_t level_end = t.cells.size();
+    for (size_t ci = level_begin; ci < level_end; ++ci) {
+      Cell& c = t.cells[ci];
+      c.child_first = -1;
+      c.n_child = 0;
+      c.is_leaf = !(c.count > t.n_leaf && L < kBits);
+      if (c.is_leaf) continue;
+      int shift = 3 * (kBits - (L + 1));
+      int64_t j = c.first, end = c.first + c.count;
+      int64_t cf = (int64_t)t.cells.size();
+      int nc = 0;
+      while (j < end) {
+        uint64_t pre = t.key[j] >> shift;
+        int64_t k = j;
+        while (k < end && (t.key[k] >> shift) == pre) ++k;
+        Cell ch{};
+        ch.level = L + 1;
+        ch.key = pre;
+        ch.first = j;
+        ch.count = k - j;
+        ch.parent = (int64_t)ci;
+        t.cells.push_back(ch);
+        ++nc;
+        j = k;
+      }
+      t.cells[ci].child_first = cf;
+      t.cells[ci].n_child = nc;
+    }
+    level_begin = level_end;
+    if (level_begin == t.cells.size()) break;
+  }
+  t.max_level = 0;
+  t.leaf_of.assign(n, -1);
+  for (size_t ci = 0; ci < t.cells.size(); ++ci) {
+    Cell& c = t.cells[ci];
+    cell_centre(t, c.level, c.key, c.centre);
+    c.bmax = cell_bmax(spos.data(), c);
+    t.max_level = std::max(t.max_level, c.level);
+    if (c.is_leaf)
+      for (int64_t j = c.first; j < c.first + c.count; ++j) t.leaf_of[j] = (int64_t)ci;
+  }
+  // Sink groups: the topmost cells holding at most n_group particles, or a
+  // leaf that still holds more.
+  t.groups.clear();
+  for (size_t ci = 0; ci < t.cells.size(); ++ci) {
+    const Cell& c = t.cells[ci];
+    bool top_small = c.count <= t.n_group &&
+                     (c.parent < 0 || t.cells[c.parent].count > t.n_group);
+    bool big_leaf = c.is_leaf && c.count > t.n_group;
+    if (top_small || big_leaf) t.groups.push_back((int64_t)ci);
+  }
+  std::sort(t.groups.begin(), t.groups.end(),
+            [&](int64_t a, int64_t b) { return t.cells[a].first < t.cells[b].first; });
+  t.group_of.assign(n, -1);
+  for (size_t g = 0; g < t.groups.size(); ++g) {
+    const Cell& c = t.cells[t.groups[g]];
+    for (int64_t j = c.first; j < c.first + c.count; ++j) t.group_of[j] = (int64_t)g;
+  }
+  for (int64_t j = 0; j < n; ++j)
+    if (t.group_of[j] < 0) return fail("internal: particle without a group");
+  t.has_lists = false;
+  t.p = -1;
+  t.mom.clear();
+  t.mom_valid.clear();
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Multipole acceptance (Multipole Error Bounds section, figure of the source
+// cell V of radius b_max and sink cell W): reading used here is the group
+// form of the b_max / theta criterion -- accept iff the centre distance
+// exceeds b_source / theta + b_sink, compared in squares, strict.
+// ---------------------------------------------------------------------------
+bool accept(const Cell& g, const Cell& c, double theta) {
+  double dx = g.centre[0] - c.centre[0];
+  double dy = g.centre[1] - c.centre[1];
+  double dz = g.centre[2] - c.centre[2];
+  double d2 = (dx * dx + dy * dy) + dz * dz;
+  double r = c.bmax / theta + g.bmax;
+  return d2 > r * r;
+}
+
+void walk(const Tree& t, const Cell& g, int64_t ci, double theta, int direct_max,
+          std::vector<int32_t>& p2p, std::vector<int32_t>& m2p) {
+  const Cell& c = t.cells[ci];
+  if (accept(g, c, theta)) {
+    if (c.count <= direct_max)
+      p2p.push_back((int32_t)ci);
+    else
+      m2p.push_back((int32_t)ci);
+    return;
+  }
+  if (c.is_leaf) {
+    p2p.push_back((int32_t)ci);
+    return;
+  }
+  for (int k = 0; k < c.n_child; ++k) walk(t, g, c.child_first + k, theta, direct_max, p2p, m2p);
+}
+
+int build_lists(Tree& t, double theta, int direct_max) {
+  const int64_t G = (int64_t)t.groups.size();
+  std::vector<std::vector<int32_t>> lp(G), lm(G);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < G; ++g)
+    walk(t, t.cells[t.groups[g]], 0, theta, direct_max, lp[g], lm[g]);
+  t.p2p_off.assign(G + 1, 0);
+  t.m2p_off.assign(G + 1, 0);
+  for (int64_t g = 0; g < G; ++g) {
+    t.p2p_off[g + 1] = t.p2p_off[g] + (int64_t)lp[g].size();
+    t.m2p_off[g + 1] = t.m2p_off[g] + (int64_t)lm[g].size();
+  }
+  t.p2p.resize(t.p2p_off[G]);
+  t.m2p.resize(t.m2p_off[G]);
+  for (int64_t g = 0; g < G; ++g) {
+    std::copy(lp[g].begin(), lp[g].end(), t.p2p.begin() + t.p2p_off[g]);
+    std::copy(lm[g].begin(), lm[g].end(), t.m2p.begin() + t.m2p_off[g]);
+  }
+  t.has_lists = true;
+  t.theta = theta;
+  t.direct_max = direct_max;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Moments (Multipole Error Bounds section, the moment tensor about a centre z):
+// M_alpha(z) = sum_j m_j (y_j - z)^alpha, raw (not traceless) multi-index
+// moments, |alpha| <= p, about the geometric cell centre.
+// ---------------------------------------------------------------------------
+void p2m_direct(const double* spos, const double* smass, const Cell& c, int p, double* out) {
+  const int K = nm(p);
+  for (int s = 0; s < K; ++s) out[s] = 0.0;
+  for (int64_t j = c.first; j < c.first + c.count; ++j) {
+    double d[3] = {spos[3 * j] - c.centre[0], spos[3 * j + 1] - c.centre[1],
+                   spos[3 * j + 2] - c.centre[2]};
+    for (int s = 0; s < K; ++s) {
+      const int* al = &g_alpha[3 * s];
+      out[s] += smass[j] * (ipow(d[0], al[0]) * ipow(d[1], al[1]) * ipow(d[2], al[2]));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Derivatives of the softened Green's function G(R) = -(|R|^2 + eps^2)^(-1/2)
+// (Force Smoothing section: Plummer smoothing; the expansion of the Multipole
+// Error Bounds section is written for an arbitrary G). For any f(s) with
+// s = |R|^2 + eps^2, the chain rule gives, per axis,
+//   d^a/dx^a f = sum_j a! / (j! (a-2j)!) (2x)^(a-2j) f^(a-j)(s),
+// and the three axes compose. With f(s) = -s^(-1/2),
+//   2^n f^(n)(s) = (-1)^(n+1) (2n-1)!! s^(-n-1/2).
+// ---------------------------------------------------------------------------
+struct Radial {
+  double F[16];  // F[n] = 2^n f^(n)(s)
+};
+
+Radial radial(double s, int nmax) {
+  Radial r;
+  double is = 1.0 / s;
+  double v = 1.0 / std::sqrt(s);  // s^(-1/2)
+  double dfact = 1.0;             // (2n-1)!!, with (-1)!! = 1
+  for (int n = 0; n <= nmax; ++n) {
+    double sign = (n % 2 == 0) ? -1.0 : 1.0;  // (-1)^(n+1)
+    r.F[n] = sign * dfact * v;
+    dfact *= (double)(2 * n + 1);
+    v *= is;
+  }
+  return r;
+}
+
+// d^alpha G at R, from the closed-form sum above.
+double dG(int a, int b, int c, const double R[3], const Radial& rad) {
+  const int al[3] = {a, b, c};
+  double total = 0.0;
+  for (int gx = 0; 2 * gx <= a; ++gx)
+    for (int gy = 0; 2 * gy <= b; ++gy)
+      for (int gz = 0; 2 * gz <= c; ++gz) {
+        const int g[3] = {gx, gy, gz};
+        double term = 1.0;
+        for (int d = 0; d < 3; ++d) {
+          int e = al[d] - 2 * g[d];
+          term *= factorial(al[d]) / (factorial(g[d]) * factorial(e)) * ipow(2.0 * R[d], e);
+        }
+        int order = a + b + c - (gx + gy + gz);
+        // (2R)^e f^(order) = R^e 2^(sum e) f^(order) and sum e = 2 order - |alpha|,
+        // so term * f^(order) = term * F[order] / 2^order.
+        total += term * rad.F[order] * std::ldexp(1.0, -order);
+      }
+  return total;
+}
+
+// Cell-body expansion (Delta = 0): the potential at R = x - centre is
+//   phi = sum_{|alpha|<=p} (-1)^|alpha| / alpha! M_alpha d^alpha G(R)
+// and the acceleration a_k = -d phi / d x_k.
+void m2p_one(const double* M, int p, const double R[3], double eps, double acc[3], double* phi) {
+  double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
+  Radial rad = radial(s, p + 1);
+  double a[3] = {0, 0, 0}, ph = 0.0;
+  for (int sl = 0; sl < nm(p); ++sl) {
+    const int* al = &g_alpha[3 * sl];
+    int n = al[0] + al[1] + al[2];
+    double w = ((n % 2) ? -1.0 : 1.0) / (factorial(al[0]) * factorial(al[1]) * factorial(al[2]));
+    double wm = w * M[sl];
+    ph += wm * dG(al[0], al[1], al[2], R, rad);
+    a[0] -= wm * dG(al[0] + 1, al[1], al[2], R, rad);
+    a[1] -= wm * dG(al[0], al[1] + 1, al[2], R, rad);
+    a[2] -= wm * dG(al[0], al[1], al[2] + 1, R, rad);
+  }
+  acc[0] = a[0];
+  acc[1] = a[1];
+  acc[2] = a[2];
+  if (phi) *phi = ph;
+}
+
+// Softened pair kernel: contribution of source j (mass m, offset r = x_j - x_i).
+inline void p2p_pair(double m, const double r[3], double eps, double acc[3], double* phi) {
+  double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
+  if (s == 0.0) return;
+  double inv = 1.0 / std::sqrt(s);
+  double inv3 = inv * inv * inv;
+  for (int d = 0; d < 3; ++d) acc[d] += m * r[d] * inv3;
+  if (phi) *phi -= m * inv;
+}
+
+// Neumaier-compensated accumulator.
+struct NSum {
+  double s = 0, c = 0;
+  void add(double x) {
+    double t = s + x;
+    if (std::fabs(s) >= std::fabs(x))
+      c += (s - t) + x;
+    else
+      c += (x - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+}  // namespace
+
+// ===========================================================================
+// C ABI (host pointers only)
+// ===========================================================================
+extern "C" {
+
+const char* oracle_last_error(void) { return g_err.c_str(); }
+
+int oracle_nm(int p) { return nm(p); }
+
+// Keys in caller order plus the root cube (lo[3], side) actually used.
+int oracle_morton_keys(int64_t n, const double* pos, const double* box, double* lo_side,
+                       uint64_t* keys) {
+  if (n < 1 || !pos || !keys) return fail("bad arguments");
+  double lo[3], side;
+  if (box) {
+    lo[0] = box[0], lo[1] = box[1], lo[2] = box[2], side = box[3];
+    if (!is_pow2(side)) return fail("box side must be a positive power of two");
+  } else {
+    root_cube(n, pos, lo, &side);
+  }
+  int e;
+  std::frexp(side, &e);
+  double scale = std::ldexp(1.0, kBits - (e - 1));
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) q[d] = quantise(pos[3 * i + d], lo[d], scale);
+    keys[i] = (1ull << 63) | interleave(q[0], q[1], q[2]);
+  }
+  if (lo_side) {
+    lo_side[0] = lo[0], lo_side[1] = lo[1], lo_side[2] = lo[2], lo_side[3] = side;
+  }
+  return 0;
+}
+
+int oracle_tree_build(int64_t n, const double* pos, int n_leaf, int n_group, const double* box,
+                      void** out) {
+  ensure_alpha();
+  if (n < 1 || !pos || !out) return fail("bad arguments");
+  if (n_leaf < 1 || n_group < n_leaf) return fail("need 1 <= n_leaf <= n_group");
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(pos[i])) return fail("non-finite position");
+  if (box) {
+    if (!is_pow2(box[3])) return fail("box side must be a positive power of two");
+    for (int64_t i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d)
+        if (pos[3 * i + d] < box[d] || pos[3 * i + d] > box[d] + box[3])
+          return fail("point outside the given box");
+  }
+  Tree* t = new Tree();
+  t->n_leaf = n_leaf;
+  t->n_group = n_group;
+  int rc = build_tree(*t, n, pos, box);
+  if (rc) {
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return 0;
+}
+
+void oracle_tree_destroy(void* h) { delete (Tree*)h; }
+
+// counts: n, n_cells, n_groups, n_leaves, max_level, n_p2p_entries,
+// n_m2p_entries, lo[3] and side as bits are not included (see get_root).
+int oracle_tree_counts(void* h, int64_t* out) {
+  Tree* t = (Tree*)h;
+  int64_t leaves = 0;
+  for (auto& c : t->cells) leaves += c.is_leaf;
+  out[0] = t->n;
+  out[1] = (int64_t)t->cells.size();
+  out[2] = (int64_t)t->groups.size();
+  out[3] = leaves;
+  out[4] = t->max_level;
+  out[5] = t->has_lists ? (int64_t)t->p2p.size() : -1;
+  out[6] = t->has_lists ? (int64_t)t->m2p.size() : -1;
+  return 0;
+}
+
+int oracle_tree_root(void* h, double* lo_side) {
+  Tree* t = (Tree*)h;
+  lo_side[0] = t->lo[0], lo_side[1] = t->lo[1], lo_side[2] = t->lo[2], lo_side[3] = t->side;
+  return 0;
+}
+
+int oracle_tree_get_keys(void* h, uint64_t* keys, int64_t* perm) {
+  Tree* t = (Tree*)h;
+  if (keys) std::copy(t->key.begin(), t->key.end(), keys);
+  if (perm) std::copy(t->perm.begin(), t->perm.end(), perm);
+  return 0;
+}
+
+int oracle_tree_get_cells(void* h, int32_t* level, uint64_t* key, int64_t* first, int64_t* count,
+                          int64_t* parent, int64_t* child_first, int32_t* n_child,
+                          int32_t* is_leaf, double* centre, double* bmax) {
+  Tree* t = (Tree*)h;
+  for (size_t i = 0; i < t->cells.size(); ++i) {
+    const Cell& c = t->cells[i];
+    if (level) level[i] = c.level;
+    if (key) key[i] = c.key;
+    if (first) first[i] = c.first;
+    if (count) count[i] = c.count;
+    if (parent) parent[i] = c.parent;
+    if (child_first) child_first[i] = c.child_first;
+    if (n_child) n_child[i] = c.n_child;
+    if (is_leaf) is_leaf[i] = c.is_leaf;
+    if (centre)
+      for (int d = 0; d < 3; ++d) centre[3 * i + d] = c.centre[d];
+    if (bmax) bmax[i] = c.bmax;
+  }
+  return 0;
+}
+
+int oracle_tree_get_groups(void* h, int64_t* groups) {
+  Tree* t = (Tree*)h;
+  std::copy(t->groups.begin(), t->groups.end(), groups);
+  return 0;
+}
+
+int oracle_build_lists(void* h, double theta, int direct_max) {
+  Tree* t = (Tree*)h;
+  if (!(theta > 0 && theta < 1)) return fail("theta must lie in (0, 1)");
+  if (direct_max < 0) return fail("direct_max must be >= 0");
+  return build_lists(*t, theta, direct_max);
+}
+
+int oracle_get_lists(void* h, int64_t* p2p_off, int32_t* p2p, int64_t* m2p_off, int32_t* m2p) {
+  Tree* t = (Tree*)h;
+  if (!t->has_lists) return fail("no lists");
+  if (p2p_off) std::copy(t->p2p_off.begin(), t->p2p_off.end(), p2p_off);
+  if (p2p) std::copy(t->p2p.begin(), t->p2p.end(), p2p);
+  if (m2p_off) std::copy(t->m2p_off.begin(), t->m2p_off.end(), m2p_off);
+  if (m2p) std::copy(t->m2p.begin(), t->m2p.end(), m2p);
+  return 0;
+}
+
+// Moments of the selected cells (all cells if sel is null) from the given
+// positions (caller order); the tree's membership and centres stay fixed.
+int oracle_compute_moments(void* h, const double* pos, const double* mass, int p, int64_t n_sel,
+                           const int64_t* sel) {
+  Tree* t = (Tree*)h;
+  if (p < 0 || p > 10) return fail("p must lie in [0, 10]");
+  const int64_t n = t->n;
+  std::vector<double> spos(3 * n), sm(n);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int d = 0; d < 3; ++d) spos[3 * i + d] = pos[3 * t->perm[i] + d];
+    sm[i] = mass[t->perm[i]];
+  }
+  const int K = nm(p);
+  const int64_t C = (int64_t)t->cells.size();
+  if (t->p != p || (int64_t)t->mom.size() != C * K) {
+    t->mom.assign(C * K, 0.0);
+    t->mom_valid.assign(C, 0);
+    t->p = p;
+  }
+  std::vector<int64_t> todo;
+  if (sel) {
+    todo.assign(sel, sel + n_sel);
+  } else {
+    todo.resize(C);
+    for (int64_t i = 0; i < C; ++i) todo[i] = i;
+  }
+  // Largest cells first so that the long ones start early.
+  std::sort(todo.begin(), todo.end(),
+            [&](int64_t a, int64_t b) { return t->cells[a].count > t->cells[b].count; });
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < (int64_t)todo.size(); ++k) {
+    int64_t ci = todo[k];
+    p2m_direct(spos.data(), sm.data(), t->cells[ci], p, &t->mom[ci * K]);
+    t->mom_valid[ci] = 1;
+  }
+  return 0;
+}
+
+int oracle_get_moments(void* h, double* out) {
+  Tree* t = (Tree*)h;
+  std::copy(t->mom.begin(), t->mom.end(), out);
+  return 0;
+}
+
+// O-T: treecode accelerations (and potentials) for the selected sinks (caller
+// indices; all if null), accumulated in FP64 in list order: P2P entries first,
+// then M2P entries. counts[0] = P2P pairs (including the skipped self slot),
+// counts[1] = M2P pairs, over the evaluated sinks.
+int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps, int64_t n_sinks,
+                     const int64_t* sinks, double* acc, double* pot, int64_t* counts) {
+  Tree* t = (Tree*)h;
+  if (!t->has_lists) return fail("lists not built");
+  if (t->p < 0) return fail("moments not computed");
+  if (!(eps >= 0) || !std::isfinite(eps)) return fail("eps must be finite and >= 0");
+  const int64_t n = t->n;
+  const int K = nm(t->p);
+  std::vector<int64_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[t->perm[i]] = i;
+  std::vector<int64_t> todo;
+  if (sinks) {
+    todo.assign(sinks, sinks + n_sinks);
+  } else {
+    todo.resize(n);
+    for (int64_t i = 0; i < n; ++i) todo[i] = i;
+  }
+  const int64_t T = (int64_t)todo.size();
+  // every M2P cell used must have moments
+  for (int64_t k = 0; k < T; ++k) {
+    int64_t g = t->group_of[inv[todo[k]]];
+    for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e)
+      if (!t->mom_valid[t->m2p[e]]) return fail("moments missing for an M2P cell");
+  }
+  int64_t c_p2p = 0, c_m2p = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : c_p2p, c_m2p)
+  for (int64_t k = 0; k < T; ++k) {
+    const int64_t ci = todo[k];
+    const int64_t si = inv[ci];
+    const int64_t g = t->group_of[si];
+    const double* xi = &pos[3 * ci];
+    double a[3] = {0, 0, 0}, ph = 0.0;
+    for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) {
+      const Cell& c = t->cells[t->p2p[e]];
+      c_p2p += c.count;
+      for (int64_t j = c.first; j < c.first + c.count; ++j) {
+        if (j == si) continue;
+        const double* xj = &pos[3 * t->perm[j]];
+        double r[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+        p2p_pair(mass[t->perm[j]], r, eps, a, &ph);
+      }
+    }
+    for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e) {
+      const int64_t cid = t->m2p[e];
+      const Cell& c = t->cells[cid];
+      double R[3] = {xi[0] - c.centre[0], xi[1] - c.centre[1], xi[2] - c.centre[2]};
+      double da[3], dphi;
+      m2p_one(&t->mom[cid * K], t->p, R, eps, da, &dphi);
+      a[0] += da[0], a[1] += da[1], a[2] += da[2];
+      ph += dphi;
+      c_m2p += 1;
+    }
+    for (int d = 0; d < 3; ++d) acc[3 * k + d] = a[d];
+    if (pot) pot[k] = ph;
+  }
+  if (counts) {
+    counts[0] = c_p2p;
+    counts[1] = c_m2p;
+  }
+  return 0;
+}
+
+// O-D: exact softened direct sum for the selected sinks (caller indices; all
+// if null) over all sources, j = i skipped, compensated sums.
+int oracle_direct(int64_t n, const double* pos, const double* mass, double eps, int64_t n_sinks,
+                  const int64_t* sinks, double* acc, double* pot) {
+  if (n < 1 || !pos || !mass || !acc) return fail("bad arguments");
+  const int64_t T = sinks ? n_sinks : n;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < T; ++k) {
+    const int64_t i = sinks ? sinks[k] : k;
+    NSum a[3], ph;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double r[3] = {pos[3 * j] - pos[3 * i], pos[3 * j + 1] - pos[3 * i + 1],
+                     pos[3 * j + 2] - pos[3 * i + 2]};
+      double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
+      if (s == 0.0) continue;
+      double inv = 1.0 / std::sqrt(s);
+      double inv3 = inv * inv * inv;
+      for (int d = 0; d < 3; ++d) a[d].add(mass[j] * r[d] * inv3);
+      ph.add(-mass[j] * inv);
+    }
+    for (int d = 0; d < 3; ++d) acc[3 * k + d] = a[d].value();
+    if (pot) pot[k] = ph.value();
+  }
+  return 0;
+}
+
+// VJP of O-D: xbar_k = sum_{j != k} H(r_kj) (m_k abar_j - m_j abar_k), with
+// r_kj = x_j - x_k and H(r) = s^(-3/2) I - 3 r r^T s^(-5/2), s = |r|^2 + eps^2;
+// mbar_k = sum_{i != k} abar_i . (x_k - x_i) s^(-3/2).
+int oracle_direct_vjp(int64_t n, const double* pos, const double* mass, double eps,
+                      const double* abar, int64_t n_rows, const int64_t* rows, double* xbar,
+                      double* mbar) {
+  if (n < 1 || !pos || !mass || !abar || !xbar) return fail("bad arguments");
+  const int64_t T = rows ? n_rows : n;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < T; ++q) {
+    const int64_t k = rows ? rows[q] : q;
+    NSum xb[3], mb;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == k) continue;
+      double r[3] = {pos[3 * j] - pos[3 * k], pos[3 * j + 1] - pos[3 * k + 1],
+                     pos[3 * j + 2] - pos[3 * k + 2]};
+      double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
+      if (s == 0.0) continue;
+      double inv = 1.0 / std::sqrt(s);
+      double inv3 = inv * inv * inv;
+      double inv5 = inv3 * inv * inv;
+      double v[3];
+      for (int d = 0; d < 3; ++d) v[d] = mass[k] * abar[3 * j + d] - mass[j] * abar[3 * k + d];
+      double rv = (r[0] * v[0] + r[1] * v[1]) + r[2] * v[2];
+      for (int d = 0; d < 3; ++d) xb[d].add(v[d] * inv3 - 3.0 * r[d] * rv * inv5);
+      // d a_j / d m_k = (x_k - x_j) s^-3/2 = -r s^-3/2
+      double ra = (r[0] * abar[3 * j] + r[1] * abar[3 * j + 1]) + r[2] * abar[3 * j + 2];
+      mb.add(-ra * inv3);
+    }
+    for (int d = 0; d < 3; ++d) xbar[3 * q + d] = xb[d].value();
+    if (mbar) mbar[q] = mb.value();
+  }
+  return 0;
+}
+
+// VJP of O-T with the topology (membership, centres, b_max, lists) held
+// fixed: the gradient of sum_i abar_i . a_i with respect to every position
+// (and mass). Moments are functions of the positions through their
+// definition; centres do not move.
+int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
+                    const double* abar, double* xbar, double* mbar) {
+  Tree* t = (Tree*)h;
+  if (!t->has_lists) return fail("lists not built");
+  if (t->p < 0) return fail("moments not computed");
+  const int64_t n = t->n;
+  const int p = t->p;
+  const int K = nm(p);
+  const int64_t C = (int64_t)t->cells.size();
+  const int64_t G = (int64_t)t->groups.size();
+  for (int64_t c = 0; c < C; ++c)
+    if (!t->mom_valid[c]) return fail("all moments are needed for the VJP");
+  std::vector<double> xb(3 * n, 0.0), mb(n, 0.0);   // indexed by sorted position
+  std::vector<double> Mbar(C * K, 0.0);
+  std::vector<char> used(C, 0);
+  // (1) P2P pairs and (2) M2P sink side, per group; P2P source side and M2P
+  // cell cotangents are collected per group and then added in group order.
+  std::vector<std::vector<double>> src_x(G), src_m(G), cellbar(G);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t g = 0; g < G; ++g) {
+    const Cell& gc = t->cells[t->groups[g]];
+    // P2P source contributions of this group, in list order
+    int64_t nsrc = 0;
+    for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) nsrc += t->cells[t->p2p[e]].count;
+    src_x[g].assign(3 * nsrc, 0.0);
+    src_m[g].assign(nsrc, 0.0);
+    const int64_t nm2p = t->m2p_off[g + 1] - t->m2p_off[g];
+    cellbar[g].assign(nm2p * K, 0.0);
+    for (int64_t si = gc.first; si < gc.first + gc.count; ++si) {
+      const int64_t ci = t->perm[si];
+      const double* xi = &pos[3 * ci];
+      const double* ab = &abar[3 * ci];
+      int64_t off = 0;
+      for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) {
+        const Cell& c = t->cells[t->p2p[e]];
+        for (int64_t j = c.first; j < c.first + c.count; ++j, ++off) {
+          if (j == si) continue;
+          const int64_t cj = t->perm[j];
+          double r[3] = {pos[3 * cj] - xi[0], pos[3 * cj + 1] - xi[1], pos[3 * cj + 2] - xi[2]};
+          double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
+          if (s == 0.0) continue;
+          double inv = 1.0 / std::sqrt(s);
+          double inv3 = inv * inv * inv, inv5 = inv3 * inv * inv;
+          double ra = (r[0] * ab[0] + r[1] * ab[1]) + r[2] * ab[2];
+          double mj = mass[cj];
+          double Hab[3];
+          for (int d = 0; d < 3; ++d) Hab[d] = ab[d] * inv3 - 3.0 * r[d] * ra * inv5;
+          for (int d = 0; d < 3; ++d) {
+            xb[3 * si + d] -= mj * Hab[d];         // sink moves: r = x_j - x_i
+            src_x[g][3 * off + d] += mj * Hab[d];  // source moves
+          }
+          src_m[g][off] += ra * inv3;              // d a_i / d m_j = r s^-3/2
+        }
+      }
+      for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e) {
+        const int64_t cid = t->m2p[e];
+        const Cell& c = t->cells[cid];
+        const double* M = &t->mom[cid * K];
+        double R[3] = {xi[0] - c.centre[0], xi[1] - c.centre[1], xi[2] - c.centre[2]};
+        double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
+        Radial rad = radial(s, p + 2);
+        double* Mb = &cellbar[g][(e - t->m2p_off[g]) * K];
+        for (int sl = 0; sl < K; ++sl) {
+          const int* al = &g_alpha[3 * sl];
+          int nn = al[0] + al[1] + al[2];
+          double w = ((nn % 2) ? -1.0 : 1.0) /
+                     (factorial(al[0]) * factorial(al[1]) * factorial(al[2]));
+          // a_k = -sum w M d^{alpha+e_k} G ;  d a_k / d x_l = -sum w M d^{alpha+e_k+e_l} G
+          for (int k = 0; k < 3; ++k) {
+            int b[3] = {al[0], al[1], al[2]};
+            b[k] += 1;
+            double d1 = dG(b[0], b[1], b[2], R, rad);
+            Mb[sl] -= w * ab[k] * d1;
+            for (int l = 0; l < 3; ++l) {
+              int bb[3] = {b[0], b[1], b[2]};
+              bb[l] += 1;
+              xb[3 * si + l] -= w * M[sl] * ab[k] * dG(bb[0], bb[1], bb[2], R, rad);
+            }
+          }
+        }
+      }
+    }
+  }
+  // add the per-group source and cell parts in group order
+  for (int64_t g = 0; g < G; ++g) {
+    int64_t off = 0;
+    for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) {
+      const Cell& c = t->cells[t->p2p[e]];
+      for (int64_t j = c.first; j < c.first + c.count; ++j, ++off) {
+        for (int d = 0; d < 3; ++d) xb[3 * j + d] += src_x[g][3 * off + d];
+        mb[j] += src_m[g][off];
+      }
+    }
+    for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e) {
+      const int64_t cid = t->m2p[e];
+      used[cid] = 1;
+      for (int sl = 0; sl < K; ++sl) Mbar[cid * K + sl] += cellbar[g][(e - t->m2p_off[g]) * K + sl];
+    }
+  }
+  // (3) moment cotangents to particles through the moment definition:
+  // d M_alpha / d x_{j,d} = m_j alpha_d (x_j - c)^(alpha - e_d),
+  // d M_alpha / d m_j = (x_j - c)^alpha.
+  for (int64_t cid = 0; cid < C; ++cid) {
+    if (!used[cid]) continue;
+    const Cell& c = t->cells[cid];
+    const double* Mb = &Mbar[cid * K];
+#pragma omp parallel for schedule(static)
+    for (int64_t j = c.first; j < c.first + c.count; ++j) {
+      const int64_t cj = t->perm[j];
+      double d[3] = {pos[3 * cj] - c.centre[0], pos[3 * cj + 1] - c.centre[1],
+                     pos[3 * cj + 2] - c.centre[2]};
+      double gx[3] = {0, 0, 0}, gm = 0.0;
+      for (int sl = 0; sl < K; ++sl) {
+        const int* al = &g_alpha[3 * sl];
+        gm += Mb[sl] * ipow(d[0], al[0]) * ipow(d[1], al[1]) * ipow(d[2], al[2]);
+        for (int q = 0; q < 3; ++q) {
+          if (al[q] == 0) continue;
+          int e3[3] = {al[0], al[1], al[2]};
+          e3[q] -= 1;
+          gx[q] += Mb[sl] * (double)al[q] * ipow(d[0], e3[0]) * ipow(d[1], e3[1]) * ipow(d[2], e3[2]);
+        }
+      }
+      for (int q = 0; q < 3; ++q) xb[3 * j + q] += mass[cj] * gx[q];
+      mb[j] += gm;
+    }
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t cj = t->perm[j];
+    for (int d = 0; d < 3; ++d) xbar[3 * cj + d] = xb[3 * j + d];
+    if (mbar) mbar[cj] = mb[j];
+  }
+  return 0;
+}
+
+// Single cell-body expansion (for pins): acc[0..2], acc[3] = phi.
+int oracle_m2p(int p, const double* M, const double* R, double eps, double* acc4) {
+  ensure_alpha();
+  if (p < 0 || p > 10) return fail("p must lie in [0, 10]");
+  m2p_one(M, p, R, eps, acc4, &acc4[3]);
+  return 0;
+}
+
+// Moments of a point set about a centre (for pins).
+int oracle_p2m(int p, int64_t n, const double* pos, const double* mass, const double* centre,
+               double* out) {
+  ensure_alpha();
+  Cell c{};
+  c.first = 0;
+  c.count = n;
+  for (int d = 0; d < 3; ++d) c.centre[d] = centre[d];
+  p2m_direct(pos, mass, c, p, out);
+  return 0;
+}
+
+// All derivatives d^alpha G(R), |alpha| <= order, in storage order (for pins).
+int oracle_derivs(int order, const double* R, double eps, double* out) {
+  ensure_alpha();
+  if (order < 0 || order > 12) return fail("order must lie in [0, 12]");
+  double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
+  Radial rad = radial(s, order);
+  for (int sl = 0; sl < nm(order); ++sl) {
+    const int* al = &g_alpha[3 * sl];
+    out[sl] = dG(al[0], al[1], al[2], R, rad);
+  }
+  return 0;
+}
+
+// Re-centring of moments (Multipole Error Bounds section: M about a shifted
+// centre written as powers of the shift): given M about z, return M about
+// z' = z - shift, i.e. M'_alpha = sum_{beta <= alpha} C(alpha, beta)
+// shift^(alpha - beta) M_beta, shift = z - z'.
+int oracle_m2m(int p, const double* M, const double* shift, double* out) {
+  ensure_alpha();
+  const int K = nm(p);
+  for (int s = 0; s < K; ++s) {
+    const int* al = &g_alpha[3 * s];
+    double acc = 0.0;
+    for (int b0 = 0; b0 <= al[0]; ++b0)
+      for (int b1 = 0; b1 <= al[1]; ++b1)
+        for (int b2 = 0; b2 <= al[2]; ++b2) {
+          double binom = factorial(al[0]) / (factorial(b0) * factorial(al[0] - b0)) *
+                         factorial(al[1]) / (factorial(b1) * factorial(al[1] - b1)) *
+                         factorial(al[2]) / (factorial(b2) * factorial(al[2] - b2));
+          acc += binom * ipow(shift[0], al[0] - b0) * ipow(shift[1], al[1] - b1) *
+                 ipow(shift[2], al[2] - b2) * M[mindex(b0, b1, b2)];
+        }
+    out[s] = acc;
+  }
+  return 0;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  // extern "C"
