@@ -1,0 +1,204 @@
+/*
+ * hot.h -- C ABI of the MI355X hashed oct-tree gravitational force library.
+ *
+ * The library evaluates the softened Newtonian accelerations of N particles
+ * (eq. "eom" of the Mathematical Approach section at scale factor a = 1 and
+ * G = 1, with the Plummer smoothing of the Force Smoothing section) by the
+ * cell-body multipole treecode of the paper: integer Morton keys and a sort
+ * (Domain Decomposition section), an oct-tree of key-addressed cells kept in
+ * a hash table (Tree Construction and Traversal section), moments about
+ * geometric cell centres (Background Subtraction and Multipole Error Bounds
+ * sections), a multipole acceptance walk per sink cell with m x n blocking
+ * (Improving instruction-level parallelism section) and the Cartesian
+ * expansion with Delta = 0 (Multipole Error Bounds section). It also gives
+ * the reverse derivative (vector-Jacobian product) of that evaluation with the
+ * tree topology held fixed.
+ *
+ * Conventions shared by every call:
+ *  - All array arguments are DEVICE pointers unless the comment says host.
+ *  - pos / acc / pos_bar / acc_bar: N x 3 row-major float64 (x0 y0 z0 x1 ...).
+ *    mass / pot / mass_bar: N float64. Outputs are in caller order.
+ *  - Work is enqueued on the context's HIP stream and may still be running
+ *    when a call returns. The caller keeps its buffers alive until the stream
+ *    has passed the call. Calls that must size device buffers from device
+ *    results (tree_build, build_interaction_lists) synchronise the stream.
+ *  - Return value: HOT_OK (0) or a negative HOT_E_* code; hot_last_error()
+ *    gives a message. A failed call leaves the tree as it was before the call
+ *    or marks it invalid (then only tree_destroy is accepted); nothing leaks.
+ *  - One context per host thread. A tree belongs to the context that built it.
+ */
+#ifndef HOT_H
+#define HOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HOT_OK = 0,
+  HOT_E_INVALID = -1,  /* bad argument: see each call */
+  HOT_E_STATE = -2,    /* call out of order (e.g. eval before moments) */
+  HOT_E_OOM = -3,      /* device allocation failed */
+  HOT_E_DEVICE = -4,   /* a HIP runtime error */
+  HOT_E_CAPACITY = -5  /* a size limit of this build was exceeded */
+};
+
+enum { HOT_MIXED = 0, HOT_FP64 = 1 };
+
+typedef struct hot_ctx hot_ctx;
+typedef struct hot_tree hot_tree;
+
+/* Optional device allocator. alloc returns NULL on failure; both run on the
+ * caller's thread and receive the context stream. NULL selects
+ * hipMallocAsync / hipFreeAsync on the context stream. */
+typedef struct hot_allocator {
+  void* (*alloc)(void* user, size_t bytes, void* stream);
+  void (*free)(void* user, void* ptr, void* stream);
+  void* user;
+} hot_allocator;
+
+/* Tree shape. n_leaf: a cell holding more than n_leaf particles is split
+ * (1 <= n_leaf <= n_group). n_group: sink groups are the topmost cells with at
+ * most n_group particles, or leaves that still hold more (1 <= n_group <=
+ * 4096). box (HOST pointer, may be NULL): lo[3], side -- the root cube, side
+ * a positive power of two, every point inside [lo, lo + side]; NULL derives
+ * it from the data (per-axis minimum, next power of two of the largest
+ * extent). Unless set, n_leaf = 16 and n_group = 64. */
+typedef struct hot_build_opts {
+  int n_leaf;
+  int n_group;
+  const double* box;
+} hot_build_opts;
+
+/* Counters filled by eval_forces when stats is not NULL (HOST struct). The
+ * call then synchronises the stream and times its kernels. */
+typedef struct hot_stats {
+  int64_t p2p_pairs;     /* sum over sinks of the particles in their P2P cells */
+  int64_t m2p_pairs;     /* sum over sinks of their M2P cells */
+  double ms_p2p;
+  double ms_m2p;
+  double ms_total;
+} hot_stats;
+
+/* Context on one device. hip_stream (hipStream_t) may be NULL for the null
+ * stream. allocator may be NULL (see hot_allocator). */
+int hot_ctx_create(int device, void* hip_stream, const hot_allocator* allocator, hot_ctx** out);
+int hot_ctx_destroy(hot_ctx* ctx);
+/* Message of the last failure on this context (never NULL). */
+const char* hot_last_error(hot_ctx* ctx);
+/* Wait for the stream; returns a deferred device-side error (e.g. a
+ * non-finite position or mass found by an asynchronous call) as
+ * HOT_E_INVALID, or a HIP error as HOT_E_DEVICE. */
+int hot_sync(hot_ctx* ctx);
+
+/*
+ * tree_build -- keys, sort, cells, hash table, sink groups and b_max.
+ * Domain Decomposition section (keys mapped from coordinates, sorted) and
+ * Tree Construction and Traversal section (hashed oct-tree cells).
+ * Keys: 21 bits per axis quantised as floor((x - lo) 2^21 / side), clamped to
+ * 2^21 - 1; octant digit 4x + 2y + z from the most significant level; a
+ * leading placeholder bit (the root key is 1). Sort: stable by key. A cell at
+ * level L < 21 with more than n_leaf particles has its non-empty octants as
+ * children. Centres are the geometric cube centres, b_max the largest
+ * particle distance from the centre.
+ * n: 1 .. 2^31 - 1. pos: N x 3 (device). Errors: HOT_E_INVALID for bad sizes
+ * or options, non-finite positions, a box side that is not a power of two, a
+ * point outside the given box. The tree holds device memory until
+ * tree_destroy.
+ */
+int tree_build(hot_ctx* ctx, int64_t n, const double* pos, const hot_build_opts* opts,
+               hot_tree** out);
+int tree_destroy(hot_ctx* ctx, hot_tree* tree);
+
+/*
+ * compute_moments -- raw Cartesian moments of every cell to order p about its
+ * geometric centre, M_alpha = sum_j m_j (x_j - c)^alpha, |alpha| <= p (the
+ * moment tensor of the Multipole Error Bounds section; order p = 2 is the
+ * quadrupole, 4 the hexadecapole). Leaves from their particles, other cells by
+ * re-centring their children's moments. FP64. pos may differ from the
+ * positions the tree was built from: membership and centres stay fixed.
+ * mass: N (device), finite and >= 0 (checked asynchronously, reported by the
+ * next synchronising call). p: 0 .. 8.
+ */
+int compute_moments(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass, int p);
+
+/*
+ * build_interaction_lists -- for every sink group g, a depth-first walk of the
+ * source tree from the root, children in octant order: a cell c passing the
+ * acceptance test goes to the M2P list (or to the P2P list if it holds at
+ * most direct_max particles); a leaf failing it goes to the P2P list; any
+ * other cell is opened. Acceptance: with d the distance between the group and
+ * cell centres, d^2 > (b_c / theta + b_g)^2 (FP64, no fused multiply-add);
+ * the group form of the b_max criterion in the source/sink geometry of the
+ * Multipole Error Bounds section. Lists are in depth-first preorder.
+ * theta: (0, 1). direct_max: >= 0. Synchronises the stream once.
+ */
+int build_interaction_lists(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
+
+/*
+ * eval_forces -- accelerations (and optionally potentials) of all particles:
+ *   a_i = sum over P2P cells, j != i:  m_j (x_j - x_i) (|x_j - x_i|^2 + eps^2)^(-3/2)
+ *       + sum over M2P cells c:  -sum_{|alpha|<=p} (-1)^|alpha|/alpha! M_alpha
+ *                                 d^(alpha+e_k) G(x_i - c),  G(R) = -(|R|^2+eps^2)^(-1/2)
+ * (pair kernel of eq. "eom" with Plummer smoothing; the cell-body expansion
+ * with Delta = 0 of the Multipole Error Bounds section, softened G).
+ * precision HOT_MIXED: pair and expansion arithmetic in FP32 on offsets from
+ * FP64 group centres, expansions scaled by the source cell side, per-sink
+ * compensated (Kahan) FP32 sums, FP64 output; HOT_FP64: all FP64.
+ * eps: finite, >= 0. acc: N x 3 out. pot: N out or NULL (phi_i = -sum m_j
+ * (r^2+eps^2)^(-1/2) + expansion). stats: HOST or NULL. Needs
+ * compute_moments and build_interaction_lists on this tree first.
+ */
+int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass, double eps,
+                int precision, double* acc, double* pot, hot_stats* stats);
+
+/*
+ * eval_forces_adjoint -- the vector-Jacobian product of eval_forces with the
+ * topology (membership, centres, b_max, lists) held fixed:
+ *   pos_bar = d(sum_i acc_bar_i . a_i)/d pos,  mass_bar = d(...)/d mass.
+ * Pair terms move both the sink and the source; expansion terms move the sink
+ * (second derivatives of the expansion) and the source particles through the
+ * moments (centres fixed). acc_bar: N x 3 (device). pos_bar: N x 3 out.
+ * mass_bar: N out or NULL. Same precision modes as eval_forces. The first call
+ * on a tree builds and caches transposed lists.
+ */
+int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass,
+                        double eps, int precision, const double* acc_bar, double* pos_bar,
+                        double* mass_bar);
+
+/* ---- host-copy getters (synchronise; for tests and diagnostics) ---------- */
+
+/* out[16]: n, n_cells, n_groups, n_leaves, max_level, n_p2p_entries,
+ * n_m2p_entries, p (or -1), n_work_items, hash_slots, 0... (-1 where not yet
+ * built). */
+int tree_get_counts(hot_ctx* ctx, hot_tree* tree, int64_t* out);
+/* HOST: lo_side[4] = root cube lo[3], side. */
+int tree_get_root(hot_ctx* ctx, hot_tree* tree, double* lo_side);
+/* HOST: sorted keys [N] and perm [N] (sorted position -> caller index). */
+int tree_get_keys(hot_ctx* ctx, hot_tree* tree, uint64_t* keys, uint32_t* perm);
+/* HOST arrays of n_cells entries (any may be NULL), canonical order
+ * (level, key): level, key (with placeholder), first particle (sorted
+ * position), count, parent (-1 root), first child (-1 none), number of
+ * children, leaf flag, centre (x y z per cell), b_max. */
+int tree_get_cells(hot_ctx* ctx, hot_tree* tree, int32_t* level, uint64_t* key, int32_t* first,
+                   int32_t* count, int32_t* parent, int32_t* child_first, int32_t* n_child,
+                   int32_t* is_leaf, double* centre, double* bmax);
+/* HOST: group cell ids [n_groups], ordered by first particle. */
+int tree_get_groups(hot_ctx* ctx, hot_tree* tree, int32_t* groups);
+/* HOST: CSR lists over groups: p2p_off [n_groups+1], p2p [n_p2p_entries],
+ * m2p_off, m2p (cell ids); any may be NULL. */
+int tree_get_lists(hot_ctx* ctx, hot_tree* tree, int64_t* p2p_off, int32_t* p2p,
+                   int64_t* m2p_off, int32_t* m2p);
+/* HOST: FP64 moments [n_cells x (p+1)(p+2)(p+3)/6], slot order by order n,
+ * then x exponent descending, then y exponent descending. */
+int tree_get_moments(hot_ctx* ctx, hot_tree* tree, double* out);
+/* Hash-table lookup of cell keys (HOST arrays): cell id or -1. */
+int tree_lookup(hot_ctx* ctx, hot_tree* tree, int64_t nq, const uint64_t* keys, int32_t* cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOT_H */

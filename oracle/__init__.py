@@ -135,8 +135,16 @@ class Tree:
         _chk(lib().oracle_tree_get_groups(self.h, _p(g)))
         return g
 
-    def build_lists(self, theta, direct_max=0):
-        _chk(lib().oracle_build_lists(self.h, ctypes.c_double(theta), int(direct_max)))
+    def build_lists(self, theta, direct_max=0, groups=None):
+        sel = _i64(groups)
+        ns = 0 if sel is None else sel.shape[0]
+        _chk(lib().oracle_build_lists(self.h, ctypes.c_double(theta), int(direct_max),
+                                      ctypes.c_int64(ns), _p(sel)))
+
+    def group_of(self):
+        out = np.empty(self.n, np.int64)
+        _chk(lib().oracle_group_of(self.h, _p(out)))
+        return out
 
     def lists(self):
         c = self.counts()

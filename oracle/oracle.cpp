@@ -146,6 +146,7 @@ struct Tree {
   int direct_max = 0;
   std::vector<int64_t> p2p_off, m2p_off;
   std::vector<int32_t> p2p, m2p;
+  std::vector<char> list_sel;  // empty: every group has its lists
   // moments
   int p = -1;
   std::vector<double> mom;        // n_cells x nm(p)
@@ -350,12 +351,12 @@ void walk(const Tree& t, const Cell& g, int64_t ci, double theta, int direct_max
   for (int k = 0; k < c.n_child; ++k) walk(t, g, c.child_first + k, theta, direct_max, p2p, m2p);
 }
 
-int build_lists(Tree& t, double theta, int direct_max) {
+int build_lists(Tree& t, double theta, int direct_max, const std::vector<char>& want) {
   const int64_t G = (int64_t)t.groups.size();
   std::vector<std::vector<int32_t>> lp(G), lm(G);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t g = 0; g < G; ++g)
-    walk(t, t.cells[t.groups[g]], 0, theta, direct_max, lp[g], lm[g]);
+    if (want.empty() || want[g]) walk(t, t.cells[t.groups[g]], 0, theta, direct_max, lp[g], lm[g]);
   t.p2p_off.assign(G + 1, 0);
   t.m2p_off.assign(G + 1, 0);
   for (int64_t g = 0; g < G; ++g) {
@@ -607,11 +608,28 @@ int oracle_tree_get_groups(void* h, int64_t* groups) {
   return 0;
 }
 
-int oracle_build_lists(void* h, double theta, int direct_max) {
+// Lists of every group, or only of the selected group ordinals (the others
+// stay empty; evaluating a sink of an unselected group is then an error).
+int oracle_build_lists(void* h, double theta, int direct_max, int64_t n_sel, const int64_t* sel) {
   Tree* t = (Tree*)h;
   if (!(theta > 0 && theta < 1)) return fail("theta must lie in (0, 1)");
   if (direct_max < 0) return fail("direct_max must be >= 0");
-  return build_lists(*t, theta, direct_max);
+  std::vector<char> want;
+  if (sel) {
+    want.assign(t->groups.size(), 0);
+    for (int64_t k = 0; k < n_sel; ++k) {
+      if (sel[k] < 0 || sel[k] >= (int64_t)t->groups.size()) return fail("bad group ordinal");
+      want[sel[k]] = 1;
+    }
+  }
+  t->list_sel = want;
+  return build_lists(*t, theta, direct_max, want);
+}
+
+int oracle_group_of(void* h, int64_t* out) {
+  Tree* t = (Tree*)h;
+  std::copy(t->group_of.begin(), t->group_of.end(), out);
+  return 0;
 }
 
 int oracle_get_lists(void* h, int64_t* p2p_off, int32_t* p2p, int64_t* m2p_off, int32_t* m2p) {
@@ -690,9 +708,10 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
     for (int64_t i = 0; i < n; ++i) todo[i] = i;
   }
   const int64_t T = (int64_t)todo.size();
-  // every M2P cell used must have moments
+  // every sink's group must have lists and every M2P cell used must have moments
   for (int64_t k = 0; k < T; ++k) {
     int64_t g = t->group_of[inv[todo[k]]];
+    if (!t->list_sel.empty() && !t->list_sel[g]) return fail("sink of a group without lists");
     for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e)
       if (!t->mom_valid[t->m2p[e]]) return fail("moments missing for an M2P cell");
   }
@@ -804,6 +823,7 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
                     const double* abar, double* xbar, double* mbar) {
   Tree* t = (Tree*)h;
   if (!t->has_lists) return fail("lists not built");
+  if (!t->list_sel.empty()) return fail("the VJP needs the lists of every group");
   if (t->p < 0) return fail("moments not computed");
   const int64_t n = t->n;
   const int p = t->p;

@@ -1,0 +1,218 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/hot.h"
+
+namespace hot {
+
+constexpr int kBits = 21;          // bits per axis in a key
+constexpr int kMaxLevel = 21;      // deepest cell level
+constexpr int kMaxP = 8;           // highest expansion order
+constexpr int kWave = 64;
+
+__host__ __device__ constexpr int nm(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+// moment slot of (a, b, c): by order, then a descending, then b descending
+__host__ __device__ constexpr int mslot(int a, int b, int c) {
+  return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 +
+         (b + c) * (b + c + 1) / 2 + c;
+}
+// padded stride (floats) of one cell's FP32 expansion coefficients
+__host__ __device__ constexpr int nm_pad(int p) { return (nm(p) + 3) & ~3; }
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define HOT_HIP(call)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::hot::Error{HOT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define HOT_CHECK_LAUNCH() HOT_HIP(hipGetLastError())
+
+inline void invalid(const std::string& m) { throw Error{HOT_E_INVALID, m}; }
+inline void state(const std::string& m) { throw Error{HOT_E_STATE, m}; }
+
+// Device-side error flags (bit set by kernels, read by the host).
+enum : unsigned {
+  FLAG_NONFINITE_POS = 1u,
+  FLAG_BAD_MASS = 2u,
+  FLAG_OUTSIDE_BOX = 4u,
+  FLAG_HASH_FULL = 8u,
+  FLAG_INTERNAL = 16u,  // a kernel's own consistency check failed
+};
+
+}  // namespace hot
+
+// ---------------------------------------------------------------------------
+// Context and tree (opaque in the C ABI)
+// ---------------------------------------------------------------------------
+struct hot_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hot_allocator alloc{};
+  bool user_alloc = false;
+  std::string err;
+  unsigned* d_flags = nullptr;     // device error flags
+  unsigned* h_flags = nullptr;     // pinned host mirror
+  hipEvent_t ev[8]{};
+  void* malloc_dev(size_t bytes);
+  void free_dev(void* p);
+};
+
+namespace hot {
+
+// A device allocation owned by a tree or by a call.
+struct DBuf {
+  hot_ctx* ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p && ctx) ctx->free_dev(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(hot_ctx* c, size_t b) {
+    if (p && bytes >= b && ctx == c) return;
+    release();
+    ctx = c;
+    bytes = b;
+    p = b ? c->malloc_dev(b) : nullptr;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace hot
+
+struct hot_tree {
+  hot_ctx* ctx = nullptr;
+  bool valid = false;
+  int64_t n = 0;
+  int n_leaf = 16, n_group = 64;
+  double lo[3] = {0, 0, 0};
+  double side = 1.0;
+  // particles (sorted order)
+  hot::DBuf key, perm, spos, lambda, group_of, leaf_of;
+  // root cube on device: lo[3], side, scale = 2^21 / side
+  hot::DBuf root;
+  // cells
+  int64_t n_cells = 0, n_leaves = 0;
+  int max_level = 0;
+  std::vector<int64_t> level_off;  // host: first cell of each level, size 23
+  hot::DBuf c_key, c_level, c_first, c_count, c_parent, c_child, c_nchild, c_leaf, c_centre,
+      c_bmax2, c_bmax;
+  // hash table key -> cell
+  uint64_t hash_slots = 0;
+  hot::DBuf h_keys, h_vals;
+  // groups
+  int64_t n_groups = 0;
+  hot::DBuf g_cell, g_first, g_count;
+  // moments
+  int p = -1;
+  hot::DBuf mom64, mom32, momw64;
+  bool momw64_valid = false;
+  // P2P / M2P pair counts of the current lists (host copies)
+  int64_t p2p_pairs = 0, m2p_pairs = 0;
+  // lists
+  bool has_lists = false;
+  double theta = 0;
+  int direct_max = 0;
+  int64_t n_p2p = 0, n_m2p = 0;
+  hot::DBuf p2p_off, p2p, m2p_off, m2p;
+  // eval work items: (group, first sink) per wave
+  int64_t n_items = 0;
+  hot::DBuf items;
+  // adjoint caches: transposed lists (cell -> groups)
+  bool has_transpose = false;
+  hot::DBuf tp2p_cells, tp2p_off, tp2p_grp, tm2p_cells, tm2p_off, tm2p_grp;
+  int64_t n_tp2p_cells = 0, n_tm2p_cells = 0;
+};
+
+namespace hot {
+
+// ---------------------------------------------------------------------------
+// Building blocks implemented in the .hip files
+// ---------------------------------------------------------------------------
+// Exclusive prefix sums (in place allowed), element types u32 -> u32 and
+// i64 -> i64. total (device, may be null) receives the sum.
+void scan_u32(hot_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
+void scan_i64(hot_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, int64_t* total);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
+// Buffers are swapped internally; the result ends in keys/vals.
+void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits);
+
+void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box);
+void gather_sorted(hot_ctx* ctx, const hot_tree* t, const double* pos, const double* mass,
+                   double* spos, double* smass, int check_mass);
+void build_moments(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, int p);
+void weighted_fp64(hot_ctx* ctx, hot_tree* t);
+void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
+void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+            int precision, double* acc, double* pot, hot_stats* stats);
+void adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+             int precision, const double* abar, double* xbar, double* mbar);
+void hash_lookup(hot_ctx* ctx, const hot_tree* t, const uint64_t* keys, int32_t* out, int64_t nq);
+
+inline unsigned grid_for(int64_t n, int block) {
+  return (unsigned)((n + block - 1) / block);
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = __lane_id();
+  return l ? (~0ull >> (64 - l)) : 0ull;
+}
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float hot_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double hot_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// s^(-1/2): the hardware reciprocal square root in FP32, IEEE divide and
+// square root in FP64.
+__device__ __forceinline__ float hot_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double hot_rsq(double x) { return 1.0 / sqrt(x); }
+
+// 64-bit mixer for the cell hash table (splitmix64 finaliser).
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+constexpr uint64_t kEmptyKey = 0;  // cell keys always carry the placeholder bit
+
+__device__ __forceinline__ int32_t hash_find(const uint64_t* __restrict__ hk,
+                                             const int32_t* __restrict__ hv, uint64_t mask,
+                                             uint64_t key) {
+  uint64_t s = mix64(key) & mask;
+  while (true) {
+    uint64_t k = hk[s];
+    if (k == key) return hv[s];
+    if (k == kEmptyKey) return -1;
+    s = (s + 1) & mask;
+  }
+}
+
+}  // namespace hot

@@ -1,0 +1,341 @@
+// Force evaluation over the interaction lists.
+//
+// Pair kernel: the softened Newtonian pair force (eq. "eom" at a = 1, G = 1,
+// with the Plummer smoothing of the Force Smoothing section). Expansion
+// kernel: the cell-body Cartesian multipole expansion with Delta = 0 of the
+// Multipole Error Bounds section, with the softened Green's function.
+//
+// m x n blocking (Improving instruction-level parallelism section): one
+// wavefront serves up to 64 sinks of one group (one sink per lane) and runs
+// over the group's list; every source particle or source cell is
+// wavefront-uniform, so its data arrives through scalar loads shared by all
+// 64 sinks. The interaction vector of a sink is written back once per
+// kernel (the paper's multi-stage write-back), with compensated (Kahan)
+// accumulation per list entry in mixed precision.
+//
+// Mixed precision: every position enters as an FP32 offset from its own
+// group's FP64 centre; the FP64 difference of two centres is formed once per
+// (group, entry) and rounded to FP32. Expansions run on coordinates scaled by
+// the source cell side s (a power of two): R/s, eps/s and the weighted moments
+// M_alpha / s^|alpha| are all O(1), and the result is rescaled by s^-2.
+#include "common.h"
+#include "generated/expansions.h"
+
+namespace hot {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kWavesPerBlock = kB / 64;
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+template <typename T>
+using V4 = typename Vec4<T>::type;
+
+template <typename T>
+__device__ __forceinline__ void kahan_add(T& s, T& c, T x) {
+  const T y = x - c;
+  const T t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// Offsets of every particle (sorted order) from its group's centre, and mass.
+template <typename T>
+__global__ void k_offsets(const double* __restrict__ pos, const double* __restrict__ mass,
+                          const uint32_t* __restrict__ perm, const int32_t* __restrict__ group_of,
+                          const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+                          int64_t n, V4<T>* __restrict__ off, unsigned* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = perm[i];
+  const int gc = g_cell[group_of[i]];
+  const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2], m = mass[j];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(flags, FLAG_NONFINITE_POS);
+  if (!(isfinite(m) && m >= 0.0)) atomicOr(flags, FLAG_BAD_MASS);
+  V4<T> o;
+  o.x = (T)(x - c_centre[3 * gc]);
+  o.y = (T)(y - c_centre[3 * gc + 1]);
+  o.z = (T)(z - c_centre[3 * gc + 2]);
+  o.w = (T)m;
+  off[i] = o;
+}
+
+// State per sorted particle: s_x s_y s_z s_phi c_x c_y c_z c_phi.
+template <typename T, bool POT, bool EPS0>
+__global__ __launch_bounds__(kB) void k_p2p(
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
+    const int32_t* __restrict__ p2p, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
+    const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
+    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+    const V4<T>* __restrict__ off, T eps2, T* __restrict__ state, int64_t n) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (it >= n_items) return;
+  const int2 item = items[it];
+  const int g = uniform_i32(item.x);
+  const int gend = g_first[g] + g_count[g];
+  const int i = item.y + lane;
+  const bool active = i < gend;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  V4<T> me;
+  me.x = me.y = me.z = me.w = T(0);
+  if (active) me = off[i];
+  T sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
+  const int64_t e0 = p2p_off[g], e1 = p2p_off[g + 1];
+  for (int64_t e = e0; e < e1; ++e) {
+    const int c = p2p[e];
+    const int f = c_first[c];
+    const int end = f + c_count[c];
+    T ax = 0, ay = 0, az = 0, ap = 0;
+    int j = f;
+    while (j < end) {
+      const int sg = group_of[j];
+      const int sgend = g_first[sg] + g_count[sg];
+      const int jend = end < sgend ? end : sgend;
+      if (jend <= j) break;  // never true for a valid tree
+      const int sc = g_cell[sg];
+      const T tx = (T)(c_centre[3 * sc] - cgx) - me.x;
+      const T ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
+      const T tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+      if (sg == g) {
+        for (int jj = j; jj < jend; ++jj) {
+          const V4<T> s = off[jj];
+          const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;
+          const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
+          T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
+          if (jj == i) inv = T(0);
+          const T mi = s.w * inv;
+          const T f3 = mi * (inv * inv);
+          ax = hot_fma(f3, rx, ax);
+          ay = hot_fma(f3, ry, ay);
+          az = hot_fma(f3, rz, az);
+          if (POT) ap -= mi;
+        }
+      } else {
+#pragma unroll 4
+        for (int jj = j; jj < jend; ++jj) {
+          const V4<T> s = off[jj];
+          const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;
+          const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
+          const T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
+          const T mi = s.w * inv;
+          const T f3 = mi * (inv * inv);
+          ax = hot_fma(f3, rx, ax);
+          ay = hot_fma(f3, ry, ay);
+          az = hot_fma(f3, rz, az);
+          if (POT) ap -= mi;
+        }
+      }
+      j = jend;
+    }
+    kahan_add(sx, cx, ax);
+    kahan_add(sy, cy, ay);
+    kahan_add(sz, cz, az);
+    if (POT) kahan_add(sp, cp, ap);
+  }
+  if (active) {
+    T* st = state + (int64_t)i * 8;
+    st[0] = sx;
+    st[1] = sy;
+    st[2] = sz;
+    st[3] = sp;
+    st[4] = cx;
+    st[5] = cy;
+    st[6] = cz;
+    st[7] = cp;
+  }
+}
+
+template <int P, typename T, bool POT>
+__global__ __launch_bounds__(kB) void k_m2p(
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
+    const int32_t* __restrict__ m2p, const int8_t* __restrict__ c_level,
+    const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
+    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+    const V4<T>* __restrict__ off, const T* __restrict__ momw, double inv_side, double eps,
+    T* __restrict__ state) {
+  constexpr int stride = nm_pad(P);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (it >= n_items) return;
+  const int2 item = items[it];
+  const int g = uniform_i32(item.x);
+  const int gend = g_first[g] + g_count[g];
+  const int i = item.y + lane;
+  const bool active = i < gend;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  V4<T> me;
+  me.x = me.y = me.z = me.w = T(0);
+  if (active) me = off[i];
+  T sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
+  if (active) {
+    const T* st = state + (int64_t)i * 8;
+    sx = st[0];
+    sy = st[1];
+    sz = st[2];
+    sp = st[3];
+    cx = st[4];
+    cy = st[5];
+    cz = st[6];
+    cp = st[7];
+  }
+  const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
+  for (int64_t e = e0; e < e1; ++e) {
+    const int c = m2p[e];
+    const double inv_s = ldexp(inv_side, (int)c_level[c]);
+    const T X = (T)((cgx - c_centre[3 * c]) * inv_s) + me.x * (T)inv_s;
+    const T Y = (T)((cgy - c_centre[3 * c + 1]) * inv_s) + me.y * (T)inv_s;
+    const T Z = (T)((cgz - c_centre[3 * c + 2]) * inv_s) + me.z * (T)inv_s;
+    const double es = eps * inv_s;
+    const T e2 = (T)(es * es);
+    T ax = 0, ay = 0, az = 0, ph = 0;
+    expansion_fwd<P, T, POT>(X, Y, Z, e2, momw + (int64_t)c * stride, ax, ay, az, ph);
+    const T sa = (T)(-(inv_s * inv_s));
+    kahan_add(sx, cx, ax * sa);
+    kahan_add(sy, cy, ay * sa);
+    kahan_add(sz, cz, az * sa);
+    if (POT) kahan_add(sp, cp, ph * (T)inv_s);
+  }
+  if (active) {
+    T* st = state + (int64_t)i * 8;
+    st[0] = sx;
+    st[1] = sy;
+    st[2] = sz;
+    st[3] = sp;
+    st[4] = cx;
+    st[5] = cy;
+    st[6] = cz;
+    st[7] = cp;
+  }
+}
+
+template <typename T>
+__global__ void k_finalize(const T* __restrict__ state, const uint32_t* __restrict__ perm,
+                           int64_t n, double* __restrict__ acc, double* __restrict__ pot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T* st = state + i * 8;
+  const int64_t j = perm[i];
+  acc[3 * j] = (double)st[0] - (double)st[4];
+  acc[3 * j + 1] = (double)st[1] - (double)st[5];
+  acc[3 * j + 2] = (double)st[2] - (double)st[6];
+  if (pot) pot[j] = (double)st[3] - (double)st[7];
+}
+
+template <typename T, bool POT>
+void launch_p2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, double eps, T* state) {
+  const unsigned grid = grid_for(t->n_items, kWavesPerBlock);
+  const T e2 = (T)(eps * eps);
+  auto go = [&](auto kern) {
+    kern<<<grid, kB, 0, ctx->stream>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
+                                       t->p2p.as<int32_t>(), t->c_first.as<int32_t>(),
+                                       t->c_count.as<int32_t>(), t->group_of.as<int32_t>(),
+                                       t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+                                       t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, e2,
+                                       state, t->n);
+    HOT_CHECK_LAUNCH();
+  };
+  if (e2 > T(0))
+    go(k_p2p<T, POT, false>);
+  else
+    go(k_p2p<T, POT, true>);
+}
+
+template <int P, typename T, bool POT>
+void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, double eps,
+                  T* state) {
+  const unsigned grid = grid_for(t->n_items, kWavesPerBlock);
+  k_m2p<P, T, POT><<<grid, kB, 0, ctx->stream>>>(
+      t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
+      t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+      t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, momw, 1.0 / t->side, eps, state);
+  HOT_CHECK_LAUNCH();
+}
+
+template <typename T, bool POT>
+void launch_m2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, double eps, T* state) {
+  switch (t->p) {
+    case 0: launch_m2p_p<0, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 1: launch_m2p_p<1, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 2: launch_m2p_p<2, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 3: launch_m2p_p<3, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 4: launch_m2p_p<4, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 5: launch_m2p_p<5, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 6: launch_m2p_p<6, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 7: launch_m2p_p<7, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 8: launch_m2p_p<8, T, POT>(ctx, t, off, momw, eps, state); break;
+    default: invalid("p out of range");
+  }
+}
+
+template <typename T>
+void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+              double* acc, double* pot, hot_stats* stats) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = t->n;
+  DBuf off, state;
+  off.alloc(ctx, n * sizeof(V4<T>));
+  state.alloc(ctx, n * 8 * sizeof(T));
+  k_offsets<T><<<grid_for(n, kB), kB, 0, st>>>(pos, mass, t->perm.as<uint32_t>(),
+                                               t->group_of.as<int32_t>(), t->g_cell.as<int32_t>(),
+                                               t->c_centre.as<double>(), n, off.as<V4<T>>(),
+                                               ctx->d_flags);
+  HOT_CHECK_LAUNCH();
+  const T* momw = nullptr;
+  if constexpr (sizeof(T) == 4) {
+    momw = t->mom32.as<T>();
+  } else {
+    weighted_fp64(ctx, t);
+    momw = t->momw64.as<T>();
+  }
+  if (stats) HOT_HIP(hipEventRecord(ctx->ev[0], st));
+  if (pot)
+    launch_p2p<T, true>(ctx, t, off.as<V4<T>>(), eps, state.as<T>());
+  else
+    launch_p2p<T, false>(ctx, t, off.as<V4<T>>(), eps, state.as<T>());
+  if (stats) HOT_HIP(hipEventRecord(ctx->ev[1], st));
+  if (pot)
+    launch_m2p<T, true>(ctx, t, off.as<V4<T>>(), momw, eps, state.as<T>());
+  else
+    launch_m2p<T, false>(ctx, t, off.as<V4<T>>(), momw, eps, state.as<T>());
+  if (stats) HOT_HIP(hipEventRecord(ctx->ev[2], st));
+  k_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(state.as<T>(), t->perm.as<uint32_t>(), n, acc, pot);
+  HOT_CHECK_LAUNCH();
+  if (stats) {
+    HOT_HIP(hipEventRecord(ctx->ev[3], st));
+    HOT_HIP(hipEventSynchronize(ctx->ev[3]));
+    float a = 0, b = 0, c = 0;
+    HOT_HIP(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+    HOT_HIP(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+    HOT_HIP(hipEventElapsedTime(&c, ctx->ev[0], ctx->ev[3]));
+    stats->ms_p2p = a;
+    stats->ms_m2p = b;
+    stats->ms_total = c;
+    stats->p2p_pairs = t->p2p_pairs;
+    stats->m2p_pairs = t->m2p_pairs;
+  }
+}
+
+}  // namespace
+
+void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+            int precision, double* acc, double* pot, hot_stats* stats) {
+  if (precision == HOT_FP64)
+    forces_t<double>(ctx, t, pos, mass, eps, acc, pot, stats);
+  else
+    forces_t<float>(ctx, t, pos, mass, eps, acc, pot, stats);
+}
+
+}  // namespace hot

@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Generate straight-line HIP code for the cell-body multipole expansion.
+
+The paper produces its interaction routines up to p = 8 by metaprogramming
+(Multipole Error Bounds section: translating a computer-algebra
+representation directly into C). This build step does the same for the GPU:
+for every order p it emits fully unrolled code, with no loops and no arrays,
+so that every intermediate lives in a register.
+
+Derivatives of the softened Green's function G(R) = -(|R|^2 + e^2)^(-1/2)
+are built with the Hermite recursion of McMurchie and Davidson for radial
+functions f(s), s = |R|^2 + e^2:
+    R^(n)_000 = F_n = 2^n f^(n)(s) = (-1)^(n+1) (2n-1)!! s^(-n-1/2),
+    R^(n)_{..,k+1,..} = k R^(n+1)_{..,k-1,..} + x_k R^(n+1)_{..,k,..},
+    d^alpha G = R^(0)_alpha.
+The recursion is used along z and y; along x the closed form
+    R^(0)_{t,u,v} = sum_j t! / (j! (t-2j)! 2^j) X^(t-2j) R^(t-j)_{0,u,v}
+replaces the last triangle of the recursion (fewer operations when only
+n = 0 is needed).
+
+Emitted functions (T is float or double):
+  expansion_fwd<P,T,POT>(X,Y,Z,e2,M,ax,ay,az,ph)
+      ax += sum_alpha M[alpha] d^(alpha+e_x) G (likewise y, z); ph += sum M d^alpha G
+  expansion_sink_adj<P,T>(X,Y,Z,e2,M,bx,by,bz,gx,gy,gz)
+      g_l += sum_k b_k sum_alpha M[alpha] d^(alpha+e_k+e_l) G
+  expansion_cell_adj<P,T>(X,Y,Z,e2,bx,by,bz,row)
+      row[alpha] += sum_k b_k d^(alpha+e_k) G   (row: LDS, private to the lane)
+M holds the (weighted, scaled) moments in slot order: by order, then x
+exponent descending, then y exponent descending.
+"""
+import math
+import os
+import sys
+
+PMAX = 8
+
+
+def slot(a, b, c):
+    n = a + b + c
+    return n * (n + 1) * (n + 2) // 6 + (b + c) * (b + c + 1) // 2 + c
+
+
+def lit(x):
+    return f"T({float(x)!r})"
+
+
+class Emitter:
+    def __init__(self, K):
+        self.K = K
+        self.lines = []
+
+    def e(self, s):
+        self.lines.append("  " + s)
+
+    def radial(self):
+        K = self.K
+        e = self.e
+        e("const T s_ = hot_fma(X, X, hot_fma(Y, Y, hot_fma(Z, Z, e2)));")
+        e("const T u_ = hot_rsq(s_);")
+        e("const T is_ = u_ * u_;")
+        e("const T F0 = -u_;")
+        if K >= 1:
+            e("const T F1 = u_ * is_;")
+        for n in range(1, K):
+            e(f"const T F{n + 1} = (F{n} * is_) * {lit(-(2 * n + 1))};")
+        # powers of X
+        if K >= 2:
+            e("const T X2 = X * X;")
+        for k in range(3, K + 1):
+            e(f"const T X{k} = X{k - 1} * X;")
+
+    def xpow(self, k):
+        return "X" if k == 1 else f"X{k}"
+
+    def derivs(self, consume):
+        """Emit R_{t,u,v} for all t+u+v <= K, calling consume(t,u,v,name)."""
+        K = self.K
+        e = self.e
+        # z chain rows are emitted lazily: row v needs rows v-1 and v-2
+        def zname(v, n):
+            return f"F{n}" if v == 0 else f"Z{v}_{n}"
+
+        def yname(v, u, n):
+            return zname(v, n) if u == 0 else f"Y{v}_{u}_{n}"
+
+        for v in range(0, K + 1):
+            if v >= 1:
+                for n in range(0, K - v + 1):
+                    if v == 1:
+                        e(f"const T Z1_{n} = Z * F{n + 1};")
+                    else:
+                        e(f"const T Z{v}_{n} = hot_fma(Z, {zname(v - 1, n + 1)}, {lit(v - 1)} * {zname(v - 2, n + 1)});")
+            for u in range(0, K - v + 1):
+                if u >= 1:
+                    for n in range(0, K - v - u + 1):
+                        if u == 1:
+                            e(f"const T Y{v}_1_{n} = Y * {zname(v, n + 1)};")
+                        else:
+                            e(f"const T Y{v}_{u}_{n} = hot_fma(Y, {yname(v, u - 1, n + 1)}, {lit(u - 1)} * {yname(v, u - 2, n + 1)});")
+                for t in range(0, K - v - u + 1):
+                    name = f"R{t}_{u}_{v}"
+                    terms = []
+                    for j in range(0, t // 2 + 1):
+                        c = math.factorial(t) // (math.factorial(j) * math.factorial(t - 2 * j)) / 2 ** j
+                        terms.append((c, t - 2 * j, yname(v, u, t - j)))
+                    # first term
+                    c, px, yv = terms[0]
+                    if px == 0:
+                        expr = yv if c == 1 else f"{lit(c)} * {yv}"
+                    else:
+                        xp = self.xpow(px)
+                        expr = f"{xp} * {yv}" if c == 1 else f"({lit(c)} * {xp}) * {yv}"
+                    e(f"T {name} = {expr};")
+                    for c, px, yv in terms[1:]:
+                        if px == 0:
+                            e(f"{name} = hot_fma({lit(c)}, {yv}, {name});")
+                        else:
+                            xp = self.xpow(px)
+                            co = xp if c == 1 else f"({lit(c)} * {xp})"
+                            e(f"{name} = hot_fma({co}, {yv}, {name});")
+                    consume(t, u, v, name)
+
+
+def gen_fwd(P):
+    K = P + 1
+    em = Emitter(K)
+    em.radial()
+
+    def consume(t, u, v, r):
+        if t >= 1:
+            em.e(f"ax = hot_fma(M[{slot(t - 1, u, v)}], {r}, ax);")
+        if u >= 1:
+            em.e(f"ay = hot_fma(M[{slot(t, u - 1, v)}], {r}, ay);")
+        if v >= 1:
+            em.e(f"az = hot_fma(M[{slot(t, u, v - 1)}], {r}, az);")
+        if t + u + v <= P:
+            em.e(f"if constexpr (POT) ph = hot_fma(M[{slot(t, u, v)}], {r}, ph);")
+
+    em.derivs(consume)
+    return em.lines
+
+
+PAIRS = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+
+
+def gen_sink_adj(P):
+    K = P + 2
+    em = Emitter(K)
+    em.radial()
+    for k, l in PAIRS:
+        em.e(f"T H{k}{l} = T(0);")
+
+    def consume(t, u, v, r):
+        b = [t, u, v]
+        for k, l in PAIRS:
+            a = list(b)
+            a[k] -= 1
+            a[l] -= 1
+            if min(a) < 0 or sum(a) > P:
+                continue
+            em.e(f"H{k}{l} = hot_fma(M[{slot(*a)}], {r}, H{k}{l});")
+
+    em.derivs(consume)
+    em.e("gx = hot_fma(H00, bx, hot_fma(H01, by, hot_fma(H02, bz, gx)));")
+    em.e("gy = hot_fma(H01, bx, hot_fma(H11, by, hot_fma(H12, bz, gy)));")
+    em.e("gz = hot_fma(H02, bx, hot_fma(H12, by, hot_fma(H22, bz, gz)));")
+    return em.lines
+
+
+def gen_cell_adj(P):
+    K = P + 1
+    em = Emitter(K)
+    em.radial()
+    remaining = {}
+    declared = set()
+    bname = ["bx", "by", "bz"]
+    for n in range(P + 1):
+        for a in range(n, -1, -1):
+            for b_ in range(n - a, -1, -1):
+                remaining[slot(a, b_, n - a - b_)] = 3
+
+    def consume(t, u, v, r):
+        b = [t, u, v]
+        for k in range(3):
+            a = list(b)
+            a[k] -= 1
+            if a[k] < 0:
+                continue
+            s = slot(*a)
+            if s not in declared:
+                em.e(f"T V{s} = {bname[k]} * {r};")
+                declared.add(s)
+            else:
+                em.e(f"V{s} = hot_fma({bname[k]}, {r}, V{s});")
+            remaining[s] -= 1
+            if remaining[s] == 0:
+                em.e(f"row[{s}] += V{s};")
+
+    em.derivs(consume)
+    assert all(v == 0 for v in remaining.values())
+    return em.lines
+
+
+def gen_p2m_order(N):
+    """acc[k] += m * (dx^a dy^b dz^c) for the order-N slots, a descending,
+    then b descending (the product associates as (x-part * y-part) * z-part)."""
+    L = []
+    for name, var in (("px", "dx"), ("py", "dy"), ("pz", "dz")):
+        L.append(f"  const double {name}0 = 1.0;")
+        for k in range(1, N + 1):
+            L.append(f"  const double {name}{k} = {name}{k - 1} * {var};")
+    k = 0
+    for a in range(N, -1, -1):
+        for b in range(N - a, -1, -1):
+            c = N - a - b
+            L.append(f"  acc[{k}] += m * ((px{a} * py{b}) * pz{c});")
+            k += 1
+    return L
+
+
+def gen_m2m_order(N):
+    """Re-centre a child's moments (shift = child centre - parent centre) into
+    the order-N slots: acc[alpha] += sum_{beta <= alpha} C(alpha,beta)
+    shift^(alpha-beta) M[beta]."""
+    L = []
+    for name, var in (("px", "dx"), ("py", "dy"), ("pz", "dz")):
+        L.append(f"  const double {name}0 = 1.0;")
+        for k in range(1, N + 1):
+            L.append(f"  const double {name}{k} = {name}{k - 1} * {var};")
+    k = 0
+    for a in range(N, -1, -1):
+        for b in range(N - a, -1, -1):
+            c = N - a - b
+            terms = []
+            for a2 in range(a + 1):
+                for b2 in range(b + 1):
+                    for c2 in range(c + 1):
+                        co = math.comb(a, a2) * math.comb(b, b2) * math.comb(c, c2)
+                        terms.append(f"({float(co)!r} * ((px{a - a2} * py{b - b2}) * pz{c - c2})) * M[{slot(a2, b2, c2)}]")
+            L.append(f"  acc[{k}] += " + " + ".join(terms) + ";")
+            k += 1
+    return L
+
+
+def main(out_path):
+    parts = ["// Generated by gen_expansions.py -- do not edit.",
+             "#pragma once",
+             "namespace hot {",
+             ""]
+    parts.append("template <int P, typename T, bool POT>")
+    parts.append("__device__ __forceinline__ void expansion_fwd(T X, T Y, T Z, T e2, "
+                 "const T* __restrict__ M, T& ax, T& ay, T& az, T& ph) {")
+    for P in range(PMAX + 1):
+        kw = "if constexpr" if P == 0 else "} else if constexpr"
+        parts.append(f"  {kw} (P == {P}) {{")
+        parts += ["  " + l for l in gen_fwd(P)]
+    parts.append("  }")
+    parts.append("}")
+    parts.append("")
+    parts.append("template <int P, typename T>")
+    parts.append("__device__ __forceinline__ void expansion_sink_adj(T X, T Y, T Z, T e2, "
+                 "const T* __restrict__ M, T bx, T by, T bz, T& gx, T& gy, T& gz) {")
+    for P in range(PMAX + 1):
+        kw = "if constexpr" if P == 0 else "} else if constexpr"
+        parts.append(f"  {kw} (P == {P}) {{")
+        parts += ["  " + l for l in gen_sink_adj(P)]
+    parts.append("  }")
+    parts.append("}")
+    parts.append("")
+    parts.append("template <int P, typename T>")
+    parts.append("__device__ __forceinline__ void expansion_cell_adj(T X, T Y, T Z, T e2, "
+                 "T bx, T by, T bz, T* row) {")
+    for P in range(PMAX + 1):
+        kw = "if constexpr" if P == 0 else "} else if constexpr"
+        parts.append(f"  {kw} (P == {P}) {{")
+        parts += ["  " + l for l in gen_cell_adj(P)]
+    parts.append("  }")
+    parts.append("}")
+    parts.append("")
+    for N in range(PMAX + 1):
+        parts.append(f"__device__ __forceinline__ void p2m_order{N}(double dx, double dy, double dz, "
+                     "double m, double* acc) {")
+        parts += gen_p2m_order(N)
+        parts.append("}")
+        parts.append(f"__device__ __forceinline__ void m2m_order{N}(const double* __restrict__ M, "
+                     "double dx, double dy, double dz, double* acc) {")
+        parts += gen_m2m_order(N)
+        parts.append("}")
+    parts.append("")
+    parts.append("}  // namespace hot")
+    text = "\n".join(parts) + "\n"
+    os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    tmp = out_path + ".tmp"
+    with open(tmp, "w") as f:
+        f.write(text)
+    os.replace(tmp, out_path)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else
+         os.path.join(os.path.dirname(os.path.abspath(__file__)), "generated", "expansions.h"))

@@ -1,0 +1,262 @@
+// Device-wide exclusive scans and the stable LSD radix sort of (key, value)
+// pairs used for the key sort (Domain Decomposition section: the keys are put
+// in order by a radix sort) and for transposing interaction lists.
+#include "common.h"
+
+namespace hot {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_block_reduce(const T* __restrict__ in, int64_t n,
+                                                               T* __restrict__ sums) {
+  __shared__ T sh[kScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + (int64_t)k * kScanThreads + tid;
+    if (i < n) s += in[i];
+  }
+  sh[tid] = s;
+  __syncthreads();
+  for (int off = kScanThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] += sh[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) sums[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_block_scan(const T* in, T* out, int64_t n,
+                                                             const T* __restrict__ offsets,
+                                                             T* __restrict__ total) {
+  __shared__ T sh[kScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : T(0);
+    s += v[k];
+  }
+  sh[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    T t = (tid >= off) ? sh[tid - off] : T(0);
+    __syncthreads();
+    sh[tid] += t;
+    __syncthreads();
+  }
+  T run = sh[tid] - s + (offsets ? offsets[blockIdx.x] : T(0));
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (total && blockIdx.x == gridDim.x - 1 && tid == kScanThreads - 1) *total = run;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+void scan_impl(hot_ctx* ctx, const T* in, T* out, int64_t n, T* total) {
+  if (n <= 0) {
+    if (total) {
+      k_fill<T><<<1, 1, 0, ctx->stream>>>(total, 1, T(0));
+      HOT_CHECK_LAUNCH();
+    }
+    return;
+  }
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 1) {
+    k_block_scan<T><<<1, kScanThreads, 0, ctx->stream>>>(in, out, n, nullptr, total);
+    HOT_CHECK_LAUNCH();
+    return;
+  }
+  DBuf sums;
+  sums.alloc(ctx, nb * sizeof(T));
+  k_block_reduce<T><<<(unsigned)nb, kScanThreads, 0, ctx->stream>>>(in, n, sums.as<T>());
+  HOT_CHECK_LAUNCH();
+  scan_impl<T>(ctx, sums.as<T>(), sums.as<T>(), nb, nullptr);
+  k_block_scan<T><<<(unsigned)nb, kScanThreads, 0, ctx->stream>>>(in, out, n, sums.as<T>(), total);
+  HOT_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort: 9-bit digits, tiles of 4096 pairs per 256-thread block.
+// Pass = per-tile digit histogram -> scan over (digit, tile) -> stable scatter.
+// The scatter ranks each wave's 1024-pair sub-tile with ballots (64 pairs per
+// round, in order), combines waves through LDS, stages the tile in LDS in
+// digit order and writes each digit run contiguously.
+// ---------------------------------------------------------------------------
+constexpr int kRBits = 9;
+constexpr int kRBins = 1 << kRBits;
+constexpr int kRThreads = 256;
+constexpr int kRWaves = kRThreads / 64;
+constexpr int kRRounds = 16;                     // rounds of 64 per wave
+constexpr int kRTile = kRThreads * kRRounds;     // 4096
+
+__global__ __launch_bounds__(kRThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
+                                                          int64_t n, int shift,
+                                                          uint32_t* __restrict__ hist,
+                                                          int64_t ntiles) {
+  __shared__ uint32_t h[kRBins];
+  for (int i = threadIdx.x; i < kRBins; i += kRThreads) h[i] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRTile;
+  for (int k = 0; k < kRRounds; ++k) {
+    int64_t i = base + (int64_t)k * kRThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(unsigned)(keys[i] >> shift) & (kRBins - 1)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRBins; i += kRThreads)
+    hist[(int64_t)i * ntiles + blockIdx.x] = h[i];
+}
+
+__global__ __launch_bounds__(kRThreads) void k_radix_scatter(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
+    const uint32_t* __restrict__ offs, int64_t ntiles) {
+  __shared__ uint64_t sk[kRTile];
+  __shared__ uint32_t sv[kRTile];
+  __shared__ uint32_t cnt[kRWaves][kRBins];
+  __shared__ uint32_t tot[kRBins];
+  __shared__ uint32_t loc[kRBins];
+  __shared__ uint32_t gof[kRBins];
+  __shared__ uint32_t part[kRThreads];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < kRWaves * kRBins; i += kRThreads) (&cnt[0][0])[i] = 0;
+  for (int i = tid; i < kRBins; i += kRThreads) gof[i] = offs[(int64_t)i * ntiles + blockIdx.x];
+  __syncthreads();
+
+  const int64_t tile0 = (int64_t)blockIdx.x * kRTile;
+  const int64_t base = tile0 + (int64_t)w * (kRTile / kRWaves);
+  uint64_t kk[kRRounds];
+  uint32_t vv[kRRounds];
+  uint32_t rk[kRRounds];
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int r = 0; r < kRRounds; ++r) {
+    const int64_t i = base + (int64_t)r * 64 + lane;
+    const bool valid = i < n;
+    const uint64_t key = valid ? kin[i] : 0ull;
+    kk[r] = key;
+    vv[r] = valid ? vin[i] : 0u;
+    const unsigned d = (unsigned)(key >> shift) & (kRBins - 1);
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    uint32_t before = 0;
+    if (valid) before = cnt[w][d];
+    __builtin_amdgcn_wave_barrier();
+    rk[r] = before + (uint32_t)__popcll(m & lt);
+    if (valid && (m & lt) == 0) cnt[w][d] = before + (uint32_t)__popcll(m);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // exclusive prefix over waves per digit, and digit totals
+  for (int d = tid; d < kRBins; d += kRThreads) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kRWaves; ++q) {
+      uint32_t c = cnt[q][d];
+      cnt[q][d] = s;
+      s += c;
+    }
+    tot[d] = s;
+  }
+  __syncthreads();
+  // block-local exclusive offsets over digits (2 digits per thread)
+  {
+    uint32_t a = tot[2 * tid], b = tot[2 * tid + 1];
+    part[tid] = a + b;
+    __syncthreads();
+    for (int off = 1; off < kRThreads; off <<= 1) {
+      uint32_t t = (tid >= off) ? part[tid - off] : 0u;
+      __syncthreads();
+      part[tid] += t;
+      __syncthreads();
+    }
+    uint32_t ex = part[tid] - (a + b);
+    loc[2 * tid] = ex;
+    loc[2 * tid + 1] = ex + a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRRounds; ++r) {
+    const int64_t i = base + (int64_t)r * 64 + lane;
+    if (i < n) {
+      const unsigned d = (unsigned)(kk[r] >> shift) & (kRBins - 1);
+      const uint32_t pos = loc[d] + cnt[w][d] + rk[r];
+      sk[pos] = kk[r];
+      sv[pos] = vv[r];
+    }
+  }
+  __syncthreads();
+  const int64_t tile_n = (n - tile0) < kRTile ? (n - tile0) : kRTile;
+  for (int q = tid; q < tile_n; q += kRThreads) {
+    const uint64_t key = sk[q];
+    const unsigned d = (unsigned)(key >> shift) & (kRBins - 1);
+    const uint32_t o = gof[d] + ((uint32_t)q - loc[d]);
+    kout[o] = key;
+    vout[o] = sv[q];
+  }
+}
+
+}  // namespace
+
+void scan_u32(hot_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total) {
+  scan_impl<uint32_t>(ctx, in, out, n, total);
+}
+void scan_i64(hot_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, int64_t* total) {
+  scan_impl<int64_t>(ctx, in, out, n, total);
+}
+
+void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits) {
+  if (n <= 1 || bits <= 0) return;
+  const int passes = (bits + kRBits - 1) / kRBits;
+  const int64_t ntiles = (n + kRTile - 1) / kRTile;
+  if ((int64_t)kRBins * ntiles >= (int64_t)UINT32_MAX) throw Error{HOT_E_CAPACITY, "sort too large"};
+  if (n >= (int64_t)UINT32_MAX) throw Error{HOT_E_CAPACITY, "sort too large"};
+  DBuf k2, v2, hist;
+  k2.alloc(ctx, n * sizeof(uint64_t));
+  v2.alloc(ctx, n * sizeof(uint32_t));
+  hist.alloc(ctx, (size_t)kRBins * ntiles * sizeof(uint32_t));
+  uint64_t* ks = keys;
+  uint32_t* vs = vals;
+  uint64_t* kd = k2.as<uint64_t>();
+  uint32_t* vd = v2.as<uint32_t>();
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = pass * kRBits;
+    k_radix_hist<<<(unsigned)ntiles, kRThreads, 0, ctx->stream>>>(ks, n, shift,
+                                                                    hist.as<uint32_t>(), ntiles);
+    HOT_CHECK_LAUNCH();
+    scan_u32(ctx, hist.as<uint32_t>(), hist.as<uint32_t>(), (int64_t)kRBins * ntiles, nullptr);
+    k_radix_scatter<<<(unsigned)ntiles, kRThreads, 0, ctx->stream>>>(
+        ks, vs, kd, vd, n, shift, hist.as<uint32_t>(), ntiles);
+    HOT_CHECK_LAUNCH();
+    std::swap(ks, kd);
+    std::swap(vs, vd);
+  }
+  if (ks != keys) {
+    HOT_HIP(hipMemcpyAsync(keys, ks, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream));
+    HOT_HIP(hipMemcpyAsync(vals, vs, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
+  }
+}
+
+}  // namespace hot

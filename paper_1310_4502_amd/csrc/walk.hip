@@ -1,0 +1,180 @@
+// Interaction lists: one depth-first walk of the source tree per sink group
+// (the source/sink cell traversal of the Tree Construction and Traversal
+// section, restricted to cell-body interactions; the m x n blocking of the
+// Improving instruction-level parallelism section: one list per sink cell,
+// shared by all its sinks).
+//
+// One wavefront walks one group. The unit of work is a run of sibling cells
+// (contiguous in the canonical cell order): the lanes test the run against
+// the acceptance criterion at once, the cells before the first opened one are
+// emitted in order with ballot compaction, the rest of the run is kept on an
+// LDS stack and the opened cell's children become the next run. The output is
+// therefore exactly the depth-first preorder. The kernel runs twice: once to
+// count, once to fill at offsets from a scan of the counts.
+#include "common.h"
+
+namespace hot {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kWavesPerBlock = kB / 64;
+constexpr int kStack = kMaxLevel + 4;
+
+enum { CLS_NONE = 0, CLS_P2P = 1, CLS_M2P = 2, CLS_OPEN = 3 };
+
+template <bool FILL>
+__global__ __launch_bounds__(kB) void k_walk(
+    const int32_t* __restrict__ g_cell, int64_t G, const double* __restrict__ c_centre,
+    const double* __restrict__ c_bmax, const int32_t* __restrict__ c_count,
+    const uint8_t* __restrict__ c_leaf, const int32_t* __restrict__ c_child,
+    const int32_t* __restrict__ c_nchild, double theta, int direct_max,
+    int64_t* __restrict__ cnt_p2p, int64_t* __restrict__ cnt_m2p, int64_t* __restrict__ pairs_p2p,
+    const int64_t* __restrict__ off_p2p, const int64_t* __restrict__ off_m2p,
+    int32_t* __restrict__ p2p, int32_t* __restrict__ m2p, int64_t C, unsigned* __restrict__ flags) {
+  __shared__ int2 stk[kWavesPerBlock][kStack];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (g >= G) return;
+  const int gc = g_cell[g];
+  const double gx = c_centre[3 * gc], gy = c_centre[3 * gc + 1], gz = c_centre[3 * gc + 2];
+  const double gb = c_bmax[gc];
+  const uint64_t lt = lanemask_lt();
+  int64_t np = 0, nmm = 0, npairs = 0;
+  int64_t bp = 0, bm = 0;
+  if (FILL) {
+    bp = off_p2p[g];
+    bm = off_m2p[g];
+  }
+  if (lane == 0) stk[w][0] = make_int2(0, 1);
+  int top = 0;
+  while (top >= 0) {
+    __builtin_amdgcn_wave_barrier();
+    const int2 r = stk[w][top];
+    const int lo = uniform_i32(r.x), hi = uniform_i32(r.y);
+    if (lo < 0 || hi > C || hi - lo > 8 || lo >= hi) {  // never true for a valid tree
+      if (lane == 0) atomicOr(flags, FLAG_INTERNAL);
+      break;
+    }
+    const int c = lo + lane;
+    int cls = CLS_NONE;
+    int cnt = 0;
+    if (c < hi) {
+      const double dx = gx - c_centre[3 * c], dy = gy - c_centre[3 * c + 1],
+                   dz = gz - c_centre[3 * c + 2];
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      const double rr = c_bmax[c] / theta + gb;
+      cnt = c_count[c];
+      if (d2 > rr * rr)
+        cls = cnt <= direct_max ? CLS_P2P : CLS_M2P;
+      else
+        cls = c_leaf[c] ? CLS_P2P : CLS_OPEN;
+    }
+    const uint64_t om = __ballot(cls == CLS_OPEN);
+    const int k = om ? (__ffsll((long long)om) - 1) : 64;
+    const uint64_t before = k >= 64 ? ~0ull : ((1ull << k) - 1ull);
+    const uint64_t pm = __ballot(cls == CLS_P2P) & before;
+    const uint64_t mm = __ballot(cls == CLS_M2P) & before;
+    if (FILL) {
+      if ((pm >> lane) & 1ull) p2p[bp + np + __popcll(pm & lt)] = c;
+      if ((mm >> lane) & 1ull) m2p[bm + nmm + __popcll(mm & lt)] = c;
+    } else {
+      if ((pm >> lane) & 1ull) npairs += cnt;
+    }
+    np += __popcll(pm);
+    nmm += __popcll(mm);
+    if (om) {
+      const int oc = lo + k;
+      const int cf = c_child[oc], nc = c_nchild[oc];
+      int nt = top;
+      if (nc < 1 || cf < 0 || top + 2 >= kStack) {  // never true for a valid tree
+        if (lane == 0) atomicOr(flags, FLAG_INTERNAL);
+        break;
+      }
+      if (oc + 1 < hi) {
+        if (lane == 0) stk[w][top] = make_int2(oc + 1, hi);
+        nt = top + 1;
+      }
+      if (lane == 0) stk[w][nt] = make_int2(cf, cf + nc);
+      top = nt;
+    } else {
+      --top;
+    }
+  }
+  if (!FILL) {
+    // sum of P2P source particles over lanes
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) npairs += __shfl_xor(npairs, off);
+    if (lane == 0) {
+      cnt_p2p[g] = np;
+      cnt_m2p[g] = nmm;
+      pairs_p2p[g] = npairs;
+    }
+  }
+}
+
+__global__ void k_pair_weights(const int32_t* __restrict__ g_count, int64_t G,
+                               int64_t* __restrict__ pp, int64_t* __restrict__ mp) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  pp[g] *= g_count[g];
+  mp[g] *= g_count[g];
+}
+
+}  // namespace
+
+void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+  hipStream_t st = ctx->stream;
+  const int64_t G = t->n_groups;
+  t->has_lists = false;
+  t->has_transpose = false;
+  t->p2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
+  t->m2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
+  DBuf pairs, mcount, totals;
+  pairs.alloc(ctx, (G + 1) * sizeof(int64_t));
+  mcount.alloc(ctx, (G + 1) * sizeof(int64_t));
+  totals.alloc(ctx, 4 * sizeof(int64_t));
+  const unsigned grid = grid_for(G, kWavesPerBlock);
+  k_walk<false><<<grid, kB, 0, st>>>(
+      t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
+      t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
+      t->c_nchild.as<int32_t>(), theta, direct_max, t->p2p_off.as<int64_t>(),
+      t->m2p_off.as<int64_t>(), pairs.as<int64_t>(), nullptr, nullptr, nullptr, nullptr,
+      t->n_cells, ctx->d_flags);
+  HOT_CHECK_LAUNCH();
+  // pair counts: P2P sources x sinks, M2P cells x sinks
+  HOT_HIP(hipMemcpyAsync(mcount.p, t->m2p_off.p, G * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  k_pair_weights<<<grid_for(G, kB), kB, 0, st>>>(t->g_count.as<int32_t>(), G, pairs.as<int64_t>(),
+                                                 mcount.as<int64_t>());
+  HOT_CHECK_LAUNCH();
+  int64_t* tot = totals.as<int64_t>();
+  scan_i64(ctx, pairs.as<int64_t>(), pairs.as<int64_t>(), G, tot + 2);
+  scan_i64(ctx, mcount.as<int64_t>(), mcount.as<int64_t>(), G, tot + 3);
+  scan_i64(ctx, t->p2p_off.as<int64_t>(), t->p2p_off.as<int64_t>(), G, t->p2p_off.as<int64_t>() + G);
+  scan_i64(ctx, t->m2p_off.as<int64_t>(), t->m2p_off.as<int64_t>(), G, t->m2p_off.as<int64_t>() + G);
+  int64_t h[4];
+  unsigned flags = 0;
+  HOT_HIP(hipMemcpyAsync(&flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipMemcpyAsync(&h[0], t->p2p_off.as<int64_t>() + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipMemcpyAsync(&h[1], t->m2p_off.as<int64_t>() + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipMemcpyAsync(&h[2], tot + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipStreamSynchronize(st));
+  if (flags & FLAG_INTERNAL) throw Error{HOT_E_DEVICE, "walk consistency check failed"};
+  t->n_p2p = h[0];
+  t->n_m2p = h[1];
+  t->p2p_pairs = h[2];
+  t->m2p_pairs = h[3];
+  t->p2p.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_p2p) * sizeof(int32_t));
+  t->m2p.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_m2p) * sizeof(int32_t));
+  k_walk<true><<<grid, kB, 0, st>>>(
+      t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
+      t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
+      t->c_nchild.as<int32_t>(), theta, direct_max, nullptr, nullptr, nullptr,
+      t->p2p_off.as<int64_t>(), t->m2p_off.as<int64_t>(), t->p2p.as<int32_t>(),
+      t->m2p.as<int32_t>(), t->n_cells, ctx->d_flags);
+  HOT_CHECK_LAUNCH();
+  t->theta = theta;
+  t->direct_max = direct_max;
+  t->has_lists = true;
+}
+
+}  // namespace hot

@@ -1,0 +1,78 @@
+// Host build of the generated expansion code (test harness only): the device
+// qualifiers become plain inline functions and T = double.
+#include <cmath>
+#define __device__
+#define __forceinline__ inline
+namespace hot {
+inline double hot_fma(double a, double b, double c) { return std::fma(a, b, c); }
+inline double hot_rsq(double x) { return 1.0 / std::sqrt(x); }
+}  // namespace hot
+#include "expansions.h"
+
+template <int P>
+static void fwd(const double* M, const double* R, double e2, double* out) {
+  double ax = 0, ay = 0, az = 0, ph = 0;
+  hot::expansion_fwd<P, double, true>(R[0], R[1], R[2], e2, M, ax, ay, az, ph);
+  out[0] = ax, out[1] = ay, out[2] = az, out[3] = ph;
+}
+template <int P>
+static void sink(const double* M, const double* R, double e2, const double* b, double* g) {
+  double gx = 0, gy = 0, gz = 0;
+  hot::expansion_sink_adj<P, double>(R[0], R[1], R[2], e2, M, b[0], b[1], b[2], gx, gy, gz);
+  g[0] = gx, g[1] = gy, g[2] = gz;
+}
+template <int P>
+static void cell(const double* R, double e2, const double* b, double* row) {
+  hot::expansion_cell_adj<P, double>(R[0], R[1], R[2], e2, b[0], b[1], b[2], row);
+}
+
+#define DISPATCH(F, ...)                 \
+  switch (p) {                           \
+    case 0: F<0>(__VA_ARGS__); break;    \
+    case 1: F<1>(__VA_ARGS__); break;    \
+    case 2: F<2>(__VA_ARGS__); break;    \
+    case 3: F<3>(__VA_ARGS__); break;    \
+    case 4: F<4>(__VA_ARGS__); break;    \
+    case 5: F<5>(__VA_ARGS__); break;    \
+    case 6: F<6>(__VA_ARGS__); break;    \
+    case 7: F<7>(__VA_ARGS__); break;    \
+    case 8: F<8>(__VA_ARGS__); break;    \
+  }
+
+extern "C" {
+void shim_fwd(int p, const double* M, const double* R, double e2, double* out) {
+  DISPATCH(fwd, M, R, e2, out);
+}
+void shim_sink(int p, const double* M, const double* R, double e2, const double* b, double* g) {
+  DISPATCH(sink, M, R, e2, b, g);
+}
+void shim_cell(int p, const double* R, double e2, const double* b, double* row) {
+  DISPATCH(cell, R, e2, b, row);
+}
+void shim_p2m(int N, double dx, double dy, double dz, double m, double* acc) {
+  switch (N) {
+    case 0: hot::p2m_order0(dx, dy, dz, m, acc); break;
+    case 1: hot::p2m_order1(dx, dy, dz, m, acc); break;
+    case 2: hot::p2m_order2(dx, dy, dz, m, acc); break;
+    case 3: hot::p2m_order3(dx, dy, dz, m, acc); break;
+    case 4: hot::p2m_order4(dx, dy, dz, m, acc); break;
+    case 5: hot::p2m_order5(dx, dy, dz, m, acc); break;
+    case 6: hot::p2m_order6(dx, dy, dz, m, acc); break;
+    case 7: hot::p2m_order7(dx, dy, dz, m, acc); break;
+    case 8: hot::p2m_order8(dx, dy, dz, m, acc); break;
+  }
+}
+void shim_m2m(int N, const double* M, double dx, double dy, double dz, double* acc) {
+  switch (N) {
+    case 0: hot::m2m_order0(M, dx, dy, dz, acc); break;
+    case 1: hot::m2m_order1(M, dx, dy, dz, acc); break;
+    case 2: hot::m2m_order2(M, dx, dy, dz, acc); break;
+    case 3: hot::m2m_order3(M, dx, dy, dz, acc); break;
+    case 4: hot::m2m_order4(M, dx, dy, dz, acc); break;
+    case 5: hot::m2m_order5(M, dx, dy, dz, acc); break;
+    case 6: hot::m2m_order6(M, dx, dy, dz, acc); break;
+    case 7: hot::m2m_order7(M, dx, dy, dz, acc); break;
+    case 8: hot::m2m_order8(M, dx, dy, dz, acc); break;
+  }
+}
+}

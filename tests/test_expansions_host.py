@@ -1,0 +1,114 @@
+"""The generated expansion code (the GPU kernels' arithmetic, built here for
+the host with T = double) against the oracle's independent formulas."""
+import ctypes
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1310_4502_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    gen = os.path.join(CSRC, "generated", "expansions.h")
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_expansions.py"), gen], check=True)
+    out = str(tmp_path_factory.mktemp("shim") / "libshim.so")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I", os.path.dirname(gen), os.path.join(ROOT, "tests", "host", "expansions_shim.cpp"),
+                    "-o", out], check=True)
+    L = ctypes.CDLL(out)
+    for f in ("shim_fwd", "shim_sink", "shim_cell", "shim_p2m", "shim_m2m"):
+        getattr(L, f).restype = None
+    L.shim_fwd.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
+    L.shim_sink.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    L.shim_cell.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    L.shim_p2m.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [ctypes.c_void_p]
+    L.shim_m2m.argtypes = [ctypes.c_int, ctypes.c_void_p] + [ctypes.c_double] * 3 + [ctypes.c_void_p]
+    return L
+
+
+def P(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def weights(orc, p):
+    return np.array([(-1.0) ** (a + b + c) / (math.factorial(a) * math.factorial(b) * math.factorial(c))
+                     for a, b, c in orc.multi_indices(p)])
+
+
+@pytest.mark.parametrize("p", range(9))
+@pytest.mark.parametrize("eps", [0.0, 0.4])
+def test_forward_matches_oracle(orc, shim, p, eps):
+    rng = np.random.default_rng(p)
+    pts = rng.random((30, 3)) - 0.5
+    m = rng.random(30)
+    M = orc.p2m(p, pts, m, np.zeros(3))
+    Mw = M * weights(orc, p)
+    for _ in range(5):
+        R = rng.normal(size=3) * 3
+        out = np.zeros(4)
+        shim.shim_fwd(p, P(Mw), P(R), eps * eps, P(out))
+        a, phi = orc.m2p(p, M, R, eps)
+        assert np.allclose(-out[:3], a, rtol=1e-12, atol=1e-14 * np.abs(a).max())
+        assert abs(out[3] - phi) <= 1e-12 * abs(phi)
+
+
+@pytest.mark.parametrize("p", range(9))
+def test_adjoint_parts_match_oracle_derivatives(orc, shim, p):
+    rng = np.random.default_rng(100 + p)
+    idx = {a: i for i, a in enumerate(orc.multi_indices(p + 2))}
+    al = orc.multi_indices(p)
+    Mw = rng.normal(size=len(al))
+    E = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    for eps in (0.0, 0.3):
+        R = rng.normal(size=3) * 2.5
+        b = rng.normal(size=3)
+        D = orc.derivs(p + 2, R, eps)
+        # sink part: g_l = sum_k b_k sum_alpha Mw[alpha] d^(alpha+e_k+e_l) G
+        ref = np.zeros(3)
+        for l in range(3):
+            for k in range(3):
+                for s, a in enumerate(al):
+                    t = tuple(a[q] + E[k][q] + E[l][q] for q in range(3))
+                    ref[l] += b[k] * Mw[s] * D[idx[t]]
+        g = np.zeros(3)
+        shim.shim_sink(p, P(Mw), P(R), eps * eps, P(b), P(g))
+        assert np.allclose(g, ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+        # cell part: row[alpha] += sum_k b_k d^(alpha+e_k) G
+        refc = np.array([sum(b[k] * D[idx[tuple(a[q] + E[k][q] for q in range(3))]] for k in range(3))
+                         for a in al])
+        row = np.full(len(al), 0.25)
+        shim.shim_cell(p, P(R), eps * eps, P(b), P(row))
+        assert np.allclose(row - 0.25, refc, rtol=1e-11, atol=1e-13 * np.abs(refc).max())
+
+
+@pytest.mark.parametrize("p", [0, 3, 8])
+def test_p2m_m2m_match_oracle(orc, shim, p):
+    rng = np.random.default_rng(7)
+    pts = rng.random((20, 3)) * 0.5
+    m = rng.random(20)
+    c = np.array([0.25, 0.25, 0.25])
+    ref = orc.p2m(p, pts, m, c)
+    got = np.zeros(orc.nm(p))
+    for N in range(p + 1):
+        off = N * (N + 1) * (N + 2) // 6
+        acc = np.zeros((N + 1) * (N + 2) // 2)
+        for j in range(20):
+            d = pts[j] - c
+            shim.shim_p2m(N, d[0], d[1], d[2], m[j], P(acc))
+        got[off:off + len(acc)] = acc
+    assert np.array_equal(got, ref)  # same operations in the same order
+    parent = np.array([0.5, 0.5, 0.5])
+    refp = orc.m2m(p, ref, c - parent)
+    gotp = np.zeros(orc.nm(p))
+    for N in range(p + 1):
+        off = N * (N + 1) * (N + 2) // 6
+        acc = np.zeros((N + 1) * (N + 2) // 2)
+        shim.shim_m2m(N, P(ref), *(c - parent), P(acc))
+        gotp[off:off + len(acc)] = acc
+    assert np.allclose(gotp, refp, rtol=1e-14, atol=1e-15 * np.abs(refp).max())

@@ -1,0 +1,243 @@
+"""GPU forward path vs the oracle, through the C ABI.
+
+Keys, order, cells, centres, b_max, groups and lists must be bit-exact (they
+are integer or exactly specified IEEE results); moments agree to 1e-13 per
+cell; accelerations to 1e-5 relative RMS (mixed FP32 + Kahan) or 1e-12 (FP64)
+against the oracle treecode on the same lists, and to the paper-style 1e-3
+against direct summation.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1310_4502_amd import workloads as W
+from paper_1310_4502_amd.binding import (HOT_FP64, HOT_MIXED, HotError, Tree, Context,
+                                         HOT_E_INVALID, HOT_E_STATE, HOT_E_OOM)
+from gpu_util import (assert_lists_equal, assert_tree_equal, build_both, rel_rms, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _special(name):
+    rng = np.random.default_rng(9)
+    if name == "ties":
+        pos = np.repeat(rng.random((300, 3)), 7, axis=0)
+        rng.shuffle(pos)
+    elif name == "faces":
+        pos = rng.random((5000, 3))
+        pos[::7, 0] = 1.0
+        pos[::11, 1] = 0.0
+        pos[::13, 2] = 1.0
+        pos[::17] = 1.0
+    elif name == "one":
+        pos = np.array([[0.3, 0.4, 0.5]])
+    elif name == "few":
+        pos = rng.random((10, 3))
+    elif name == "bigleaf":
+        pos = np.concatenate([rng.random((3000, 3)), np.full((200, 3), 0.371)])
+    else:
+        raise KeyError(name)
+    n = pos.shape[0]
+    box = (0.0, 0.0, 0.0, 1.0) if name == "faces" else None
+    return W.Workload(name, pos, np.full(n, 1.0 / n), 1e-3, 0.5, 4, box=box)
+
+
+CASES = [("uniform4k", None), ("plummer1m", 20000), ("clustered4m", 30000), ("ties", None),
+         ("faces", None), ("one", None), ("few", None), ("bigleaf", None)]
+
+
+def _make(name, n):
+    if name in ("ties", "faces", "one", "few", "bigleaf"):
+        return _special(name)
+    return W.make(name, n=n)
+
+
+@pytest.mark.parametrize("name,n", CASES)
+def test_tree_lists_moments_bitexact(name, n):
+    w = _make(name, n)
+    _log("case", name, w.n)
+    gt, ot, pos, mass, p = build_both(w)
+    assert_tree_equal(gt, ot)
+    assert_lists_equal(gt, ot)
+    ot.compute_moments(w.pos, w.mass, p)
+    gm, om = gt.moments(), ot.moments()
+    scale = np.maximum(np.abs(om).max(axis=1, keepdims=True), 1e-300)
+    assert np.max(np.abs(gm - om) / scale) <= 1e-13
+    # hash table: every cell key finds its cell; absent keys find nothing
+    c = gt.cells()
+    assert np.array_equal(gt.lookup(c["key"]), np.arange(len(c["key"]), dtype=np.int32))
+    absent = np.array([0, 2, 3, (1 << 62) + 12345], dtype=np.uint64)
+    absent = absent[~np.isin(absent, c["key"])]
+    assert np.all(gt.lookup(absent) == -1)
+
+
+@pytest.mark.parametrize("theta,direct_max,n_leaf,n_group", [
+    (0.3, 0, 8, 32), (0.7, 0, 16, 64), (0.5, 40, 16, 64), (0.5, 0, 4, 128), (0.6, 0, 32, 256)])
+def test_lists_bitexact_parameters(theta, direct_max, n_leaf, n_group):
+    w = W.make("clustered4m", n=20000)
+    w.n_leaf, w.n_group = n_leaf, n_group
+    gt, ot, *_ = build_both(w, theta=theta, direct_max=direct_max)
+    assert_tree_equal(gt, ot)
+    assert_lists_equal(gt, ot)
+    c = gt.counts()
+    assert c["n_p2p"] == ot.counts()["n_p2p"] and c["n_m2p"] == ot.counts()["n_m2p"]
+
+
+@pytest.mark.parametrize("name,n,p", [("uniform4k", None, 2), ("plummer1m", 20000, 4),
+                                      ("clustered4m", 30000, 6), ("plummer1m", 8000, 8),
+                                      ("bigleaf", None, 3), ("ties", None, 4)])
+@pytest.mark.parametrize("with_pot", [False, True])
+def test_forces_vs_oracle_tree(name, n, p, with_pot):
+    w = _make(name, n)
+    gt, ot, pos, mass, p = build_both(w, p=p)
+    ot.compute_moments(w.pos, w.mass, p)
+    oa, op, ocnt = ot.eval(w.pos, w.mass, w.eps)
+    ga, gp, st = gt.eval_forces(pos, mass, w.eps, HOT_MIXED, with_pot=with_pot, stats=True)
+    ga = ga.cpu().numpy()
+    err = rel_rms(ga, oa)
+    _log(name, w.n, "p", p, "mixed rel rms vs oracle tree", err)
+    assert err <= 1e-5
+    assert st.p2p_pairs == ocnt[0] and st.m2p_pairs == ocnt[1]
+    if with_pot:
+        assert rel_rms(gp.cpu().numpy(), op) <= 1e-5
+    ga64, gp64, _ = gt.eval_forces(pos, mass, w.eps, HOT_FP64, with_pot=with_pot)
+    err64 = rel_rms(ga64.cpu().numpy(), oa)
+    _log(name, "fp64 rel rms vs oracle tree", err64)
+    assert err64 <= 1e-12
+    if with_pot:
+        assert rel_rms(gp64.cpu().numpy(), op) <= 1e-12
+
+
+def test_forces_vs_direct_paper_level():
+    w = W.make("plummer1m", n=30000)
+    gt, ot, pos, mass, p = build_both(w, theta=0.5, p=4, lists=False)
+    gt.build_interaction_lists(0.5, 0)
+    ga, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    sinks = W.sample_indices(w.n, 3000, 12)
+    ad, _ = oracle.direct(w.pos, w.mass, w.eps, sinks=sinks)
+    err = rel_rms(ga.cpu().numpy()[sinks], ad)
+    _log("mixed vs direct", err)
+    assert err <= 1e-3
+
+
+def test_deterministic_and_replay():
+    w = W.make("clustered4m", n=20000)
+    gt, ot, pos, mass, p = build_both(w, p=4)
+    a1, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    a2, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    assert torch.equal(a1, a2)
+    # topology replay: new positions, same tree (moments recomputed)
+    rng = np.random.default_rng(3)
+    pos2 = w.pos + rng.normal(scale=1e-4, size=w.pos.shape)
+    p2 = torch.from_numpy(pos2).cuda()
+    gt.compute_moments(p2, mass, p)
+    ga, _, _ = gt.eval_forces(p2, mass, w.eps, HOT_FP64)
+    ot.compute_moments(pos2, w.mass, p)
+    oa, _, _ = ot.eval(pos2, w.mass, w.eps)
+    assert rel_rms(ga.cpu().numpy(), oa) <= 1e-12
+    # rebuilding gives the identical tree and result
+    gt2 = Tree(pos, w.n_leaf, w.n_group, w.box)
+    gt2.build_interaction_lists(w.theta, 0)
+    gt2.compute_moments(pos, mass, p)
+    a3, _, _ = gt2.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    assert torch.equal(a1, a3)
+
+
+def test_eps_zero_and_coincident():
+    w = _special("ties")
+    w.eps = 0.0
+    gt, ot, pos, mass, p = build_both(w, p=3)
+    ot.compute_moments(w.pos, w.mass, p)
+    oa, _, _ = ot.eval(w.pos, w.mass, 0.0)
+    ga, _, _ = gt.eval_forces(pos, mass, 0.0, HOT_FP64)
+    ga = ga.cpu().numpy()
+    assert np.all(np.isfinite(ga))
+    assert rel_rms(ga, oa) <= 1e-12
+
+
+def test_argument_and_state_errors():
+    w = W.make("uniform4k")
+    pos, mass = to_dev(w)
+    t = Tree(pos, box=w.box)
+    with pytest.raises(HotError) as e:
+        t.eval_forces(pos, mass, 1e-3)
+    assert e.value.code == HOT_E_STATE
+    for th in (0.0, 1.0, -0.5, float("nan")):
+        with pytest.raises(HotError) as e:
+            t.build_interaction_lists(th)
+        assert e.value.code == HOT_E_INVALID
+    for p in (-1, 9):
+        with pytest.raises(HotError) as e:
+            t.compute_moments(pos, mass, p)
+        assert e.value.code == HOT_E_INVALID
+    t.build_interaction_lists(0.5)
+    t.compute_moments(pos, mass, 2)
+    for eps in (-1.0, float("inf")):
+        with pytest.raises(HotError):
+            t.eval_forces(pos, mass, eps)
+    with pytest.raises(HotError):
+        Tree(pos, n_leaf=100, n_group=64)
+    with pytest.raises(HotError):
+        Tree(pos, box=(0, 0, 0, 3.0))
+    with pytest.raises(HotError):
+        Tree(pos * 2.0, box=(0, 0, 0, 1.0))
+    bad = pos.clone()
+    bad[5, 1] = float("nan")
+    with pytest.raises(HotError):
+        Tree(bad)
+    # negative mass is reported at the next synchronisation
+    m2 = mass.clone()
+    m2[3] = -1.0
+    t.compute_moments(pos, m2, 2)
+    with pytest.raises(HotError) as e:
+        t.ctx.sync()
+    assert e.value.code == HOT_E_INVALID
+    t.ctx.sync()  # flags cleared
+    a, _, _ = t.eval_forces(pos, mass, 1e-3)  # the tree is still usable
+    assert torch.isfinite(a).all()
+
+
+def test_allocator_failure_is_reported_and_leaves_no_tree():
+    w = W.make("uniform4k")
+    pos, mass = to_dev(w)
+    ctx = Context(0, torch.cuda.current_stream(), torch_alloc=True)
+    calls = {"n": 0}
+    orig = ctx._afn
+
+    # replace the allocator with one that fails after a few allocations
+    from paper_1310_4502_amd import binding
+    blocks = {}
+
+    def _a(user, nbytes, stream):
+        calls["n"] += 1
+        if calls["n"] > 6:
+            return None
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        blocks[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _f(user, ptr, stream):
+        blocks.pop(ptr, None)
+
+    afn, ffn = binding.ALLOC_FN(_a), binding.FREE_FN(_f)
+    alloc = binding._Allocator(afn, ffn, None)
+    h = ctypes.c_void_p()
+    L = binding.load()
+    assert L.hot_ctx_create(0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                            ctypes.byref(alloc), ctypes.byref(h)) == 0
+    out = ctypes.c_void_p()
+    rc = L.tree_build(h, w.n, ctypes.c_void_p(pos.data_ptr()), None, ctypes.byref(out))
+    assert rc == HOT_E_OOM
+    assert not out.value
+    assert L.hot_sync(h) == 0
+    assert len(blocks) == 0  # everything the failed call allocated was freed
+    L.hot_ctx_destroy(h)
+    ctx.close()
