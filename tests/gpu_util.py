@@ -59,6 +59,17 @@ def assert_lists_equal(gt, ot, groups=None):
             assert np.array_equal(gml[gmo[g]:gmo[g + 1]], oml[omo[g]:omo[g + 1]]), g
 
 
+def assert_moments_close(gm, om, count):
+    """FP64 moments from re-centred children vs direct sums: 1e-13 relative to
+    the cell's largest moment, times sqrt(count / 64) above 64 particles (the
+    expected growth of rounding differences between two summation orders)."""
+    scale = np.maximum(np.abs(om).max(axis=1), 1e-300)
+    tol = 1e-13 * np.maximum(1.0, np.sqrt(np.asarray(count, dtype=np.float64) / 64.0))
+    err = np.abs(gm - om).max(axis=1) / scale
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, (bad[:5], err[bad[:5]], tol[bad[:5]])
+
+
 def rel_rms(a, ref):
     return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
 

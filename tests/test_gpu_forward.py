@@ -2,7 +2,8 @@
 
 Keys, order, cells, centres, b_max, groups and lists must be bit-exact (they
 are integer or exactly specified IEEE results); moments agree to 1e-13 per
-cell; accelerations to 1e-5 relative RMS (mixed FP32 + Kahan) or 1e-12 (FP64)
+cell relative to the cell's largest moment, widened by sqrt(count / 64) for
+cells of more than 64 particles (FP64 sums of many terms in another order); accelerations to 1e-5 relative RMS (mixed FP32 + Kahan) or 1e-12 (FP64)
 against the oracle treecode on the same lists, and to the paper-style 1e-3
 against direct summation.
 """
@@ -17,7 +18,8 @@ import oracle
 from paper_1310_4502_amd import workloads as W
 from paper_1310_4502_amd.binding import (HOT_FP64, HOT_MIXED, HotError, Tree, Context,
                                          HOT_E_INVALID, HOT_E_STATE, HOT_E_OOM)
-from gpu_util import (assert_lists_equal, assert_tree_equal, build_both, rel_rms, to_dev)
+from gpu_util import (assert_lists_equal, assert_moments_close, assert_tree_equal, build_both,
+                      rel_rms, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -69,8 +71,7 @@ def test_tree_lists_moments_bitexact(name, n):
     assert_lists_equal(gt, ot)
     ot.compute_moments(w.pos, w.mass, p)
     gm, om = gt.moments(), ot.moments()
-    scale = np.maximum(np.abs(om).max(axis=1, keepdims=True), 1e-300)
-    assert np.max(np.abs(gm - om) / scale) <= 1e-13
+    assert_moments_close(gm, om, gt.cells()["count"])
     # hash table: every cell key finds its cell; absent keys find nothing
     c = gt.cells()
     assert np.array_equal(gt.lookup(c["key"]), np.arange(len(c["key"]), dtype=np.int32))
