@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the tree-force hot path on one MI355X.
+
+One step = tree_build + compute_moments + build_interaction_lists +
+eval_forces + eval_forces_adjoint on one synthetic batch whose inputs are
+already resident in HBM. Prints one JSON line.
+
+value = particle interactions (P2P pairs + M2P sink-cell pairs of the
+forward lists) per second of whole step time. The line also carries
+forces/s, the per-kernel split, the adjoint/forward cost ratio, the RMS
+force error against direct summation on sampled sinks, the roofline of the
+dominant kernel (timed with HIP events on the library's stream) and the
+CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("particle interactions/sec & forces/sec at ≤1e-3 RMS force err; "
+          "adjoint/fwd cost")
+FP32_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (n_leaf, n_group, direct_max, description)
+    "zeldovich16m": (16, 96, 64, "2^24 particles, 256^3 grid displaced by a P(k)~k^-2 "
+                                 "Gaussian field (RMS 0.3 cells), eps=2e-5, theta=0.5, p=8, "
+                                 "forward + one adjoint VJP"),
+    "clustered16m": (16, 64, 32, "2^24 particles, half in 512 Plummer halos, half uniform, "
+                                 "eps=5e-5, theta=0.5, p=6"),
+    "clustered4m": (16, 64, 32, "2^22 particles, half in 512 Plummer halos, half uniform, "
+                                "eps=5e-5, theta=0.5, p=6"),
+    "plummer1m": (16, 64, 16, "2^20 Plummer sphere a=1/16, eps=1e-4, theta=0.6, p=4"),
+    "uniform4k": (16, 64, 0, "4096 uniform, eps=1e-3, theta=0.5, p=2"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_flops():
+    """FP32 operations per interaction of the P2P and M2P kernels, counted
+    from the code the generator emits (FMA = 2)."""
+    sys.path.insert(0, os.path.join(ROOT, "paper_1310_4502_amd", "csrc"))
+    import gen_expansions as ge
+    return ge.flops_p2p(), {p: ge.flops_m2p(p) for p in range(9)}
+
+
+def source_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel_key)
+    except Exception:
+        return None
+    if not rec:
+        return None
+    if rec.get("source_digest") != source_digest(rec.get("sources", [])):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="zeldovich16m", choices=sorted(WORKLOADS))
+    ap.add_argument("--n-group", type=int, default=None)
+    ap.add_argument("--n-leaf", type=int, default=None)
+    ap.add_argument("--direct-max", type=int, default=None)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-groups", type=int, default=24,
+                    help="sink groups evaluated by the CPU oracle sample")
+    ap.add_argument("--err-sinks", type=int, default=256)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the force path of "
+              "this library is single-GPU; see the sharding design notes.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1310_4502_amd import workloads as W
+    from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    n_leaf, n_group, direct_max, desc = WORKLOADS[args.workload]
+    n_leaf = args.n_leaf or n_leaf
+    n_group = args.n_group or n_group
+    direct_max = direct_max if args.direct_max is None else args.direct_max
+    prec = HOT_FP64 if args.precision == "fp64" else HOT_MIXED
+
+    t0 = time.time()
+    w = W.make(args.workload)
+    log(f"workload {args.workload}: N={w.n} generated in {time.time() - t0:.1f}s")
+    pos = torch.from_numpy(w.pos).cuda()
+    mass = torch.from_numpy(w.mass).cuda()
+    abar = torch.from_numpy(W.cotangent(w.n, 404)).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        t = Tree(pos, n_leaf, n_group, w.box)
+        t.compute_moments(pos, mass, w.p)
+        t.build_interaction_lists(w.theta, direct_max)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev2 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        acc, _, st = t.eval_forces(pos, mass, w.eps, prec, stats=True)
+        ev1.record()
+        try:
+            xbar, _ = t.eval_forces_adjoint(pos, mass, w.eps, abar, prec)
+        except HotError as e:
+            if "adjoint not available" not in str(e):
+                raise
+            xbar = None
+        ev2.record()
+        return t, acc, xbar, st, (ev0, ev1, ev2)
+
+    for k in range(args.warmup):
+        t, *_ = step()
+        del t
+        torch.cuda.synchronize()
+        log(f"warmup step {k + 1}/{args.warmup} done")
+
+    recs = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        t, acc, xbar, st, evs = step()
+        recs.append((st.ms_p2p, st.ms_m2p, st.ms_total, st.p2p_pairs, st.m2p_pairs, evs))
+        last = (t, acc, xbar)
+        log(f"timed step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1000.0 * elapsed / args.steps
+    ms_p2p = float(np.mean([r[0] for r in recs]))
+    ms_m2p = float(np.mean([r[1] for r in recs]))
+    ms_fwd_eval = float(np.mean([r[2] for r in recs]))
+    ms_adj = float(np.mean([r[5][1].elapsed_time(r[5][2]) for r in recs]))
+    p2p_pairs, m2p_pairs = recs[-1][3], recs[-1][4]
+    inter = p2p_pairs + m2p_pairs
+    tree, acc, xbar = last
+    counts = tree.counts()
+
+    f_p2p, f_m2p = kernel_flops()
+    # dominant kernel: the longer of P2P and M2P in eval_forces
+    if ms_m2p >= ms_p2p:
+        dom, dom_ms, dom_flops = f"m2p_p{w.p}", ms_m2p, m2p_pairs * f_m2p[w.p]
+    else:
+        dom, dom_ms, dom_flops = "p2p", ms_p2p, p2p_pairs * f_p2p
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    traffic = traffic_from_profiles(dom)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": traffic, "kernel": dom,
+                "flops_per_interaction": f_m2p[w.p] if dom.startswith("m2p") else f_p2p,
+                "ms_per_launch": round(dom_ms, 3)}
+
+    out = {
+        "metric": METRIC,
+        "value": inter / (ms_step * 1e-3),
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == HOT_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n": w.n, "p": w.p,
+                   "theta": w.theta, "eps": w.eps, "n_leaf": n_leaf, "n_group": n_group,
+                   "direct_max": direct_max, "precision": args.precision},
+        "forces_per_s": w.n / (ms_step * 1e-3),
+        "p2p_pairs": p2p_pairs,
+        "m2p_pairs": m2p_pairs,
+        "ms_eval_forces": ms_fwd_eval,
+        "ms_p2p": ms_p2p,
+        "ms_m2p": ms_m2p,
+        "ms_adjoint": ms_adj,
+        "adjoint_over_eval": ms_adj / ms_fwd_eval if ms_fwd_eval > 0 else None,
+        "interactions_per_s_eval": inter / (ms_fwd_eval * 1e-3),
+        "p2p_gflops_28flop_convention": p2p_pairs * 28 / (ms_p2p * 1e-3) / 1e9,
+        "tree": {k: counts[k] for k in ("n_cells", "n_groups", "n_leaves", "max_level",
+                                        "n_p2p", "n_m2p", "n_items")},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["rms_err_vs_direct"] = cpu_baseline(
+            w, acc, n_leaf, n_group, direct_max, args.cpu_groups, args.err_sinks)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, acc_gpu, n_leaf, n_group, direct_max, n_groups_sample, n_err):
+    """The CPU oracle (FP64 scalar treecode, OpenMP) on a bounded sample of the
+    same workload: its interaction rate over the sampled sinks' evaluation
+    (tree build and moments excluded), plus the GPU's RMS force error against
+    the oracle's direct summation on sampled sinks."""
+    import numpy as np
+
+    import oracle
+    from paper_1310_4502_amd import workloads as W
+
+    t0 = time.time()
+    ot = oracle.Tree(w.pos, n_leaf, n_group, w.box)
+    gof = ot.group_of()
+    G = ot.counts()["n_groups"]
+    groups = W.sample_indices(G, n_groups_sample, 77)
+    ot.build_lists(w.theta, direct_max, groups=groups)
+    po, pl, mo, ml = ot.lists()
+    cells = np.unique(np.concatenate([ml[mo[g]:mo[g + 1]] for g in groups]))
+    ot.compute_moments(w.pos, w.mass, w.p, cells=cells)
+    _, perm = ot.keys()
+    sinks = np.sort(perm[np.isin(gof, groups)])
+    log(f"cpu oracle: tree+lists+moments for {len(groups)} groups in {time.time() - t0:.1f}s")
+    t1 = time.perf_counter()
+    _, _, cnt = ot.eval(w.pos, w.mass, w.eps, sinks=sinks, with_pot=False)
+    dt = time.perf_counter() - t1
+    inter = int(cnt[0] + cnt[1])
+    log(f"cpu oracle: {len(sinks)} sinks, {inter} interactions in {dt:.1f}s")
+    base = {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 scalar treecode (O-T) evaluation of {len(sinks)} sinks in "
+                      f"{len(groups)} sampled groups of the same workload; tree build and "
+                      f"moments not timed"}
+    es = W.sample_indices(w.n, n_err, 102)
+    t2 = time.time()
+    ad, _ = oracle.direct(w.pos, w.mass, w.eps, sinks=es)
+    a = acc_gpu.cpu().numpy()[es]
+    err = float(np.linalg.norm(a - ad) / np.linalg.norm(ad))
+    log(f"direct-sum check on {n_err} sinks in {time.time() - t2:.1f}s: rel RMS {err:.3e}")
+    return base, err
+
+
+if __name__ == "__main__":
+    main()

@@ -1,10 +1,756 @@
-// Reverse derivative of the force evaluation (placeholder until the adjoint
-// kernels land).
+// Reverse derivative of the force evaluation: the vector-Jacobian product
+// xbar = d(sum_i abar_i . a_i)/dx (and mbar = d/dm) with the tree topology
+// (membership, centres, b_max, lists) held fixed. The paper has no adjoint;
+// this differentiates exactly the map eval_forces computes.
+//
+//  pair terms    a_i += m_j K(x_j - x_i), K(r) = r (|r|^2+eps^2)^(-3/2),
+//                dK/dr = H(r) = s^(-3/2) I - 3 r r^T s^(-5/2):
+//                  sink   xbar_i -= m_j H(r_ij) abar_i      (group-major, like the forward)
+//                  source xbar_j += m_j H(r_ij) abar_i      (source-major over transposed lists)
+//                                 mbar_j += abar_i . r_ij s^(-3/2)
+//  expansion     a_i = -sum_alpha w_alpha M_alpha d^(alpha+e_k) G(x_i - c):
+//                  sink   xbar_i += -sum_k abar_ik sum_alpha w M d^(alpha+e_k+e_l) G
+//                  cell   Mbar_alpha += -w_alpha sum_i sum_k abar_ik d^(alpha+e_k) G
+//                  Mbar flows down the tree through the transpose of the
+//                  re-centring (M2M^T) and into the particles of each leaf
+//                  through the transpose of the moment definition (P2M^T).
+// Every reduction is a gather in a fixed order: no floating-point atomics.
 #include "common.h"
+#include "eval_common.h"
+#include "generated/expansions.h"
 
 namespace hot {
-void adjoint(hot_ctx*, hot_tree*, const double*, const double*, double, int, const double*,
-             double*, double*) {
-  throw Error{HOT_E_STATE, "adjoint not available in this build"};
+
+namespace {
+
+static __constant__ AlphaTable kAlpha = make_alpha_table();
+
+constexpr int kB = 256;
+constexpr int kWPB = kB / 64;
+constexpr int kCellItemGroups = 48;  // groups per work item of the cell-side kernel
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
+
+int bits_for(int64_t v) {
+  int b = 1;
+  while (b < 62 && ((int64_t)1 << b) <= v) ++b;
+  return b;
+}
+
+// ---------------------------------------------------------------- transposes
+__global__ void k_srec_count(const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p,
+                             int64_t G, const int32_t* __restrict__ c_first,
+                             const int32_t* __restrict__ c_count,
+                             const int32_t* __restrict__ item_of, int64_t* __restrict__ cnt) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int64_t k = 0;
+  for (int64_t e = p2p_off[g]; e < p2p_off[g + 1]; ++e) {
+    const int c = p2p[e];
+    const int f = c_first[c];
+    k += item_of[f + c_count[c] - 1] - item_of[f] + 1;
+  }
+  cnt[g] = k;
+}
+
+__global__ void k_srec_fill(const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p,
+                            int64_t G, const int32_t* __restrict__ c_first,
+                            const int32_t* __restrict__ c_count,
+                            const int32_t* __restrict__ item_of,
+                            const int64_t* __restrict__ rec_off, int gbits,
+                            uint64_t* __restrict__ key, uint32_t* __restrict__ val,
+                            uint32_t* __restrict__ per_item) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int64_t o = rec_off[g];
+  for (int64_t e = p2p_off[g]; e < p2p_off[g + 1]; ++e) {
+    const int c = p2p[e];
+    const int f = c_first[c];
+    const int q0 = item_of[f], q1 = item_of[f + c_count[c] - 1];
+    for (int q = q0; q <= q1; ++q) {
+      key[o] = ((uint64_t)q << gbits) | (uint64_t)g;
+      val[o] = (uint32_t)e;
+      ++o;
+      atomicAdd(&per_item[q], 1u);
+    }
+  }
+}
+
+__global__ void k_mrec_fill(const int64_t* __restrict__ m2p_off, const int32_t* __restrict__ m2p,
+                            int64_t G, uint64_t* __restrict__ key, uint32_t* __restrict__ val,
+                            uint32_t* __restrict__ per_cell) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  for (int64_t e = m2p_off[g]; e < m2p_off[g + 1]; ++e) {
+    const int c = m2p[e];
+    key[e] = (uint64_t)c;
+    val[e] = (uint32_t)g;
+    atomicAdd(&per_cell[c], 1u);
+  }
+}
+
+__global__ void k_items_per_cell(const uint32_t* __restrict__ cnt, int64_t C,
+                                 uint32_t* __restrict__ nit) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < C) nit[c] = (cnt[c] + kCellItemGroups - 1) / kCellItemGroups;
+}
+
+__global__ void k_cell_items(const uint32_t* __restrict__ rec_off, const uint32_t* __restrict__ it_off,
+                             int64_t C, uint32_t* __restrict__ citem_rec,
+                             int32_t* __restrict__ citem_cell) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const uint32_t r0 = rec_off[c], i0 = it_off[c], i1 = it_off[c + 1];
+  for (uint32_t k = i0; k < i1; ++k) {
+    citem_rec[k] = r0 + (k - i0) * kCellItemGroups;
+    citem_cell[k] = (int32_t)c;
+  }
+}
+
+// ------------------------------------------------------------------- gathers
+template <typename T>
+__global__ void k_abar(const double* __restrict__ abar, const uint32_t* __restrict__ perm,
+                       int64_t n, V4<T>* __restrict__ ab) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = perm[i];
+  V4<T> v;
+  v.x = (T)abar[3 * j];
+  v.y = (T)abar[3 * j + 1];
+  v.z = (T)abar[3 * j + 2];
+  v.w = T(0);
+  ab[i] = v;
+}
+
+// ------------------------------------------------------- pair terms, sink side
+// state per sorted particle: s_x s_y s_z - c_x c_y c_z -
+template <typename T, bool EPS0>
+__global__ __launch_bounds__(kB) void k_p2p_sink_adj(
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
+    const int32_t* __restrict__ p2p, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
+    const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
+    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+    const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, T eps2,
+    T* __restrict__ state) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * kWPB + w;
+  if (it >= n_items) return;
+  const int2 item = items[it];
+  const int g = uniform_i32(item.x);
+  const int gend = g_first[g] + g_count[g];
+  const int i = item.y + lane;
+  const bool active = i < gend;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  V4<T> me, ab;
+  me.x = me.y = me.z = me.w = T(0);
+  ab = me;
+  if (active) {
+    me = off[i];
+    ab = ab4[i];
+  }
+  T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
+  for (int64_t e = p2p_off[g]; e < p2p_off[g + 1]; ++e) {
+    const int c = p2p[e];
+    const int f = c_first[c];
+    const int end = f + c_count[c];
+    T A = 0, Bx = 0, By = 0, Bz = 0;  // sum m inv3 ; sum 3 m (r.ab) inv5 r
+    int j = f;
+    while (j < end) {
+      const int sg = group_of[j];
+      const int sgend = g_first[sg] + g_count[sg];
+      const int jend = end < sgend ? end : sgend;
+      if (jend <= j) break;
+      const int sc = g_cell[sg];
+      const T tx = (T)(c_centre[3 * sc] - cgx) - me.x;
+      const T ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
+      const T tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+      for (int jj = j; jj < jend; ++jj) {
+        const V4<T> s = off[jj];
+        const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;
+        const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
+        T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
+        if (sg == g && jj == i) inv = T(0);
+        const T inv2 = inv * inv;
+        const T m3 = s.w * (inv * inv2);
+        const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));
+        const T q = (T(3) * m3) * (rd * inv2);
+        A += m3;
+        Bx = hot_fma(q, rx, Bx);
+        By = hot_fma(q, ry, By);
+        Bz = hot_fma(q, rz, Bz);
+      }
+      j = jend;
+    }
+    // xbar_i -= m_j H ab = -(sum m inv3) ab + sum 3 m rd inv5 r
+    kahan_add(sx, cx, hot_fma(-A, ab.x, Bx));
+    kahan_add(sy, cy, hot_fma(-A, ab.y, By));
+    kahan_add(sz, cz, hot_fma(-A, ab.z, Bz));
+  }
+  if (active) {
+    T* st = state + (int64_t)i * 8;
+    st[0] = sx;
+    st[1] = sy;
+    st[2] = sz;
+    st[4] = cx;
+    st[5] = cy;
+    st[6] = cz;
+  }
+}
+
+// ------------------------------------------------- expansion terms, sink side
+template <int P, typename T>
+__global__ __launch_bounds__(kB) void k_m2p_sink_adj(
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
+    const int32_t* __restrict__ m2p, const int8_t* __restrict__ c_level,
+    const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
+    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+    const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, const T* __restrict__ momw,
+    double inv_side, double eps, T* __restrict__ state) {
+  constexpr int stride = nm_pad(P);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * kWPB + w;
+  if (it >= n_items) return;
+  const int2 item = items[it];
+  const int g = uniform_i32(item.x);
+  const int gend = g_first[g] + g_count[g];
+  const int i = item.y + lane;
+  const bool active = i < gend;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  V4<T> me, ab;
+  me.x = me.y = me.z = me.w = T(0);
+  ab = me;
+  T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
+  if (active) {
+    me = off[i];
+    ab = ab4[i];
+    const T* st = state + (int64_t)i * 8;
+    sx = st[0];
+    sy = st[1];
+    sz = st[2];
+    cx = st[4];
+    cy = st[5];
+    cz = st[6];
+  }
+  for (int64_t e = m2p_off[g]; e < m2p_off[g + 1]; ++e) {
+    const int c = m2p[e];
+    const double inv_s = ldexp(inv_side, (int)c_level[c]);
+    const T X = (T)((cgx - c_centre[3 * c]) * inv_s) + me.x * (T)inv_s;
+    const T Y = (T)((cgy - c_centre[3 * c + 1]) * inv_s) + me.y * (T)inv_s;
+    const T Z = (T)((cgz - c_centre[3 * c + 2]) * inv_s) + me.z * (T)inv_s;
+    const double es = eps * inv_s;
+    T gx = 0, gy = 0, gz = 0;
+    expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), momw + (int64_t)c * stride, ab.x, ab.y, ab.z,
+                             gx, gy, gz);
+    const T sc = (T)(-(inv_s * inv_s * inv_s));
+    kahan_add(sx, cx, gx * sc);
+    kahan_add(sy, cy, gy * sc);
+    kahan_add(sz, cz, gz * sc);
+  }
+  if (active) {
+    T* st = state + (int64_t)i * 8;
+    st[0] = sx;
+    st[1] = sy;
+    st[2] = sz;
+    st[4] = cx;
+    st[5] = cy;
+    st[6] = cz;
+  }
+}
+
+// ----------------------------------------------------- pair terms, source side
+// One wavefront per source item (at most 64 particles of one group); lanes are
+// source particles. The records of the item are sorted by sink group; runs of
+// one group are merged into a lane mask (the lanes whose particles lie in one
+// of that group's P2P cells), then the group's sinks are swept uniformly.
+// out per sorted particle: s_x s_y s_z s_m c_x c_y c_z c_m
+template <typename T, bool EPS0>
+__global__ __launch_bounds__(kB) void k_p2p_src_adj(
+    const int2* __restrict__ items, int64_t n_items, const uint64_t* __restrict__ skey,
+    const uint32_t* __restrict__ sval, const uint32_t* __restrict__ soff, uint64_t gmask,
+    const int32_t* __restrict__ p2p, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ c_count, const int32_t* __restrict__ g_first,
+    const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
+    const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
+    const V4<T>* __restrict__ ab4, T eps2, T* __restrict__ out) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * kWPB + w;
+  if (q >= n_items) return;
+  const int2 item = items[q];
+  const int gs = uniform_i32(item.x);
+  const int j = item.y + lane;
+  const bool active = j < g_first[gs] + g_count[gs];
+  const int gsc = g_cell[gs];
+  const double csx = c_centre[3 * gsc], csy = c_centre[3 * gsc + 1], csz = c_centre[3 * gsc + 2];
+  V4<T> me;
+  me.x = me.y = me.z = me.w = T(0);
+  if (active) me = off[j];
+  T sx = 0, sy = 0, sz = 0, sm = 0, cx = 0, cy = 0, cz = 0, cm = 0;
+  uint32_t r = soff[q];
+  const uint32_t rend = soff[q + 1];
+  while (r < rend) {
+    const uint64_t k0 = skey[r];
+    const int g = (int)(k0 & gmask);
+    bool mine = false;
+    while (r < rend && skey[r] == k0) {
+      const int c = p2p[sval[r]];
+      const int f = c_first[c];
+      mine |= (j >= f) && (j < f + c_count[c]);
+      ++r;
+    }
+    const int gc = g_cell[g];
+    const T tx = (T)(csx - c_centre[3 * gc]) + me.x;  // r_ij = x_j - x_i = t - off_i
+    const T ty = (T)(csy - c_centre[3 * gc + 1]) + me.y;
+    const T tz = (T)(csz - c_centre[3 * gc + 2]) + me.z;
+    const int i0 = g_first[g], i1 = i0 + g_count[g];
+    T gx = 0, gy = 0, gz = 0, gm = 0;
+    for (int i = i0; i < i1; ++i) {
+      const V4<T> si = off[i];
+      const V4<T> ab = ab4[i];
+      const T rx = tx - si.x, ry = ty - si.y, rz = tz - si.z;
+      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
+      T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
+      if (g == gs && i == j) inv = T(0);
+      const T inv2 = inv * inv;
+      const T inv3 = inv * inv2;
+      const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));
+      const T qq = (T(3) * rd) * (inv3 * inv2);
+      gx = hot_fma(ab.x, inv3, hot_fma(-qq, rx, gx));
+      gy = hot_fma(ab.y, inv3, hot_fma(-qq, ry, gy));
+      gz = hot_fma(ab.z, inv3, hot_fma(-qq, rz, gz));
+      gm = hot_fma(rd, inv3, gm);
+    }
+    if (mine) {
+      kahan_add(sx, cx, me.w * gx);
+      kahan_add(sy, cy, me.w * gy);
+      kahan_add(sz, cz, me.w * gz);
+      kahan_add(sm, cm, gm);
+    }
+  }
+  if (active) {
+    T* o = out + (int64_t)j * 8;
+    o[0] = sx;
+    o[1] = sy;
+    o[2] = sz;
+    o[3] = sm;
+    o[4] = cx;
+    o[5] = cy;
+    o[6] = cz;
+    o[7] = cm;
+  }
+}
+
+// ---------------------------------------- expansion terms, moment cotangents
+// One wavefront per cell item (a run of at most kCellItemGroups groups whose
+// M2P lists hold the cell); lanes are the sinks of each group in turn. Each
+// lane accumulates sum_k abar_k d^(alpha+e_k) G for all alpha in registers; the
+// item's partial sums are reduced across lanes with a fixed butterfly.
+template <int P, typename T>
+__global__ __launch_bounds__(64) void k_m2p_cell_adj(
+    int64_t n_citems, const uint32_t* __restrict__ citem_rec, const int32_t* __restrict__ citem_cell,
+    const uint32_t* __restrict__ crec_off, const uint32_t* __restrict__ mval,
+    const int8_t* __restrict__ c_level, const int32_t* __restrict__ g_first,
+    const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
+    const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
+    const V4<T>* __restrict__ ab4, double inv_side, double eps, T* __restrict__ part) {
+  constexpr int NM = nm(P);
+  const int lane = threadIdx.x;
+  const int64_t it = blockIdx.x;
+  if (it >= n_citems) return;
+  const int c = citem_cell[it];
+  const uint32_t r0 = citem_rec[it];
+  const uint32_t rc = crec_off[c + 1];
+  const uint32_t r1 = r0 + kCellItemGroups < rc ? r0 + kCellItemGroups : rc;
+  const double inv_s = ldexp(inv_side, (int)c_level[c]);
+  const double es = eps * inv_s;
+  const T e2 = (T)(es * es);
+  const double ccx = c_centre[3 * c], ccy = c_centre[3 * c + 1], ccz = c_centre[3 * c + 2];
+  T row[NM];
+#pragma unroll
+  for (int a = 0; a < NM; ++a) row[a] = T(0);
+  for (uint32_t r = r0; r < r1; ++r) {
+    const int g = (int)mval[r];
+    const int gc = g_cell[g];
+    const T Dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
+    const T Dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
+    const T Dz = (T)((c_centre[3 * gc + 2] - ccz) * inv_s);
+    const int gf = g_first[g], ge = gf + g_count[g];
+    for (int s0 = gf; s0 < ge; s0 += 64) {
+      const int i = s0 + lane;
+      T X = T(1), Y = T(0), Z = T(0), bx = T(0), by = T(0), bz = T(0);
+      if (i < ge) {
+        const V4<T> me = off[i];
+        const V4<T> ab = ab4[i];
+        X = Dx + me.x * (T)inv_s;
+        Y = Dy + me.y * (T)inv_s;
+        Z = Dz + me.z * (T)inv_s;
+        bx = ab.x;
+        by = ab.y;
+        bz = ab.z;
+      }
+      expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
+    }
+  }
+  T* o = part + it * (int64_t)nm_pad(P);
+#pragma unroll
+  for (int a = 0; a < NM; ++a) {
+    T v = row[a];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == (a & 63)) o[a] = v;
+  }
+}
+
+// Mbar_alpha(c) = -w_alpha s^(-2-|alpha|) * sum over the cell's items (in order).
+template <typename T>
+__global__ void k_mbar_final(const T* __restrict__ part, const uint32_t* __restrict__ it_off,
+                             int64_t C, const int8_t* __restrict__ c_level, double inv_side, int p,
+                             double* __restrict__ mbar) {
+  const int nmv = nm(p), stride = nm_pad(p);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = t / nmv;
+  const int a = (int)(t - c * nmv);
+  if (c >= C) return;
+  double s = 0.0;
+  for (uint32_t k = it_off[c]; k < it_off[c + 1]; ++k) s += (double)part[(int64_t)k * stride + a];
+  const int order = kAlpha.a[a] + kAlpha.b[a] + kAlpha.c[a];
+  const double inv_s = ldexp(inv_side, (int)c_level[c]);
+  double sc = inv_s * inv_s;
+  for (int k = 0; k < order; ++k) sc *= inv_s;
+  mbar[c * nmv + a] = -kAlpha.w[a] * sc * s;
+}
+
+// M2M transpose for one level: child Mbar += shift^T of the parent's Mbar.
+#define HOT_M2MT_CASE(P, N)                                                \
+  case N: {                                                                \
+    double acc[((N) + 1) * ((N) + 2) / 2];                                 \
+    _Pragma("unroll") for (int k = 0; k < ((N) + 1) * ((N) + 2) / 2; ++k) acc[k] = 0.0; \
+    m2mT_p##P##_order##N(Mb, dx, dy, dz, acc);                             \
+    double* out = mbar + c * NMV + (N) * ((N) + 1) * ((N) + 2) / 6;        \
+    _Pragma("unroll") for (int k = 0; k < ((N) + 1) * ((N) + 2) / 2; ++k) out[k] += acc[k]; \
+  } break;
+
+template <int P>
+__global__ __launch_bounds__(kB) void k_m2mT(int64_t c0, int64_t c1,
+                                             const int32_t* __restrict__ parent,
+                                             const double* __restrict__ c_centre,
+                                             double* __restrict__ mbar) {
+  constexpr int NMV = nm(P);
+  const int64_t c = c0 + (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (c >= c1) return;
+  const int pa = parent[c];
+  const int N = blockIdx.y;
+  const double dx = c_centre[3 * c] - c_centre[3 * pa];
+  const double dy = c_centre[3 * c + 1] - c_centre[3 * pa + 1];
+  const double dz = c_centre[3 * c + 2] - c_centre[3 * pa + 2];
+  const double* Mb = mbar + (int64_t)pa * NMV;
+  if constexpr (P == 0) {
+    switch (N) { HOT_M2MT_CASE(0, 0) }
+  } else if constexpr (P == 1) {
+    switch (N) { HOT_M2MT_CASE(1, 0) HOT_M2MT_CASE(1, 1) }
+  } else if constexpr (P == 2) {
+    switch (N) { HOT_M2MT_CASE(2, 0) HOT_M2MT_CASE(2, 1) HOT_M2MT_CASE(2, 2) }
+  } else if constexpr (P == 3) {
+    switch (N) { HOT_M2MT_CASE(3, 0) HOT_M2MT_CASE(3, 1) HOT_M2MT_CASE(3, 2) HOT_M2MT_CASE(3, 3) }
+  } else if constexpr (P == 4) {
+    switch (N) {
+      HOT_M2MT_CASE(4, 0) HOT_M2MT_CASE(4, 1) HOT_M2MT_CASE(4, 2) HOT_M2MT_CASE(4, 3)
+      HOT_M2MT_CASE(4, 4)
+    }
+  } else if constexpr (P == 5) {
+    switch (N) {
+      HOT_M2MT_CASE(5, 0) HOT_M2MT_CASE(5, 1) HOT_M2MT_CASE(5, 2) HOT_M2MT_CASE(5, 3)
+      HOT_M2MT_CASE(5, 4) HOT_M2MT_CASE(5, 5)
+    }
+  } else if constexpr (P == 6) {
+    switch (N) {
+      HOT_M2MT_CASE(6, 0) HOT_M2MT_CASE(6, 1) HOT_M2MT_CASE(6, 2) HOT_M2MT_CASE(6, 3)
+      HOT_M2MT_CASE(6, 4) HOT_M2MT_CASE(6, 5) HOT_M2MT_CASE(6, 6)
+    }
+  } else if constexpr (P == 7) {
+    switch (N) {
+      HOT_M2MT_CASE(7, 0) HOT_M2MT_CASE(7, 1) HOT_M2MT_CASE(7, 2) HOT_M2MT_CASE(7, 3)
+      HOT_M2MT_CASE(7, 4) HOT_M2MT_CASE(7, 5) HOT_M2MT_CASE(7, 6) HOT_M2MT_CASE(7, 7)
+    }
+  } else {
+    switch (N) {
+      HOT_M2MT_CASE(8, 0) HOT_M2MT_CASE(8, 1) HOT_M2MT_CASE(8, 2) HOT_M2MT_CASE(8, 3)
+      HOT_M2MT_CASE(8, 4) HOT_M2MT_CASE(8, 5) HOT_M2MT_CASE(8, 6) HOT_M2MT_CASE(8, 7)
+      HOT_M2MT_CASE(8, 8)
+    }
+  }
+}
+
+// P2M transpose at the leaves: xbar_j += m_j sum_alpha Mbar alpha_k d^(alpha-e_k),
+// mbar_j += sum_alpha Mbar d^alpha, d = x_j - leaf centre (FP64).
+template <int P>
+__global__ __launch_bounds__(kB) void k_p2mT(const double* __restrict__ spos,
+                                             const double* __restrict__ smass, int64_t n,
+                                             const int32_t* __restrict__ leaf_of,
+                                             const double* __restrict__ c_centre,
+                                             const double* __restrict__ mbar,
+                                             double* __restrict__ xb, double* __restrict__ mb) {
+  constexpr int NMV = nm(P);
+  const int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (j >= n) return;
+  const int lf = leaf_of[j];
+  const double dx = spos[j] - c_centre[3 * lf], dy = spos[n + j] - c_centre[3 * lf + 1],
+               dz = spos[2 * n + j] - c_centre[3 * lf + 2];
+  double gx = 0, gy = 0, gz = 0, gm = 0;
+  const double* Mb = mbar + (int64_t)lf * NMV;
+  if constexpr (P == 0) p2mT_p0(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 1) p2mT_p1(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 2) p2mT_p2(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 3) p2mT_p3(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 4) p2mT_p4(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 5) p2mT_p5(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 6) p2mT_p6(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 7) p2mT_p7(Mb, dx, dy, dz, gx, gy, gz, gm);
+  if constexpr (P == 8) p2mT_p8(Mb, dx, dy, dz, gx, gy, gz, gm);
+  const double m = smass[j];
+  xb[3 * j] = m * gx;
+  xb[3 * j + 1] = m * gy;
+  xb[3 * j + 2] = m * gz;
+  mb[j] = gm;
+}
+
+template <typename T>
+__global__ void k_adj_finalize(const T* __restrict__ sink, const T* __restrict__ src,
+                               const double* __restrict__ xb, const double* __restrict__ mb,
+                               const uint32_t* __restrict__ perm, int64_t n,
+                               double* __restrict__ xbar, double* __restrict__ mbar) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T* a = sink + i * 8;
+  const T* b = src + i * 8;
+  const int64_t j = perm[i];
+  for (int d = 0; d < 3; ++d)
+    xbar[3 * j + d] = (((double)a[d] - (double)a[4 + d]) + ((double)b[d] - (double)b[4 + d])) +
+                      xb[3 * i + d];
+  if (mbar) mbar[j] = ((double)b[3] - (double)b[7]) + mb[i];
+}
+
+// ------------------------------------------------------------- host drivers
+void build_transpose(hot_ctx* ctx, hot_tree* t) {
+  hipStream_t st = ctx->stream;
+  const int64_t G = t->n_groups, C = t->n_cells, NI = t->n_items;
+  // ---- pair records by source item
+  {
+    DBuf cnt, tot;
+    cnt.alloc(ctx, (G + 1) * sizeof(int64_t));
+    tot.alloc(ctx, sizeof(int64_t));
+    k_srec_count<<<grid_for(G, kB), kB, 0, st>>>(t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), G,
+                                                 t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+                                                 t->item_of.as<int32_t>(), cnt.as<int64_t>());
+    HOT_CHECK_LAUNCH();
+    scan_i64(ctx, cnt.as<int64_t>(), cnt.as<int64_t>(), G, tot.as<int64_t>());
+    int64_t nrec = 0;
+    HOT_HIP(hipMemcpyAsync(&nrec, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HOT_HIP(hipStreamSynchronize(st));
+    if (nrec >= (int64_t)UINT32_MAX) throw Error{HOT_E_CAPACITY, "too many P2P records"};
+    t->n_srec = nrec;
+    const int gbits = bits_for(G);
+    const int qbits = bits_for(NI);
+    if (gbits + qbits > 63) throw Error{HOT_E_CAPACITY, "P2P record key too wide"};
+    t->srec_key.alloc(ctx, std::max<int64_t>(1, nrec) * sizeof(uint64_t));
+    t->srec_val.alloc(ctx, std::max<int64_t>(1, nrec) * sizeof(uint32_t));
+    t->srec_off.alloc(ctx, (NI + 1) * sizeof(uint32_t));
+    k_fill_u32<<<grid_for(NI + 1, kB), kB, 0, st>>>(t->srec_off.as<uint32_t>(), NI + 1, 0u);
+    HOT_CHECK_LAUNCH();
+    k_srec_fill<<<grid_for(G, kB), kB, 0, st>>>(
+        t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), G, t->c_first.as<int32_t>(),
+        t->c_count.as<int32_t>(), t->item_of.as<int32_t>(), cnt.as<int64_t>(), gbits,
+        t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>(), t->srec_off.as<uint32_t>());
+    HOT_CHECK_LAUNCH();
+    radix_sort(ctx, t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>(), nrec, gbits + qbits);
+    scan_u32(ctx, t->srec_off.as<uint32_t>(), t->srec_off.as<uint32_t>(), NI,
+             t->srec_off.as<uint32_t>() + NI);
+    t->srec_gbits = gbits;
+  }
+  // ---- expansion records by source cell, split into items
+  {
+    const int64_t E = t->n_m2p;
+    t->n_mrec = E;
+    t->mrec_key.alloc(ctx, std::max<int64_t>(1, E) * sizeof(uint64_t));
+    t->mrec_val.alloc(ctx, std::max<int64_t>(1, E) * sizeof(uint32_t));
+    t->mcell_rec.alloc(ctx, (C + 1) * sizeof(uint32_t));
+    t->mcell_item.alloc(ctx, (C + 1) * sizeof(uint32_t));
+    k_fill_u32<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C + 1, 0u);
+    HOT_CHECK_LAUNCH();
+    k_mrec_fill<<<grid_for(G, kB), kB, 0, st>>>(t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(), G,
+                                                t->mrec_key.as<uint64_t>(),
+                                                t->mrec_val.as<uint32_t>(),
+                                                t->mcell_rec.as<uint32_t>());
+    HOT_CHECK_LAUNCH();
+    radix_sort(ctx, t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(), E, bits_for(C));
+    k_items_per_cell<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
+                                                     t->mcell_item.as<uint32_t>());
+    HOT_CHECK_LAUNCH();
+    scan_u32(ctx, t->mcell_rec.as<uint32_t>(), t->mcell_rec.as<uint32_t>(), C,
+             t->mcell_rec.as<uint32_t>() + C);
+    scan_u32(ctx, t->mcell_item.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C,
+             t->mcell_item.as<uint32_t>() + C);
+    uint32_t nci = 0;
+    HOT_HIP(hipMemcpyAsync(&nci, t->mcell_item.as<uint32_t>() + C, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, st));
+    HOT_HIP(hipStreamSynchronize(st));
+    t->n_citems = nci;
+    t->citem_rec.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(uint32_t));
+    t->citem_cell.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(int32_t));
+    k_cell_items<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(),
+                                                 t->mcell_item.as<uint32_t>(), C,
+                                                 t->citem_rec.as<uint32_t>(),
+                                                 t->citem_cell.as<int32_t>());
+    HOT_CHECK_LAUNCH();
+  }
+  t->has_transpose = true;
+}
+
+template <int P, typename T>
+void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<T>* ab,
+                          const T* momw, double eps, T* sink_state, double* mbar64) {
+  hipStream_t st = ctx->stream;
+  const double inv_side = 1.0 / t->side;
+  k_m2p_sink_adj<P, T><<<grid_for(t->n_items, kWPB), kB, 0, st>>>(
+      t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
+      t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+      t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state);
+  HOT_CHECK_LAUNCH();
+  const int64_t C = t->n_cells;
+  DBuf part;
+  part.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_citems) * nm_pad(P) * sizeof(T));
+  if (t->n_citems > 0) {
+    k_m2p_cell_adj<P, T><<<(unsigned)t->n_citems, 64, 0, st>>>(
+        t->n_citems, t->citem_rec.as<uint32_t>(), t->citem_cell.as<int32_t>(),
+        t->mcell_rec.as<uint32_t>(), t->mrec_val.as<uint32_t>(), t->c_level.as<int8_t>(),
+        t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
+        t->c_centre.as<double>(), off, ab, inv_side, eps, part.as<T>());
+    HOT_CHECK_LAUNCH();
+  }
+  const int64_t tot = C * nm(P);
+  k_mbar_final<T><<<grid_for(tot, kB), kB, 0, st>>>(part.as<T>(), t->mcell_item.as<uint32_t>(), C,
+                                                    t->c_level.as<int8_t>(), inv_side, P, mbar64);
+  HOT_CHECK_LAUNCH();
+  // down the tree: level L+1 cells take their parents' cotangents
+  for (int L = 1; L <= t->max_level; ++L) {
+    const int64_t c0 = t->level_off[L], c1 = t->level_off[L + 1];
+    if (c1 <= c0) continue;
+    dim3 grid(grid_for(c1 - c0, kB), P + 1);
+    k_m2mT<P><<<grid, kB, 0, st>>>(c0, c1, t->c_parent.as<int32_t>(), t->c_centre.as<double>(),
+                                   mbar64);
+    HOT_CHECK_LAUNCH();
+  }
+}
+
+template <int P>
+void launch_p2mT(hot_ctx* ctx, hot_tree* t, const double* spos, const double* smass,
+                 const double* mbar64, double* xb, double* mb) {
+  k_p2mT<P><<<grid_for(t->n, kB), kB, 0, ctx->stream>>>(spos, smass, t->n, t->leaf_of.as<int32_t>(),
+                                                        t->c_centre.as<double>(), mbar64, xb, mb);
+  HOT_CHECK_LAUNCH();
+}
+
+template <typename T>
+void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+               const double* abar, double* xbar, double* mbar) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = t->n, C = t->n_cells;
+  const int p = t->p;
+  if (!t->has_transpose) build_transpose(ctx, t);
+  DBuf off, ab, sink, src, mbar64, spos, smass, xb, mb;
+  off.alloc(ctx, n * sizeof(V4<T>));
+  ab.alloc(ctx, n * sizeof(V4<T>));
+  sink.alloc(ctx, n * 8 * sizeof(T));
+  src.alloc(ctx, n * 8 * sizeof(T));
+  mbar64.alloc(ctx, (size_t)C * nm(p) * sizeof(double));
+  spos.alloc(ctx, 3 * n * sizeof(double));
+  smass.alloc(ctx, n * sizeof(double));
+  xb.alloc(ctx, 3 * n * sizeof(double));
+  mb.alloc(ctx, n * sizeof(double));
+  k_offsets<T><<<grid_for(n, kB), kB, 0, st>>>(pos, mass, t->perm.as<uint32_t>(),
+                                               t->group_of.as<int32_t>(), t->g_cell.as<int32_t>(),
+                                               t->c_centre.as<double>(), n, off.as<V4<T>>(),
+                                               ctx->d_flags);
+  HOT_CHECK_LAUNCH();
+  k_abar<T><<<grid_for(n, kB), kB, 0, st>>>(abar, t->perm.as<uint32_t>(), n, ab.as<V4<T>>());
+  HOT_CHECK_LAUNCH();
+  gather_sorted(ctx, t, pos, mass, spos.as<double>(), smass.as<double>(), 0);
+  const T e2 = (T)(eps * eps);
+  const unsigned gi = grid_for(t->n_items, kWPB);
+  // pair terms
+  auto sink_k = e2 > T(0) ? k_p2p_sink_adj<T, false> : k_p2p_sink_adj<T, true>;
+  sink_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
+                            t->p2p.as<int32_t>(), t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+                            t->group_of.as<int32_t>(), t->g_first.as<int32_t>(),
+                            t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
+                            t->c_centre.as<double>(), off.as<V4<T>>(), ab.as<V4<T>>(), e2,
+                            sink.as<T>());
+  HOT_CHECK_LAUNCH();
+  auto src_k = e2 > T(0) ? k_p2p_src_adj<T, false> : k_p2p_src_adj<T, true>;
+  src_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->srec_key.as<uint64_t>(),
+                           t->srec_val.as<uint32_t>(), t->srec_off.as<uint32_t>(),
+                           (1ull << t->srec_gbits) - 1ull, t->p2p.as<int32_t>(),
+                           t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+                           t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+                           t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off.as<V4<T>>(),
+                           ab.as<V4<T>>(), e2, src.as<T>());
+  HOT_CHECK_LAUNCH();
+  // expansion terms
+  const T* momw = nullptr;
+  if constexpr (sizeof(T) == 4) {
+    momw = t->mom32.as<T>();
+  } else {
+    weighted_fp64(ctx, t);
+    momw = t->momw64.as<T>();
+  }
+  V4<T>* o4 = off.as<V4<T>>();
+  V4<T>* a4 = ab.as<V4<T>>();
+  double* M = mbar64.as<double>();
+  T* S = sink.as<T>();
+  switch (p) {
+    case 0: launch_expansion_adj<0, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 1: launch_expansion_adj<1, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 2: launch_expansion_adj<2, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 3: launch_expansion_adj<3, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 4: launch_expansion_adj<4, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 5: launch_expansion_adj<5, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 6: launch_expansion_adj<6, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 7: launch_expansion_adj<7, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 8: launch_expansion_adj<8, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    default: invalid("p out of range");
+  }
+  const double* sp = spos.as<double>();
+  const double* sm = smass.as<double>();
+  switch (p) {
+    case 0: launch_p2mT<0>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 1: launch_p2mT<1>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 2: launch_p2mT<2>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 3: launch_p2mT<3>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 4: launch_p2mT<4>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 5: launch_p2mT<5>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 6: launch_p2mT<6>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 7: launch_p2mT<7>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+    case 8: launch_p2mT<8>(ctx, t, sp, sm, M, xb.as<double>(), mb.as<double>()); break;
+  }
+  k_adj_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(sink.as<T>(), src.as<T>(), xb.as<double>(),
+                                                    mb.as<double>(), t->perm.as<uint32_t>(), n,
+                                                    xbar, mbar);
+  HOT_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+             int precision, const double* abar, double* xbar, double* mbar) {
+  if (precision == HOT_FP64)
+    adjoint_t<double>(ctx, t, pos, mass, eps, abar, xbar, mbar);
+  else
+    adjoint_t<float>(ctx, t, pos, mass, eps, abar, xbar, mbar);
+}
+
 }  // namespace hot

@@ -109,7 +109,7 @@ struct hot_tree {
   double lo[3] = {0, 0, 0};
   double side = 1.0;
   // particles (sorted order)
-  hot::DBuf key, perm, spos, lambda, group_of, leaf_of;
+  hot::DBuf key, perm, spos, lambda, group_of, leaf_of, item_of;
   // root cube on device: lo[3], side, scale = 2^21 / side
   hot::DBuf root;
   // cells
@@ -139,10 +139,16 @@ struct hot_tree {
   // eval work items: (group, first sink) per wave
   int64_t n_items = 0;
   hot::DBuf items;
-  // adjoint caches: transposed lists (cell -> groups)
+  // adjoint caches built from the lists on first use
   bool has_transpose = false;
-  hot::DBuf tp2p_cells, tp2p_off, tp2p_grp, tm2p_cells, tm2p_off, tm2p_grp;
-  int64_t n_tp2p_cells = 0, n_tm2p_cells = 0;
+  // P2P by source item: records sorted by (item, group); rec_off per item
+  int64_t n_srec = 0;
+  int srec_gbits = 1;
+  hot::DBuf srec_key, srec_val, srec_off;
+  // M2P by source cell: records sorted by (cell, group), split in items of
+  // at most kCellItemGroups groups; citem_rec: first record of each item
+  int64_t n_mrec = 0, n_citems = 0, n_mcells = 0;
+  hot::DBuf mrec_key, mrec_val, citem_rec, citem_cell, mcell_rec, mcell_item;
 };
 
 namespace hot {

@@ -19,6 +19,7 @@
 // the source cell side s (a power of two): R/s, eps/s and the weighted moments
 // M_alpha / s^|alpha| are all O(1), and the result is rescaled by s^-2.
 #include "common.h"
+#include "eval_common.h"
 #include "generated/expansions.h"
 
 namespace hot {
@@ -26,48 +27,6 @@ namespace {
 
 constexpr int kB = 256;
 constexpr int kWavesPerBlock = kB / 64;
-
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<float> {
-  using type = float4;
-};
-template <>
-struct Vec4<double> {
-  using type = double4;
-};
-template <typename T>
-using V4 = typename Vec4<T>::type;
-
-template <typename T>
-__device__ __forceinline__ void kahan_add(T& s, T& c, T x) {
-  const T y = x - c;
-  const T t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
-// Offsets of every particle (sorted order) from its group's centre, and mass.
-template <typename T>
-__global__ void k_offsets(const double* __restrict__ pos, const double* __restrict__ mass,
-                          const uint32_t* __restrict__ perm, const int32_t* __restrict__ group_of,
-                          const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
-                          int64_t n, V4<T>* __restrict__ off, unsigned* __restrict__ flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t j = perm[i];
-  const int gc = g_cell[group_of[i]];
-  const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2], m = mass[j];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(flags, FLAG_NONFINITE_POS);
-  if (!(isfinite(m) && m >= 0.0)) atomicOr(flags, FLAG_BAD_MASS);
-  V4<T> o;
-  o.x = (T)(x - c_centre[3 * gc]);
-  o.y = (T)(y - c_centre[3 * gc + 1]);
-  o.z = (T)(z - c_centre[3 * gc + 2]);
-  o.w = (T)m;
-  off[i] = o;
-}
 
 // State per sorted particle: s_x s_y s_z s_phi c_x c_y c_z c_phi.
 template <typename T, bool POT, bool EPS0>

@@ -1,0 +1,76 @@
+// Device helpers shared by the force and adjoint kernels.
+#pragma once
+#include "common.h"
+
+namespace hot {
+
+// Multi-index (a, b, c) of every moment slot up to order 8 and the expansion
+// weight (-1)^|alpha| / alpha! of each.
+struct AlphaTable {
+  int8_t a[nm(kMaxP)], b[nm(kMaxP)], c[nm(kMaxP)];
+  double w[nm(kMaxP)];
+};
+
+constexpr AlphaTable make_alpha_table() {
+  AlphaTable t{};
+  int s = 0;
+  for (int n = 0; n <= kMaxP; ++n)
+    for (int a = n; a >= 0; --a)
+      for (int b = n - a; b >= 0; --b) {
+        const int c = n - a - b;
+        double f = 1.0;
+        for (int k = 2; k <= a; ++k) f *= k;
+        for (int k = 2; k <= b; ++k) f *= k;
+        for (int k = 2; k <= c; ++k) f *= k;
+        t.a[s] = (int8_t)a;
+        t.b[s] = (int8_t)b;
+        t.c[s] = (int8_t)c;
+        t.w[s] = ((n & 1) ? -1.0 : 1.0) / f;
+        ++s;
+      }
+  return t;
+}
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+template <typename T>
+using V4 = typename Vec4<T>::type;
+
+template <typename T>
+__device__ __forceinline__ void kahan_add(T& s, T& c, T x) {
+  const T y = x - c;
+  const T t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// Offsets of every particle (sorted order) from its group's centre, and mass.
+template <typename T>
+__global__ void k_offsets(const double* __restrict__ pos, const double* __restrict__ mass,
+                          const uint32_t* __restrict__ perm, const int32_t* __restrict__ group_of,
+                          const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+                          int64_t n, V4<T>* __restrict__ off, unsigned* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = perm[i];
+  const int gc = g_cell[group_of[i]];
+  const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2], m = mass[j];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(flags, FLAG_NONFINITE_POS);
+  if (!(isfinite(m) && m >= 0.0)) atomicOr(flags, FLAG_BAD_MASS);
+  V4<T> o;
+  o.x = (T)(x - c_centre[3 * gc]);
+  o.y = (T)(y - c_centre[3 * gc + 1]);
+  o.z = (T)(z - c_centre[3 * gc + 2]);
+  o.w = (T)m;
+  off[i] = o;
+}
+
+}  // namespace hot

@@ -242,6 +242,84 @@ def gen_m2m_order(N):
     return L
 
 
+def gen_m2mT_order(P, N):
+    """Transpose of the re-centring for the order-N output slots beta:
+    acc[beta] += sum_{alpha >= beta, |alpha| <= P} C(alpha,beta)
+    shift^(alpha-beta) Mbar[alpha]  (shift = child centre - parent centre)."""
+    L = []
+    for name, var in (("px", "dx"), ("py", "dy"), ("pz", "dz")):
+        L.append(f"  const double {name}0 = 1.0;")
+        for k in range(1, P - N + 1):
+            L.append(f"  const double {name}{k} = {name}{k - 1} * {var};")
+    k = 0
+    for b0 in range(N, -1, -1):
+        for b1 in range(N - b0, -1, -1):
+            b2 = N - b0 - b1
+            terms = []
+            for n in range(N, P + 1):
+                for a0 in range(n, -1, -1):
+                    for a1 in range(n - a0, -1, -1):
+                        a2 = n - a0 - a1
+                        if a0 < b0 or a1 < b1 or a2 < b2:
+                            continue
+                        co = math.comb(a0, b0) * math.comb(a1, b1) * math.comb(a2, b2)
+                        terms.append(f"({float(co)!r} * ((px{a0 - b0} * py{a1 - b1}) * pz{a2 - b2})) * Mb[{slot(a0, a1, a2)}]")
+            L.append(f"  acc[{k}] += " + " + ".join(terms) + ";")
+            k += 1
+    return L
+
+
+def gen_p2mT(P):
+    """Moment cotangents to one particle at offset d from the cell centre:
+    g_k += sum_alpha Mb[alpha] alpha_k d^(alpha-e_k), gm += sum_alpha Mb[alpha] d^alpha."""
+    L = []
+    for name, var in (("px", "dx"), ("py", "dy"), ("pz", "dz")):
+        L.append(f"  const double {name}0 = 1.0;")
+        for k in range(1, P + 1):
+            L.append(f"  const double {name}{k} = {name}{k - 1} * {var};")
+    for n in range(P + 1):
+        for a in range(n, -1, -1):
+            for b in range(n - a, -1, -1):
+                c = n - a - b
+                s_ = slot(a, b, c)
+                L.append(f"  gm = fma(Mb[{s_}], (px{a} * py{b}) * pz{c}, gm);")
+                if a:
+                    L.append(f"  gx = fma({float(a)!r} * Mb[{s_}], (px{a - 1} * py{b}) * pz{c}, gx);")
+                if b:
+                    L.append(f"  gy = fma({float(b)!r} * Mb[{s_}], (px{a} * py{b - 1}) * pz{c}, gy);")
+                if c:
+                    L.append(f"  gz = fma({float(c)!r} * Mb[{s_}], (px{a} * py{b}) * pz{c - 1}, gz);")
+    return L
+
+
+def _count_ops(lines):
+    """FP operations in emitted lines: fused multiply-add = 2, multiply or
+    add = 1, reciprocal square root = 1; multiplications or FMAs by the
+    literal 1 are not counted as multiplies."""
+    n = 0
+    for l in lines:
+        n += 2 * l.count("hot_fma(") - l.count("hot_fma(T(1.0),")
+        n += l.count(" * ") - l.count("T(1.0) * ")
+        n += l.count("hot_rsq(")
+    return n
+
+
+def flops_m2p(P):
+    """FP32 operations per (sink, cell) of the forward expansion kernel without
+    the potential: the generated expansion plus the per-interaction setup of the
+    kernel (scaled R: 3 multiplies and 3 adds; result scaling: 3 multiplies;
+    compensated accumulation: 4 adds for each of 3 components)."""
+    body = [l for l in gen_fwd(P) if "if constexpr (POT)" not in l]
+    return _count_ops(body) + 6 + 3 + 12
+
+
+def flops_p2p():
+    """FP32 operations per (sink, source) pair of the pair kernel without the
+    potential: r = s + t (3 adds), r^2 + eps^2 (3 FMAs), rsq, m*inv, inv*inv,
+    times (3 multiplies), accumulation (3 FMAs)."""
+    return 3 + 6 + 1 + 3 + 6
+
+
 def main(out_path):
     parts = ["// Generated by gen_expansions.py -- do not edit.",
              "#pragma once",
@@ -285,6 +363,16 @@ def main(out_path):
         parts.append(f"__device__ __forceinline__ void m2m_order{N}(const double* __restrict__ M, "
                      "double dx, double dy, double dz, double* acc) {")
         parts += gen_m2m_order(N)
+        parts.append("}")
+    for P in range(PMAX + 1):
+        for N in range(P + 1):
+            parts.append(f"__device__ __forceinline__ void m2mT_p{P}_order{N}(const double* __restrict__ Mb, "
+                         "double dx, double dy, double dz, double* acc) {")
+            parts += gen_m2mT_order(P, N)
+            parts.append("}")
+        parts.append(f"__device__ __forceinline__ void p2mT_p{P}(const double* __restrict__ Mb, "
+                     "double dx, double dy, double dz, double& gx, double& gy, double& gz, double& gm) {")
+        parts += gen_p2mT(P)
         parts.append("}")
     parts.append("")
     parts.append("}  // namespace hot")

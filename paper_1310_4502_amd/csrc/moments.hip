@@ -8,36 +8,12 @@
 // expansion kernels:  Mw_alpha = (-1)^|alpha| / alpha! * M_alpha / s^|alpha|,
 // s = cell side (an exact power of two).
 #include "common.h"
+#include "eval_common.h"
 #include "generated/expansions.h"
 
 namespace hot {
 
-struct AlphaTable {
-  int8_t a[nm(kMaxP)], b[nm(kMaxP)], c[nm(kMaxP)];
-  double w[nm(kMaxP)];
-};
-
-constexpr AlphaTable make_alpha_table() {
-  AlphaTable t{};
-  int s = 0;
-  for (int n = 0; n <= kMaxP; ++n)
-    for (int a = n; a >= 0; --a)
-      for (int b = n - a; b >= 0; --b) {
-        const int c = n - a - b;
-        double f = 1.0;
-        for (int k = 2; k <= a; ++k) f *= k;
-        for (int k = 2; k <= b; ++k) f *= k;
-        for (int k = 2; k <= c; ++k) f *= k;
-        t.a[s] = (int8_t)a;
-        t.b[s] = (int8_t)b;
-        t.c[s] = (int8_t)c;
-        t.w[s] = ((n & 1) ? -1.0 : 1.0) / f;
-        ++s;
-      }
-  return t;
-}
-
-__constant__ AlphaTable kAlpha = make_alpha_table();
+static __constant__ AlphaTable kAlpha = make_alpha_table();
 
 namespace {
 

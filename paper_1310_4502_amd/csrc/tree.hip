@@ -420,6 +420,27 @@ __global__ void k_items(const int32_t* __restrict__ g_first, const int32_t* __re
   for (int s = 0; s < cnt; s += kWave) items[o++] = make_int2((int)g, f + s);
 }
 
+__global__ void k_leaf_fill(const int32_t* __restrict__ c_first, const int32_t* __restrict__ c_count,
+                            const uint8_t* __restrict__ c_leaf, int64_t C,
+                            int32_t* __restrict__ leaf_of) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C || !c_leaf[c]) return;
+  const int f = c_first[c], e = f + c_count[c];
+  for (int j = f; j < e; ++j) leaf_of[j] = (int32_t)c;
+}
+
+// item_of[j]: the eval work item (group chunk of at most 64 particles) of j.
+__global__ void k_item_of(const int2* __restrict__ items, int64_t n_items,
+                          const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
+                          int32_t* __restrict__ item_of) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_items) return;
+  const int2 it = items[q];
+  const int gend = g_first[it.x] + g_count[it.x];
+  const int e = it.y + kWave < gend ? it.y + kWave : gend;
+  for (int j = it.y; j < e; ++j) item_of[j] = (int32_t)q;
+}
+
 __global__ void k_hash_lookup(const uint64_t* __restrict__ q, int64_t nq,
                               const uint64_t* __restrict__ hk, const int32_t* __restrict__ hv,
                               uint64_t mask, int32_t* __restrict__ out) {
@@ -594,6 +615,14 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   t->items.alloc(ctx, (size_t)NI * sizeof(int2));
   k_items<<<grid_for(G, kB), kB, 0, st>>>(t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
                                          nch.as<uint32_t>(), G, t->items.as<int2>());
+  HOT_CHECK_LAUNCH();
+  t->leaf_of.alloc(ctx, n * sizeof(int32_t));
+  k_leaf_fill<<<gc, kB, 0, st>>>(t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+                                t->c_leaf.as<uint8_t>(), C, t->leaf_of.as<int32_t>());
+  HOT_CHECK_LAUNCH();
+  t->item_of.alloc(ctx, n * sizeof(int32_t));
+  k_item_of<<<grid_for(NI, kB), kB, 0, st>>>(t->items.as<int2>(), NI, t->g_first.as<int32_t>(),
+                                            t->g_count.as<int32_t>(), t->item_of.as<int32_t>());
   HOT_CHECK_LAUNCH();
   t->c_bmax2.release();
 }

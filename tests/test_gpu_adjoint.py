@@ -1,0 +1,132 @@
+"""GPU adjoint (eval_forces_adjoint) vs the oracle's VJP of its treecode with
+the topology frozen, vs central finite differences of the GPU's own FP64
+forward, and vs the direct-sum VJP as theta -> 0."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1310_4502_amd import workloads as W
+from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, Tree
+from gpu_util import build_both, rel_rms, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+CASES = [
+    # name, n, p, theta, direct_max, n_leaf, n_group
+    ("uniform4k", None, 2, 0.5, 0, 16, 64),
+    ("plummer1m", 6000, 4, 0.6, 0, 16, 64),
+    ("clustered4m", 5000, 6, 0.5, 24, 8, 32),
+    ("plummer1m", 2500, 8, 0.5, 0, 16, 96),
+]
+
+
+@pytest.mark.parametrize("name,n,p,theta,dmax,n_leaf,n_group", CASES)
+def test_adjoint_vs_oracle_vjp(name, n, p, theta, dmax, n_leaf, n_group):
+    w = W.make(name, n=n)
+    w.n_leaf, w.n_group = n_leaf, n_group
+    _log("case", name, w.n, "p", p)
+    gt, ot, pos, mass, p = build_both(w, theta=theta, direct_max=dmax, p=p)
+    ot.compute_moments(w.pos, w.mass, p)
+    abar_np = W.cotangent(w.n, 404)
+    ox, om = ot.vjp(w.pos, w.mass, w.eps, abar_np)
+    abar = torch.from_numpy(abar_np).cuda()
+    gx64, gm64 = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64, with_mass=True)
+    e64 = rel_rms(gx64.cpu().numpy(), ox)
+    m64 = rel_rms(gm64.cpu().numpy(), om)
+    _log("fp64 xbar", e64, "mbar", m64)
+    assert e64 <= 1e-11 and m64 <= 1e-11
+    gx, gm = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED, with_mass=True)
+    e32 = rel_rms(gx.cpu().numpy(), ox)
+    m32 = rel_rms(gm.cpu().numpy(), om)
+    _log("mixed xbar", e32, "mbar", m32)
+    assert e32 <= 1e-5 and m32 <= 1e-5
+    # deterministic
+    gx2, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED)
+    assert torch.equal(gx, gx2)
+
+
+def test_adjoint_directional_fd():
+    """x̄ . v equals the central difference of sum abar . a along v (topology
+    frozen, FP64 GPU forward), Richardson-extrapolated from h = 2e-6 and 1e-6.
+    The softening is kept well above h (truncation error ~ (h/eps)^2)."""
+    w = W.make("clustered4m", n=20000)
+    w.eps = 1e-3
+    gt, ot, pos, mass, p = build_both(w, p=4)
+    abar = torch.from_numpy(W.cotangent(w.n, 7)).cuda()
+    v = torch.from_numpy(np.random.default_rng(8).normal(size=(w.n, 3))).cuda()
+    xbar, mbar = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64, with_mass=True)
+    h = 1e-6
+
+    def L(x, m):
+        gt.compute_moments(x, m, p)
+        a, _, _ = gt.eval_forces(x, m, w.eps, HOT_FP64)
+        return float((a * abar).sum())
+
+    def cd(f, hh):
+        return (f(hh) - f(-hh)) / (2 * hh)
+
+    fx = lambda hh: L(pos + hh * v, mass)
+    fd = (4 * cd(fx, h) - cd(fx, 2 * h)) / 3
+    an = float((xbar * v).sum())
+    _log("directional", an, fd)
+    assert abs(an - fd) <= 1e-6 * abs(fd)
+    u = torch.from_numpy(np.random.default_rng(9).random(w.n)).cuda()
+    fm = lambda hh: L(pos, mass * (1 + hh * u))
+    fdm = (4 * cd(fm, h) - cd(fm, 2 * h)) / 3
+    anm = float((mbar * mass * u).sum())
+    _log("directional mass", anm, fdm)
+    assert abs(anm - fdm) <= 1e-6 * abs(fdm)
+    gt.compute_moments(pos, mass, p)
+
+
+def test_adjoint_theta_zero_is_direct_vjp():
+    w = W.make("plummer1m", n=3000)
+    w.n_leaf, w.n_group = 8, 32
+    gt, ot, pos, mass, p = build_both(w, theta=1e-6, p=2)
+    abar_np = W.cotangent(w.n, 3)
+    xd, md = oracle.direct_vjp(w.pos, w.mass, w.eps, abar_np)
+    gx, gm = gt.eval_forces_adjoint(pos, mass, w.eps, torch.from_numpy(abar_np).cuda(), HOT_FP64,
+                                    with_mass=True)
+    assert rel_rms(gx.cpu().numpy(), xd) <= 1e-12
+    assert rel_rms(gm.cpu().numpy(), md) <= 1e-12
+    # translation invariance of the exact pair VJP
+    assert np.linalg.norm(gx.cpu().numpy().sum(axis=0)) <= 1e-10 * np.abs(xd).sum()
+
+
+@pytest.mark.parametrize("eps", [1e-3, 0.0])
+def test_adjoint_ties_and_big_leaf(eps):
+    rng = np.random.default_rng(5)
+    pos = np.concatenate([rng.random((2000, 3)), np.full((150, 3), 0.4321),
+                          np.repeat(rng.random((50, 3)), 4, axis=0)])
+    n = pos.shape[0]
+    w = W.Workload("mix", pos, np.full(n, 1.0 / n), eps, 0.5, 3)
+    gt, ot, tpos, tmass, p = build_both(w)
+    ot.compute_moments(w.pos, w.mass, p)
+    abar = W.cotangent(n, 11)
+    ox, om = ot.vjp(w.pos, w.mass, eps, abar)
+    gx, gm = gt.eval_forces_adjoint(tpos, tmass, eps, torch.from_numpy(abar).cuda(), HOT_FP64,
+                                    with_mass=True)
+    assert rel_rms(gx.cpu().numpy(), ox) <= 1e-11
+    assert rel_rms(gm.cpu().numpy(), om) <= 1e-11
+
+
+def test_torch_autograd_function():
+    from paper_1310_4502_amd.binding import TreeForce
+    w = W.make("plummer1m", n=4000)
+    pos, mass = to_dev(w)
+    t = Tree(pos, 16, 64, w.box)
+    t.build_interaction_lists(0.6, 0)
+    x = pos.clone().requires_grad_(True)
+    acc = TreeForce.apply(x, mass, t, w.eps, 4, HOT_FP64)
+    abar = torch.from_numpy(W.cotangent(w.n, 2)).cuda()
+    (acc * abar).sum().backward()
+    ref, _ = t.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64)
+    assert torch.allclose(x.grad, ref, rtol=0, atol=0)
