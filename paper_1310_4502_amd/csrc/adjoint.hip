@@ -29,10 +29,6 @@ constexpr int kB = 256;
 constexpr int kWPB = kB / 64;
 constexpr int kCellItemGroups = 48;  // groups per work item of the cell-side kernel
 
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
 
 int bits_for(int64_t v) {
   int b = 1;
@@ -61,8 +57,7 @@ __global__ void k_srec_fill(const int64_t* __restrict__ p2p_off, const int32_t* 
                             const int32_t* __restrict__ c_count,
                             const int32_t* __restrict__ item_of,
                             const int64_t* __restrict__ rec_off, int gbits,
-                            uint64_t* __restrict__ key, uint32_t* __restrict__ val,
-                            uint32_t* __restrict__ per_item) {
+                            uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   int64_t o = rec_off[g];
@@ -74,28 +69,42 @@ __global__ void k_srec_fill(const int64_t* __restrict__ p2p_off, const int32_t* 
       key[o] = ((uint64_t)q << gbits) | (uint64_t)g;
       val[o] = (uint32_t)e;
       ++o;
-      atomicAdd(&per_item[q], 1u);
     }
   }
 }
 
 __global__ void k_mrec_fill(const int64_t* __restrict__ m2p_off, const int32_t* __restrict__ m2p,
-                            int64_t G, uint64_t* __restrict__ key, uint32_t* __restrict__ val,
-                            uint32_t* __restrict__ per_cell) {
+                            int64_t G, uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   for (int64_t e = m2p_off[g]; e < m2p_off[g + 1]; ++e) {
-    const int c = m2p[e];
-    key[e] = (uint64_t)c;
+    key[e] = (uint64_t)m2p[e];
     val[e] = (uint32_t)g;
-    atomicAdd(&per_cell[c], 1u);
   }
 }
 
-__global__ void k_items_per_cell(const uint32_t* __restrict__ cnt, int64_t C,
+// out[t] = first index of sorted keys with key >= (t << shift), t in [0, T].
+__global__ void k_lower_bound(const uint64_t* __restrict__ keys, int64_t n, int shift, int64_t T,
+                              uint32_t* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > T) return;
+  const uint64_t k = (uint64_t)t << shift;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  out[t] = (uint32_t)lo;
+}
+
+// number of items of each cell from its record range
+__global__ void k_items_from_off(const uint32_t* __restrict__ rec_off, int64_t C,
                                  uint32_t* __restrict__ nit) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < C) nit[c] = (cnt[c] + kCellItemGroups - 1) / kCellItemGroups;
+  if (c < C) nit[c] = (rec_off[c + 1] - rec_off[c] + kCellItemGroups - 1) / kCellItemGroups;
 }
 
 __global__ void k_cell_items(const uint32_t* __restrict__ rec_off, const uint32_t* __restrict__ it_off,
@@ -211,7 +220,8 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
     const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, const T* __restrict__ momw,
     double inv_side, double eps, T* __restrict__ state) {
-  constexpr int stride = nm_pad(P);
+  using Stage = MomentStage<P, T>;
+  __shared__ T smom[Stage::kLds ? kWPB * Stage::kStride : 1];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * kWPB + w;
   if (it >= n_items) return;
@@ -245,8 +255,8 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     const T Z = (T)((cgz - c_centre[3 * c + 2]) * inv_s) + me.z * (T)inv_s;
     const double es = eps * inv_s;
     T gx = 0, gy = 0, gz = 0;
-    expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), momw + (int64_t)c * stride, ab.x, ab.y, ab.z,
-                             gx, gy, gz);
+    const T* M = Stage::get(momw, c, smom + (Stage::kLds ? w * Stage::kStride : 0), lane);
+    expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
     const T sc = (T)(-(inv_s * inv_s * inv_s));
     kahan_add(sx, cx, gx * sc);
     kahan_add(sy, cy, gy * sc);
@@ -560,16 +570,15 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     t->srec_key.alloc(ctx, std::max<int64_t>(1, nrec) * sizeof(uint64_t));
     t->srec_val.alloc(ctx, std::max<int64_t>(1, nrec) * sizeof(uint32_t));
     t->srec_off.alloc(ctx, (NI + 1) * sizeof(uint32_t));
-    k_fill_u32<<<grid_for(NI + 1, kB), kB, 0, st>>>(t->srec_off.as<uint32_t>(), NI + 1, 0u);
-    HOT_CHECK_LAUNCH();
     k_srec_fill<<<grid_for(G, kB), kB, 0, st>>>(
         t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), G, t->c_first.as<int32_t>(),
         t->c_count.as<int32_t>(), t->item_of.as<int32_t>(), cnt.as<int64_t>(), gbits,
-        t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>(), t->srec_off.as<uint32_t>());
+        t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>());
     HOT_CHECK_LAUNCH();
     radix_sort(ctx, t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>(), nrec, gbits + qbits);
-    scan_u32(ctx, t->srec_off.as<uint32_t>(), t->srec_off.as<uint32_t>(), NI,
-             t->srec_off.as<uint32_t>() + NI);
+    k_lower_bound<<<grid_for(NI + 1, kB), kB, 0, st>>>(t->srec_key.as<uint64_t>(), nrec, gbits, NI,
+                                                       t->srec_off.as<uint32_t>());
+    HOT_CHECK_LAUNCH();
     t->srec_gbits = gbits;
   }
   // ---- expansion records by source cell, split into items
@@ -580,19 +589,17 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     t->mrec_val.alloc(ctx, std::max<int64_t>(1, E) * sizeof(uint32_t));
     t->mcell_rec.alloc(ctx, (C + 1) * sizeof(uint32_t));
     t->mcell_item.alloc(ctx, (C + 1) * sizeof(uint32_t));
-    k_fill_u32<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C + 1, 0u);
-    HOT_CHECK_LAUNCH();
     k_mrec_fill<<<grid_for(G, kB), kB, 0, st>>>(t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(), G,
                                                 t->mrec_key.as<uint64_t>(),
-                                                t->mrec_val.as<uint32_t>(),
-                                                t->mcell_rec.as<uint32_t>());
+                                                t->mrec_val.as<uint32_t>());
     HOT_CHECK_LAUNCH();
     radix_sort(ctx, t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(), E, bits_for(C));
-    k_items_per_cell<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
+    k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, 0, C,
+                                                      t->mcell_rec.as<uint32_t>());
+    HOT_CHECK_LAUNCH();
+    k_items_from_off<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
                                                      t->mcell_item.as<uint32_t>());
     HOT_CHECK_LAUNCH();
-    scan_u32(ctx, t->mcell_rec.as<uint32_t>(), t->mcell_rec.as<uint32_t>(), C,
-             t->mcell_rec.as<uint32_t>() + C);
     scan_u32(ctx, t->mcell_item.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C,
              t->mcell_item.as<uint32_t>() + C);
     uint32_t nci = 0;

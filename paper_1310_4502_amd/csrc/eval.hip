@@ -124,7 +124,8 @@ __global__ __launch_bounds__(kB) void k_m2p(
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
     const V4<T>* __restrict__ off, const T* __restrict__ momw, double inv_side, double eps,
     T* __restrict__ state) {
-  constexpr int stride = nm_pad(P);
+  using Stage = MomentStage<P, T>;
+  __shared__ T smom[Stage::kLds ? kWavesPerBlock * Stage::kStride : 1];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (it >= n_items) return;
@@ -160,7 +161,8 @@ __global__ __launch_bounds__(kB) void k_m2p(
     const double es = eps * inv_s;
     const T e2 = (T)(es * es);
     T ax = 0, ay = 0, az = 0, ph = 0;
-    expansion_fwd<P, T, POT>(X, Y, Z, e2, momw + (int64_t)c * stride, ax, ay, az, ph);
+    const T* M = Stage::get(momw, c, smom + (Stage::kLds ? w * Stage::kStride : 0), lane);
+    expansion_fwd<P, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph);
     const T sa = (T)(-(inv_s * inv_s));
     kahan_add(sx, cx, ax * sa);
     kahan_add(sy, cy, ay * sa);
