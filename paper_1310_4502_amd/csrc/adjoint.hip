@@ -164,35 +164,43 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
   }
   T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
   for (int64_t e = p2p_off[g]; e < p2p_off[g + 1]; ++e) {
-    const int c = p2p[e];
-    const int f = c_first[c];
-    const int end = f + c_count[c];
+    const int c = uniform_i32(p2p[e]);
+    const int f = uniform_i32(c_first[c]);
+    const int end = f + uniform_i32(c_count[c]);
     T A = 0, Bx = 0, By = 0, Bz = 0;  // sum m inv3 ; sum 3 m (r.ab) inv5 r
     int j = f;
     while (j < end) {
-      const int sg = group_of[j];
-      const int sgend = g_first[sg] + g_count[sg];
+      const int sg = uniform_i32(group_of[j]);
+      const int sgend = uniform_i32(g_first[sg] + g_count[sg]);
       const int jend = end < sgend ? end : sgend;
       if (jend <= j) break;
       const int sc = g_cell[sg];
       const T tx = (T)(c_centre[3 * sc] - cgx) - me.x;
       const T ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
       const T tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
-      for (int jj = j; jj < jend; ++jj) {
-        const V4<T> s = off[jj];
-        const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;
-        const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
-        T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
-        if (sg == g && jj == i) inv = T(0);
-        const T inv2 = inv * inv;
-        const T m3 = s.w * (inv * inv2);
-        const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));
-        const T q = (T(3) * m3) * (rd * inv2);
-        A += m3;
-        Bx = hot_fma(q, rx, Bx);
-        By = hot_fma(q, ry, By);
-        Bz = hot_fma(q, rz, Bz);
+#define HOT_SINK_PAIR(SELF)                                                          \
+  {                                                                                  \
+    const V4<T> s = off[jj];                                                         \
+    const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;                             \
+    const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
+    T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
+    if (SELF && jj == i) inv = T(0);                                                 \
+    const T inv2 = inv * inv;                                                        \
+    const T m3 = s.w * (inv * inv2);                                                 \
+    const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));                    \
+    const T q = (T(3) * m3) * (rd * inv2);                                           \
+    A += m3;                                                                         \
+    Bx = hot_fma(q, rx, Bx);                                                         \
+    By = hot_fma(q, ry, By);                                                         \
+    Bz = hot_fma(q, rz, Bz);                                                         \
+  }
+      if (sg == g) {
+        for (int jj = j; jj < jend; ++jj) HOT_SINK_PAIR(true)
+      } else {
+#pragma unroll 4
+        for (int jj = j; jj < jend; ++jj) HOT_SINK_PAIR(false)
       }
+#undef HOT_SINK_PAIR
       j = jend;
     }
     // xbar_i -= m_j H ab = -(sum m inv3) ab + sum 3 m rd inv5 r
@@ -247,15 +255,36 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     cy = st[5];
     cz = st[6];
   }
-  for (int64_t e = m2p_off[g]; e < m2p_off[g + 1]; ++e) {
-    const int c = m2p[e];
-    const double inv_s = ldexp(inv_side, (int)c_level[c]);
-    const T X = (T)((cgx - c_centre[3 * c]) * inv_s) + me.x * (T)inv_s;
-    const T Y = (T)((cgy - c_centre[3 * c + 1]) * inv_s) + me.y * (T)inv_s;
-    const T Z = (T)((cgz - c_centre[3 * c + 2]) * inv_s) + me.z * (T)inv_s;
+  const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
+  T* slot = smom + (Stage::kLds ? w * Stage::kStride : 0);
+  typename Stage::Regs pre;
+  int cn = 0, ln = 0;
+  double nx = 0, ny = 0, nz = 0;
+  if (e0 < e1) {
+    cn = uniform_i32(m2p[e0]);
+    Stage::prefetch(pre, momw, cn, lane);
+    ln = c_level[cn];
+    nx = c_centre[3 * cn];
+    ny = c_centre[3 * cn + 1];
+    nz = c_centre[3 * cn + 2];
+  }
+  for (int64_t e = e0; e < e1; ++e) {
+    const int c = cn;
+    const double inv_s = ldexp(inv_side, ln);
+    const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
+    const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
+    const T Z = (T)((cgz - nz) * inv_s) + me.z * (T)inv_s;
+    const T* M = Stage::commit(pre, momw, c, slot, lane);
+    if (e + 1 < e1) {
+      cn = uniform_i32(m2p[e + 1]);
+      Stage::prefetch(pre, momw, cn, lane);
+      ln = c_level[cn];
+      nx = c_centre[3 * cn];
+      ny = c_centre[3 * cn + 1];
+      nz = c_centre[3 * cn + 2];
+    }
     const double es = eps * inv_s;
     T gx = 0, gy = 0, gz = 0;
-    const T* M = Stage::get(momw, c, smom + (Stage::kLds ? w * Stage::kStride : 0), lane);
     expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
     const T sc = (T)(-(inv_s * inv_s * inv_s));
     kahan_add(sx, cx, gx * sc);
@@ -305,7 +334,7 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
   const uint32_t rend = soff[q + 1];
   while (r < rend) {
     const uint64_t k0 = skey[r];
-    const int g = (int)(k0 & gmask);
+    const int g = uniform_i32((int)(k0 & gmask));
     bool mine = false;
     while (r < rend && skey[r] == k0) {
       const int c = p2p[sval[r]];
@@ -313,28 +342,37 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
       mine |= (j >= f) && (j < f + c_count[c]);
       ++r;
     }
-    const int gc = g_cell[g];
+    const int gc = uniform_i32(g_cell[g]);
     const T tx = (T)(csx - c_centre[3 * gc]) + me.x;  // r_ij = x_j - x_i = t - off_i
     const T ty = (T)(csy - c_centre[3 * gc + 1]) + me.y;
     const T tz = (T)(csz - c_centre[3 * gc + 2]) + me.z;
-    const int i0 = g_first[g], i1 = i0 + g_count[g];
+    const int i0 = uniform_i32(g_first[g]);
+    const int i1 = i0 + uniform_i32(g_count[g]);
     T gx = 0, gy = 0, gz = 0, gm = 0;
-    for (int i = i0; i < i1; ++i) {
-      const V4<T> si = off[i];
-      const V4<T> ab = ab4[i];
-      const T rx = tx - si.x, ry = ty - si.y, rz = tz - si.z;
-      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
-      T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
-      if (g == gs && i == j) inv = T(0);
-      const T inv2 = inv * inv;
-      const T inv3 = inv * inv2;
-      const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));
-      const T qq = (T(3) * rd) * (inv3 * inv2);
-      gx = hot_fma(ab.x, inv3, hot_fma(-qq, rx, gx));
-      gy = hot_fma(ab.y, inv3, hot_fma(-qq, ry, gy));
-      gz = hot_fma(ab.z, inv3, hot_fma(-qq, rz, gz));
-      gm = hot_fma(rd, inv3, gm);
+#define HOT_SRC_PAIR(SELF)                                                           \
+  {                                                                                  \
+    const V4<T> si = off[i];                                                         \
+    const V4<T> ab = ab4[i];                                                         \
+    const T rx = tx - si.x, ry = ty - si.y, rz = tz - si.z;                          \
+    const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
+    T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
+    if (SELF && i == j) inv = T(0);                                                  \
+    const T inv2 = inv * inv;                                                        \
+    const T inv3 = inv * inv2;                                                       \
+    const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));                    \
+    const T qq = (T(3) * rd) * (inv3 * inv2);                                        \
+    gx = hot_fma(ab.x, inv3, hot_fma(-qq, rx, gx));                                  \
+    gy = hot_fma(ab.y, inv3, hot_fma(-qq, ry, gy));                                  \
+    gz = hot_fma(ab.z, inv3, hot_fma(-qq, rz, gz));                                  \
+    gm = hot_fma(rd, inv3, gm);                                                      \
+  }
+    if (g == gs) {
+      for (int i = i0; i < i1; ++i) HOT_SRC_PAIR(true)
+    } else {
+#pragma unroll 4
+      for (int i = i0; i < i1; ++i) HOT_SRC_PAIR(false)
     }
+#undef HOT_SRC_PAIR
     if (mine) {
       kahan_add(sx, cx, me.w * gx);
       kahan_add(sy, cy, me.w * gy);
@@ -383,25 +421,52 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
   T row[NM];
 #pragma unroll
   for (int a = 0; a < NM; ++a) row[a] = T(0);
+  // prefetched state of the next (group, chunk)
+  int gn = 0, gfn = 0, gen = 0;
+  double gx_ = 0, gy_ = 0, gz_ = 0;
+  V4<T> pme, pab;
+  auto fetch_group = [&](uint32_t r) {
+    gn = uniform_i32((int)mval[r]);
+    const int gc = uniform_i32(g_cell[gn]);
+    gx_ = c_centre[3 * gc];
+    gy_ = c_centre[3 * gc + 1];
+    gz_ = c_centre[3 * gc + 2];
+    gfn = uniform_i32(g_first[gn]);
+    gen = gfn + uniform_i32(g_count[gn]);
+  };
+  auto fetch_sinks = [&](int s0, int ge) {
+    const int i = s0 + lane;
+    if (i < ge) {
+      pme = off[i];
+      pab = ab4[i];
+    }
+  };
+  if (r0 < r1) {
+    fetch_group(r0);
+    fetch_sinks(gfn, gen);
+  }
   for (uint32_t r = r0; r < r1; ++r) {
-    const int g = (int)mval[r];
-    const int gc = g_cell[g];
-    const T Dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
-    const T Dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
-    const T Dz = (T)((c_centre[3 * gc + 2] - ccz) * inv_s);
-    const int gf = g_first[g], ge = gf + g_count[g];
+    const int gf = gfn, ge = gen;
+    const T Dx = (T)((gx_ - ccx) * inv_s);
+    const T Dy = (T)((gy_ - ccy) * inv_s);
+    const T Dz = (T)((gz_ - ccz) * inv_s);
     for (int s0 = gf; s0 < ge; s0 += 64) {
       const int i = s0 + lane;
       T X = T(1), Y = T(0), Z = T(0), bx = T(0), by = T(0), bz = T(0);
       if (i < ge) {
-        const V4<T> me = off[i];
-        const V4<T> ab = ab4[i];
-        X = Dx + me.x * (T)inv_s;
-        Y = Dy + me.y * (T)inv_s;
-        Z = Dz + me.z * (T)inv_s;
-        bx = ab.x;
-        by = ab.y;
-        bz = ab.z;
+        X = Dx + pme.x * (T)inv_s;
+        Y = Dy + pme.y * (T)inv_s;
+        Z = Dz + pme.z * (T)inv_s;
+        bx = pab.x;
+        by = pab.y;
+        bz = pab.z;
+      }
+      // fetch the next chunk of this group, or the first chunk of the next group
+      if (s0 + 64 < ge) {
+        fetch_sinks(s0 + 64, ge);
+      } else if (r + 1 < r1) {
+        fetch_group(r + 1);
+        fetch_sinks(gfn, gen);
       }
       expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
     }

@@ -152,16 +152,36 @@ __global__ __launch_bounds__(kB) void k_m2p(
     cp = st[7];
   }
   const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
+  T* slot = smom + (Stage::kLds ? w * Stage::kStride : 0);
+  typename Stage::Regs pre;
+  int cn = 0, ln = 0;
+  double nx = 0, ny = 0, nz = 0;
+  if (e0 < e1) {
+    cn = uniform_i32(m2p[e0]);
+    Stage::prefetch(pre, momw, cn, lane);
+    ln = c_level[cn];
+    nx = c_centre[3 * cn];
+    ny = c_centre[3 * cn + 1];
+    nz = c_centre[3 * cn + 2];
+  }
   for (int64_t e = e0; e < e1; ++e) {
-    const int c = m2p[e];
-    const double inv_s = ldexp(inv_side, (int)c_level[c]);
-    const T X = (T)((cgx - c_centre[3 * c]) * inv_s) + me.x * (T)inv_s;
-    const T Y = (T)((cgy - c_centre[3 * c + 1]) * inv_s) + me.y * (T)inv_s;
-    const T Z = (T)((cgz - c_centre[3 * c + 2]) * inv_s) + me.z * (T)inv_s;
+    const int c = cn;
+    const double inv_s = ldexp(inv_side, ln);
+    const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
+    const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
+    const T Z = (T)((cgz - nz) * inv_s) + me.z * (T)inv_s;
+    const T* M = Stage::commit(pre, momw, c, slot, lane);
+    if (e + 1 < e1) {
+      cn = uniform_i32(m2p[e + 1]);
+      Stage::prefetch(pre, momw, cn, lane);
+      ln = c_level[cn];
+      nx = c_centre[3 * cn];
+      ny = c_centre[3 * cn + 1];
+      nz = c_centre[3 * cn + 2];
+    }
     const double es = eps * inv_s;
     const T e2 = (T)(es * es);
     T ax = 0, ay = 0, az = 0, ph = 0;
-    const T* M = Stage::get(momw, c, smom + (Stage::kLds ? w * Stage::kStride : 0), lane);
     expansion_fwd<P, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph);
     const T sa = (T)(-(inv_s * inv_s));
     kahan_add(sx, cx, ax * sa);

@@ -76,25 +76,39 @@ __global__ void k_offsets(const double* __restrict__ pos, const double* __restri
 // Expansion coefficients of one cell, for a wavefront. Up to ~400 bytes they
 // are read straight from global memory at wavefront-uniform addresses (scalar
 // loads into SGPRs); larger sets do not fit the SGPR budget, so the wavefront
-// stages them in its own LDS slot (one 16-byte copy per lane) and every lane
-// reads them back as broadcasts. Only wavefront-level ordering is needed: the
-// LDS operations of one wavefront execute in program order.
+// stages them in its own LDS slot (16 bytes per lane) and every lane reads
+// them back as broadcasts. The next entry's coefficients are fetched into
+// registers (prefetch) while the current one is evaluated, and written to the
+// slot (commit) at the top of the next iteration. Only wavefront-level
+// ordering is needed: the LDS operations of one wavefront execute in order.
 template <int P, typename T>
 struct MomentStage {
   static constexpr int kStride = nm_pad(P);
   static constexpr bool kLds = nm(P) * (int)sizeof(T) > 400;
   static constexpr int kChunks = kStride * (int)sizeof(T) / 16;
-  __device__ static __forceinline__ const T* get(const T* __restrict__ momw, int64_t c, T* slot,
-                                                 int lane) {
+  static constexpr int kPre = kLds ? (kChunks + 63) / 64 : 1;
+  struct Regs {
+    uint4 v[kPre];
+  };
+  __device__ static __forceinline__ void prefetch(Regs& r, const T* __restrict__ momw, int64_t c,
+                                                  int lane) {
+    if constexpr (kLds) {
+      const uint4* src = reinterpret_cast<const uint4*>(momw + c * kStride);
+#pragma unroll
+      for (int k = 0; k < kPre; ++k)
+        if (lane + 64 * k < kChunks) r.v[k] = src[lane + 64 * k];
+    }
+  }
+  __device__ static __forceinline__ const T* commit(const Regs& r, const T* __restrict__ momw,
+                                                    int64_t c, T* slot, int lane) {
     if constexpr (!kLds) {
       return momw + c * kStride;
     } else {
-      const uint4* src = reinterpret_cast<const uint4*>(momw + c * kStride);
       uint4* dst = reinterpret_cast<uint4*>(slot);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      for (int k = lane; k < kChunks; k += 64) dst[k] = src[k];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+      for (int k = 0; k < kPre; ++k)
+        if (lane + 64 * k < kChunks) dst[lane + 64 * k] = r.v[k];
       __builtin_amdgcn_wave_barrier();
       return slot;
     }
