@@ -1,0 +1,103 @@
+"""Parity at the benchmark workloads' full sizes, in the configuration bench.py
+times: the whole tree (keys, order, cells, centres, b_max, groups) bit-exact
+against the oracle; lists bit-exact and moments close on sampled groups;
+accelerations on every sink of the sampled groups against the oracle
+treecode, and on sampled sinks against direct summation; for the 2^24
+Zel'dovich field also the adjoint (directional FD of the FP64 forward with
+the topology frozen, and direct-sum VJP rows)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1310_4502_amd import workloads as W
+from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, Tree
+from gpu_util import (assert_lists_equal, assert_moments_close, assert_tree_equal, rel_rms,
+                      to_dev)
+
+pytestmark = pytest.mark.gpu
+
+# workload -> (n_leaf, n_group, direct_max) as timed by bench.py
+BENCH = {"plummer1m": (16, 64, 16), "clustered4m": (16, 64, 32), "zeldovich16m": (16, 96, 64),
+         "clustered16m": (16, 64, 32)}
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _check(name, n_groups_sample, n_direct):
+    t0 = time.time()
+    w = W.make(name)
+    n_leaf, n_group, dmax = BENCH[name]
+    pos, mass = to_dev(w)
+    gt = Tree(pos, n_leaf, n_group, w.box)
+    gt.build_interaction_lists(w.theta, dmax)
+    gt.compute_moments(pos, mass, w.p)
+    ga, _, st = gt.eval_forces(pos, mass, w.eps, HOT_MIXED, stats=True)
+    ga = ga.cpu().numpy()
+    _log(f"{name}: N={w.n} gpu done {time.time() - t0:.1f}s")
+    ot = oracle.Tree(w.pos, n_leaf, n_group, w.box)
+    assert_tree_equal(gt, ot)
+    _log(f"{name}: tree bit-exact {time.time() - t0:.1f}s")
+    G = ot.counts()["n_groups"]
+    groups = W.sample_indices(G, n_groups_sample, 77)
+    ot.build_lists(w.theta, dmax, groups=groups)
+    assert_lists_equal(gt, ot, groups=groups)
+    po, pl, mo, ml = ot.lists()
+    cells = np.unique(np.concatenate([ml[mo[g]:mo[g + 1]] for g in groups] +
+                                     [np.arange(0, ot.counts()["n_cells"], 997)]))
+    ot.compute_moments(w.pos, w.mass, w.p, cells=cells)
+    gm = gt.moments()[cells]
+    om = ot.moments()[cells]
+    assert_moments_close(gm, om, gt.cells()["count"][cells])
+    _log(f"{name}: lists + moments ok {time.time() - t0:.1f}s")
+    _, perm = ot.keys()
+    sinks = np.sort(perm[np.isin(ot.group_of(), groups)])
+    oa, _, cnt = ot.eval(w.pos, w.mass, w.eps, sinks=sinks, with_pot=False)
+    e_tree = rel_rms(ga[sinks], oa)
+    ds = W.sample_indices(w.n, n_direct, 102)
+    ad, _ = oracle.direct(w.pos, w.mass, w.eps, sinks=ds)
+    e_dir = rel_rms(ga[ds], ad)
+    _log(f"{name}: vs oracle treecode {e_tree:.3e} ({len(sinks)} sinks), vs direct {e_dir:.3e} "
+         f"({n_direct} sinks) {time.time() - t0:.1f}s")
+    assert e_tree <= 1e-5
+    assert e_dir <= 1e-3
+    return w, gt, pos, mass
+
+
+@pytest.mark.parametrize("name,ng,nd", [("plummer1m", 64, 4096), ("clustered4m", 48, 2048),
+                                        ("clustered16m", 24, 1024)])
+def test_forward_full_size(name, ng, nd):
+    _check(name, ng, nd)
+
+
+def test_zeldovich16m_forward_and_adjoint():
+    w, gt, pos, mass = _check("zeldovich16m", 24, 1024)
+    abar = torch.from_numpy(W.cotangent(w.n, 404)).cuda()
+    xbar, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED)
+    xb = xbar.cpu().numpy()
+    # direct-sum VJP rows: the tree adjoint approximates them at the expansion's accuracy
+    rows = W.sample_indices(w.n, 256, 405)
+    xd, _ = oracle.direct_vjp(w.pos, w.mass, w.eps, abar.cpu().numpy(), rows=rows)
+    e_rows = rel_rms(xb[rows], xd)
+    # directional derivative of the FP64 forward with the topology frozen
+    v = torch.from_numpy(np.random.default_rng(8).normal(size=(w.n, 3))).cuda() * 1e-3
+
+    def L(x):
+        gt.compute_moments(x, mass, w.p)
+        a, _, _ = gt.eval_forces(x, mass, w.eps, HOT_FP64)
+        return (a * abar).sum().item()
+
+    h = 1e-4
+    d1 = (L(pos + h * v) - L(pos - h * v)) / (2 * h)
+    d2 = (L(pos + 2 * h * v) - L(pos - 2 * h * v)) / (4 * h)
+    fd = (4 * d1 - d2) / 3
+    an = float((xbar * v).sum())
+    gt.compute_moments(pos, mass, w.p)
+    _log(f"zeldovich16m adjoint: vs direct VJP rows {e_rows:.3e}; directional {an:.9e} vs FD {fd:.9e}")
+    assert e_rows <= 1e-3
+    assert abs(an - fd) <= 1e-4 * abs(fd)
