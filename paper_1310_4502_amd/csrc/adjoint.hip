@@ -163,10 +163,19 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     ab = ab4[i];
   }
   T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
-  for (int64_t e = p2p_off[g]; e < p2p_off[g + 1]; ++e) {
-    const int c = uniform_i32(p2p[e]);
+  const int64_t e1 = p2p_off[g + 1];
+  int64_t e = p2p_off[g];
+  while (e < e1) {
+    // a run of consecutive entries with contiguous particle ranges
+    int c = uniform_i32(p2p[e]);
     const int f = uniform_i32(c_first[c]);
-    const int end = f + uniform_i32(c_count[c]);
+    int end = f + uniform_i32(c_count[c]);
+    for (++e; e < e1; ++e) {
+      c = uniform_i32(p2p[e]);
+      const int f2 = uniform_i32(c_first[c]);
+      if (f2 != end) break;
+      end = f2 + uniform_i32(c_count[c]);
+    }
     T A = 0, Bx = 0, By = 0, Bz = 0;  // sum m inv3 ; sum 3 m (r.ab) inv5 r
     int j = f;
     while (j < end) {

@@ -51,57 +51,64 @@ __global__ __launch_bounds__(kB) void k_p2p(
   me.x = me.y = me.z = me.w = T(0);
   if (active) me = off[i];
   T sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
-  const int64_t e0 = p2p_off[g], e1 = p2p_off[g + 1];
-  for (int64_t e = e0; e < e1; ++e) {
-    const int c = p2p[e];
-    const int f = c_first[c];
-    const int end = f + c_count[c];
+  const int64_t e1 = p2p_off[g + 1];
+  int64_t e = p2p_off[g];
+  while (e < e1) {
+    // a run of consecutive entries whose particle ranges are contiguous
+    // (typically the sibling leaves of one opened cell)
+    int c = uniform_i32(p2p[e]);
+    const int f = uniform_i32(c_first[c]);
+    int end = f + uniform_i32(c_count[c]);
+    for (++e; e < e1; ++e) {
+      c = uniform_i32(p2p[e]);
+      const int f2 = uniform_i32(c_first[c]);
+      if (f2 != end) break;
+      end = f2 + uniform_i32(c_count[c]);
+    }
     T ax = 0, ay = 0, az = 0, ap = 0;
+    T bx = 0, by = 0, bz = 0, bp = 0;
     int j = f;
     while (j < end) {
-      const int sg = group_of[j];
-      const int sgend = g_first[sg] + g_count[sg];
+      const int sg = uniform_i32(group_of[j]);
+      const int sgend = uniform_i32(g_first[sg] + g_count[sg]);
       const int jend = end < sgend ? end : sgend;
       if (jend <= j) break;  // never true for a valid tree
-      const int sc = g_cell[sg];
+      const int sc = uniform_i32(g_cell[sg]);
       const T tx = (T)(c_centre[3 * sc] - cgx) - me.x;
       const T ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
       const T tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+#define HOT_PAIR(SELF, JJ, AX, AY, AZ, AP)                                            \
+  {                                                                                  \
+    const V4<T> s = off[JJ];                                                         \
+    const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;                             \
+    const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
+    T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
+    if (SELF && (JJ) == i) inv = T(0);                                               \
+    const T mi = s.w * inv;                                                          \
+    const T f3 = mi * (inv * inv);                                                   \
+    AX = hot_fma(f3, rx, AX);                                                        \
+    AY = hot_fma(f3, ry, AY);                                                        \
+    AZ = hot_fma(f3, rz, AZ);                                                        \
+    if (POT) AP -= mi;                                                               \
+  }
       if (sg == g) {
-        for (int jj = j; jj < jend; ++jj) {
-          const V4<T> s = off[jj];
-          const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;
-          const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
-          T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
-          if (jj == i) inv = T(0);
-          const T mi = s.w * inv;
-          const T f3 = mi * (inv * inv);
-          ax = hot_fma(f3, rx, ax);
-          ay = hot_fma(f3, ry, ay);
-          az = hot_fma(f3, rz, az);
-          if (POT) ap -= mi;
-        }
+        for (int jj = j; jj < jend; ++jj) HOT_PAIR(true, jj, ax, ay, az, ap)
       } else {
-#pragma unroll 4
-        for (int jj = j; jj < jend; ++jj) {
-          const V4<T> s = off[jj];
-          const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;
-          const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));
-          const T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);
-          const T mi = s.w * inv;
-          const T f3 = mi * (inv * inv);
-          ax = hot_fma(f3, rx, ax);
-          ay = hot_fma(f3, ry, ay);
-          az = hot_fma(f3, rz, az);
-          if (POT) ap -= mi;
+        int jj = j;
+#pragma unroll 2
+        for (; jj + 1 < jend; jj += 2) {
+          HOT_PAIR(false, jj, ax, ay, az, ap)
+          HOT_PAIR(false, jj + 1, bx, by, bz, bp)
         }
+        if (jj < jend) HOT_PAIR(false, jj, ax, ay, az, ap)
       }
+#undef HOT_PAIR
       j = jend;
     }
-    kahan_add(sx, cx, ax);
-    kahan_add(sy, cy, ay);
-    kahan_add(sz, cz, az);
-    if (POT) kahan_add(sp, cp, ap);
+    kahan_add(sx, cx, ax + bx);
+    kahan_add(sy, cy, ay + by);
+    kahan_add(sz, cz, az + bz);
+    if (POT) kahan_add(sp, cp, ap + bp);
   }
   if (active) {
     T* st = state + (int64_t)i * 8;

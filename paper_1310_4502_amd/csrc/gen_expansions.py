@@ -45,9 +45,12 @@ def lit(x):
 
 
 class Emitter:
-    def __init__(self, K):
+    def __init__(self, K, row_barriers=False):
         self.K = K
         self.lines = []
+        # scheduling barriers between z-rows keep the operands (moments) of each
+        # row from being loaded all at once at the top: fewer live registers
+        self.row_barriers = row_barriers
 
     def e(self, s):
         self.lines.append("  " + s)
@@ -84,6 +87,8 @@ class Emitter:
             return zname(v, n) if u == 0 else f"Y{v}_{u}_{n}"
 
         for v in range(0, K + 1):
+            if v >= 1 and self.row_barriers:
+                e("HOT_ROW_BARRIER();")
             if v >= 1:
                 for n in range(0, K - v + 1):
                     if v == 1:
@@ -121,9 +126,12 @@ class Emitter:
                     consume(t, u, v, name)
 
 
+ROW_BARRIER_MIN_P = 7
+
+
 def gen_fwd(P):
     K = P + 1
-    em = Emitter(K)
+    em = Emitter(K, row_barriers=P >= ROW_BARRIER_MIN_P)
     em.radial()
 
     def consume(t, u, v, r):
@@ -145,7 +153,7 @@ PAIRS = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
 
 def gen_sink_adj(P):
     K = P + 2
-    em = Emitter(K)
+    em = Emitter(K, row_barriers=P >= ROW_BARRIER_MIN_P)
     em.radial()
     for k, l in PAIRS:
         em.e(f"T H{k}{l} = T(0);")
@@ -304,6 +312,7 @@ def _count_ops(lines):
     return n
 
 
+
 def flops_m2p(P):
     """FP32 operations per (sink, cell) of the forward expansion kernel without
     the potential: the generated expansion plus the per-interaction setup of the
@@ -323,6 +332,9 @@ def flops_p2p():
 def main(out_path):
     parts = ["// Generated by gen_expansions.py -- do not edit.",
              "#pragma once",
+             "#ifndef HOT_ROW_BARRIER",
+             "#define HOT_ROW_BARRIER() __builtin_amdgcn_sched_barrier(0)",
+             "#endif",
              "namespace hot {",
              ""]
     parts.append("template <int P, typename T, bool POT>")

@@ -3,6 +3,7 @@
 #include <cmath>
 #define __device__
 #define __forceinline__ inline
+#define HOT_ROW_BARRIER()
 namespace hot {
 inline double hot_fma(double a, double b, double c) { return std::fma(a, b, c); }
 inline double hot_rsq(double x) { return 1.0 / std::sqrt(x); }
