@@ -94,7 +94,20 @@ def main():
     ap.add_argument("--cpu-groups", type=int, default=24,
                     help="sink groups evaluated by the CPU oracle sample")
     ap.add_argument("--err-sinks", type=int, default=256)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized buffer once (known traffic for the HBM "
+                         "byte counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the force path of "
