@@ -430,55 +430,51 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
   T row[NM];
 #pragma unroll
   for (int a = 0; a < NM; ++a) row[a] = T(0);
-  // prefetched state of the next (group, chunk)
-  int gn = 0, gfn = 0, gen = 0;
-  double gx_ = 0, gy_ = 0, gz_ = 0;
+  // one loop over the (group, chunk of 64 sinks) pairs of the item, with the
+  // next pair's data prefetched; a single back edge keeps the row registers in
+  // place across iterations
+  auto group_centre = [&](uint32_t r, int& gf, int& ge, T& dx, T& dy, T& dz) {
+    const int g = uniform_i32((int)mval[r]);
+    const int gc = uniform_i32(g_cell[g]);
+    dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
+    dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
+    dz = (T)((c_centre[3 * gc + 2] - ccz) * inv_s);
+    gf = uniform_i32(g_first[g]);
+    ge = gf + uniform_i32(g_count[g]);
+  };
+  uint32_t r = r0;
+  int s0 = 0, ge = 0;
+  T Dx = T(0), Dy = T(0), Dz = T(0);
   V4<T> pme, pab;
-  auto fetch_group = [&](uint32_t r) {
-    gn = uniform_i32((int)mval[r]);
-    const int gc = uniform_i32(g_cell[gn]);
-    gx_ = c_centre[3 * gc];
-    gy_ = c_centre[3 * gc + 1];
-    gz_ = c_centre[3 * gc + 2];
-    gfn = uniform_i32(g_first[gn]);
-    gen = gfn + uniform_i32(g_count[gn]);
-  };
-  auto fetch_sinks = [&](int s0, int ge) {
-    const int i = s0 + lane;
-    if (i < ge) {
-      pme = off[i];
-      pab = ab4[i];
+  pme.x = pme.y = pme.z = pme.w = T(0);
+  pab = pme;
+  if (r < r1) {
+    group_centre(r, s0, ge, Dx, Dy, Dz);
+    if (s0 + lane < ge) {
+      pme = off[s0 + lane];
+      pab = ab4[s0 + lane];
     }
-  };
-  if (r0 < r1) {
-    fetch_group(r0);
-    fetch_sinks(gfn, gen);
   }
-  for (uint32_t r = r0; r < r1; ++r) {
-    const int gf = gfn, ge = gen;
-    const T Dx = (T)((gx_ - ccx) * inv_s);
-    const T Dy = (T)((gy_ - ccy) * inv_s);
-    const T Dz = (T)((gz_ - ccz) * inv_s);
-    for (int s0 = gf; s0 < ge; s0 += 64) {
-      const int i = s0 + lane;
-      T X = T(1), Y = T(0), Z = T(0), bx = T(0), by = T(0), bz = T(0);
-      if (i < ge) {
-        X = Dx + pme.x * (T)inv_s;
-        Y = Dy + pme.y * (T)inv_s;
-        Z = Dz + pme.z * (T)inv_s;
-        bx = pab.x;
-        by = pab.y;
-        bz = pab.z;
-      }
-      // fetch the next chunk of this group, or the first chunk of the next group
-      if (s0 + 64 < ge) {
-        fetch_sinks(s0 + 64, ge);
-      } else if (r + 1 < r1) {
-        fetch_group(r + 1);
-        fetch_sinks(gfn, gen);
-      }
-      expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
+  while (r < r1) {
+    T X = T(1), Y = T(0), Z = T(0), bx = T(0), by = T(0), bz = T(0);
+    if (s0 + lane < ge) {
+      X = Dx + pme.x * (T)inv_s;
+      Y = Dy + pme.y * (T)inv_s;
+      Z = Dz + pme.z * (T)inv_s;
+      bx = pab.x;
+      by = pab.y;
+      bz = pab.z;
     }
+    s0 += 64;
+    if (s0 >= ge) {
+      ++r;
+      if (r < r1) group_centre(r, s0, ge, Dx, Dy, Dz);
+    }
+    if (r < r1 && s0 + lane < ge) {
+      pme = off[s0 + lane];
+      pab = ab4[s0 + lane];
+    }
+    expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
   }
   T* o = part + it * (int64_t)nm_pad(P);
 #pragma unroll

@@ -123,8 +123,14 @@ __global__ __launch_bounds__(kB) void k_p2p(
   }
 }
 
+// The FP32 kernels of the two highest orders are held to 128 VGPRs (four
+// waves per SIMD instead of three; the cost is a few spilled FP64 centre words).
+template <int P, typename T>
+constexpr int m2p_waves_per_simd() { return (sizeof(T) == 4 && P >= 7) ? 4 : 1; }
+
 template <int P, typename T, bool POT>
-__global__ __launch_bounds__(kB) void k_m2p(
+__global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(m2p_waves_per_simd<P, T>())))
+void k_m2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
     const int32_t* __restrict__ m2p, const int8_t* __restrict__ c_level,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,

@@ -24,7 +24,7 @@ Emitted functions (T is float or double):
   expansion_sink_adj<P,T>(X,Y,Z,e2,M,bx,by,bz,gx,gy,gz)
       g_l += sum_k b_k sum_alpha M[alpha] d^(alpha+e_k+e_l) G
   expansion_cell_adj<P,T>(X,Y,Z,e2,bx,by,bz,row)
-      row[alpha] += sum_k b_k d^(alpha+e_k) G   (row: LDS, private to the lane)
+      row[alpha] += sum_k b_k d^(alpha+e_k) G   (row: registers of the lane)
 M holds the (weighted, scaled) moments in slot order: by order, then x
 exponent descending, then y exponent descending.
 """
@@ -180,13 +180,15 @@ def gen_cell_adj(P):
     em = Emitter(K)
     em.radial()
     remaining = {}
-    declared = set()
-    bname = ["bx", "by", "bz"]
     for n in range(P + 1):
         for a in range(n, -1, -1):
             for b_ in range(n - a, -1, -1):
                 remaining[slot(a, b_, n - a - b_)] = 3
+    bname = ["bx", "by", "bz"]
 
+    # each derivative goes straight into the row entries it feeds (per-sink
+    # partial sums would stay live until their z term arrives with the next
+    # z row)
     def consume(t, u, v, r):
         b = [t, u, v]
         for k in range(3):
@@ -195,14 +197,8 @@ def gen_cell_adj(P):
             if a[k] < 0:
                 continue
             s = slot(*a)
-            if s not in declared:
-                em.e(f"T V{s} = {bname[k]} * {r};")
-                declared.add(s)
-            else:
-                em.e(f"V{s} = hot_fma({bname[k]}, {r}, V{s});")
+            em.e(f"row[{s}] = hot_fma({bname[k]}, {r}, row[{s}]);")
             remaining[s] -= 1
-            if remaining[s] == 0:
-                em.e(f"row[{s}] += V{s};")
 
     em.derivs(consume)
     assert all(v == 0 for v in remaining.values())
