@@ -83,15 +83,17 @@ def traffic_from_profiles(kernel_key):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zeldovich16m", choices=sorted(WORKLOADS))
     ap.add_argument("--n-group", type=int, default=None)
     ap.add_argument("--n-leaf", type=int, default=None)
     ap.add_argument("--direct-max", type=int, default=None)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-groups", type=int, default=24,
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 evaluation on the last tree (mixed/FP64 speed-up)")
+    ap.add_argument("--cpu-groups", type=int, default=160,
                     help="sink groups evaluated by the CPU oracle sample")
     ap.add_argument("--err-sinks", type=int, default=256)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -138,12 +140,12 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        evs[3].record()
         t = Tree(pos, n_leaf, n_group, w.box)
         t.compute_moments(pos, mass, w.p)
         t.build_interaction_lists(w.theta, direct_max)
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev2 = torch.cuda.Event(enable_timing=True)
+        ev0, ev1, ev2 = evs[:3]
         ev0.record()
         acc, _, st = t.eval_forces(pos, mass, w.eps, prec, stats=True)
         ev1.record()
@@ -154,7 +156,7 @@ def main():
                 raise
             xbar = None
         ev2.record()
-        return t, acc, xbar, st, (ev0, ev1, ev2)
+        return t, acc, xbar, st, evs
 
     for k in range(args.warmup):
         t, *_ = step()
@@ -177,10 +179,34 @@ def main():
     ms_m2p = float(np.mean([r[1] for r in recs]))
     ms_fwd_eval = float(np.mean([r[2] for r in recs]))
     ms_adj = float(np.mean([r[5][1].elapsed_time(r[5][2]) for r in recs]))
+    step_ms = [r[5][3].elapsed_time(r[5][2]) for r in recs]
     p2p_pairs, m2p_pairs = recs[-1][3], recs[-1][4]
     inter = p2p_pairs + m2p_pairs
     tree, acc, xbar = last
     counts = tree.counts()
+
+    # after the timed region, on the last step's tree: the adjoint again (its
+    # transposed lists are now cached, so this excludes their construction) and
+    # the FP64 evaluation on identical lists
+    def timed(fn, reps=2):
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts), r
+    ms_adj_cached = None
+    if xbar is not None:
+        ms_adj_cached, _ = timed(lambda: tree.eval_forces_adjoint(pos, mass, w.eps, abar, prec))
+    acc64, ms_eval64 = None, None
+    if prec == HOT_MIXED and not args.no_fp64:
+        ms_eval64, r64 = timed(lambda: tree.eval_forces(pos, mass, w.eps, HOT_FP64))
+        acc64 = r64[0]
+        log(f"fp64 eval on the same lists: {ms_eval64:.1f} ms")
 
     f_p2p, f_m2p = kernel_flops()
     # dominant kernel: the longer of P2P and M2P in eval_forces
@@ -204,6 +230,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median_min_max": [float(np.median(step_ms)), float(np.min(step_ms)),
+                                       float(np.max(step_ms))],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -220,6 +248,11 @@ def main():
         "ms_m2p": ms_m2p,
         "ms_adjoint": ms_adj,
         "adjoint_over_eval": ms_adj / ms_fwd_eval if ms_fwd_eval > 0 else None,
+        "ms_adjoint_lists_cached": ms_adj_cached,
+        "adjoint_over_eval_lists_cached": (ms_adj_cached / ms_fwd_eval
+                                           if ms_adj_cached and ms_fwd_eval > 0 else None),
+        "ms_eval_forces_fp64": ms_eval64,
+        "fp64_over_mixed_eval": ms_eval64 / ms_fwd_eval if ms_eval64 else None,
         "interactions_per_s_eval": inter / (ms_fwd_eval * 1e-3),
         "p2p_gflops_28flop_convention": p2p_pairs * 28 / (ms_p2p * 1e-3) / 1e9,
         "tree": {k: counts[k] for k in ("n_cells", "n_groups", "n_leaves", "max_level",
@@ -229,16 +262,20 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["rms_err_vs_direct"] = cpu_baseline(
-            w, acc, n_leaf, n_group, direct_max, args.cpu_groups, args.err_sinks)
+        out["cpu_baseline"], errs = cpu_baseline(
+            w, {"mixed": acc, "fp64": acc64}, n_leaf, n_group, direct_max, args.cpu_groups,
+            args.err_sinks)
+        out["rms_err_vs_direct"] = errs.get("mixed" if prec == HOT_MIXED else "fp64")
+        if acc64 is not None:
+            out["rms_err_vs_direct_fp64"] = errs["fp64"]
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, acc_gpu, n_leaf, n_group, direct_max, n_groups_sample, n_err):
+def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err):
     """The CPU oracle (FP64 scalar treecode, OpenMP) on a bounded sample of the
     same workload: its interaction rate over the sampled sinks' evaluation
-    (tree build and moments excluded), plus the GPU's RMS force error against
-    the oracle's direct summation on sampled sinks."""
+    (tree build and moments excluded), plus the relative RMS error of each GPU
+    result in `accs` against the oracle's direct summation on sampled sinks."""
     import numpy as np
 
     import oracle
@@ -269,10 +306,14 @@ def cpu_baseline(w, acc_gpu, n_leaf, n_group, direct_max, n_groups_sample, n_err
     es = W.sample_indices(w.n, n_err, 102)
     t2 = time.time()
     ad, _ = oracle.direct(w.pos, w.mass, w.eps, sinks=es)
-    a = acc_gpu.cpu().numpy()[es]
-    err = float(np.linalg.norm(a - ad) / np.linalg.norm(ad))
-    log(f"direct-sum check on {n_err} sinks in {time.time() - t2:.1f}s: rel RMS {err:.3e}")
-    return base, err
+    errs = {}
+    for k, acc in accs.items():
+        if acc is None:
+            continue
+        a = acc.cpu().numpy()[es]
+        errs[k] = float(np.linalg.norm(a - ad) / np.linalg.norm(ad))
+    log(f"direct-sum check on {n_err} sinks in {time.time() - t2:.1f}s: rel RMS {errs}")
+    return base, errs
 
 
 if __name__ == "__main__":
