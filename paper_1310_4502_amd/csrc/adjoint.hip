@@ -37,47 +37,89 @@ int bits_for(int64_t v) {
 }
 
 // ---------------------------------------------------------------- transposes
-__global__ void k_srec_count(const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p,
-                             int64_t G, const int32_t* __restrict__ c_first,
-                             const int32_t* __restrict__ c_count,
-                             const int32_t* __restrict__ item_of, int64_t* __restrict__ cnt) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  int64_t k = 0;
-  for (int64_t e = p2p_off[g]; e < p2p_off[g + 1]; ++e) {
-    const int c = p2p[e];
-    const int f = c_first[c];
-    k += item_of[f + c_count[c] - 1] - item_of[f] + 1;
-  }
-  cnt[g] = k;
+// One wavefront per sink group; its lanes stride over the group's list (the
+// loads of consecutive entries coalesce), so records come out in entry order.
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  return v;
 }
 
-__global__ void k_srec_fill(const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p,
-                            int64_t G, const int32_t* __restrict__ c_first,
-                            const int32_t* __restrict__ c_count,
-                            const int32_t* __restrict__ item_of,
-                            const int64_t* __restrict__ rec_off, int gbits,
-                            uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// exclusive prefix sum over the lanes of a wavefront; *total gets the sum
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total) {
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  *total = __shfl(x, 63);
+  return x - v;
+}
+
+// records of one P2P entry: the source items its particle range touches
+__device__ __forceinline__ void srec_range(const int32_t* __restrict__ p2p,
+                                           const int32_t* __restrict__ c_first,
+                                           const int32_t* __restrict__ c_count,
+                                           const int32_t* __restrict__ item_of, int64_t e,
+                                           int& q0, int& q1) {
+  const int c = p2p[e];
+  const int f = c_first[c];
+  q0 = item_of[f];
+  q1 = item_of[f + c_count[c] - 1];
+}
+
+__global__ __launch_bounds__(kB) void k_srec_count(
+    const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p, int64_t G,
+    const int32_t* __restrict__ c_first, const int32_t* __restrict__ c_count,
+    const int32_t* __restrict__ item_of, int64_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kWPB + (threadIdx.x >> 6);
+  if (g >= G) return;
+  const int64_t e1 = p2p_off[g + 1];
+  int64_t k = 0;
+  for (int64_t e = p2p_off[g] + lane; e < e1; e += 64) {
+    int q0, q1;
+    srec_range(p2p, c_first, c_count, item_of, e, q0, q1);
+    k += q1 - q0 + 1;
+  }
+  k = wave_sum_i64(k);
+  if (lane == 0) cnt[g] = k;
+}
+
+__global__ __launch_bounds__(kB) void k_srec_fill(
+    const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p, int64_t G,
+    const int32_t* __restrict__ c_first, const int32_t* __restrict__ c_count,
+    const int32_t* __restrict__ item_of, const int64_t* __restrict__ rec_off, int gbits,
+    uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kWPB + (threadIdx.x >> 6);
   if (g >= G) return;
   int64_t o = rec_off[g];
-  for (int64_t e = p2p_off[g]; e < p2p_off[g + 1]; ++e) {
-    const int c = p2p[e];
-    const int f = c_first[c];
-    const int q0 = item_of[f], q1 = item_of[f + c_count[c] - 1];
+  const int64_t e0 = p2p_off[g], e1 = p2p_off[g + 1];
+  for (int64_t b = e0; b < e1; b += 64) {
+    const int64_t e = b + lane;
+    int q0 = 0, q1 = -1;
+    if (e < e1) srec_range(p2p, c_first, c_count, item_of, e, q0, q1);
+    int total;
+    const int64_t at = o + wave_excl_scan(q1 - q0 + 1, lane, &total);
     for (int q = q0; q <= q1; ++q) {
-      key[o] = ((uint64_t)q << gbits) | (uint64_t)g;
-      val[o] = (uint32_t)e;
-      ++o;
+      key[at + (q - q0)] = ((uint64_t)q << gbits) | (uint64_t)g;
+      val[at + (q - q0)] = (uint32_t)e;
     }
+    o += total;
   }
 }
 
-__global__ void k_mrec_fill(const int64_t* __restrict__ m2p_off, const int32_t* __restrict__ m2p,
-                            int64_t G, uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kB) void k_mrec_fill(const int64_t* __restrict__ m2p_off,
+                                                  const int32_t* __restrict__ m2p, int64_t G,
+                                                  uint64_t* __restrict__ key,
+                                                  uint32_t* __restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kWPB + (threadIdx.x >> 6);
   if (g >= G) return;
-  for (int64_t e = m2p_off[g]; e < m2p_off[g + 1]; ++e) {
+  const int64_t e1 = m2p_off[g + 1];
+  for (int64_t e = m2p_off[g] + lane; e < e1; e += 64) {
     key[e] = (uint64_t)m2p[e];
     val[e] = (uint32_t)g;
   }
@@ -624,7 +666,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     DBuf cnt, tot;
     cnt.alloc(ctx, (G + 1) * sizeof(int64_t));
     tot.alloc(ctx, sizeof(int64_t));
-    k_srec_count<<<grid_for(G, kB), kB, 0, st>>>(t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), G,
+    k_srec_count<<<grid_for(G, kWPB), kB, 0, st>>>(t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), G,
                                                  t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
                                                  t->item_of.as<int32_t>(), cnt.as<int64_t>());
     HOT_CHECK_LAUNCH();
@@ -640,7 +682,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     t->srec_key.alloc(ctx, std::max<int64_t>(1, nrec) * sizeof(uint64_t));
     t->srec_val.alloc(ctx, std::max<int64_t>(1, nrec) * sizeof(uint32_t));
     t->srec_off.alloc(ctx, (NI + 1) * sizeof(uint32_t));
-    k_srec_fill<<<grid_for(G, kB), kB, 0, st>>>(
+    k_srec_fill<<<grid_for(G, kWPB), kB, 0, st>>>(
         t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), G, t->c_first.as<int32_t>(),
         t->c_count.as<int32_t>(), t->item_of.as<int32_t>(), cnt.as<int64_t>(), gbits,
         t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>());
@@ -659,7 +701,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     t->mrec_val.alloc(ctx, std::max<int64_t>(1, E) * sizeof(uint32_t));
     t->mcell_rec.alloc(ctx, (C + 1) * sizeof(uint32_t));
     t->mcell_item.alloc(ctx, (C + 1) * sizeof(uint32_t));
-    k_mrec_fill<<<grid_for(G, kB), kB, 0, st>>>(t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(), G,
+    k_mrec_fill<<<grid_for(G, kWPB), kB, 0, st>>>(t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(), G,
                                                 t->mrec_key.as<uint64_t>(),
                                                 t->mrec_val.as<uint32_t>());
     HOT_CHECK_LAUNCH();
