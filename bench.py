@@ -297,12 +297,24 @@ def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err):
     _, _, cnt = ot.eval(w.pos, w.mass, w.eps, sinks=sinks, with_pot=False)
     dt = time.perf_counter() - t1
     inter = int(cnt[0] + cnt[1])
-    log(f"cpu oracle: {len(sinks)} sinks, {inter} interactions in {dt:.1f}s")
-    base = {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    cores = oracle.num_threads()
+    log(f"cpu oracle: {len(sinks)} sinks, {inter} interactions in {dt:.1f}s on {cores} threads")
+    # the same evaluation on one core, over the sinks of the first tenth of the sampled groups
+    one = np.sort(perm[np.isin(gof, groups[:max(1, len(groups) // 10)])])
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    _, _, cnt1 = ot.eval(w.pos, w.mass, w.eps, sinks=one, with_pot=False)
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
+    inter1 = int(cnt1[0] + cnt1[1])
+    log(f"cpu oracle, one core: {len(one)} sinks, {inter1} interactions in {dt1:.1f}s")
+    base = {"value": inter / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 scalar treecode (O-T) evaluation of {len(sinks)} sinks in "
                       f"{len(groups)} sampled groups of the same workload; tree build and "
-                      f"moments not timed"}
+                      f"moments not timed",
+            "forces_per_s": len(sinks) / dt,
+            "one_core": {"value": inter1 / dt1, "unit": "interactions/s",
+                         "forces_per_s": len(one) / dt1, "sinks": len(one)}}
     es = W.sample_indices(w.n, n_err, 102)
     t2 = time.time()
     ad, _ = oracle.direct(w.pos, w.mass, w.eps, sinks=es)

@@ -41,6 +41,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.oracle_last_error.restype = ctypes.c_char_p
         L.oracle_tree_destroy.restype = None
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -68,6 +69,10 @@ def nm(p: int) -> int:
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))
 
 
 def morton_keys(pos, box=None):

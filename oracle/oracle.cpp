@@ -1019,4 +1019,13 @@ int oracle_num_threads(void) {
 #endif
 }
 
+// Threads for the following parallel regions (timing on one core and on all).
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 }  // extern "C"
