@@ -146,6 +146,20 @@ class Tree:
         _chk(lib().oracle_build_lists(self.h, ctypes.c_double(theta), int(direct_max),
                                       ctypes.c_int64(ns), _p(sel)))
 
+    def build_lists_err(self, mass, tol, p_max, direct_max=0, groups=None):
+        """Error-bound lists: every M2P entry carries the lowest order whose
+        field-error bound is at most tol (see accept_order in oracle.cpp)."""
+        sel = _i64(groups)
+        ns = 0 if sel is None else sel.shape[0]
+        _chk(lib().oracle_build_lists_err(self.h, _p(_f64(mass)), ctypes.c_double(tol),
+                                          int(p_max), int(direct_max), ctypes.c_int64(ns),
+                                          _p(sel)))
+
+    def m2p_orders(self):
+        out = np.empty(self.counts()["n_m2p"], np.int8)
+        _chk(lib().oracle_get_m2p_orders(self.h, _p(out)))
+        return out
+
     def group_of(self):
         out = np.empty(self.n, np.int64)
         _chk(lib().oracle_group_of(self.h, _p(out)))

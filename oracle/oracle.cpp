@@ -147,6 +147,9 @@ struct Tree {
   std::vector<int64_t> p2p_off, m2p_off;
   std::vector<int32_t> p2p, m2p;
   std::vector<char> list_sel;  // empty: every group has its lists
+  // error-bound lists: expansion order of every M2P entry (empty for theta lists)
+  std::vector<int8_t> m2p_q;
+  int list_p = -1;  // highest order an entry may use (error-bound lists)
   // moments
   int p = -1;
   std::vector<double> mom;        // n_cells x nm(p)
@@ -351,12 +354,80 @@ void walk(const Tree& t, const Cell& g, int64_t ci, double theta, int direct_max
   for (int k = 0; k < c.n_child; ++k) walk(t, g, c.child_first + k, theta, direct_max, p2p, m2p);
 }
 
-int build_lists(Tree& t, double theta, int direct_max, const std::vector<char>& want) {
+// ---------------------------------------------------------------------------
+// Error-bound acceptance with the order chosen per interaction (Multipole
+// Error Bounds section: an absolute-error MAC that picks, per interaction,
+// the cheapest expansion order meeting the accuracy). The paper's own bounds
+// are in a reference that is not at hand; the reading used here is the
+// classical bound on the field of a truncated cell-body expansion of 1/r:
+// sources of total mass M within radius b of the expansion centre, field
+// point at distance d > b from it, expansion to order q:
+//   |a - a_q| <= M / (d - b)^2 * ((q + 2) - (q + 1) t) * t^(q + 1),  t = b / d,
+// the sum over n > q of (n + 1) b^n / d^(n + 2) (each degree-n term of the
+// Taylor series is a Legendre term bounded by b^n / d^(n + 1), its gradient
+// by (n + 1) b^n / d^(n + 2)). A sink of group g lies within b_max(g) of its
+// centre, so d = |centre_g - centre_c| - b_max(g); M is bounded by the
+// cell's particle count times the largest particle mass (exact arithmetic on
+// both sides of the parity tests). The smallest q in [0, p_max] whose bound is
+// at most tol is taken; if there is none (or d <= b), the cell is opened.
+// FP64, no FMA, this exact order of operations.
+// ---------------------------------------------------------------------------
+int accept_order(const Cell& g, const Cell& c, double tol, double mmax, int pmax) {
+  double dx = g.centre[0] - c.centre[0];
+  double dy = g.centre[1] - c.centre[1];
+  double dz = g.centre[2] - c.centre[2];
+  double d = std::sqrt((dx * dx + dy * dy) + dz * dz) - g.bmax;
+  double b = c.bmax;
+  if (!(d > b)) return -1;
+  double t = b / d;
+  double h = d - b;
+  double A = ((double)c.count * mmax) / (h * h);
+  double tp = t;
+  for (int q = 0; q <= pmax; ++q) {
+    double E = (A * ((double)(q + 2) - (double)(q + 1) * t)) * tp;
+    if (E <= tol) return q;
+    tp = tp * t;
+  }
+  return -1;
+}
+
+void walk_err(const Tree& t, const Cell& g, int64_t ci, double tol, double mmax, int pmax,
+              int direct_max, std::vector<int32_t>& p2p, std::vector<int32_t>& m2p,
+              std::vector<int8_t>& m2p_q) {
+  const Cell& c = t.cells[ci];
+  const int q = accept_order(g, c, tol, mmax, pmax);
+  if (q >= 0) {
+    if (c.count <= direct_max) {
+      p2p.push_back((int32_t)ci);
+    } else {
+      m2p.push_back((int32_t)ci);
+      m2p_q.push_back((int8_t)q);
+    }
+    return;
+  }
+  if (c.is_leaf) {
+    p2p.push_back((int32_t)ci);
+    return;
+  }
+  for (int k = 0; k < c.n_child; ++k)
+    walk_err(t, g, c.child_first + k, tol, mmax, pmax, direct_max, p2p, m2p, m2p_q);
+}
+
+// theta >= 0: theta lists; theta < 0: error-bound lists with (tol, mmax, pmax)
+int build_lists(Tree& t, double theta, int direct_max, const std::vector<char>& want,
+                double tol = 0, double mmax = 0, int pmax = -1) {
   const int64_t G = (int64_t)t.groups.size();
+  const bool err = theta < 0;
   std::vector<std::vector<int32_t>> lp(G), lm(G);
+  std::vector<std::vector<int8_t>> lq(G);
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t g = 0; g < G; ++g)
-    if (want.empty() || want[g]) walk(t, t.cells[t.groups[g]], 0, theta, direct_max, lp[g], lm[g]);
+  for (int64_t g = 0; g < G; ++g) {
+    if (!(want.empty() || want[g])) continue;
+    if (err)
+      walk_err(t, t.cells[t.groups[g]], 0, tol, mmax, pmax, direct_max, lp[g], lm[g], lq[g]);
+    else
+      walk(t, t.cells[t.groups[g]], 0, theta, direct_max, lp[g], lm[g]);
+  }
   t.p2p_off.assign(G + 1, 0);
   t.m2p_off.assign(G + 1, 0);
   for (int64_t g = 0; g < G; ++g) {
@@ -369,6 +440,12 @@ int build_lists(Tree& t, double theta, int direct_max, const std::vector<char>& 
     std::copy(lp[g].begin(), lp[g].end(), t.p2p.begin() + t.p2p_off[g]);
     std::copy(lm[g].begin(), lm[g].end(), t.m2p.begin() + t.m2p_off[g]);
   }
+  t.m2p_q.clear();
+  if (err) {
+    t.m2p_q.resize(t.m2p_off[G]);
+    for (int64_t g = 0; g < G; ++g) std::copy(lq[g].begin(), lq[g].end(), t.m2p_q.begin() + t.m2p_off[g]);
+  }
+  t.list_p = err ? pmax : -1;
   t.has_lists = true;
   t.theta = theta;
   t.direct_max = direct_max;
@@ -626,6 +703,37 @@ int oracle_build_lists(void* h, double theta, int direct_max, int64_t n_sel, con
   return build_lists(*t, theta, direct_max, want);
 }
 
+// Error-bound lists (see accept_order) with orders up to pmax; mass in
+// caller order (only its largest value is used).
+int oracle_build_lists_err(void* h, const double* mass, double tol, int pmax, int direct_max,
+                           int64_t n_sel, const int64_t* sel) {
+  Tree* t = (Tree*)h;
+  if (!mass) return fail("bad arguments");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail("tol must be finite and > 0");
+  if (pmax < 0 || pmax > 8) return fail("pmax must lie in [0, 8]");
+  if (direct_max < 0) return fail("direct_max must be >= 0");
+  double mmax = 0.0;
+  for (int64_t i = 0; i < t->n; ++i) mmax = std::max(mmax, mass[i]);
+  std::vector<char> want;
+  if (sel) {
+    want.assign(t->groups.size(), 0);
+    for (int64_t k = 0; k < n_sel; ++k) {
+      if (sel[k] < 0 || sel[k] >= (int64_t)t->groups.size()) return fail("bad group ordinal");
+      want[sel[k]] = 1;
+    }
+  }
+  t->list_sel = want;
+  return build_lists(*t, -1.0, direct_max, want, tol, mmax, pmax);
+}
+
+int oracle_get_m2p_orders(void* h, int8_t* out) {
+  Tree* t = (Tree*)h;
+  if (!t->has_lists) return fail("no lists");
+  if (t->list_p < 0) return fail("lists have no per-entry orders");
+  std::copy(t->m2p_q.begin(), t->m2p_q.end(), out);
+  return 0;
+}
+
 int oracle_group_of(void* h, int64_t* out) {
   Tree* t = (Tree*)h;
   std::copy(t->group_of.begin(), t->group_of.end(), out);
@@ -695,6 +803,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
   Tree* t = (Tree*)h;
   if (!t->has_lists) return fail("lists not built");
   if (t->p < 0) return fail("moments not computed");
+  if (t->p < t->list_p) return fail("moments of lower order than the lists");
   if (!(eps >= 0) || !std::isfinite(eps)) return fail("eps must be finite and >= 0");
   const int64_t n = t->n;
   const int K = nm(t->p);
@@ -738,7 +847,8 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
       const Cell& c = t->cells[cid];
       double R[3] = {xi[0] - c.centre[0], xi[1] - c.centre[1], xi[2] - c.centre[2]};
       double da[3], dphi;
-      m2p_one(&t->mom[cid * K], t->p, R, eps, da, &dphi);
+      const int q = t->list_p >= 0 ? (int)t->m2p_q[e] : t->p;
+      m2p_one(&t->mom[cid * K], q, R, eps, da, &dphi);
       a[0] += da[0], a[1] += da[1], a[2] += da[2];
       ph += dphi;
       c_m2p += 1;
@@ -825,6 +935,7 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
   if (!t->has_lists) return fail("lists not built");
   if (!t->list_sel.empty()) return fail("the VJP needs the lists of every group");
   if (t->p < 0) return fail("moments not computed");
+  if (t->p < t->list_p) return fail("moments of lower order than the lists");
   const int64_t n = t->n;
   const int p = t->p;
   const int K = nm(p);
@@ -880,9 +991,10 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
         const double* M = &t->mom[cid * K];
         double R[3] = {xi[0] - c.centre[0], xi[1] - c.centre[1], xi[2] - c.centre[2]};
         double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
-        Radial rad = radial(s, p + 2);
+        const int q = t->list_p >= 0 ? (int)t->m2p_q[e] : p;
+        Radial rad = radial(s, q + 2);
         double* Mb = &cellbar[g][(e - t->m2p_off[g]) * K];
-        for (int sl = 0; sl < K; ++sl) {
+        for (int sl = 0; sl < nm(q); ++sl) {
           const int* al = &g_alpha[3 * sl];
           int nn = al[0] + al[1] + al[2];
           double w = ((nn % 2) ? -1.0 : 1.0) /
