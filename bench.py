@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--n-leaf", type=int, default=None)
     ap.add_argument("--direct-max", type=int, default=None)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--err-tol", type=float, default=None,
+                    help="error-bound lists with this absolute acceleration tolerance per "
+                         "interaction (orders up to the workload's p) instead of theta lists")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 evaluation on the last tree (mixed/FP64 speed-up)")
@@ -144,7 +147,10 @@ def main():
         evs[3].record()
         t = Tree(pos, n_leaf, n_group, w.box)
         t.compute_moments(pos, mass, w.p)
-        t.build_interaction_lists(w.theta, direct_max)
+        if args.err_tol is None:
+            t.build_interaction_lists(w.theta, direct_max)
+        else:
+            t.build_interaction_lists_err(mass, args.err_tol, w.p, direct_max)
         ev0, ev1, ev2 = evs[:3]
         ev0.record()
         acc, _, st = t.eval_forces(pos, mass, w.eps, prec, stats=True)
@@ -209,17 +215,30 @@ def main():
         log(f"fp64 eval on the same lists: {ms_eval64:.1f} ms")
 
     f_p2p, f_m2p = kernel_flops()
+    if args.err_tol is None:
+        m2p_flops = m2p_pairs * f_m2p[w.p]
+        orders = None
+    else:
+        # per-entry orders: flops of each entry's order times its group's sinks
+        _, _, mo, _ = tree.lists()
+        q = tree.m2p_orders()
+        gcount = tree.cells()["count"][tree.groups()].astype(np.int64)
+        per_entry = np.repeat(gcount, np.diff(mo))
+        fq = np.array([f_m2p[k] for k in range(9)], dtype=np.int64)
+        m2p_flops = int((per_entry * fq[q]).sum())
+        orders = np.bincount(q, minlength=w.p + 1).tolist()
     # dominant kernel: the longer of P2P and M2P in eval_forces
     if ms_m2p >= ms_p2p:
-        dom, dom_ms, dom_flops = f"m2p_p{w.p}", ms_m2p, m2p_pairs * f_m2p[w.p]
+        dom, dom_ms, dom_flops = f"m2p_p{w.p}", ms_m2p, m2p_flops
     else:
         dom, dom_ms, dom_flops = "p2p", ms_p2p, p2p_pairs * f_p2p
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
-    traffic = traffic_from_profiles(dom)
+    traffic = traffic_from_profiles(dom) if args.err_tol is None else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": traffic, "kernel": dom,
-                "flops_per_interaction": f_m2p[w.p] if dom.startswith("m2p") else f_p2p,
+                "flops_per_interaction": (round(m2p_flops / max(m2p_pairs, 1), 1)
+                                          if dom.startswith("m2p") else f_p2p),
                 "ms_per_launch": round(dom_ms, 3)}
 
     out = {
@@ -238,8 +257,9 @@ def main():
         "dtype": "f32" if prec == HOT_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n": w.n, "p": w.p,
-                   "theta": w.theta, "eps": w.eps, "n_leaf": n_leaf, "n_group": n_group,
-                   "direct_max": direct_max, "precision": args.precision},
+                   "theta": w.theta if args.err_tol is None else None,
+                   "err_tol": args.err_tol, "eps": w.eps, "n_leaf": n_leaf,
+                   "n_group": n_group, "direct_max": direct_max, "precision": args.precision},
         "forces_per_s": w.n / (ms_step * 1e-3),
         "p2p_pairs": p2p_pairs,
         "m2p_pairs": m2p_pairs,
@@ -258,20 +278,21 @@ def main():
         "tree": {k: counts[k] for k in ("n_cells", "n_groups", "n_leaves", "max_level",
                                         "n_p2p", "n_m2p", "n_items")},
         "roofline": roofline,
+        "m2p_orders": orders,
         "cpu_baseline": None,
     }
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"], errs = cpu_baseline(
             w, {"mixed": acc, "fp64": acc64}, n_leaf, n_group, direct_max, args.cpu_groups,
-            args.err_sinks)
+            args.err_sinks, args.err_tol)
         out["rms_err_vs_direct"] = errs.get("mixed" if prec == HOT_MIXED else "fp64")
         if acc64 is not None:
             out["rms_err_vs_direct_fp64"] = errs["fp64"]
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err):
+def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err, err_tol=None):
     """The CPU oracle (FP64 scalar treecode, OpenMP) on a bounded sample of the
     same workload: its interaction rate over the sampled sinks' evaluation
     (tree build and moments excluded), plus the relative RMS error of each GPU
@@ -286,7 +307,10 @@ def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err):
     gof = ot.group_of()
     G = ot.counts()["n_groups"]
     groups = W.sample_indices(G, n_groups_sample, 77)
-    ot.build_lists(w.theta, direct_max, groups=groups)
+    if err_tol is None:
+        ot.build_lists(w.theta, direct_max, groups=groups)
+    else:
+        ot.build_lists_err(w.mass, err_tol, w.p, direct_max, groups=groups)
     po, pl, mo, ml = ot.lists()
     cells = np.unique(np.concatenate([ml[mo[g]:mo[g + 1]] for g in groups]))
     ot.compute_moments(w.pos, w.mass, w.p, cells=cells)

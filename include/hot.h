@@ -139,6 +139,26 @@ int compute_moments(hot_ctx* ctx, hot_tree* tree, const double* pos, const doubl
 int build_interaction_lists(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
 
 /*
+ * build_interaction_lists_err -- the same walk with an absolute-error
+ * acceptance test that also picks the expansion order of each interaction
+ * (Multipole Error Bounds section: an error-based MAC that chooses the
+ * cheapest order meeting a given accuracy). For cell c and group g, with
+ * d = |centre_g - centre_c| - b_g, b = b_c, t = b / d and M = count_c times the
+ * largest particle mass, the field error of the order-q expansion at any sink
+ * of g is bounded (unsoftened) by
+ *   E_q = M / (d - b)^2 * ((q + 2) - (q + 1) t) * t^(q + 1);
+ * c is accepted at the smallest q in [0, p_max] with E_q <= err_tol (FP64, no
+ * fused multiply-add, d > b required), otherwise opened (P2P if a leaf).
+ * Accepted cells with at most direct_max particles go to the P2P list. The
+ * M2P entries carry their order (tree_get_m2p_orders); evaluation and adjoint
+ * need moments of order >= p_max.
+ * mass: N (device; only its maximum is used). err_tol: finite, > 0 (an
+ * acceleration). p_max: 0 .. 8. direct_max: >= 0. Synchronises the stream.
+ */
+int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass, double err_tol,
+                                int p_max, int direct_max);
+
+/*
  * eval_forces -- accelerations (and optionally potentials) of all particles:
  *   a_i = sum over P2P cells, j != i:  m_j (x_j - x_i) (|x_j - x_i|^2 + eps^2)^(-3/2)
  *       + sum over M2P cells c:  -sum_{|alpha|<=p} (-1)^|alpha|/alpha! M_alpha
@@ -192,6 +212,11 @@ int tree_get_groups(hot_ctx* ctx, hot_tree* tree, int32_t* groups);
  * m2p_off, m2p (cell ids); any may be NULL. */
 int tree_get_lists(hot_ctx* ctx, hot_tree* tree, int64_t* p2p_off, int32_t* p2p,
                    int64_t* m2p_off, int32_t* m2p);
+
+/* Expansion order of every M2P entry (host out, n_m2p int8, list order);
+ * HOT_E_STATE unless the lists came from build_interaction_lists_err. */
+int tree_get_m2p_orders(hot_ctx* ctx, hot_tree* tree, int8_t* orders);
+
 /* HOST: FP64 moments [n_cells x (p+1)(p+2)(p+3)/6], slot order by order n,
  * then x exponent descending, then y exponent descending. */
 int tree_get_moments(hot_ctx* ctx, hot_tree* tree, double* out);

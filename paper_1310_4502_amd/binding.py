@@ -26,7 +26,7 @@ EXPORTS = ["hot_ctx_create", "hot_ctx_destroy", "hot_last_error", "hot_sync", "t
            "tree_destroy", "compute_moments", "build_interaction_lists", "eval_forces",
            "eval_forces_adjoint", "tree_get_counts", "tree_get_root", "tree_get_keys",
            "tree_get_cells", "tree_get_groups", "tree_get_lists", "tree_get_moments",
-           "tree_lookup"]
+           "tree_lookup", "build_interaction_lists_err", "tree_get_m2p_orders"]
 
 
 class HotError(RuntimeError):
@@ -76,6 +76,8 @@ def load(path: Optional[str] = None):
     L.tree_destroy.argtypes = [vp, vp]
     L.compute_moments.argtypes = [vp, vp, vp, vp, i32]
     L.build_interaction_lists.argtypes = [vp, vp, dbl, i32]
+    L.build_interaction_lists_err.argtypes = [vp, vp, vp, dbl, i32, i32]
+    L.tree_get_m2p_orders.argtypes = [vp, vp, vp]
     L.eval_forces.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     L.eval_forces_adjoint.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, vp]
     L.tree_get_counts.argtypes = [vp, vp, vp]
@@ -217,6 +219,19 @@ class Tree:
     def build_interaction_lists(self, theta, direct_max=0):
         self.ctx.check(load().build_interaction_lists(self.ctx.h, self.h, float(theta),
                                                       int(direct_max)))
+
+    def build_interaction_lists_err(self, mass, err_tol, p_max, direct_max=0):
+        """Error-bound lists: each M2P entry gets the lowest order <= p_max
+        whose field-error bound is at most err_tol (an acceleration)."""
+        mass = _as_vec(mass, self.n)
+        self.ctx.check(load().build_interaction_lists_err(self.ctx.h, self.h, _dev(mass),
+                                                          float(err_tol), int(p_max),
+                                                          int(direct_max)))
+
+    def m2p_orders(self):
+        out = np.empty(max(self.counts()["n_m2p"], 0), np.int8)
+        self.ctx.check(load().tree_get_m2p_orders(self.ctx.h, self.h, _np(out)))
+        return out
 
     def eval_forces(self, pos, mass, eps, precision=HOT_MIXED, with_pot=False, stats=False,
                     out=None):

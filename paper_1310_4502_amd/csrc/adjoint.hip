@@ -17,6 +17,7 @@
 // Every reduction is a gather in a fixed order: no floating-point atomics.
 #include "common.h"
 #include "eval_common.h"
+#include "expansion_q.h"
 #include "generated/expansions.h"
 
 namespace hot {
@@ -111,8 +112,11 @@ __global__ __launch_bounds__(kB) void k_srec_fill(
   }
 }
 
+// key: the cell, followed by the entry's order in 4 low bits when the lists
+// carry orders (m2p_q not null)
 __global__ __launch_bounds__(kB) void k_mrec_fill(const int64_t* __restrict__ m2p_off,
-                                                  const int32_t* __restrict__ m2p, int64_t G,
+                                                  const int32_t* __restrict__ m2p,
+                                                  const int8_t* __restrict__ m2p_q, int64_t G,
                                                   uint64_t* __restrict__ key,
                                                   uint32_t* __restrict__ val) {
   const int lane = threadIdx.x & 63;
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(kB) void k_mrec_fill(const int64_t* __restrict__ m2
   if (g >= G) return;
   const int64_t e1 = m2p_off[g + 1];
   for (int64_t e = m2p_off[g] + lane; e < e1; e += 64) {
-    key[e] = (uint64_t)m2p[e];
+    key[e] = m2p_q ? (((uint64_t)m2p[e] << 4) | (uint64_t)m2p_q[e]) : (uint64_t)m2p[e];
     val[e] = (uint32_t)g;
   }
 }
@@ -271,10 +275,12 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
 }
 
 // ------------------------------------------------- expansion terms, sink side
-template <int P, typename T>
+// MIXQ: per-entry orders (error-bound lists)
+template <int P, typename T, bool MIXQ>
 __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
-    const int32_t* __restrict__ m2p, const int8_t* __restrict__ c_level,
+    const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_q,
+    const int8_t* __restrict__ c_level,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
     const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, const T* __restrict__ momw,
@@ -309,10 +315,11 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
   const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
   T* slot = smom + (Stage::kLds ? w * Stage::kStride : 0);
   typename Stage::Regs pre;
-  int cn = 0, ln = 0;
+  int cn = 0, ln = 0, qn = P;
   double nx = 0, ny = 0, nz = 0;
   if (e0 < e1) {
     cn = uniform_i32(m2p[e0]);
+    if (MIXQ) qn = uniform_i32(m2p_q[e0]);
     Stage::prefetch(pre, momw, cn, lane);
     ln = c_level[cn];
     nx = c_centre[3 * cn];
@@ -321,6 +328,7 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
   }
   for (int64_t e = e0; e < e1; ++e) {
     const int c = cn;
+    const int q = qn;
     const double inv_s = ldexp(inv_side, ln);
     const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
     const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
@@ -328,6 +336,7 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     const T* M = Stage::commit(pre, momw, c, slot, lane);
     if (e + 1 < e1) {
       cn = uniform_i32(m2p[e + 1]);
+      if (MIXQ) qn = uniform_i32(m2p_q[e + 1]);
       Stage::prefetch(pre, momw, cn, lane);
       ln = c_level[cn];
       nx = c_centre[3 * cn];
@@ -336,7 +345,10 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     }
     const double es = eps * inv_s;
     T gx = 0, gy = 0, gz = 0;
-    expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
+    if (MIXQ)
+      expansion_sink_adj_q<P, T>(q, X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
+    else
+      expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
     const T sc = (T)(-(inv_s * inv_s * inv_s));
     kahan_add(sx, cx, gx * sc);
     kahan_add(sy, cy, gy * sc);
@@ -449,10 +461,12 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
 // M2P lists hold the cell); lanes are the sinks of each group in turn. Each
 // lane accumulates sum_k abar_k d^(alpha+e_k) G for all alpha in registers; the
 // item's partial sums are reduced across lanes with a fixed butterfly.
-template <int P, typename T>
+// MIXQ: records carry the order of their entry in the low 4 bits of the key.
+template <int P, typename T, bool MIXQ>
 __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     int64_t n_citems, const uint32_t* __restrict__ citem_rec, const int32_t* __restrict__ citem_cell,
-    const uint32_t* __restrict__ crec_off, const uint32_t* __restrict__ mval,
+    const uint32_t* __restrict__ crec_off, const uint64_t* __restrict__ mkey,
+    const uint32_t* __restrict__ mval,
     const int8_t* __restrict__ c_level, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
     const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
@@ -475,8 +489,9 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
   // one loop over the (group, chunk of 64 sinks) pairs of the item, with the
   // next pair's data prefetched; a single back edge keeps the row registers in
   // place across iterations
-  auto group_centre = [&](uint32_t r, int& gf, int& ge, T& dx, T& dy, T& dz) {
+  auto group_centre = [&](uint32_t r, int& gf, int& ge, T& dx, T& dy, T& dz, int& q) {
     const int g = uniform_i32((int)mval[r]);
+    q = MIXQ ? uniform_i32((int)(mkey[r] & 15u)) : P;
     const int gc = uniform_i32(g_cell[g]);
     dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
     dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
@@ -485,19 +500,20 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     ge = gf + uniform_i32(g_count[g]);
   };
   uint32_t r = r0;
-  int s0 = 0, ge = 0;
+  int s0 = 0, ge = 0, q = P, qn = P;
   T Dx = T(0), Dy = T(0), Dz = T(0);
   V4<T> pme, pab;
   pme.x = pme.y = pme.z = pme.w = T(0);
   pab = pme;
   if (r < r1) {
-    group_centre(r, s0, ge, Dx, Dy, Dz);
+    group_centre(r, s0, ge, Dx, Dy, Dz, qn);
     if (s0 + lane < ge) {
       pme = off[s0 + lane];
       pab = ab4[s0 + lane];
     }
   }
   while (r < r1) {
+    q = qn;
     T X = T(1), Y = T(0), Z = T(0), bx = T(0), by = T(0), bz = T(0);
     if (s0 + lane < ge) {
       X = Dx + pme.x * (T)inv_s;
@@ -510,13 +526,16 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     s0 += 64;
     if (s0 >= ge) {
       ++r;
-      if (r < r1) group_centre(r, s0, ge, Dx, Dy, Dz);
+      if (r < r1) group_centre(r, s0, ge, Dx, Dy, Dz, qn);
     }
     if (r < r1 && s0 + lane < ge) {
       pme = off[s0 + lane];
       pab = ab4[s0 + lane];
     }
-    expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
+    if (MIXQ)
+      expansion_cell_adj_q<P, T>(q, X, Y, Z, e2, bx, by, bz, row);
+    else
+      expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
   }
   T* o = part + it * (int64_t)nm_pad(P);
 #pragma unroll
@@ -701,12 +720,14 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     t->mrec_val.alloc(ctx, std::max<int64_t>(1, E) * sizeof(uint32_t));
     t->mcell_rec.alloc(ctx, (C + 1) * sizeof(uint32_t));
     t->mcell_item.alloc(ctx, (C + 1) * sizeof(uint32_t));
-    k_mrec_fill<<<grid_for(G, kWPB), kB, 0, st>>>(t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(), G,
-                                                t->mrec_key.as<uint64_t>(),
-                                                t->mrec_val.as<uint32_t>());
+    const int qsh = t->list_p >= 0 ? 4 : 0;  // order bits below the cell id
+    k_mrec_fill<<<grid_for(G, kWPB), kB, 0, st>>>(
+        t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
+        t->list_p >= 0 ? t->m2p_q.as<int8_t>() : nullptr, G, t->mrec_key.as<uint64_t>(),
+        t->mrec_val.as<uint32_t>());
     HOT_CHECK_LAUNCH();
-    radix_sort(ctx, t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(), E, bits_for(C));
-    k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, 0, C,
+    radix_sort(ctx, t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(), E, bits_for(C) + qsh);
+    k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, qsh, C,
                                                       t->mcell_rec.as<uint32_t>());
     HOT_CHECK_LAUNCH();
     k_items_from_off<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
@@ -735,21 +756,36 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
                           const T* momw, double eps, T* sink_state, double* mbar64) {
   hipStream_t st = ctx->stream;
   const double inv_side = 1.0 / t->side;
-  k_m2p_sink_adj<P, T><<<grid_for(t->n_items, kWPB), kB, 0, st>>>(
-      t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
-      t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
-      t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state);
-  HOT_CHECK_LAUNCH();
+  const bool mixq = t->list_p >= 0;
+  auto sink = [&](auto kern) {
+    kern<<<grid_for(t->n_items, kWPB), kB, 0, st>>>(
+        t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
+        t->m2p_q.as<int8_t>(), t->c_level.as<int8_t>(), t->g_first.as<int32_t>(),
+        t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab,
+        momw, inv_side, eps, sink_state);
+    HOT_CHECK_LAUNCH();
+  };
+  if (mixq)
+    sink(k_m2p_sink_adj<P, T, true>);
+  else
+    sink(k_m2p_sink_adj<P, T, false>);
   const int64_t C = t->n_cells;
   DBuf part;
   part.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_citems) * nm_pad(P) * sizeof(T));
   if (t->n_citems > 0) {
-    k_m2p_cell_adj<P, T><<<(unsigned)t->n_citems, 64, 0, st>>>(
-        t->n_citems, t->citem_rec.as<uint32_t>(), t->citem_cell.as<int32_t>(),
-        t->mcell_rec.as<uint32_t>(), t->mrec_val.as<uint32_t>(), t->c_level.as<int8_t>(),
-        t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
-        t->c_centre.as<double>(), off, ab, inv_side, eps, part.as<T>());
-    HOT_CHECK_LAUNCH();
+    auto cell = [&](auto kern) {
+      kern<<<(unsigned)t->n_citems, 64, 0, st>>>(
+          t->n_citems, t->citem_rec.as<uint32_t>(), t->citem_cell.as<int32_t>(),
+          t->mcell_rec.as<uint32_t>(), t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(),
+          t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+          t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab, inv_side, eps,
+          part.as<T>());
+      HOT_CHECK_LAUNCH();
+    };
+    if (mixq)
+      cell(k_m2p_cell_adj<P, T, true>);
+    else
+      cell(k_m2p_cell_adj<P, T, false>);
   }
   const int64_t tot = C * nm(P);
   k_mbar_final<T><<<grid_for(tot, kB), kB, 0, st>>>(part.as<T>(), t->mcell_item.as<uint32_t>(), C,

@@ -230,6 +230,23 @@ int build_interaction_lists(hot_ctx* ctx, hot_tree* tree, double theta, int dire
   });
 }
 
+int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass, double err_tol,
+                                int p_max, int direct_max) {
+  return guard(ctx, [&] {
+    need_tree(ctx, tree);
+    if (!mass) hot::invalid("null masses");
+    if (!(err_tol > 0.0) || !std::isfinite(err_tol)) hot::invalid("err_tol must be finite and > 0");
+    if (p_max < 0 || p_max > 8) hot::invalid("p_max must lie in [0, 8]");
+    if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    try {
+      hot::build_lists_err(ctx, tree, mass, err_tol, p_max, direct_max);
+    } catch (...) {
+      tree->has_lists = false;
+      throw;
+    }
+  });
+}
+
 int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass, double eps,
                 int precision, double* acc, double* pot, hot_stats* stats) {
   return guard(ctx, [&] {
@@ -239,6 +256,7 @@ int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* m
     if (precision != HOT_MIXED && precision != HOT_FP64) hot::invalid("unknown precision");
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
+    if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
     hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats);
   });
 }
@@ -253,6 +271,7 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     if (precision != HOT_MIXED && precision != HOT_FP64) hot::invalid("unknown precision");
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
+    if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
     hot::adjoint(ctx, tree, pos, mass, eps, precision, acc_bar, pos_bar, mass_bar);
   });
 }
@@ -342,6 +361,16 @@ int tree_get_lists(hot_ctx* ctx, hot_tree* t, int64_t* p2p_off, int32_t* p2p, in
     d2h<int64_t>(ctx, m2p_off, t->m2p_off.p, t->n_groups + 1);
     d2h<int32_t>(ctx, p2p, t->p2p.p, t->n_p2p);
     d2h<int32_t>(ctx, m2p, t->m2p.p, t->n_m2p);
+    HOT_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tree_get_m2p_orders(hot_ctx* ctx, hot_tree* t, int8_t* orders) {
+  return guard(ctx, [&] {
+    need_tree(ctx, t);
+    if (!t->has_lists || t->list_p < 0) hot::state("no error-bound lists");
+    if (!orders) hot::invalid("null output");
+    d2h<int8_t>(ctx, orders, t->m2p_q.p, t->n_m2p);
     HOT_HIP(hipStreamSynchronize(ctx->stream));
   });
 }

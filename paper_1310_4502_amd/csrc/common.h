@@ -136,6 +136,10 @@ struct hot_tree {
   int direct_max = 0;
   int64_t n_p2p = 0, n_m2p = 0;
   hot::DBuf p2p_off, p2p, m2p_off, m2p;
+  // error-bound lists: expansion order (int8) of every M2P entry and the
+  // highest order allowed; list_p = -1 for theta lists (every entry at p)
+  hot::DBuf m2p_q;
+  int list_p = -1;
   // eval work items: (group, first sink) per wave
   int64_t n_items = 0;
   hot::DBuf items;
@@ -171,6 +175,8 @@ void gather_sorted(hot_ctx* ctx, const hot_tree* t, const double* pos, const dou
 void build_moments(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, int p);
 void weighted_fp64(hot_ctx* ctx, hot_tree* t);
 void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
+void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
+                     int direct_max);
 void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
             int precision, double* acc, double* pot, hot_stats* stats);
 void adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,

@@ -20,6 +20,7 @@
 // M_alpha / s^|alpha| are all O(1), and the result is rescaled by s^-2.
 #include "common.h"
 #include "eval_common.h"
+#include "expansion_q.h"
 #include "generated/expansions.h"
 
 namespace hot {
@@ -128,11 +129,13 @@ __global__ __launch_bounds__(kB) void k_p2p(
 template <int P, typename T>
 constexpr int m2p_waves_per_simd() { return (sizeof(T) == 4 && P >= 7) ? 4 : 1; }
 
-template <int P, typename T, bool POT>
+// MIXQ: every entry carries its own order q <= P (m2p_q), error-bound lists.
+template <int P, typename T, bool POT, bool MIXQ>
 __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(m2p_waves_per_simd<P, T>())))
 void k_m2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
-    const int32_t* __restrict__ m2p, const int8_t* __restrict__ c_level,
+    const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_q,
+    const int8_t* __restrict__ c_level,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
     const V4<T>* __restrict__ off, const T* __restrict__ momw, double inv_side, double eps,
@@ -167,10 +170,11 @@ void k_m2p(
   const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
   T* slot = smom + (Stage::kLds ? w * Stage::kStride : 0);
   typename Stage::Regs pre;
-  int cn = 0, ln = 0;
+  int cn = 0, ln = 0, qn = P;
   double nx = 0, ny = 0, nz = 0;
   if (e0 < e1) {
     cn = uniform_i32(m2p[e0]);
+    if (MIXQ) qn = uniform_i32(m2p_q[e0]);
     Stage::prefetch(pre, momw, cn, lane);
     ln = c_level[cn];
     nx = c_centre[3 * cn];
@@ -179,6 +183,7 @@ void k_m2p(
   }
   for (int64_t e = e0; e < e1; ++e) {
     const int c = cn;
+    const int q = qn;
     const double inv_s = ldexp(inv_side, ln);
     const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
     const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
@@ -186,6 +191,7 @@ void k_m2p(
     const T* M = Stage::commit(pre, momw, c, slot, lane);
     if (e + 1 < e1) {
       cn = uniform_i32(m2p[e + 1]);
+      if (MIXQ) qn = uniform_i32(m2p_q[e + 1]);
       Stage::prefetch(pre, momw, cn, lane);
       ln = c_level[cn];
       nx = c_centre[3 * cn];
@@ -195,7 +201,10 @@ void k_m2p(
     const double es = eps * inv_s;
     const T e2 = (T)(es * es);
     T ax = 0, ay = 0, az = 0, ph = 0;
-    expansion_fwd<P, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph);
+    if (MIXQ)
+      expansion_fwd_q<P, T, POT>(q, X, Y, Z, e2, M, ax, ay, az, ph);
+    else
+      expansion_fwd<P, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph);
     const T sa = (T)(-(inv_s * inv_s));
     kahan_add(sx, cx, ax * sa);
     kahan_add(sy, cy, ay * sa);
@@ -251,11 +260,18 @@ template <int P, typename T, bool POT>
 void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, double eps,
                   T* state) {
   const unsigned grid = grid_for(t->n_items, kWavesPerBlock);
-  k_m2p<P, T, POT><<<grid, kB, 0, ctx->stream>>>(
-      t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
-      t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
-      t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, momw, 1.0 / t->side, eps, state);
-  HOT_CHECK_LAUNCH();
+  auto go = [&](auto kern) {
+    kern<<<grid, kB, 0, ctx->stream>>>(
+        t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
+        t->m2p_q.as<int8_t>(), t->c_level.as<int8_t>(), t->g_first.as<int32_t>(),
+        t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, momw,
+        1.0 / t->side, eps, state);
+    HOT_CHECK_LAUNCH();
+  };
+  if (t->list_p >= 0)
+    go(k_m2p<P, T, POT, true>);
+  else
+    go(k_m2p<P, T, POT, false>);
 }
 
 template <typename T, bool POT>

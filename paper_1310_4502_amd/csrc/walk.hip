@@ -11,6 +11,15 @@
 // LDS stack and the opened cell's children become the next run. The output is
 // therefore exactly the depth-first preorder. The kernel runs twice: once to
 // count, once to fill at offsets from a scan of the counts.
+//
+// Two acceptance tests: the theta criterion, and an absolute-error test that
+// also picks the expansion order of each accepted cell (Multipole Error
+// Bounds section: the cheapest order meeting the accuracy). The error test
+// bounds the field of the truncated order-q cell-body expansion of 1/r by
+// the tail sum over n > q of (n + 1) b^n / d^(n + 2):
+//   E_q = M / (d - b)^2 * ((q + 2) - (q + 1) t) * t^(q + 1),  t = b / d,
+// with d the distance from the cell centre to the group's bounding sphere,
+// b the cell's b_max and M its particle count times the largest mass.
 #include "common.h"
 
 namespace hot {
@@ -22,12 +31,38 @@ constexpr int kStack = kMaxLevel + 4;
 
 enum { CLS_NONE = 0, CLS_P2P = 1, CLS_M2P = 2, CLS_OPEN = 3 };
 
-template <bool FILL>
+// Parameters of the error-bound test (unused by the theta walk).
+struct ErrMac {
+  double tol;
+  const double* mmax;  // device scalar: the largest particle mass
+  int pmax;
+  int8_t* m2p_q;       // fill pass: order of every M2P entry
+};
+
+// Order accepted for cell c (-1: not acceptable). FP64, no FMA; the same
+// operations in the same order as the oracle's test.
+__device__ __forceinline__ int accept_order(double dx, double dy, double dz, double gb, double b,
+                                            int count, double mmax, double tol, int pmax) {
+  const double d = sqrt((dx * dx + dy * dy) + dz * dz) - gb;
+  if (!(d > b)) return -1;
+  const double t = b / d;
+  const double h = d - b;
+  const double A = ((double)count * mmax) / (h * h);
+  double tp = t;
+  for (int q = 0; q <= pmax; ++q) {
+    const double E = (A * ((double)(q + 2) - (double)(q + 1) * t)) * tp;
+    if (E <= tol) return q;
+    tp = tp * t;
+  }
+  return -1;
+}
+
+template <bool FILL, bool ERR>
 __global__ __launch_bounds__(kB) void k_walk(
     const int32_t* __restrict__ g_cell, int64_t G, const double* __restrict__ c_centre,
     const double* __restrict__ c_bmax, const int32_t* __restrict__ c_count,
     const uint8_t* __restrict__ c_leaf, const int32_t* __restrict__ c_child,
-    const int32_t* __restrict__ c_nchild, double theta, int direct_max,
+    const int32_t* __restrict__ c_nchild, double theta, ErrMac em, int direct_max,
     int64_t* __restrict__ cnt_p2p, int64_t* __restrict__ cnt_m2p, int64_t* __restrict__ pairs_p2p,
     const int64_t* __restrict__ off_p2p, const int64_t* __restrict__ off_m2p,
     int32_t* __restrict__ p2p, int32_t* __restrict__ m2p, int64_t C, unsigned* __restrict__ flags) {
@@ -38,6 +73,7 @@ __global__ __launch_bounds__(kB) void k_walk(
   const int gc = g_cell[g];
   const double gx = c_centre[3 * gc], gy = c_centre[3 * gc + 1], gz = c_centre[3 * gc + 2];
   const double gb = c_bmax[gc];
+  const double mmax = ERR ? *em.mmax : 0.0;
   const uint64_t lt = lanemask_lt();
   int64_t np = 0, nmm = 0, npairs = 0;
   int64_t bp = 0, bm = 0;
@@ -58,13 +94,21 @@ __global__ __launch_bounds__(kB) void k_walk(
     const int c = lo + lane;
     int cls = CLS_NONE;
     int cnt = 0;
+    int q = -1;
     if (c < hi) {
       const double dx = gx - c_centre[3 * c], dy = gy - c_centre[3 * c + 1],
                    dz = gz - c_centre[3 * c + 2];
-      const double d2 = (dx * dx + dy * dy) + dz * dz;
-      const double rr = c_bmax[c] / theta + gb;
       cnt = c_count[c];
-      if (d2 > rr * rr)
+      bool acc;
+      if (ERR) {
+        q = accept_order(dx, dy, dz, gb, c_bmax[c], cnt, mmax, em.tol, em.pmax);
+        acc = q >= 0;
+      } else {
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        const double rr = c_bmax[c] / theta + gb;
+        acc = d2 > rr * rr;
+      }
+      if (acc)
         cls = cnt <= direct_max ? CLS_P2P : CLS_M2P;
       else
         cls = c_leaf[c] ? CLS_P2P : CLS_OPEN;
@@ -76,7 +120,10 @@ __global__ __launch_bounds__(kB) void k_walk(
     const uint64_t mm = __ballot(cls == CLS_M2P) & before;
     if (FILL) {
       if ((pm >> lane) & 1ull) p2p[bp + np + __popcll(pm & lt)] = c;
-      if ((mm >> lane) & 1ull) m2p[bm + nmm + __popcll(mm & lt)] = c;
+      if ((mm >> lane) & 1ull) {
+        m2p[bm + nmm + __popcll(mm & lt)] = c;
+        if (ERR) em.m2p_q[bm + nmm + __popcll(mm & lt)] = (int8_t)q;
+      }
     } else {
       if ((pm >> lane) & 1ull) npairs += cnt;
     }
@@ -120,13 +167,37 @@ __global__ void k_pair_weights(const int32_t* __restrict__ g_count, int64_t G,
   mp[g] *= g_count[g];
 }
 
+// largest particle mass (the bit patterns of non-negative doubles order as
+// their values); flags non-finite or negative masses
+__global__ void k_mass_max(const double* __restrict__ mass, int64_t n,
+                           unsigned long long* __restrict__ out, unsigned* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double m = 0.0;
+  if (i < n) {
+    m = mass[i];
+    if (!(isfinite(m) && m >= 0.0)) {
+      atomicOr(flags, FLAG_BAD_MASS);
+      m = 0.0;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
 }  // namespace
 
-void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+namespace {
+
+template <bool ERR>
+void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_max) {
   hipStream_t st = ctx->stream;
   const int64_t G = t->n_groups;
   t->has_lists = false;
   t->has_transpose = false;
+  t->list_p = -1;
   t->p2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
   t->m2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
   DBuf pairs, mcount, totals;
@@ -134,10 +205,10 @@ void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
   mcount.alloc(ctx, (G + 1) * sizeof(int64_t));
   totals.alloc(ctx, 4 * sizeof(int64_t));
   const unsigned grid = grid_for(G, kWavesPerBlock);
-  k_walk<false><<<grid, kB, 0, st>>>(
+  k_walk<false, ERR><<<grid, kB, 0, st>>>(
       t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
-      t->c_nchild.as<int32_t>(), theta, direct_max, t->p2p_off.as<int64_t>(),
+      t->c_nchild.as<int32_t>(), theta, em, direct_max, t->p2p_off.as<int64_t>(),
       t->m2p_off.as<int64_t>(), pairs.as<int64_t>(), nullptr, nullptr, nullptr, nullptr,
       t->n_cells, ctx->d_flags);
   HOT_CHECK_LAUNCH();
@@ -159,22 +230,50 @@ void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
   HOT_HIP(hipMemcpyAsync(&h[2], tot + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipStreamSynchronize(st));
   if (flags & FLAG_INTERNAL) throw Error{HOT_E_DEVICE, "walk consistency check failed"};
+  if (ERR && (flags & FLAG_BAD_MASS)) throw Error{HOT_E_INVALID, "non-finite or negative mass"};
   t->n_p2p = h[0];
   t->n_m2p = h[1];
   t->p2p_pairs = h[2];
   t->m2p_pairs = h[3];
   t->p2p.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_p2p) * sizeof(int32_t));
   t->m2p.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_m2p) * sizeof(int32_t));
-  k_walk<true><<<grid, kB, 0, st>>>(
+  if (ERR) {
+    t->m2p_q.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_m2p) * sizeof(int8_t));
+    em.m2p_q = t->m2p_q.as<int8_t>();
+  } else {
+    t->m2p_q.release();
+  }
+  k_walk<true, ERR><<<grid, kB, 0, st>>>(
       t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
-      t->c_nchild.as<int32_t>(), theta, direct_max, nullptr, nullptr, nullptr,
+      t->c_nchild.as<int32_t>(), theta, em, direct_max, nullptr, nullptr, nullptr,
       t->p2p_off.as<int64_t>(), t->m2p_off.as<int64_t>(), t->p2p.as<int32_t>(),
       t->m2p.as<int32_t>(), t->n_cells, ctx->d_flags);
   HOT_CHECK_LAUNCH();
   t->theta = theta;
   t->direct_max = direct_max;
+  t->list_p = ERR ? em.pmax : -1;
   t->has_lists = true;
+}
+
+}  // namespace
+
+void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+  ErrMac em{0.0, nullptr, 0, nullptr};
+  walk_lists<false>(ctx, t, theta, em, direct_max);
+}
+
+void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
+                     int direct_max) {
+  DBuf mm;
+  mm.alloc(ctx, sizeof(unsigned long long));
+  k_zero_u64<<<1, 1, 0, ctx->stream>>>(mm.as<unsigned long long>());
+  HOT_CHECK_LAUNCH();
+  k_mass_max<<<grid_for(t->n, kB), kB, 0, ctx->stream>>>(mass, t->n, mm.as<unsigned long long>(),
+                                                         ctx->d_flags);
+  HOT_CHECK_LAUNCH();
+  ErrMac em{tol, mm.as<double>(), p_max, nullptr};
+  walk_lists<true>(ctx, t, 0.0, em, direct_max);
 }
 
 }  // namespace hot

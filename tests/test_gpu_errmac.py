@@ -1,0 +1,139 @@
+"""GPU error-bound lists (absolute-error acceptance with a per-interaction
+expansion order) against the oracle: lists and orders bit-exact, forces and
+adjoint against the oracle's evaluation and VJP on the same lists, the
+adjoint against finite differences, and the state checks of the entry point."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1310_4502_amd import workloads as W
+from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
+from gpu_util import assert_lists_equal, rel_rms, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+CASES = [
+    # name, n, tol, p_max, direct_max, n_leaf, n_group
+    ("uniform4k", None, 1e-3, 4, 0, 16, 64),
+    ("plummer1m", 20000, 1e-4, 8, 16, 16, 64),
+    ("clustered4m", 20000, 3e-5, 6, 0, 8, 32),
+    ("clustered4m", 30000, 1e-3, 8, 32, 16, 96),
+]
+
+
+def _both(name, n, tol, p_max, dmax, n_leaf, n_group):
+    w = W.make(name, n=n)
+    pos, mass = to_dev(w)
+    gt = Tree(pos, n_leaf, n_group, w.box)
+    ot = oracle.Tree(w.pos, n_leaf, n_group, w.box)
+    gt.build_interaction_lists_err(mass, tol, p_max, dmax)
+    ot.build_lists_err(w.mass, tol, p_max, dmax)
+    return w, gt, ot, pos, mass
+
+
+@pytest.mark.parametrize("name,n,tol,p_max,dmax,n_leaf,n_group", CASES)
+def test_lists_orders_forces_bit_exact_and_close(name, n, tol, p_max, dmax, n_leaf, n_group):
+    w, gt, ot, pos, mass = _both(name, n, tol, p_max, dmax, n_leaf, n_group)
+    assert_lists_equal(gt, ot)
+    gq, oq = gt.m2p_orders(), ot.m2p_orders()
+    assert np.array_equal(gq, oq), "orders differ"
+    _log(name, w.n, "orders", np.bincount(gq, minlength=p_max + 1))
+    assert np.unique(gq).size >= 2
+    gt.compute_moments(pos, mass, p_max)
+    ot.compute_moments(w.pos, w.mass, p_max)
+    oa, _, _ = ot.eval(w.pos, w.mass, w.eps, with_pot=False)
+    g64, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_FP64)
+    g32, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    e64 = rel_rms(g64.cpu().numpy(), oa)
+    e32 = rel_rms(g32.cpu().numpy(), oa)
+    _log("fp64", e64, "mixed", e32)
+    assert e64 <= 1e-12 and e32 <= 1e-5
+    # the accuracy the bound promises: against direct summation on sampled
+    # sinks, no sink is off by more than tol times its number of M2P entries
+    # plus the pair kernel's rounding (softened fields: the unsoftened bound
+    # is used as an estimate)
+    sinks = W.sample_indices(w.n, 512, 9)
+    ad, _ = oracle.direct(w.pos, w.mass, w.eps, sinks=sinks)
+    po, pl, mo, ml = ot.lists()
+    nm2p = np.diff(mo)[ot.group_of()[np.argsort(ot.keys()[1])][sinks]]
+    err = np.linalg.norm(g64.cpu().numpy()[sinks] - ad, axis=1)
+    assert np.all(err <= tol * nm2p + 1e-9 * np.linalg.norm(ad, axis=1))
+
+
+@pytest.mark.parametrize("name,n,tol,p_max,dmax,n_leaf,n_group", CASES[1:3])
+def test_adjoint_vs_oracle_vjp(name, n, tol, p_max, dmax, n_leaf, n_group):
+    w, gt, ot, pos, mass = _both(name, n, tol, p_max, dmax, n_leaf, n_group)
+    gt.compute_moments(pos, mass, p_max)
+    ot.compute_moments(w.pos, w.mass, p_max)
+    abar_np = W.cotangent(w.n, 404)
+    ox, om = ot.vjp(w.pos, w.mass, w.eps, abar_np)
+    abar = torch.from_numpy(abar_np).cuda()
+    gx64, gm64 = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64, with_mass=True)
+    gx, gm = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED, with_mass=True)
+    e64, m64 = rel_rms(gx64.cpu().numpy(), ox), rel_rms(gm64.cpu().numpy(), om)
+    e32, m32 = rel_rms(gx.cpu().numpy(), ox), rel_rms(gm.cpu().numpy(), om)
+    _log("adjoint fp64", e64, m64, "mixed", e32, m32)
+    assert e64 <= 1e-11 and m64 <= 1e-11
+    assert e32 <= 1e-5 and m32 <= 1e-5
+    gx2, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED)
+    assert torch.equal(gx, gx2)
+
+
+def test_adjoint_directional_fd():
+    w, gt, ot, pos, mass = _both("clustered4m", 20000, 1e-4, 6, 0, 16, 64)
+    eps = 1e-3
+    gt.compute_moments(pos, mass, 6)
+    abar = torch.from_numpy(W.cotangent(w.n, 7)).cuda()
+    v = torch.from_numpy(np.random.default_rng(8).normal(size=(w.n, 3))).cuda()
+    xbar, _ = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_FP64)
+
+    def L(x):
+        gt.compute_moments(x, mass, 6)
+        a, _, _ = gt.eval_forces(x, mass, eps, HOT_FP64)
+        return float((a * abar).sum())
+
+    def cd(h):
+        return (L(pos + h * v) - L(pos - h * v)) / (2 * h)
+
+    h = 1e-6
+    fd = (4 * cd(h) - cd(2 * h)) / 3
+    an = float((xbar * v).sum())
+    _log("directional", an, fd)
+    assert abs(an - fd) <= 1e-6 * abs(fd)
+
+
+def test_state_and_argument_errors():
+    w = W.make("uniform4k")
+    pos, mass = to_dev(w)
+    t = Tree(pos, 16, 64, w.box)
+    t.build_interaction_lists(0.5, 0)
+    with pytest.raises(HotError):
+        t.m2p_orders()  # theta lists carry no orders
+    for tol, pm in ((0.0, 4), (float("nan"), 4), (1e-3, 9), (1e-3, -1)):
+        with pytest.raises(HotError):
+            t.build_interaction_lists_err(mass, tol, pm, 0)
+    t.build_interaction_lists_err(mass, 1e-3, 6, 0)
+    t.compute_moments(pos, mass, 4)
+    with pytest.raises(HotError):
+        t.eval_forces(pos, mass, w.eps, HOT_MIXED)  # moments below the lists' order
+    t.compute_moments(pos, mass, 6)
+    a, _, _ = t.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    # switching back to theta lists drops the orders
+    t.build_interaction_lists(0.5, 0)
+    with pytest.raises(HotError):
+        t.m2p_orders()
+    bad = mass.clone()
+    bad[5] = -1.0
+    with pytest.raises(HotError):
+        t.build_interaction_lists_err(bad, 1e-3, 4, 0)
+    with pytest.raises(HotError):
+        t.ctx.sync()  # the flag is also reported by the next synchronising call
+    t.ctx.sync()  # flags cleared
