@@ -165,6 +165,58 @@ __global__ void k_cell_items(const uint32_t* __restrict__ rec_off, const uint32_
   }
 }
 
+// Lists with per-entry orders: the records of a cell are sorted by order
+// (key = cell << 4 | q); items are runs of at most kCellItemGroups records of
+// one order. Per cell, the end of the order-q records is the first key above
+// (cell << 4 | q), found by binary search within the cell's range.
+__device__ __forceinline__ uint32_t order_end(const uint64_t* __restrict__ key, uint32_t lo,
+                                              uint32_t hi, uint64_t k) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_cq_count(const uint64_t* __restrict__ key, const uint32_t* __restrict__ rec_off,
+                           int64_t C, uint32_t* __restrict__ nit) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const uint32_t hi = rec_off[c + 1];
+  uint32_t b = rec_off[c], n = 0;
+  for (int q = 0; q <= kMaxP; ++q) {
+    const uint32_t e = order_end(key, b, hi, ((uint64_t)c << 4) | (uint64_t)(q + 1));
+    n += (e - b + kCellItemGroups - 1) / kCellItemGroups;
+    b = e;
+  }
+  nit[c] = n;
+}
+
+__global__ void k_cq_items(const uint64_t* __restrict__ key, const uint32_t* __restrict__ rec_off,
+                           const uint32_t* __restrict__ it_off, int64_t C,
+                           uint32_t* __restrict__ citem_rec, uint32_t* __restrict__ citem_end,
+                           int32_t* __restrict__ citem_cell, uint64_t* __restrict__ qkey,
+                           uint32_t* __restrict__ qval) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const uint32_t hi = rec_off[c + 1];
+  uint32_t b = rec_off[c], k = it_off[c];
+  for (int q = 0; q <= kMaxP; ++q) {
+    const uint32_t e = order_end(key, b, hi, ((uint64_t)c << 4) | (uint64_t)(q + 1));
+    for (uint32_t r = b; r < e; r += kCellItemGroups, ++k) {
+      citem_rec[k] = r;
+      citem_end[k] = r + kCellItemGroups < e ? r + kCellItemGroups : e;
+      citem_cell[k] = (int32_t)c;
+      qkey[k] = (uint64_t)q;
+      qval[k] = k;
+    }
+    b = e;
+  }
+}
+
 // ------------------------------------------------------------------- gathers
 template <typename T>
 __global__ void k_abar(const double* __restrict__ abar, const uint32_t* __restrict__ perm,
@@ -461,11 +513,15 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
 // M2P lists hold the cell); lanes are the sinks of each group in turn. Each
 // lane accumulates sum_k abar_k d^(alpha+e_k) G for all alpha in registers; the
 // item's partial sums are reduced across lanes with a fixed butterfly.
-// MIXQ: records carry the order of their entry in the low 4 bits of the key.
+// P: the expansion order of the item's records. MIXQ (lists with per-entry
+// orders): the block's item is qitems[qbase + block], its records end at
+// citem_end, and the row is written with stride out_stride, zero-filled from
+// nm(P) up to out_nm (the cell's full moment count).
 template <int P, typename T, bool MIXQ>
 __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     int64_t n_citems, const uint32_t* __restrict__ citem_rec, const int32_t* __restrict__ citem_cell,
-    const uint32_t* __restrict__ crec_off, const uint64_t* __restrict__ mkey,
+    const uint32_t* __restrict__ crec_off, const uint32_t* __restrict__ qitems, int64_t qbase,
+    const uint32_t* __restrict__ citem_end, int out_stride, int out_nm,
     const uint32_t* __restrict__ mval,
     const int8_t* __restrict__ c_level, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
@@ -473,12 +529,17 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     const V4<T>* __restrict__ ab4, double inv_side, double eps, T* __restrict__ part) {
   constexpr int NM = nm(P);
   const int lane = threadIdx.x;
-  const int64_t it = blockIdx.x;
-  if (it >= n_citems) return;
+  if ((int64_t)blockIdx.x >= n_citems) return;
+  const int64_t it = MIXQ ? (int64_t)qitems[qbase + blockIdx.x] : (int64_t)blockIdx.x;
   const int c = citem_cell[it];
   const uint32_t r0 = citem_rec[it];
-  const uint32_t rc = crec_off[c + 1];
-  const uint32_t r1 = r0 + kCellItemGroups < rc ? r0 + kCellItemGroups : rc;
+  uint32_t r1;
+  if (MIXQ) {
+    r1 = citem_end[it];
+  } else {
+    const uint32_t rc = crec_off[c + 1];
+    r1 = r0 + kCellItemGroups < rc ? r0 + kCellItemGroups : rc;
+  }
   const double inv_s = ldexp(inv_side, (int)c_level[c]);
   const double es = eps * inv_s;
   const T e2 = (T)(es * es);
@@ -489,9 +550,8 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
   // one loop over the (group, chunk of 64 sinks) pairs of the item, with the
   // next pair's data prefetched; a single back edge keeps the row registers in
   // place across iterations
-  auto group_centre = [&](uint32_t r, int& gf, int& ge, T& dx, T& dy, T& dz, int& q) {
+  auto group_centre = [&](uint32_t r, int& gf, int& ge, T& dx, T& dy, T& dz) {
     const int g = uniform_i32((int)mval[r]);
-    q = MIXQ ? uniform_i32((int)(mkey[r] & 15u)) : P;
     const int gc = uniform_i32(g_cell[g]);
     dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
     dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
@@ -500,20 +560,19 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     ge = gf + uniform_i32(g_count[g]);
   };
   uint32_t r = r0;
-  int s0 = 0, ge = 0, q = P, qn = P;
+  int s0 = 0, ge = 0;
   T Dx = T(0), Dy = T(0), Dz = T(0);
   V4<T> pme, pab;
   pme.x = pme.y = pme.z = pme.w = T(0);
   pab = pme;
   if (r < r1) {
-    group_centre(r, s0, ge, Dx, Dy, Dz, qn);
+    group_centre(r, s0, ge, Dx, Dy, Dz);
     if (s0 + lane < ge) {
       pme = off[s0 + lane];
       pab = ab4[s0 + lane];
     }
   }
   while (r < r1) {
-    q = qn;
     T X = T(1), Y = T(0), Z = T(0), bx = T(0), by = T(0), bz = T(0);
     if (s0 + lane < ge) {
       X = Dx + pme.x * (T)inv_s;
@@ -526,18 +585,15 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     s0 += 64;
     if (s0 >= ge) {
       ++r;
-      if (r < r1) group_centre(r, s0, ge, Dx, Dy, Dz, qn);
+      if (r < r1) group_centre(r, s0, ge, Dx, Dy, Dz);
     }
     if (r < r1 && s0 + lane < ge) {
       pme = off[s0 + lane];
       pab = ab4[s0 + lane];
     }
-    if (MIXQ)
-      expansion_cell_adj_q<P, T>(q, X, Y, Z, e2, bx, by, bz, row);
-    else
-      expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
+    expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
   }
-  T* o = part + it * (int64_t)nm_pad(P);
+  T* o = part + it * (int64_t)(MIXQ ? out_stride : nm_pad(P));
 #pragma unroll
   for (int a = 0; a < NM; ++a) {
     T v = row[a];
@@ -545,6 +601,8 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
     if (lane == (a & 63)) o[a] = v;
   }
+  if (MIXQ)
+    for (int a = NM + lane; a < out_nm; a += 64) o[a] = T(0);
 }
 
 // Mbar_alpha(c) = -w_alpha s^(-2-|alpha|) * sum over the cell's items (in order).
@@ -730,8 +788,13 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, qsh, C,
                                                       t->mcell_rec.as<uint32_t>());
     HOT_CHECK_LAUNCH();
-    k_items_from_off<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
-                                                     t->mcell_item.as<uint32_t>());
+    if (qsh)
+      k_cq_count<<<grid_for(C, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(),
+                                                 t->mcell_rec.as<uint32_t>(), C,
+                                                 t->mcell_item.as<uint32_t>());
+    else
+      k_items_from_off<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
+                                                       t->mcell_item.as<uint32_t>());
     HOT_CHECK_LAUNCH();
     scan_u32(ctx, t->mcell_item.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C,
              t->mcell_item.as<uint32_t>() + C);
@@ -742,11 +805,34 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     t->n_citems = nci;
     t->citem_rec.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(uint32_t));
     t->citem_cell.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(int32_t));
-    k_cell_items<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(),
-                                                 t->mcell_item.as<uint32_t>(), C,
-                                                 t->citem_rec.as<uint32_t>(),
-                                                 t->citem_cell.as<int32_t>());
-    HOT_CHECK_LAUNCH();
+    if (qsh) {
+      // items of one order each, then their ids sorted by order
+      t->citem_end.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(uint32_t));
+      t->qitems.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(uint32_t));
+      DBuf qkey, qoff;
+      qkey.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(uint64_t));
+      qoff.alloc(ctx, (kMaxP + 2) * sizeof(uint32_t));
+      k_cq_items<<<grid_for(C, kB), kB, 0, st>>>(
+          t->mrec_key.as<uint64_t>(), t->mcell_rec.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C,
+          t->citem_rec.as<uint32_t>(), t->citem_end.as<uint32_t>(), t->citem_cell.as<int32_t>(),
+          qkey.as<uint64_t>(), t->qitems.as<uint32_t>());
+      HOT_CHECK_LAUNCH();
+      radix_sort(ctx, qkey.as<uint64_t>(), t->qitems.as<uint32_t>(), nci, 4);
+      k_lower_bound<<<1, kB, 0, st>>>(qkey.as<uint64_t>(), nci, 0, kMaxP + 1, qoff.as<uint32_t>());
+      HOT_CHECK_LAUNCH();
+      uint32_t h[kMaxP + 2];
+      HOT_HIP(hipMemcpyAsync(h, qoff.p, sizeof(h), hipMemcpyDeviceToHost, st));
+      HOT_HIP(hipStreamSynchronize(st));
+      for (int q = 0; q <= kMaxP + 1; ++q) t->qitem_off[q] = h[q];
+    } else {
+      t->citem_end.release();
+      t->qitems.release();
+      k_cell_items<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(),
+                                                   t->mcell_item.as<uint32_t>(), C,
+                                                   t->citem_rec.as<uint32_t>(),
+                                                   t->citem_cell.as<int32_t>());
+      HOT_CHECK_LAUNCH();
+    }
   }
   t->has_transpose = true;
 }
@@ -773,19 +859,27 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
   DBuf part;
   part.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_citems) * nm_pad(P) * sizeof(T));
   if (t->n_citems > 0) {
-    auto cell = [&](auto kern) {
-      kern<<<(unsigned)t->n_citems, 64, 0, st>>>(
-          t->n_citems, t->citem_rec.as<uint32_t>(), t->citem_cell.as<int32_t>(),
-          t->mcell_rec.as<uint32_t>(), t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(),
-          t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
-          t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab, inv_side, eps,
-          part.as<T>());
+    auto cell = [&](auto kern, int64_t n, int64_t base) {
+      if (n <= 0) return;
+      kern<<<(unsigned)n, 64, 0, st>>>(
+          n, t->citem_rec.as<uint32_t>(), t->citem_cell.as<int32_t>(), t->mcell_rec.as<uint32_t>(),
+          t->qitems.as<uint32_t>(), base, t->citem_end.as<uint32_t>(), nm_pad(P), nm(P),
+          t->mrec_val.as<uint32_t>(), t->c_level.as<int8_t>(), t->g_first.as<int32_t>(),
+          t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab,
+          inv_side, eps, part.as<T>());
       HOT_CHECK_LAUNCH();
     };
-    if (mixq)
-      cell(k_m2p_cell_adj<P, T, true>);
-    else
-      cell(k_m2p_cell_adj<P, T, false>);
+    if (mixq) {
+      // one launch per order present: each kernel holds only its order's row
+      const int64_t* qo = t->qitem_off;
+#define HOT_CELL_Q(Q) \
+  if constexpr (Q <= P) cell(k_m2p_cell_adj<Q, T, true>, qo[Q + 1] - qo[Q], qo[Q]);
+      HOT_CELL_Q(0) HOT_CELL_Q(1) HOT_CELL_Q(2) HOT_CELL_Q(3) HOT_CELL_Q(4) HOT_CELL_Q(5)
+      HOT_CELL_Q(6) HOT_CELL_Q(7) HOT_CELL_Q(8)
+#undef HOT_CELL_Q
+    } else {
+      cell(k_m2p_cell_adj<P, T, false>, t->n_citems, 0);
+    }
   }
   const int64_t tot = C * nm(P);
   k_mbar_final<T><<<grid_for(tot, kB), kB, 0, st>>>(part.as<T>(), t->mcell_item.as<uint32_t>(), C,

@@ -153,6 +153,11 @@ struct hot_tree {
   // at most kCellItemGroups groups; citem_rec: first record of each item
   int64_t n_mrec = 0, n_citems = 0, n_mcells = 0;
   hot::DBuf mrec_key, mrec_val, citem_rec, citem_cell, mcell_rec, mcell_item;
+  // lists with per-entry orders: items hold records of one order only;
+  // citem_end: one past the item's last record; qitems: item ids sorted by
+  // order, qitem_off[q] .. qitem_off[q + 1] those of order q (host copy)
+  hot::DBuf citem_end, qitems;
+  int64_t qitem_off[hot::kMaxP + 2] = {};
 };
 
 namespace hot {

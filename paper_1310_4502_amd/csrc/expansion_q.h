@@ -1,8 +1,7 @@
 // Expansions at a run-time order q <= P, for interaction lists whose entries
 // carry their own order (error-bound acceptance). The moments of a cell are
 // stored to order P in slot order (by total order first), so the moments of
-// order <= q are a prefix of them, and the cell-side row of order q is a
-// prefix of the row of order P.
+// order <= q are a prefix of them.
 #pragma once
 #include "common.h"
 #include "generated/expansions.h"
@@ -36,21 +35,6 @@ __device__ __forceinline__ void expansion_sink_adj_q(int q, T X, T Y, T Z, T e2,
 #define HOT_CASE(Q)                                                                   \
   case Q:                                                                             \
     if constexpr (Q <= P) expansion_sink_adj<Q, T>(X, Y, Z, e2, M, bx, by, bz, gx, gy, gz); \
-    break;
-    HOT_Q_CASES(HOT_CASE)
-#undef HOT_CASE
-    default:
-      break;
-  }
-}
-
-template <int P, typename T>
-__device__ __forceinline__ void expansion_cell_adj_q(int q, T X, T Y, T Z, T e2, T bx, T by,
-                                                     T bz, T* row) {
-  switch (q) {
-#define HOT_CASE(Q)                                                            \
-  case Q:                                                                      \
-    if constexpr (Q <= P) expansion_cell_adj<Q, T>(X, Y, Z, e2, bx, by, bz, row); \
     break;
     HOT_Q_CASES(HOT_CASE)
 #undef HOT_CASE
