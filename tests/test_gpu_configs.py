@@ -101,3 +101,40 @@ def test_zeldovich16m_forward_and_adjoint():
     _log(f"zeldovich16m adjoint: vs direct VJP rows {e_rows:.3e}; directional {an:.9e} vs FD {fd:.9e}")
     assert e_rows <= 1e-3
     assert abs(an - fd) <= 1e-4 * abs(fd)
+
+
+@pytest.mark.parametrize("name,tol", [("clustered4m", 1e-4), ("zeldovich16m", 1e-3)])
+def test_error_bound_lists_full_size(name, tol):
+    """Error-bound lists at full size: lists and per-entry orders bit-exact on
+    sampled groups, accelerations on their sinks against the oracle treecode."""
+    t0 = time.time()
+    w = W.make(name)
+    n_leaf, n_group, dmax = BENCH[name]
+    pos, mass = to_dev(w)
+    gt = Tree(pos, n_leaf, n_group, w.box)
+    gt.build_interaction_lists_err(mass, tol, w.p, dmax)
+    gt.compute_moments(pos, mass, w.p)
+    ga, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    ga = ga.cpu().numpy()
+    gq = gt.m2p_orders()
+    _log(f"{name} err lists: gpu done {time.time() - t0:.1f}s, orders "
+         f"{np.bincount(gq, minlength=w.p + 1).tolist()}")
+    ot = oracle.Tree(w.pos, n_leaf, n_group, w.box)
+    G = ot.counts()["n_groups"]
+    groups = W.sample_indices(G, 24, 78)
+    ot.build_lists_err(w.mass, tol, w.p, dmax, groups=groups)
+    assert_lists_equal(gt, ot, groups=groups)
+    oq = ot.m2p_orders()
+    _, _, gmo, _ = gt.lists()
+    _, _, omo, oml = ot.lists()
+    for g in groups:
+        assert np.array_equal(gq[gmo[g]:gmo[g + 1]], oq[omo[g]:omo[g + 1]]), g
+    cells = np.unique(np.concatenate([oml[omo[g]:omo[g + 1]] for g in groups]))
+    ot.compute_moments(w.pos, w.mass, w.p, cells=cells)
+    _, perm = ot.keys()
+    sinks = np.sort(perm[np.isin(ot.group_of(), groups)])
+    oa, _, _ = ot.eval(w.pos, w.mass, w.eps, sinks=sinks, with_pot=False)
+    e_tree = rel_rms(ga[sinks], oa)
+    _log(f"{name} err lists: vs oracle treecode {e_tree:.3e} ({len(sinks)} sinks) "
+         f"{time.time() - t0:.1f}s")
+    assert e_tree <= 1e-5
