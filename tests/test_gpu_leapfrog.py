@@ -65,3 +65,71 @@ def test_leapfrog_gradient_vs_fd(n, ncoord):
     err = np.max(np.abs(ad - fd)) / rms
     _log(f"N={n}: max |g_adj - g_fd| / rms(g_fd) = {err:.3e} over {ncoord} coordinates")
     assert err <= 1e-4
+
+
+def test_leapfrog_gradient_vs_oracle_replay():
+    """A few coordinates of the same kind of gradient re-checked against the
+    CPU oracle: the unperturbed run's per-step trees are rebuilt by the oracle
+    from that run's positions, and the perturbed runs replay them with the
+    oracle's FP64 treecode (moments recomputed at the replayed positions)."""
+    import oracle
+
+    n = 1 << 10
+    w = W.make("plummer256k", n=n)
+    dt, steps, every = 1e-3, 16, 4
+    x0 = torch.from_numpy(w.pos).cuda()
+    v0 = torch.from_numpy(w.extra["vel"]).cuda()
+    mass = torch.from_numpy(w.mass).cuda()
+    rng = np.random.default_rng(505)
+    xt = x0 + torch.from_numpy(0.01 * (1.0 / 16) * rng.standard_normal(w.pos.shape)).cuda()
+    field = LF.ForceField(mass, w.eps, w.theta, w.p, 16, 64, 0, HOT_MIXED)
+    xK, vK, ck = LF.run(field, x0, v0, dt, steps, every)
+    gK = 2.0 * (xK - xt) / xK.numel()
+    gx, gv = LF.grad(field, ck, dt, steps, every, gK, torch.zeros_like(vK))
+    xs, _, xr, _, _ = LF._segment(field, x0, v0, None, dt, steps, keep_trees=False)
+    assert torch.equal(xr, xK)
+    trees = []
+    for x in xs:
+        t = oracle.Tree(x.cpu().numpy(), 16, 64)
+        t.build_lists(w.theta, 0)
+        trees.append(t)
+    m = w.mass
+    xt_np = xt.cpu().numpy()
+
+    def accel(t, x):
+        t.compute_moments(x, m, w.p)
+        return t.eval(x, m, w.eps, with_pot=False)[0]
+
+    def replay(xa, va):
+        x, v = xa.copy(), va.copy()
+        a = accel(trees[0], x)
+        for k in range(steps):
+            vh = v + (0.5 * dt) * a
+            x = x + dt * vh
+            a = accel(trees[k + 1], x)
+            v = vh + (0.5 * dt) * a
+        return x
+
+    xa0, va0 = w.pos.copy(), w.extra["vel"].copy()
+
+    def central(which, i, d, hh):
+        e = np.zeros_like(xa0)
+        e[i, d] = hh
+        if which == 0:
+            xp, xm = replay(xa0 + e, va0), replay(xa0 - e, va0)
+        else:
+            xp, xm = replay(xa0, va0 + e), replay(xa0, va0 - e)
+        return float(((xp - xm) * (xp + xm - 2 * xt_np)).sum()) / xK.numel() / (2 * hh)
+
+    h = 1e-6
+    idx = np.random.default_rng(507).choice(6 * n, size=2, replace=False)
+    fd, ad = [], []
+    for q in idx:
+        which, flat = divmod(int(q), 3 * n)
+        i, d = divmod(flat, 3)
+        fd.append((4 * central(which, i, d, h) - central(which, i, d, 2 * h)) / 3)
+        ad.append(float((gx if which == 0 else gv)[i, d]))
+    fd, ad = np.array(fd), np.array(ad)
+    err = np.max(np.abs(ad - fd)) / np.sqrt(np.mean(fd ** 2))
+    _log(f"N={n} oracle replay: max |g_adj - g_fd| / rms(g_fd) = {err:.3e}; {ad} vs {fd}")
+    assert err <= 1e-4
