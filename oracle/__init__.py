@@ -155,6 +155,21 @@ class Tree:
                                           int(p_max), int(direct_max), ctypes.c_int64(ns),
                                           _p(sel)))
 
+    def build_lists_periodic(self, theta, direct_max=0, groups=None):
+        """Lists over the 125 images of the source tree (the root cube is the
+        periodic cell); evaluation then adds the far replicas."""
+        sel = _i64(groups)
+        ns = 0 if sel is None else sel.shape[0]
+        _chk(lib().oracle_build_lists_periodic(self.h, ctypes.c_double(theta), int(direct_max),
+                                               ctypes.c_int64(ns), _p(sel)))
+
+    def list_images(self):
+        c = self.counts()
+        pi = np.empty(c["n_p2p"], np.int8)
+        mi = np.empty(c["n_m2p"], np.int8)
+        _chk(lib().oracle_get_list_images(self.h, _p(pi), _p(mi)))
+        return pi, mi
+
     def m2p_orders(self):
         out = np.empty(self.counts()["n_m2p"], np.int8)
         _chk(lib().oracle_get_m2p_orders(self.h, _p(out)))
@@ -241,6 +256,34 @@ def direct_vjp(pos, mass, eps, abar, rows=None):
                                  _p(abar), ctypes.c_int64(0 if r is None else T), _p(r),
                                  _p(xbar), _p(mbar)))
     return xbar, mbar
+
+
+def lattice_tensor(L, K, split=2.0):
+    """d^gamma F(0) of the far periodic replicas, |gamma| <= K, slot order."""
+    out = np.empty((K + 1) * (K + 2) * (K + 3) // 6)
+    _chk(lib().oracle_lattice_tensor(ctypes.c_double(L), int(K), ctypes.c_double(split), _p(out)))
+    return out
+
+
+def ewald_self(L, split=2.0):
+    f = lib().oracle_ewald_self
+    f.restype = ctypes.c_double
+    return f(ctypes.c_double(L), ctypes.c_double(split))
+
+
+def ewald_direct(pos, mass, L, eps, sinks=None):
+    """Periodic accelerations by definition (near replicas softened, far by
+    Ewald sums) for the selected sinks."""
+    pos = _f64(pos)
+    mass = _f64(mass)
+    n = pos.shape[0]
+    sel = _i64(sinks)
+    ns = n if sel is None else sel.shape[0]
+    acc = np.empty((ns, 3))
+    _chk(lib().oracle_ewald_direct(ctypes.c_int64(n), _p(pos), _p(mass), ctypes.c_double(L),
+                                   ctypes.c_double(eps), ctypes.c_int64(0 if sel is None else ns),
+                                   _p(sel), _p(acc)))
+    return acc
 
 
 def m2p(p, M, R, eps):

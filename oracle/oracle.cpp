@@ -25,6 +25,7 @@
 // expression below is evaluated exactly as written (IEEE, correctly rounded,
 // no fused multiply-add).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -150,6 +151,9 @@ struct Tree {
   // error-bound lists: expansion order of every M2P entry (empty for theta lists)
   std::vector<int8_t> m2p_q;
   int list_p = -1;  // highest order an entry may use (error-bound lists)
+  // periodic lists: the image (0 .. 124) of every entry; empty otherwise
+  std::vector<int8_t> p2p_img, m2p_img;
+  bool periodic = false;
   // moments
   int p = -1;
   std::vector<double> mom;        // n_cells x nm(p)
@@ -441,6 +445,9 @@ int build_lists(Tree& t, double theta, int direct_max, const std::vector<char>& 
     std::copy(lm[g].begin(), lm[g].end(), t.m2p.begin() + t.m2p_off[g]);
   }
   t.m2p_q.clear();
+  t.p2p_img.clear();
+  t.m2p_img.clear();
+  t.periodic = false;
   if (err) {
     t.m2p_q.resize(t.m2p_off[G]);
     for (int64_t g = 0; g < G; ++g) std::copy(lq[g].begin(), lq[g].end(), t.m2p_q.begin() + t.m2p_off[g]);
@@ -480,7 +487,7 @@ void p2m_direct(const double* spos, const double* smass, const Cell& c, int p, d
 //   2^n f^(n)(s) = (-1)^(n+1) (2n-1)!! s^(-n-1/2).
 // ---------------------------------------------------------------------------
 struct Radial {
-  double F[16];  // F[n] = 2^n f^(n)(s)
+  double F[24];  // F[n] = 2^n f^(n)(s)
 };
 
 Radial radial(double s, int nmax) {
@@ -564,6 +571,237 @@ struct NSum {
   }
   double value() const { return s + c; }
 };
+
+// ---------------------------------------------------------------------------
+// Periodic boundaries (Boundary Conditions section: the periodic replicas of
+// the root cube, of side L, with the far replicas summed by the lattice sums
+// of Nijboer and De Wette). Reading: the potential of a unit mass, all its
+// replicas and a uniform neutralising background (the cosmological
+// convention, no surface term), in Ewald's split with parameter a,
+//   psi(r) = sum_n erfc(a|r+nL|)/|r+nL|
+//          + (4 pi/L^3) sum_{k != 0} exp(-k^2/(4a^2))/k^2 cos(k.r) - pi/(a^2 L^3),
+// k = 2 pi m / L; psi does not depend on a. The replicas with max|n_d| <= 2
+// (the cube and its 124 neighbours) form the near zone, summed pair by pair
+// with the softened kernel like the isolated force; the remainder
+//   F(r) = psi(r) - sum_{max|n_d|<=2} 1/|r+nL|
+// is smooth inside the cube and enters unsoftened:
+//   a_i = sum_j m_j [ sum_near (x_j + nL - x_i)(|x_j + nL - x_i|^2 + eps^2)^(-3/2)
+//                     + grad F(x_i - x_j) ]   (the (i, n = 0) self pair skipped).
+// The treecode expands F about the cube centre c (u = x_i - c, v = x_j - c):
+//   sum_j m_j F(u - v_j) = sum_beta u^beta/beta! L_beta,
+//   L_beta = sum_{|alpha| <= p} (-1)^|alpha|/alpha! M_alpha(root) T_{alpha+beta},
+//   T_gamma = d^gamma F(0), a_k(far) = sum_{|beta| <= p} u^beta/beta! L_{beta+e_k}.
+// ---------------------------------------------------------------------------
+constexpr int kWs = 2;               // near zone: max|n_d| <= kWs
+constexpr int kImages = 125;         // (2 kWs + 1)^3
+constexpr double kSplit = 2.0;       // a = kSplit / L
+constexpr double kSqrtPi = 1.7724538509055160273;
+
+void image_shift(int img, double L, double sh[3]) {
+  sh[0] = (double)(img / 25 - kWs) * L;
+  sh[1] = (double)((img / 5) % 5 - kWs) * L;
+  sh[2] = (double)(img % 5 - kWs) * L;
+}
+
+// 2^n f^(n)(s) for f(s) = erfc(a sqrt s)/sqrt s at s = r^2 > 0: with
+// B_0 = erfc(a r)/r, B_n = ((2n-1) B_{n-1} + (2a^2)^n exp(-a^2 r^2)/(a sqrt pi))/r^2,
+// the n-th value is (-1)^n B_n.
+void erfc_radial(double r, double a, int nmax, double* F) {
+  const double e = std::exp(-a * a * r * r) / (a * kSqrtPi);
+  double B = std::erfc(a * r) / r, p2 = 1.0;
+  F[0] = B;
+  for (int n = 1; n <= nmax; ++n) {
+    p2 *= 2.0 * a * a;
+    B = ((double)(2 * n - 1) * B + p2 * e) / (r * r);
+    F[n] = (n % 2) ? -B : B;
+  }
+}
+
+// the same for f(s) = erf(a sqrt s)/sqrt s = s^(-1/2) - erfc(...): at r > 0
+// the difference of the two families; at r = 0 from the Taylor series
+// f(s) = (2a/sqrt pi) sum_k (-a^2 s)^k / (k! (2k+1)).
+void erf_radial(double r, double a, int nmax, double* F) {
+  if (r == 0.0) {
+    double c = 2.0 * a / kSqrtPi;
+    for (int n = 0; n <= nmax; ++n) {
+      F[n] = c / (double)(2 * n + 1);
+      c *= -2.0 * a * a;
+    }
+    return;
+  }
+  erfc_radial(r, a, nmax, F);
+  double v = 1.0 / r, df = 1.0;
+  for (int n = 0; n <= nmax; ++n) {
+    const double inv = ((n % 2) ? -df : df) * v;  // 2^n d^n/ds^n s^(-1/2)
+    F[n] = inv - F[n];
+    df *= (double)(2 * n + 1);
+    v /= r * r;
+  }
+}
+
+// slot of a multi-index of any order (the same order as multi_upto)
+size_t slot_of(const std::array<int, 3>& m) {
+  const int n = m[0] + m[1] + m[2];
+  const int bc = m[1] + m[2];
+  return (size_t)(n * (n + 1) * (n + 2) / 6 + bc * (bc + 1) / 2 + m[2]);
+}
+
+// multi-indices of total order <= K in slot order (order, then a, b descending)
+std::vector<std::array<int, 3>> multi_upto(int K) {
+  std::vector<std::array<int, 3>> out;
+  for (int n = 0; n <= K; ++n)
+    for (int a = n; a >= 0; --a)
+      for (int b = n - a; b >= 0; --b) out.push_back({a, b, n - a - b});
+  return out;
+}
+
+// T_gamma = d^gamma F(0) for |gamma| <= K:
+//   - sum_{near n} d^gamma [erf(a rho)/rho](nL)
+//   + sum_{far n, max|n_d| <= 6} d^gamma [erfc(a rho)/rho](nL)
+//   + (4 pi/L^3) sum_{k != 0, max|m_d| <= 10} exp(-k^2/4a^2)/k^2 Re(i^|gamma|) k^gamma.
+std::vector<double> lattice_tensor(double L, int K, double split) {
+  const double a = split / L;
+  const auto mi = multi_upto(K);
+  std::vector<double> T(mi.size(), 0.0);
+  Radial rad;
+  for (int nx = -6; nx <= 6; ++nx)
+    for (int ny = -6; ny <= 6; ++ny)
+      for (int nz = -6; nz <= 6; ++nz) {
+        const int m = std::max(std::abs(nx), std::max(std::abs(ny), std::abs(nz)));
+        const double R[3] = {nx * L, ny * L, nz * L};
+        const double r = std::sqrt((R[0] * R[0] + R[1] * R[1]) + R[2] * R[2]);
+        double sign;
+        if (m <= kWs) {
+          erf_radial(r, a, K, rad.F);
+          sign = -1.0;
+        } else {
+          erfc_radial(r, a, K, rad.F);
+          sign = 1.0;
+        }
+        for (size_t g = 0; g < mi.size(); ++g)
+          T[g] += sign * dG(mi[g][0], mi[g][1], mi[g][2], R, rad);
+      }
+  const double twopi = 2.0 * M_PI / L;
+  for (int mx = -10; mx <= 10; ++mx)
+    for (int my = -10; my <= 10; ++my)
+      for (int mz = -10; mz <= 10; ++mz) {
+        if (!mx && !my && !mz) continue;
+        const double k[3] = {twopi * mx, twopi * my, twopi * mz};
+        const double k2 = (k[0] * k[0] + k[1] * k[1]) + k[2] * k[2];
+        const double w = 4.0 * M_PI / (L * L * L) * std::exp(-k2 / (4.0 * a * a)) / k2;
+        for (size_t g = 0; g < mi.size(); ++g) {
+          const int n = mi[g][0] + mi[g][1] + mi[g][2];
+          if (n % 2) continue;
+          const double sg = (n / 2) % 2 ? -1.0 : 1.0;
+          T[g] += w * sg * ipow(k[0], mi[g][0]) * ipow(k[1], mi[g][1]) * ipow(k[2], mi[g][2]);
+        }
+      }
+  // F is even in each coordinate (the cubic lattice is symmetric under each
+  // reflection x_d -> -x_d): every T_gamma with an odd component vanishes
+  // exactly; the sums above leave only rounding there
+  for (size_t g = 0; g < mi.size(); ++g)
+    if ((mi[g][0] | mi[g][1] | mi[g][2]) & 1) T[g] = 0.0;
+  return T;
+}
+
+// psi(r) - 1/r at r -> 0 (the lattice's self potential; Madelung-type constant)
+double ewald_self(double L, double split) {
+  const double a = split / L;
+  double s = -2.0 * a / kSqrtPi - M_PI / (a * a * L * L * L);
+  for (int nx = -6; nx <= 6; ++nx)
+    for (int ny = -6; ny <= 6; ++ny)
+      for (int nz = -6; nz <= 6; ++nz) {
+        if (!nx && !ny && !nz) continue;
+        const double r = L * std::sqrt((double)(nx * nx + ny * ny + nz * nz));
+        s += std::erfc(a * r) / r;
+      }
+  const double twopi = 2.0 * M_PI / L;
+  for (int mx = -10; mx <= 10; ++mx)
+    for (int my = -10; my <= 10; ++my)
+      for (int mz = -10; mz <= 10; ++mz) {
+        if (!mx && !my && !mz) continue;
+        const double k2 = twopi * twopi * (double)(mx * mx + my * my + mz * mz);
+        s += 4.0 * M_PI / (L * L * L) * std::exp(-k2 / (4.0 * a * a)) / k2;
+      }
+  return s;
+}
+
+// grad F(r) for r inside the doubled cube (max|r_d| < L), split a = split/L
+void grad_far(const double r[3], double L, double split, double g[3]) {
+  const double a = split / L;
+  g[0] = g[1] = g[2] = 0.0;
+  for (int nx = -4; nx <= 4; ++nx)
+    for (int ny = -4; ny <= 4; ++ny)
+      for (int nz = -4; nz <= 4; ++nz) {
+        const int m = std::max(std::abs(nx), std::max(std::abs(ny), std::abs(nz)));
+        const double p[3] = {r[0] + nx * L, r[1] + ny * L, r[2] + nz * L};
+        const double rho = std::sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+        const double x = a * rho;
+        double c;  // grad h = -c p
+        if (m <= kWs) {
+          // h = -erf(a rho)/rho: c = -a^3 q(a rho),
+          // q(x) = (erf x - 2x/sqrt(pi) e^(-x^2)) / x^3
+          double q;
+          if (x < 0.5) {
+            q = 0.0;
+            double t = 1.0, f = 1.0;  // x^(2k-2), k!
+            for (int k = 1; k <= 14; ++k) {
+              f *= (double)k;
+              q += ((k % 2) ? 1.0 : -1.0) * 2.0 * k * t / (f * (2 * k + 1));
+              t *= x * x;
+            }
+            q *= 2.0 / kSqrtPi;
+          } else {
+            q = (std::erf(x) - 2.0 * x / kSqrtPi * std::exp(-x * x)) / (x * x * x);
+          }
+          c = -a * a * a * q;
+        } else {
+          // h = erfc(a rho)/rho: c = erfc(x)/rho^3 + 2a/sqrt(pi) e^(-x^2)/rho^2
+          c = std::erfc(x) / (rho * rho * rho) + 2.0 * a / kSqrtPi * std::exp(-x * x) / (rho * rho);
+        }
+        for (int d = 0; d < 3; ++d) g[d] -= c * p[d];
+      }
+  const double twopi = 2.0 * M_PI / L;
+  for (int mx = -5; mx <= 5; ++mx)
+    for (int my = -5; my <= 5; ++my)
+      for (int mz = -5; mz <= 5; ++mz) {
+        if (!mx && !my && !mz) continue;
+        const double k[3] = {twopi * mx, twopi * my, twopi * mz};
+        const double k2 = (k[0] * k[0] + k[1] * k[1]) + k[2] * k[2];
+        const double w = 4.0 * M_PI / (L * L * L) * std::exp(-k2 / (4.0 * a * a)) / k2;
+        const double sn = std::sin((k[0] * r[0] + k[1] * r[1]) + k[2] * r[2]);
+        for (int d = 0; d < 3; ++d) g[d] -= w * k[d] * sn;
+      }
+}
+
+// periodic walk: the tree of image img (centres shifted), theta test as above
+void walk_image(const Tree& t, const Cell& g, int64_t ci, const double sh[3], double theta,
+                int direct_max, int img, std::vector<int32_t>& p2p, std::vector<int8_t>& pimg,
+                std::vector<int32_t>& m2p, std::vector<int8_t>& mimg) {
+  const Cell& c = t.cells[ci];
+  double dx = g.centre[0] - (c.centre[0] + sh[0]);
+  double dy = g.centre[1] - (c.centre[1] + sh[1]);
+  double dz = g.centre[2] - (c.centre[2] + sh[2]);
+  double d2 = (dx * dx + dy * dy) + dz * dz;
+  double rr = c.bmax / theta + g.bmax;
+  if (d2 > rr * rr) {
+    if (c.count <= direct_max) {
+      p2p.push_back((int32_t)ci);
+      pimg.push_back((int8_t)img);
+    } else {
+      m2p.push_back((int32_t)ci);
+      mimg.push_back((int8_t)img);
+    }
+    return;
+  }
+  if (c.is_leaf) {
+    p2p.push_back((int32_t)ci);
+    pimg.push_back((int8_t)img);
+    return;
+  }
+  for (int k = 0; k < c.n_child; ++k)
+    walk_image(t, g, c.child_first + k, sh, theta, direct_max, img, p2p, pimg, m2p, mimg);
+}
 
 }  // namespace
 
@@ -726,6 +964,120 @@ int oracle_build_lists_err(void* h, const double* mass, double tol, int pmax, in
   return build_lists(*t, -1.0, direct_max, want, tol, mmax, pmax);
 }
 
+// Periodic lists: the walk above for each of the 125 images of the source
+// tree (the cube and its neighbours, image = 25 (n_x + 2) + 5 (n_y + 2) +
+// (n_z + 2)), images in that order, each a depth-first walk; the root cube is
+// the periodic cell. The tree must have been built with a given box.
+int oracle_build_lists_periodic(void* h, double theta, int direct_max, int64_t n_sel,
+                                const int64_t* sel) {
+  Tree* t = (Tree*)h;
+  if (!(theta > 0 && theta < 1)) return fail("theta must lie in (0, 1)");
+  if (direct_max < 0) return fail("direct_max must be >= 0");
+  std::vector<char> want;
+  if (sel) {
+    want.assign(t->groups.size(), 0);
+    for (int64_t k = 0; k < n_sel; ++k) {
+      if (sel[k] < 0 || sel[k] >= (int64_t)t->groups.size()) return fail("bad group ordinal");
+      want[sel[k]] = 1;
+    }
+  }
+  const int64_t G = (int64_t)t->groups.size();
+  std::vector<std::vector<int32_t>> lp(G), lm(G);
+  std::vector<std::vector<int8_t>> ip(G), im(G);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < G; ++g) {
+    if (!(want.empty() || want[g])) continue;
+    for (int img = 0; img < kImages; ++img) {
+      double sh[3];
+      image_shift(img, t->side, sh);
+      walk_image(*t, t->cells[t->groups[g]], 0, sh, theta, direct_max, img, lp[g], ip[g], lm[g],
+                 im[g]);
+    }
+  }
+  t->p2p_off.assign(G + 1, 0);
+  t->m2p_off.assign(G + 1, 0);
+  for (int64_t g = 0; g < G; ++g) {
+    t->p2p_off[g + 1] = t->p2p_off[g] + (int64_t)lp[g].size();
+    t->m2p_off[g + 1] = t->m2p_off[g] + (int64_t)lm[g].size();
+  }
+  t->p2p.resize(t->p2p_off[G]);
+  t->m2p.resize(t->m2p_off[G]);
+  t->p2p_img.resize(t->p2p_off[G]);
+  t->m2p_img.resize(t->m2p_off[G]);
+  for (int64_t g = 0; g < G; ++g) {
+    std::copy(lp[g].begin(), lp[g].end(), t->p2p.begin() + t->p2p_off[g]);
+    std::copy(lm[g].begin(), lm[g].end(), t->m2p.begin() + t->m2p_off[g]);
+    std::copy(ip[g].begin(), ip[g].end(), t->p2p_img.begin() + t->p2p_off[g]);
+    std::copy(im[g].begin(), im[g].end(), t->m2p_img.begin() + t->m2p_off[g]);
+  }
+  t->m2p_q.clear();
+  t->list_p = -1;
+  t->list_sel = want;
+  t->has_lists = true;
+  t->periodic = true;
+  t->theta = theta;
+  t->direct_max = direct_max;
+  return 0;
+}
+
+int oracle_get_list_images(void* h, int8_t* p2p_img, int8_t* m2p_img) {
+  Tree* t = (Tree*)h;
+  if (!t->has_lists || !t->periodic) return fail("no periodic lists");
+  if (p2p_img) std::copy(t->p2p_img.begin(), t->p2p_img.end(), p2p_img);
+  if (m2p_img) std::copy(t->m2p_img.begin(), t->m2p_img.end(), m2p_img);
+  return 0;
+}
+
+// T_gamma of the far replicas for |gamma| <= K (slot order), split a = split/L.
+int oracle_lattice_tensor(double L, int K, double split, double* out) {
+  if (!(L > 0) || K < 0 || K > 20 || !(split > 0)) return fail("bad arguments");
+  const auto T = lattice_tensor(L, K, split);
+  std::copy(T.begin(), T.end(), out);
+  return 0;
+}
+
+double oracle_ewald_self(double L, double split) { return ewald_self(L, split); }
+
+// O-D periodic: the definition above, for the selected sinks (caller
+// indices; all if null), near zone softened, far part by Ewald sums.
+int oracle_ewald_direct(int64_t n, const double* pos, const double* mass, double L, double eps,
+                        int64_t n_sinks, const int64_t* sinks, double* acc) {
+  if (n < 1 || !pos || !mass || !acc || !(L > 0)) return fail("bad arguments");
+  std::vector<int64_t> todo;
+  if (sinks) {
+    todo.assign(sinks, sinks + n_sinks);
+  } else {
+    todo.resize(n);
+    for (int64_t i = 0; i < n; ++i) todo[i] = i;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < (int64_t)todo.size(); ++k) {
+    const int64_t i = todo[k];
+    const double* xi = &pos[3 * i];
+    NSum s[3];
+    for (int64_t j = 0; j < n; ++j) {
+      const double* xj = &pos[3 * j];
+      double a[3] = {0, 0, 0};
+      for (int img = 0; img < kImages; ++img) {
+        if (j == i && img == kImages / 2) continue;
+        double sh[3];
+        image_shift(img, L, sh);
+        double r[3] = {(xj[0] + sh[0]) - xi[0], (xj[1] + sh[1]) - xi[1], (xj[2] + sh[2]) - xi[2]};
+        p2p_pair(mass[j], r, eps, a, nullptr);
+      }
+      if (j != i) {
+        const double r[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+        double g[3];
+        grad_far(r, L, kSplit, g);
+        for (int d = 0; d < 3; ++d) a[d] += mass[j] * g[d];
+      }
+      for (int d = 0; d < 3; ++d) s[d].add(a[d]);
+    }
+    for (int d = 0; d < 3; ++d) acc[3 * k + d] = s[d].value();
+  }
+  return 0;
+}
+
 int oracle_get_m2p_orders(void* h, int8_t* out) {
   Tree* t = (Tree*)h;
   if (!t->has_lists) return fail("no lists");
@@ -824,6 +1176,26 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
     for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e)
       if (!t->mom_valid[t->m2p[e]]) return fail("moments missing for an M2P cell");
   }
+  // periodic lists: local coefficients of the far replicas from the root's
+  // moments, L_beta = sum_{|alpha| <= p} (-1)^|alpha|/alpha! M_alpha T_{alpha+beta}
+  std::vector<std::array<int, 3>> far_mi;
+  std::vector<double> far_L;
+  if (t->periodic) {
+    if (!t->mom_valid[0]) return fail("moments of the root are needed for periodic lists");
+    const int p = t->p;
+    const auto Tg = lattice_tensor(t->side, 2 * p + 1, kSplit);
+    far_mi = multi_upto(p + 1);
+    far_L.assign(far_mi.size(), 0.0);
+    const double* M = &t->mom[0];
+    for (size_t b = 0; b < far_mi.size(); ++b)
+      for (int sl = 0; sl < K; ++sl) {
+        const int* al = &g_alpha[3 * sl];
+        const int n = al[0] + al[1] + al[2];
+        const double w = ((n % 2) ? -1.0 : 1.0) / (factorial(al[0]) * factorial(al[1]) * factorial(al[2]));
+        const std::array<int, 3> gsum = {al[0] + far_mi[b][0], al[1] + far_mi[b][1], al[2] + far_mi[b][2]};
+        far_L[b] += w * M[sl] * Tg[slot_of(gsum)];
+      }
+  }
   int64_t c_p2p = 0, c_m2p = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : c_p2p, c_m2p)
   for (int64_t k = 0; k < T; ++k) {
@@ -834,24 +1206,46 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
     double a[3] = {0, 0, 0}, ph = 0.0;
     for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) {
       const Cell& c = t->cells[t->p2p[e]];
+      double sh[3] = {0, 0, 0};
+      const int img = t->periodic ? (int)t->p2p_img[e] : kImages / 2;
+      if (t->periodic) image_shift(img, t->side, sh);
       c_p2p += c.count;
       for (int64_t j = c.first; j < c.first + c.count; ++j) {
-        if (j == si) continue;
+        if (j == si && img == kImages / 2) continue;
         const double* xj = &pos[3 * t->perm[j]];
-        double r[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+        double r[3] = {(xj[0] + sh[0]) - xi[0], (xj[1] + sh[1]) - xi[1], (xj[2] + sh[2]) - xi[2]};
         p2p_pair(mass[t->perm[j]], r, eps, a, &ph);
       }
     }
     for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e) {
       const int64_t cid = t->m2p[e];
       const Cell& c = t->cells[cid];
-      double R[3] = {xi[0] - c.centre[0], xi[1] - c.centre[1], xi[2] - c.centre[2]};
+      double sh[3] = {0, 0, 0};
+      if (t->periodic) image_shift((int)t->m2p_img[e], t->side, sh);
+      double R[3] = {xi[0] - (c.centre[0] + sh[0]), xi[1] - (c.centre[1] + sh[1]),
+                     xi[2] - (c.centre[2] + sh[2])};
       double da[3], dphi;
       const int q = t->list_p >= 0 ? (int)t->m2p_q[e] : t->p;
       m2p_one(&t->mom[cid * K], q, R, eps, da, &dphi);
       a[0] += da[0], a[1] += da[1], a[2] += da[2];
       ph += dphi;
       c_m2p += 1;
+    }
+    if (t->periodic) {
+      // far replicas: a_k = sum_{|beta| <= p} u^beta/beta! L_{beta+e_k}
+      const double* c0 = t->cells[0].centre;
+      const double u[3] = {xi[0] - c0[0], xi[1] - c0[1], xi[2] - c0[2]};
+      for (size_t b = 0; b < far_mi.size(); ++b) {
+        const auto& be = far_mi[b];
+        if (be[0] + be[1] + be[2] > t->p) break;
+        const double mono = ipow(u[0], be[0]) * ipow(u[1], be[1]) * ipow(u[2], be[2]) /
+                            (factorial(be[0]) * factorial(be[1]) * factorial(be[2]));
+        for (int d = 0; d < 3; ++d) {
+          std::array<int, 3> bk = be;
+          bk[d] += 1;
+          a[d] += mono * far_L[slot_of(bk)];
+        }
+      }
     }
     for (int d = 0; d < 3; ++d) acc[3 * k + d] = a[d];
     if (pot) pot[k] = ph;
@@ -936,6 +1330,7 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
   if (!t->list_sel.empty()) return fail("the VJP needs the lists of every group");
   if (t->p < 0) return fail("moments not computed");
   if (t->p < t->list_p) return fail("moments of lower order than the lists");
+  if (t->periodic) return fail("the VJP of periodic lists is not available");
   const int64_t n = t->n;
   const int p = t->p;
   const int K = nm(p);
