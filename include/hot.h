@@ -159,6 +159,23 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
                                 int p_max, int direct_max);
 
 /*
+ * build_interaction_lists_periodic -- periodic boundaries (Boundary
+ * Conditions section): the root cube, which must have been given to
+ * tree_build as opts->box, is the periodic cell of side L. The theta walk
+ * above runs over each of the 125 near images of the source tree (the cube
+ * shifted by n L, max|n_d| <= 2; image = 25 (n_x + 2) + 5 (n_y + 2) + n_z + 2),
+ * images in that order, entries tagged with their image (tree_get_list_images);
+ * the self pair is skipped in the unshifted image only. eval_forces then adds
+ * the far replicas with a uniform neutralising background (Ewald's split of
+ * the lattice sum, no surface term) through their lattice sums: a local
+ * expansion about the cube centre built from the root's moments, derivatives
+ * of the far function to order 2p + 1, applied to order p. Potentials and
+ * the adjoint are not available with periodic lists (HOT_E_INVALID,
+ * HOT_E_STATE). theta: (0, 1); direct_max: >= 0. Synchronises the stream.
+ */
+int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
+
+/*
  * eval_forces -- accelerations (and optionally potentials) of all particles:
  *   a_i = sum over P2P cells, j != i:  m_j (x_j - x_i) (|x_j - x_i|^2 + eps^2)^(-3/2)
  *       + sum over M2P cells c:  -sum_{|alpha|<=p} (-1)^|alpha|/alpha! M_alpha
@@ -216,6 +233,11 @@ int tree_get_lists(hot_ctx* ctx, hot_tree* tree, int64_t* p2p_off, int32_t* p2p,
 /* Expansion order of every M2P entry (host out, n_m2p int8, list order);
  * HOT_E_STATE unless the lists came from build_interaction_lists_err. */
 int tree_get_m2p_orders(hot_ctx* ctx, hot_tree* tree, int8_t* orders);
+
+/* Image (0 .. 124) of every P2P and M2P entry of periodic lists (host out,
+ * n_p2p and n_m2p int8, list order; either may be NULL); HOT_E_STATE unless
+ * the lists came from build_interaction_lists_periodic. */
+int tree_get_list_images(hot_ctx* ctx, hot_tree* tree, int8_t* p2p_img, int8_t* m2p_img);
 
 /* HOST: FP64 moments [n_cells x (p+1)(p+2)(p+3)/6], slot order by order n,
  * then x exponent descending, then y exponent descending. */

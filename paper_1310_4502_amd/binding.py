@@ -26,7 +26,8 @@ EXPORTS = ["hot_ctx_create", "hot_ctx_destroy", "hot_last_error", "hot_sync", "t
            "tree_destroy", "compute_moments", "build_interaction_lists", "eval_forces",
            "eval_forces_adjoint", "tree_get_counts", "tree_get_root", "tree_get_keys",
            "tree_get_cells", "tree_get_groups", "tree_get_lists", "tree_get_moments",
-           "tree_lookup", "build_interaction_lists_err", "tree_get_m2p_orders"]
+           "tree_lookup", "build_interaction_lists_err", "tree_get_m2p_orders",
+           "build_interaction_lists_periodic", "tree_get_list_images"]
 
 
 class HotError(RuntimeError):
@@ -78,6 +79,8 @@ def load(path: Optional[str] = None):
     L.build_interaction_lists.argtypes = [vp, vp, dbl, i32]
     L.build_interaction_lists_err.argtypes = [vp, vp, vp, dbl, i32, i32]
     L.tree_get_m2p_orders.argtypes = [vp, vp, vp]
+    L.build_interaction_lists_periodic.argtypes = [vp, vp, dbl, i32]
+    L.tree_get_list_images.argtypes = [vp, vp, vp, vp]
     L.eval_forces.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     L.eval_forces_adjoint.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, vp]
     L.tree_get_counts.argtypes = [vp, vp, vp]
@@ -227,6 +230,19 @@ class Tree:
         self.ctx.check(load().build_interaction_lists_err(self.ctx.h, self.h, _dev(mass),
                                                           float(err_tol), int(p_max),
                                                           int(direct_max)))
+
+    def build_interaction_lists_periodic(self, theta, direct_max=0):
+        """Periodic lists: the tree's root cube (given as the box) is the
+        periodic cell; eval_forces adds the far replicas."""
+        self.ctx.check(load().build_interaction_lists_periodic(self.ctx.h, self.h, float(theta),
+                                                               int(direct_max)))
+
+    def list_images(self):
+        c = self.counts()
+        pi = np.empty(max(c["n_p2p"], 0), np.int8)
+        mi = np.empty(max(c["n_m2p"], 0), np.int8)
+        self.ctx.check(load().tree_get_list_images(self.ctx.h, self.h, _np(pi), _np(mi)))
+        return pi, mi
 
     def m2p_orders(self):
         out = np.empty(max(self.counts()["n_m2p"], 0), np.int8)

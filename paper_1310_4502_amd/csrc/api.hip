@@ -180,6 +180,7 @@ int tree_build(hot_ctx* ctx, int64_t n, const double* pos, const hot_build_opts*
     t->n = n;
     t->n_leaf = n_leaf;
     t->n_group = n_group;
+    t->box_given = box != nullptr;
     hot::build_tree(ctx, t, pos, box);
     t->valid = true;
     *out = t;
@@ -247,6 +248,22 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
   });
 }
 
+int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max) {
+  return guard(ctx, [&] {
+    need_tree(ctx, tree);
+    if (!tree->box_given) hot::state("periodic lists need a tree built with a given box");
+    if (!(theta > 0.0 && theta < 1.0)) hot::invalid("theta must lie in (0, 1)");
+    if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    try {
+      hot::build_lists_periodic(ctx, tree, theta, direct_max);
+    } catch (...) {
+      tree->has_lists = false;
+      tree->periodic = false;
+      throw;
+    }
+  });
+}
+
 int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass, double eps,
                 int precision, double* acc, double* pot, hot_stats* stats) {
   return guard(ctx, [&] {
@@ -257,7 +274,9 @@ int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* m
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
+    if (tree->periodic && pot) hot::invalid("potentials are not available with periodic lists");
     hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats);
+    if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc);
   });
 }
 
@@ -272,6 +291,7 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
+    if (tree->periodic) hot::state("the adjoint of periodic lists is not available");
     hot::adjoint(ctx, tree, pos, mass, eps, precision, acc_bar, pos_bar, mass_bar);
   });
 }
@@ -361,6 +381,16 @@ int tree_get_lists(hot_ctx* ctx, hot_tree* t, int64_t* p2p_off, int32_t* p2p, in
     d2h<int64_t>(ctx, m2p_off, t->m2p_off.p, t->n_groups + 1);
     d2h<int32_t>(ctx, p2p, t->p2p.p, t->n_p2p);
     d2h<int32_t>(ctx, m2p, t->m2p.p, t->n_m2p);
+    HOT_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tree_get_list_images(hot_ctx* ctx, hot_tree* t, int8_t* p2p_img, int8_t* m2p_img) {
+  return guard(ctx, [&] {
+    need_tree(ctx, t);
+    if (!t->has_lists || !t->periodic) hot::state("no periodic lists");
+    d2h<int8_t>(ctx, p2p_img, t->p2p_img.p, t->n_p2p);
+    d2h<int8_t>(ctx, m2p_img, t->m2p_img.p, t->n_m2p);
     HOT_HIP(hipStreamSynchronize(ctx->stream));
   });
 }

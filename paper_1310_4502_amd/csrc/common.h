@@ -68,6 +68,9 @@ struct hot_ctx {
   unsigned* d_flags = nullptr;     // device error flags
   unsigned* h_flags = nullptr;     // pinned host mirror
   hipEvent_t ev[8]{};
+  // lattice sums of the far periodic replicas (host FP64) for one cube side
+  std::vector<double> lattice;
+  double lattice_side = 0.0;
   void* malloc_dev(size_t bytes);
   void free_dev(void* p);
 };
@@ -140,6 +143,12 @@ struct hot_tree {
   // highest order allowed; list_p = -1 for theta lists (every entry at p)
   hot::DBuf m2p_q;
   int list_p = -1;
+  // periodic lists (root cube = periodic cell, given by the caller): the
+  // image 0 .. 124 of every entry, image = 25 (n_x + 2) + 5 (n_y + 2) + n_z + 2
+  // for the replica shifted by n L, and the far replicas' lattice sums
+  bool box_given = false;
+  bool periodic = false;
+  hot::DBuf p2p_img, m2p_img, lattice;
   // eval work items: (group, first sink) per wave
   int64_t n_items = 0;
   hot::DBuf items;
@@ -182,6 +191,9 @@ void weighted_fp64(hot_ctx* ctx, hot_tree* t);
 void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
                      int direct_max);
+void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
+void lattice_tensor(hot_ctx* ctx, hot_tree* t);
+void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
 void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
             int precision, double* acc, double* pot, hot_stats* stats);
 void adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,

@@ -30,10 +30,21 @@ constexpr int kB = 256;
 constexpr int kWavesPerBlock = kB / 64;
 
 // State per sorted particle: s_x s_y s_z s_phi c_x c_y c_z c_phi.
-template <typename T, bool POT, bool EPS0>
+// Image index -> shift of the source replica (periodic lists): n L with
+// n_d = digit - 2 of the index in base 5 (x most significant).
+__device__ __forceinline__ void image_shift(int img, double side, double& sx, double& sy,
+                                           double& sz) {
+  sx = (double)(img / 25 - 2) * side;
+  sy = (double)((img / 5) % 5 - 2) * side;
+  sz = (double)(img % 5 - 2) * side;
+}
+constexpr int kCentreImage = 62;  // n = (0, 0, 0)
+
+template <typename T, bool POT, bool EPS0, bool PER>
 __global__ __launch_bounds__(kB) void k_p2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
-    const int32_t* __restrict__ p2p, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
+    const int32_t* __restrict__ c_first,
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
@@ -58,14 +69,18 @@ __global__ __launch_bounds__(kB) void k_p2p(
     // a run of consecutive entries whose particle ranges are contiguous
     // (typically the sibling leaves of one opened cell)
     int c = uniform_i32(p2p[e]);
+    const int im0 = PER ? uniform_i32(p2p_img[e]) : kCentreImage;
     const int f = uniform_i32(c_first[c]);
     int end = f + uniform_i32(c_count[c]);
     for (++e; e < e1; ++e) {
       c = uniform_i32(p2p[e]);
       const int f2 = uniform_i32(c_first[c]);
       if (f2 != end) break;
+      if (PER && uniform_i32(p2p_img[e]) != im0) break;
       end = f2 + uniform_i32(c_count[c]);
     }
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    if (PER) image_shift(im0, side, shx, shy, shz);
     T ax = 0, ay = 0, az = 0, ap = 0;
     T bx = 0, by = 0, bz = 0, bp = 0;
     int j = f;
@@ -75,9 +90,16 @@ __global__ __launch_bounds__(kB) void k_p2p(
       const int jend = end < sgend ? end : sgend;
       if (jend <= j) break;  // never true for a valid tree
       const int sc = uniform_i32(g_cell[sg]);
-      const T tx = (T)(c_centre[3 * sc] - cgx) - me.x;
-      const T ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
-      const T tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+      T tx, ty, tz;
+      if (PER) {
+        tx = (T)((c_centre[3 * sc] + shx) - cgx) - me.x;
+        ty = (T)((c_centre[3 * sc + 1] + shy) - cgy) - me.y;
+        tz = (T)((c_centre[3 * sc + 2] + shz) - cgz) - me.z;
+      } else {
+        tx = (T)(c_centre[3 * sc] - cgx) - me.x;
+        ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
+        tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+      }
 #define HOT_PAIR(SELF, JJ, AX, AY, AZ, AP)                                            \
   {                                                                                  \
     const V4<T> s = off[JJ];                                                         \
@@ -92,7 +114,7 @@ __global__ __launch_bounds__(kB) void k_p2p(
     AZ = hot_fma(f3, rz, AZ);                                                        \
     if (POT) AP -= mi;                                                               \
   }
-      if (sg == g) {
+      if (sg == g && im0 == kCentreImage) {
         for (int jj = j; jj < jend; ++jj) HOT_PAIR(true, jj, ax, ay, az, ap)
       } else {
         int jj = j;
@@ -130,11 +152,13 @@ template <int P, typename T>
 constexpr int m2p_waves_per_simd() { return (sizeof(T) == 4 && P >= 7) ? 4 : 1; }
 
 // MIXQ: every entry carries its own order q <= P (m2p_q), error-bound lists.
-template <int P, typename T, bool POT, bool MIXQ>
+// PER: every entry carries the image of its cell (periodic lists).
+template <int P, typename T, bool POT, bool MIXQ, bool PER>
 __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(m2p_waves_per_simd<P, T>())))
 void k_m2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
     const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_q,
+    const int8_t* __restrict__ m2p_img, double side,
     const int8_t* __restrict__ c_level,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
@@ -180,6 +204,13 @@ void k_m2p(
     nx = c_centre[3 * cn];
     ny = c_centre[3 * cn + 1];
     nz = c_centre[3 * cn + 2];
+    if (PER) {
+      double sx, sy, sz;
+      image_shift(uniform_i32(m2p_img[e0]), side, sx, sy, sz);
+      nx += sx;
+      ny += sy;
+      nz += sz;
+    }
   }
   for (int64_t e = e0; e < e1; ++e) {
     const int c = cn;
@@ -197,6 +228,13 @@ void k_m2p(
       nx = c_centre[3 * cn];
       ny = c_centre[3 * cn + 1];
       nz = c_centre[3 * cn + 2];
+      if (PER) {
+        double sx, sy, sz;
+        image_shift(uniform_i32(m2p_img[e + 1]), side, sx, sy, sz);
+        nx += sx;
+        ny += sy;
+        nz += sz;
+      }
     }
     const double es = eps * inv_s;
     const T e2 = (T)(es * es);
@@ -243,17 +281,25 @@ void launch_p2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, double eps, T* stat
   const T e2 = (T)(eps * eps);
   auto go = [&](auto kern) {
     kern<<<grid, kB, 0, ctx->stream>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
-                                       t->p2p.as<int32_t>(), t->c_first.as<int32_t>(),
+                                       t->p2p.as<int32_t>(), t->p2p_img.as<int8_t>(), t->side,
+                                       t->c_first.as<int32_t>(),
                                        t->c_count.as<int32_t>(), t->group_of.as<int32_t>(),
                                        t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
                                        t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, e2,
                                        state, t->n);
     HOT_CHECK_LAUNCH();
   };
-  if (e2 > T(0))
-    go(k_p2p<T, POT, false>);
-  else
-    go(k_p2p<T, POT, true>);
+  if (t->periodic) {
+    if (e2 > T(0))
+      go(k_p2p<T, POT, false, true>);
+    else
+      go(k_p2p<T, POT, true, true>);
+  } else {
+    if (e2 > T(0))
+      go(k_p2p<T, POT, false, false>);
+    else
+      go(k_p2p<T, POT, true, false>);
+  }
 }
 
 template <int P, typename T, bool POT>
@@ -263,15 +309,18 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, do
   auto go = [&](auto kern) {
     kern<<<grid, kB, 0, ctx->stream>>>(
         t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
-        t->m2p_q.as<int8_t>(), t->c_level.as<int8_t>(), t->g_first.as<int32_t>(),
+        t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
+        t->g_first.as<int32_t>(),
         t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, momw,
         1.0 / t->side, eps, state);
     HOT_CHECK_LAUNCH();
   };
   if (t->list_p >= 0)
-    go(k_m2p<P, T, POT, true>);
+    go(k_m2p<P, T, POT, true, false>);
+  else if (t->periodic)
+    go(k_m2p<P, T, POT, false, true>);
   else
-    go(k_m2p<P, T, POT, false>);
+    go(k_m2p<P, T, POT, false, false>);
 }
 
 template <typename T, bool POT>

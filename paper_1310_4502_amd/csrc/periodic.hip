@@ -1,0 +1,232 @@
+// Periodic boundaries: the far replicas of the root cube (Boundary
+// Conditions section). The near replicas -- the cube and its 124 neighbours,
+// max|n_d| <= 2 -- are ordinary list entries carrying an image index; the
+// rest of the infinite lattice, with a uniform neutralising background
+// (Ewald's split; no surface term), is the smooth function
+//   F(r) = psi(r) - sum_{max|n_d| <= 2} 1/|r + nL|,
+// expanded about the cube centre c with the lattice sums T_gamma = d^gamma F(0)
+// of Nijboer and De Wette. Per evaluation:
+//   L_beta = sum_{|alpha| <= p} (-1)^|alpha|/alpha! M_alpha(root) T_{alpha+beta}   (|beta| <= p+1)
+//   a_k(x) += sum_{|beta| <= p} (x - c)^beta/beta! L_{beta+e_k}.
+// T is a constant of the cube side, computed once on the host in FP64.
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace hot {
+namespace {
+
+constexpr int kTK = 2 * kMaxP + 1;  // highest derivative order needed
+constexpr double kSplit = 2.0;      // Ewald split a = kSplit / L
+constexpr double kRootPi = 1.7724538509055160273;
+
+constexpr int tri(int n) { return n * (n + 1) * (n + 2) / 6; }
+__host__ __device__ inline int slot3(int a, int b, int c) {
+  const int n = a + b + c, bc = b + c;
+  return n * (n + 1) * (n + 2) / 6 + bc * (bc + 1) / 2 + c;
+}
+
+// All derivatives d^(t,u,v) of a radial function h(|x|) at the point x, for
+// t + u + v <= K, by the Hermite recursion of McMurchie and Davidson:
+// R^(n)_000 = G_n (G_n = 2^n d^n h / ds^n, s = |x|^2),
+// R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} + x R^(n+1)_{t,u,v} (likewise u, v).
+// out[slot3(t,u,v)] = R^(0)_{t,u,v}.
+void hermite_all(const double x[3], const double* G, int K, double* out, std::vector<double>& R) {
+  // R[n][t][u][v] with t + u + v + n <= K, stored densely (every entry read
+  // is written first)
+  const int D = K + 1;
+  R.resize((size_t)D * D * D * D);
+  auto at = [&](int n, int t, int u, int v) -> double& {
+    return R[(((size_t)n * D + t) * D + u) * D + v];
+  };
+  for (int n = 0; n <= K; ++n) at(n, 0, 0, 0) = G[n];
+  for (int s = 1; s <= K; ++s)  // total order of (t, u, v)
+    for (int n = 0; n + s <= K; ++n)
+      for (int t = s; t >= 0; --t)
+        for (int u = s - t; u >= 0; --u) {
+          const int v = s - t - u;
+          double r;
+          if (t > 0)
+            r = (t > 1 ? (t - 1) * at(n + 1, t - 2, u, v) : 0.0) + x[0] * at(n + 1, t - 1, u, v);
+          else if (u > 0)
+            r = (u > 1 ? (u - 1) * at(n + 1, t, u - 2, v) : 0.0) + x[1] * at(n + 1, t, u - 1, v);
+          else
+            r = (v > 1 ? (v - 1) * at(n + 1, t, u, v - 2) : 0.0) + x[2] * at(n + 1, t, u, v - 1);
+          at(n, t, u, v) = r;
+        }
+  for (int s = 0; s <= K; ++s)
+    for (int t = s; t >= 0; --t)
+      for (int u = s - t; u >= 0; --u) out[slot3(t, u, s - t - u)] = at(0, t, u, s - t - u);
+}
+
+// G_n for h = erfc(a r)/r (r > 0): (-1)^n B_n with B_0 = erfc(a r)/r and
+// B_n = ((2n - 1) B_{n-1} + (2 a^2)^n e^(-a^2 r^2) / (a sqrt(pi))) / r^2.
+void g_erfc(double r, double a, int K, double* G) {
+  const double e = std::exp(-a * a * r * r) / (a * kRootPi);
+  double B = std::erfc(a * r) / r, q = 1.0;
+  G[0] = B;
+  for (int n = 1; n <= K; ++n) {
+    q *= 2.0 * a * a;
+    B = ((2.0 * n - 1.0) * B + q * e) / (r * r);
+    G[n] = (n & 1) ? -B : B;
+  }
+}
+
+// G_n for h = erf(a r)/r: 1/r minus the erfc family, or the Taylor
+// coefficients (2a/sqrt(pi)) (-2a^2)^n / (2n + 1) at r = 0.
+void g_erf(double r, double a, int K, double* G) {
+  if (r == 0.0) {
+    double c = 2.0 * a / kRootPi;
+    for (int n = 0; n <= K; ++n, c *= -2.0 * a * a) G[n] = c / (2.0 * n + 1.0);
+    return;
+  }
+  g_erfc(r, a, K, G);
+  double w = 1.0 / r;
+  for (int n = 0; n <= K; ++n) {
+    G[n] = w - G[n];  // 2^n d^n/ds^n s^(-1/2) = (-1)^n (2n-1)!! r^-(2n+1)
+    w *= -(2.0 * n + 1.0) / (r * r);
+  }
+}
+
+std::vector<double> lattice_sums(double L) {
+  const int K = kTK;
+  const double a = kSplit / L;
+  std::vector<double> T(tri(K + 1), 0.0), d(tri(K + 1)), work;
+  double G[kTK + 1];
+  // real space: -erf terms over the near replicas, +erfc terms beyond
+  for (int i = -6; i <= 6; ++i)
+    for (int j = -6; j <= 6; ++j)
+      for (int k = -6; k <= 6; ++k) {
+        const int m = std::max(std::abs(i), std::max(std::abs(j), std::abs(k)));
+        const double x[3] = {i * L, j * L, k * L};
+        const double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        const double sg = m <= 2 ? -1.0 : 1.0;
+        if (m <= 2)
+          g_erf(r, a, K, G);
+        else
+          g_erfc(r, a, K, G);
+        hermite_all(x, G, K, d.data(), work);
+        for (size_t s = 0; s < T.size(); ++s) T[s] += sg * d[s];
+      }
+  // reciprocal space: (4 pi/L^3) sum_{k != 0} e^(-k^2/4a^2)/k^2 Re(i^n) k^gamma
+  const double tp = 2.0 * M_PI / L;
+  for (int i = -10; i <= 10; ++i)
+    for (int j = -10; j <= 10; ++j)
+      for (int k = -10; k <= 10; ++k) {
+        if (!i && !j && !k) continue;
+        const double kv[3] = {tp * i, tp * j, tp * k};
+        const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+        const double w = 4.0 * M_PI / (L * L * L) * std::exp(-k2 / (4.0 * a * a)) / k2;
+        double pw[3][kTK + 1];
+        for (int c = 0; c < 3; ++c) {
+          pw[c][0] = 1.0;
+          for (int e = 1; e <= K; ++e) pw[c][e] = pw[c][e - 1] * kv[c];
+        }
+        for (int s = 0; s <= K; s += 2) {
+          const double sg = (s / 2) & 1 ? -1.0 : 1.0;
+          for (int t = s; t >= 0; --t)
+            for (int u = s - t; u >= 0; --u) {
+              const int v = s - t - u;
+              T[slot3(t, u, v)] += sg * w * (pw[0][t] * pw[1][u] * pw[2][v]);
+            }
+        }
+      }
+  // F is even in every coordinate: entries with an odd exponent are zero
+  for (int s = 0; s <= K; ++s)
+    for (int t = s; t >= 0; --t)
+      for (int u = s - t; u >= 0; --u)
+        if ((t | u | (s - t - u)) & 1) T[slot3(t, u, s - t - u)] = 0.0;
+  return T;
+}
+
+// one thread per beta: L_beta from the root's moments (slot order, nm(p))
+__global__ void k_far_local(const double* __restrict__ M, int p, const double* __restrict__ T,
+                            double* __restrict__ Lc) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = tri(p + 2);
+  if (b >= nb) return;
+  // multi-index of slot b
+  int n = 0;
+  while (tri(n + 1) <= b) ++n;
+  int r = b - tri(n), bx = n, by = 0;
+  for (int a = n; a >= 0; --a) {
+    if (r <= n - a) {
+      bx = a;
+      by = n - a - r;
+      break;
+    }
+    r -= n - a + 1;
+  }
+  const int bz = n - bx - by;
+  double acc = 0.0;
+  for (int s = 0; s <= p; ++s)
+    for (int a0 = s; a0 >= 0; --a0)
+      for (int a1 = s - a0; a1 >= 0; --a1) {
+        const int a2 = s - a0 - a1;
+        double f = 1.0;
+        for (int q = 2; q <= a0; ++q) f *= q;
+        for (int q = 2; q <= a1; ++q) f *= q;
+        for (int q = 2; q <= a2; ++q) f *= q;
+        const double w = ((s & 1) ? -1.0 : 1.0) / f;
+        acc += w * M[slot3(a0, a1, a2)] * T[slot3(a0 + bx, a1 + by, a2 + bz)];
+      }
+  Lc[b] = acc;
+}
+
+// a_k(x_i) += sum_{|beta| <= p} u^beta / beta! L_{beta + e_k}, u = x_i - c
+__global__ void k_far_l2p(const double* __restrict__ pos, int64_t n, const double* __restrict__ c,
+                          int p, const double* __restrict__ Lc, double* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double u0 = pos[3 * i] - c[0], u1 = pos[3 * i + 1] - c[1], u2 = pos[3 * i + 2] - c[2];
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  double px = 1.0;  // u0^a / a!
+  for (int a = 0; a <= p; ++a) {
+    double py = 1.0;
+    for (int b = 0; a + b <= p; ++b) {
+      double pz = 1.0;
+      for (int d = 0; a + b + d <= p; ++d) {
+        const double m = (px * py) * pz;
+        ax += m * Lc[slot3(a + 1, b, d)];
+        ay += m * Lc[slot3(a, b + 1, d)];
+        az += m * Lc[slot3(a, b, d + 1)];
+        pz *= u2 / (d + 1);
+      }
+      py *= u1 / (b + 1);
+    }
+    px *= u0 / (a + 1);
+  }
+  acc[3 * i] += ax;
+  acc[3 * i + 1] += ay;
+  acc[3 * i + 2] += az;
+}
+
+}  // namespace
+
+void lattice_tensor(hot_ctx* ctx, hot_tree* t) {
+  if (ctx->lattice_side != t->side) {
+    ctx->lattice = lattice_sums(t->side);
+    ctx->lattice_side = t->side;
+  }
+  const std::vector<double>& T = ctx->lattice;
+  t->lattice.alloc(ctx, T.size() * sizeof(double));
+  HOT_HIP(hipMemcpyAsync(t->lattice.p, T.data(), T.size() * sizeof(double),
+                         hipMemcpyHostToDevice, ctx->stream));
+  HOT_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc) {
+  hipStream_t st = ctx->stream;
+  const int p = t->p;
+  DBuf Lc;
+  Lc.alloc(ctx, tri(p + 2) * sizeof(double));
+  k_far_local<<<grid_for(tri(p + 2), 256), 256, 0, st>>>(t->mom64.as<double>(), p,
+                                                         t->lattice.as<double>(), Lc.as<double>());
+  HOT_CHECK_LAUNCH();
+  k_far_l2p<<<grid_for(t->n, 256), 256, 0, st>>>(pos, t->n, t->c_centre.as<double>(), p,
+                                                 Lc.as<double>(), acc);
+  HOT_CHECK_LAUNCH();
+}
+
+}  // namespace hot

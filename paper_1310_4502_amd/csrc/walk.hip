@@ -39,6 +39,15 @@ struct ErrMac {
   int8_t* m2p_q;       // fill pass: order of every M2P entry
 };
 
+// Periodic lists: the walk runs once per near image of the source tree
+// (cell centres shifted by n L, max|n_d| <= 2), images in index order
+// 25 (n_x + 2) + 5 (n_y + 2) + n_z + 2.
+struct Images {
+  double side;
+  int8_t* p2p_img;  // fill pass: image of every entry
+  int8_t* m2p_img;
+};
+
 // Order accepted for cell c (-1: not acceptable). FP64, no FMA; the same
 // operations in the same order as the oracle's test.
 __device__ __forceinline__ int accept_order(double dx, double dy, double dz, double gb, double b,
@@ -57,12 +66,12 @@ __device__ __forceinline__ int accept_order(double dx, double dy, double dz, dou
   return -1;
 }
 
-template <bool FILL, bool ERR>
+template <bool FILL, bool ERR, bool PER>
 __global__ __launch_bounds__(kB) void k_walk(
     const int32_t* __restrict__ g_cell, int64_t G, const double* __restrict__ c_centre,
     const double* __restrict__ c_bmax, const int32_t* __restrict__ c_count,
     const uint8_t* __restrict__ c_leaf, const int32_t* __restrict__ c_child,
-    const int32_t* __restrict__ c_nchild, double theta, ErrMac em, int direct_max,
+    const int32_t* __restrict__ c_nchild, double theta, ErrMac em, Images im, int direct_max,
     int64_t* __restrict__ cnt_p2p, int64_t* __restrict__ cnt_m2p, int64_t* __restrict__ pairs_p2p,
     const int64_t* __restrict__ off_p2p, const int64_t* __restrict__ off_m2p,
     int32_t* __restrict__ p2p, int32_t* __restrict__ m2p, int64_t C, unsigned* __restrict__ flags) {
@@ -81,6 +90,15 @@ __global__ __launch_bounds__(kB) void k_walk(
     bp = off_p2p[g];
     bm = off_m2p[g];
   }
+  bool bad = false;
+  for (int img = 0; img < (PER ? 125 : 1) && !bad; ++img) {
+  double shx = 0.0, shy = 0.0, shz = 0.0;
+  if (PER) {
+    shx = (double)(img / 25 - 2) * im.side;
+    shy = (double)((img / 5) % 5 - 2) * im.side;
+    shz = (double)(img % 5 - 2) * im.side;
+  }
+  __builtin_amdgcn_wave_barrier();
   if (lane == 0) stk[w][0] = make_int2(0, 1);
   int top = 0;
   while (top >= 0) {
@@ -89,6 +107,7 @@ __global__ __launch_bounds__(kB) void k_walk(
     const int lo = uniform_i32(r.x), hi = uniform_i32(r.y);
     if (lo < 0 || hi > C || hi - lo > 8 || lo >= hi) {  // never true for a valid tree
       if (lane == 0) atomicOr(flags, FLAG_INTERNAL);
+      bad = true;
       break;
     }
     const int c = lo + lane;
@@ -96,8 +115,16 @@ __global__ __launch_bounds__(kB) void k_walk(
     int cnt = 0;
     int q = -1;
     if (c < hi) {
-      const double dx = gx - c_centre[3 * c], dy = gy - c_centre[3 * c + 1],
-                   dz = gz - c_centre[3 * c + 2];
+      double dx, dy, dz;
+      if (PER) {
+        dx = gx - (c_centre[3 * c] + shx);
+        dy = gy - (c_centre[3 * c + 1] + shy);
+        dz = gz - (c_centre[3 * c + 2] + shz);
+      } else {
+        dx = gx - c_centre[3 * c];
+        dy = gy - c_centre[3 * c + 1];
+        dz = gz - c_centre[3 * c + 2];
+      }
       cnt = c_count[c];
       bool acc;
       if (ERR) {
@@ -119,10 +146,14 @@ __global__ __launch_bounds__(kB) void k_walk(
     const uint64_t pm = __ballot(cls == CLS_P2P) & before;
     const uint64_t mm = __ballot(cls == CLS_M2P) & before;
     if (FILL) {
-      if ((pm >> lane) & 1ull) p2p[bp + np + __popcll(pm & lt)] = c;
+      if ((pm >> lane) & 1ull) {
+        p2p[bp + np + __popcll(pm & lt)] = c;
+        if (PER) im.p2p_img[bp + np + __popcll(pm & lt)] = (int8_t)img;
+      }
       if ((mm >> lane) & 1ull) {
         m2p[bm + nmm + __popcll(mm & lt)] = c;
         if (ERR) em.m2p_q[bm + nmm + __popcll(mm & lt)] = (int8_t)q;
+        if (PER) im.m2p_img[bm + nmm + __popcll(mm & lt)] = (int8_t)img;
       }
     } else {
       if ((pm >> lane) & 1ull) npairs += cnt;
@@ -135,6 +166,7 @@ __global__ __launch_bounds__(kB) void k_walk(
       int nt = top;
       if (nc < 1 || cf < 0 || top + 2 >= kStack) {  // never true for a valid tree
         if (lane == 0) atomicOr(flags, FLAG_INTERNAL);
+        bad = true;
         break;
       }
       if (oc + 1 < hi) {
@@ -146,6 +178,7 @@ __global__ __launch_bounds__(kB) void k_walk(
     } else {
       --top;
     }
+  }
   }
   if (!FILL) {
     // sum of P2P source particles over lanes
@@ -191,13 +224,15 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
 namespace {
 
-template <bool ERR>
+template <bool ERR, bool PER>
 void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_max) {
+  Images im{t->side, nullptr, nullptr};
   hipStream_t st = ctx->stream;
   const int64_t G = t->n_groups;
   t->has_lists = false;
   t->has_transpose = false;
   t->list_p = -1;
+  t->periodic = false;
   t->p2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
   t->m2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
   DBuf pairs, mcount, totals;
@@ -205,10 +240,10 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
   mcount.alloc(ctx, (G + 1) * sizeof(int64_t));
   totals.alloc(ctx, 4 * sizeof(int64_t));
   const unsigned grid = grid_for(G, kWavesPerBlock);
-  k_walk<false, ERR><<<grid, kB, 0, st>>>(
+  k_walk<false, ERR, PER><<<grid, kB, 0, st>>>(
       t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
-      t->c_nchild.as<int32_t>(), theta, em, direct_max, t->p2p_off.as<int64_t>(),
+      t->c_nchild.as<int32_t>(), theta, em, im, direct_max, t->p2p_off.as<int64_t>(),
       t->m2p_off.as<int64_t>(), pairs.as<int64_t>(), nullptr, nullptr, nullptr, nullptr,
       t->n_cells, ctx->d_flags);
   HOT_CHECK_LAUNCH();
@@ -243,16 +278,26 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
   } else {
     t->m2p_q.release();
   }
-  k_walk<true, ERR><<<grid, kB, 0, st>>>(
+  if (PER) {
+    t->p2p_img.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_p2p) * sizeof(int8_t));
+    t->m2p_img.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_m2p) * sizeof(int8_t));
+    im.p2p_img = t->p2p_img.as<int8_t>();
+    im.m2p_img = t->m2p_img.as<int8_t>();
+  } else {
+    t->p2p_img.release();
+    t->m2p_img.release();
+  }
+  k_walk<true, ERR, PER><<<grid, kB, 0, st>>>(
       t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
-      t->c_nchild.as<int32_t>(), theta, em, direct_max, nullptr, nullptr, nullptr,
+      t->c_nchild.as<int32_t>(), theta, em, im, direct_max, nullptr, nullptr, nullptr,
       t->p2p_off.as<int64_t>(), t->m2p_off.as<int64_t>(), t->p2p.as<int32_t>(),
       t->m2p.as<int32_t>(), t->n_cells, ctx->d_flags);
   HOT_CHECK_LAUNCH();
   t->theta = theta;
   t->direct_max = direct_max;
   t->list_p = ERR ? em.pmax : -1;
+  t->periodic = PER;
   t->has_lists = true;
 }
 
@@ -260,7 +305,13 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
 
 void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
   ErrMac em{0.0, nullptr, 0, nullptr};
-  walk_lists<false>(ctx, t, theta, em, direct_max);
+  walk_lists<false, false>(ctx, t, theta, em, direct_max);
+}
+
+void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+  ErrMac em{0.0, nullptr, 0, nullptr};
+  lattice_tensor(ctx, t);
+  walk_lists<false, true>(ctx, t, theta, em, direct_max);
 }
 
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
@@ -273,7 +324,7 @@ void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, 
                                                          ctx->d_flags);
   HOT_CHECK_LAUNCH();
   ErrMac em{tol, mm.as<double>(), p_max, nullptr};
-  walk_lists<true>(ctx, t, 0.0, em, direct_max);
+  walk_lists<true, false>(ctx, t, 0.0, em, direct_max);
 }
 
 }  // namespace hot

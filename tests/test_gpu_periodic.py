@@ -1,0 +1,116 @@
+"""GPU periodic boundaries (the root cube given as the box is the periodic
+cell; near replicas as image-tagged list entries, far replicas through
+lattice sums) against the oracle: lists and images bit-exact, forces against
+the oracle treecode on the same lists and against the Ewald direct sum,
+invariance under a periodic translation, and the entry point's checks."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1310_4502_amd import workloads as W
+from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
+from gpu_util import assert_lists_equal, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+BOX = np.array([0.0, 0.0, 0.0, 1.0])
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _clustered(n, seed):
+    rng = np.random.default_rng(seed)
+    pos = np.concatenate([rng.random((n // 2, 3)),
+                          (0.3 + 0.04 * rng.standard_normal((n - n // 2, 3))) % 1.0,
+                          ])
+    return pos, np.full(n, 1.0 / n)
+
+
+CASES = [
+    # name, n, p, theta, direct_max, n_leaf, n_group
+    ("uniform", 4096, 4, 0.5, 0, 16, 64),
+    ("clustered", 12000, 6, 0.5, 16, 8, 32),
+    ("clustered", 6000, 8, 0.4, 0, 16, 96),
+]
+
+
+def _pos(name, n):
+    if name == "uniform":
+        w = W.make("uniform4k")
+        return w.pos, w.mass
+    return _clustered(n, 11)
+
+
+@pytest.mark.parametrize("name,n,p,theta,dmax,n_leaf,n_group", CASES)
+def test_periodic_lists_and_forces(name, n, p, theta, dmax, n_leaf, n_group):
+    pos_np, mass_np = _pos(name, n)
+    eps = 1e-3
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    gt = Tree(pos, n_leaf, n_group, BOX)
+    ot = oracle.Tree(pos_np, n_leaf, n_group, BOX)
+    gt.build_interaction_lists_periodic(theta, dmax)
+    ot.build_lists_periodic(theta, dmax)
+    assert_lists_equal(gt, ot)
+    gpi, gmi = gt.list_images()
+    opi, omi = ot.list_images()
+    assert np.array_equal(gpi, opi) and np.array_equal(gmi, omi), "images differ"
+    _log(name, n, "entries", len(gpi), len(gmi))
+    gt.compute_moments(pos, mass, p)
+    ot.compute_moments(pos_np, mass_np, p)
+    ts = np.sort(np.random.default_rng(2).choice(n, 768, replace=False))
+    oa, _, _ = ot.eval(pos_np, mass_np, eps, sinks=ts, with_pot=False)
+    g64, _, _ = gt.eval_forces(pos, mass, eps, HOT_FP64)
+    g32, _, _ = gt.eval_forces(pos, mass, eps, HOT_MIXED)
+    e64 = rel_rms(g64.cpu().numpy()[ts], oa)
+    e32 = rel_rms(g32.cpu().numpy()[ts], oa)
+    _log("vs oracle treecode: fp64", e64, "mixed", e32)
+    assert e64 <= 1e-11 and e32 <= 1e-5
+    sinks = np.sort(np.random.default_rng(3).choice(n, 48, replace=False))
+    ad = oracle.ewald_direct(pos_np, mass_np, 1.0, eps, sinks=sinks)
+    ed = rel_rms(g64.cpu().numpy()[sinks], ad)
+    _log("vs Ewald direct sum", ed)
+    assert ed <= {4: 2e-3, 6: 1e-4, 8: 1e-5}[p]
+
+
+def test_periodic_translation_invariance():
+    pos_np, mass_np = _clustered(8000, 12)
+    eps = 1e-3
+    shift = np.array([0.4375, 0.8125, 0.0625])
+    res = []
+    for x in (pos_np, (pos_np + shift) % 1.0):
+        pos = torch.from_numpy(x).cuda()
+        mass = torch.from_numpy(mass_np).cuda()
+        t = Tree(pos, 16, 64, BOX)
+        t.build_interaction_lists_periodic(0.4, 0)
+        t.compute_moments(pos, mass, 8)
+        res.append(t.eval_forces(pos, mass, eps, HOT_FP64)[0].cpu().numpy())
+    e = rel_rms(res[1], res[0])
+    _log("translated", e)
+    assert e <= 1e-5  # two different trees: the treecode error, not rounding
+
+
+def test_periodic_checks():
+    w = W.make("uniform4k")
+    pos = torch.from_numpy(w.pos).cuda()
+    mass = torch.from_numpy(w.mass).cuda()
+    t = Tree(pos, 16, 64)  # no box given
+    with pytest.raises(HotError):
+        t.build_interaction_lists_periodic(0.5, 0)
+    t = Tree(pos, 16, 64, BOX)
+    t.build_interaction_lists(0.5, 0)
+    with pytest.raises(HotError):
+        t.list_images()
+    t.build_interaction_lists_periodic(0.5, 0)
+    t.compute_moments(pos, mass, 4)
+    with pytest.raises(HotError):
+        t.eval_forces(pos, mass, w.eps, HOT_MIXED, with_pot=True)
+    with pytest.raises(HotError):
+        t.eval_forces_adjoint(pos, mass, w.eps, torch.zeros_like(pos), HOT_MIXED)
+    a, _, _ = t.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    assert torch.isfinite(a).all()
