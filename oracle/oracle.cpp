@@ -1330,7 +1330,6 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
   if (!t->list_sel.empty()) return fail("the VJP needs the lists of every group");
   if (t->p < 0) return fail("moments not computed");
   if (t->p < t->list_p) return fail("moments of lower order than the lists");
-  if (t->periodic) return fail("the VJP of periodic lists is not available");
   const int64_t n = t->n;
   const int p = t->p;
   const int K = nm(p);
@@ -1361,10 +1360,14 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
       int64_t off = 0;
       for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) {
         const Cell& c = t->cells[t->p2p[e]];
+        double sh[3] = {0, 0, 0};
+        const int img = t->periodic ? (int)t->p2p_img[e] : kImages / 2;
+        if (t->periodic) image_shift(img, t->side, sh);
         for (int64_t j = c.first; j < c.first + c.count; ++j, ++off) {
-          if (j == si) continue;
+          if (j == si && img == kImages / 2) continue;
           const int64_t cj = t->perm[j];
-          double r[3] = {pos[3 * cj] - xi[0], pos[3 * cj + 1] - xi[1], pos[3 * cj + 2] - xi[2]};
+          double r[3] = {(pos[3 * cj] + sh[0]) - xi[0], (pos[3 * cj + 1] + sh[1]) - xi[1],
+                         (pos[3 * cj + 2] + sh[2]) - xi[2]};
           double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
           if (s == 0.0) continue;
           double inv = 1.0 / std::sqrt(s);
@@ -1384,7 +1387,10 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
         const int64_t cid = t->m2p[e];
         const Cell& c = t->cells[cid];
         const double* M = &t->mom[cid * K];
-        double R[3] = {xi[0] - c.centre[0], xi[1] - c.centre[1], xi[2] - c.centre[2]};
+        double sh[3] = {0, 0, 0};
+        if (t->periodic) image_shift((int)t->m2p_img[e], t->side, sh);
+        double R[3] = {xi[0] - (c.centre[0] + sh[0]), xi[1] - (c.centre[1] + sh[1]),
+                       xi[2] - (c.centre[2] + sh[2])};
         double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
         const int q = t->list_p >= 0 ? (int)t->m2p_q[e] : p;
         Radial rad = radial(s, q + 2);
@@ -1424,6 +1430,60 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
       const int64_t cid = t->m2p[e];
       used[cid] = 1;
       for (int sl = 0; sl < K; ++sl) Mbar[cid * K + sl] += cellbar[g][(e - t->m2p_off[g]) * K + sl];
+    }
+  }
+  // periodic lists: the far replicas. a_k(i) = sum_{|beta|<=p} u_i^beta/beta!
+  // L_{beta+e_k} with L_beta = sum_alpha w_alpha M_alpha(root) T_{alpha+beta}:
+  //   d/dx_{i,l}: sum_k abar_ik sum_{|beta|<=p-1} u^beta/beta! L_{beta+e_k+e_l}
+  //   d/dM_alpha(root): w_alpha sum_i sum_k abar_ik sum_beta u^beta/beta! T_{alpha+beta+e_k}
+  if (t->periodic) {
+    const auto Tg = lattice_tensor(t->side, 2 * p + 1, kSplit);
+    const auto bmi = multi_upto(p + 1);
+    std::vector<double> Lb(bmi.size(), 0.0);
+    const double* M0 = &t->mom[0];
+    for (size_t b = 0; b < bmi.size(); ++b)
+      for (int sl = 0; sl < K; ++sl) {
+        const int* al = &g_alpha[3 * sl];
+        const int nn = al[0] + al[1] + al[2];
+        const double w = ((nn % 2) ? -1.0 : 1.0) / (factorial(al[0]) * factorial(al[1]) * factorial(al[2]));
+        const std::array<int, 3> gs = {al[0] + bmi[b][0], al[1] + bmi[b][1], al[2] + bmi[b][2]};
+        Lb[b] += w * M0[sl] * Tg[slot_of(gs)];
+      }
+    const double* c0 = t->cells[0].centre;
+    std::vector<double> D(multi_upto(p + 1).size(), 0.0);  // sum_i sum_k abar_ik u^beta/beta! at beta+e_k
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t cj = t->perm[j];
+      const double u[3] = {pos[3 * cj] - c0[0], pos[3 * cj + 1] - c0[1], pos[3 * cj + 2] - c0[2]};
+      const double* ab = &abar[3 * cj];
+      for (size_t b = 0; b < bmi.size(); ++b) {
+        const auto& be = bmi[b];
+        if (be[0] + be[1] + be[2] > p) break;
+        const double mono = ipow(u[0], be[0]) * ipow(u[1], be[1]) * ipow(u[2], be[2]) /
+                            (factorial(be[0]) * factorial(be[1]) * factorial(be[2]));
+        for (int k = 0; k < 3; ++k) {
+          std::array<int, 3> bk = be;
+          bk[k] += 1;
+          D[slot_of(bk)] += ab[k] * mono;
+          if (be[0] + be[1] + be[2] > p - 1) continue;
+          for (int l = 0; l < 3; ++l) {
+            std::array<int, 3> bkl = bk;
+            bkl[l] += 1;
+            xb[3 * j + l] += ab[k] * mono * Lb[slot_of(bkl)];
+          }
+        }
+      }
+    }
+    used[0] = 1;
+    for (int sl = 0; sl < K; ++sl) {
+      const int* al = &g_alpha[3 * sl];
+      const int nn = al[0] + al[1] + al[2];
+      const double w = ((nn % 2) ? -1.0 : 1.0) / (factorial(al[0]) * factorial(al[1]) * factorial(al[2]));
+      double acc = 0.0;
+      for (size_t gi = 0; gi < bmi.size(); ++gi) {
+        const std::array<int, 3> gs = {al[0] + bmi[gi][0], al[1] + bmi[gi][1], al[2] + bmi[gi][2]};
+        acc += Tg[slot_of(gs)] * D[gi];
+      }
+      Mbar[sl] += w * acc;
     }
   }
   // (3) moment cotangents to particles through the moment definition:

@@ -177,3 +177,36 @@ def test_periodic_treecode_vs_direct(orc, p, theta, tol):
     ad = orc.ewald_direct(pos, mass, 1.0, eps, sinks=sinks)
     err = np.linalg.norm(a - ad) / np.linalg.norm(ad)
     assert err <= tol, err
+
+
+def test_periodic_vjp_matches_fd(orc):
+    """The oracle's VJP of the periodic treecode (near images, far replicas
+    through the root's moments) against Richardson-extrapolated central
+    differences of its own evaluation, positions and masses."""
+    rng = np.random.default_rng(6)
+    n = 400
+    pos = np.concatenate([rng.random((n // 2, 3)),
+                          (0.3 + 0.05 * rng.standard_normal((n - n // 2, 3))) % 1.0])
+    mass = rng.uniform(0.5, 1.5, n) / n
+    eps, p = 1e-2, 4
+    ot = orc.Tree(pos, 8, 32, np.array([0.0, 0.0, 0.0, 1.0]))
+    ot.build_lists_periodic(0.5, 0)
+    ot.compute_moments(pos, mass, p)
+    abar = W.cotangent(n, 3)
+    xb, mb = ot.vjp(pos, mass, eps, abar)
+
+    def L(x, m):
+        ot.compute_moments(x, m, p)
+        a, _, _ = ot.eval(x, m, eps, with_pot=False)
+        return float((a * abar).sum())
+
+    def rich(f, h=1e-6):
+        cd = lambda hh: (f(hh) - f(-hh)) / (2 * hh)
+        return (4 * cd(h) - cd(2 * h)) / 3
+
+    v = np.random.default_rng(1).normal(size=pos.shape)
+    fd = rich(lambda h: L(pos + h * v, mass))
+    assert abs(float((xb * v).sum()) - fd) <= 1e-8 * abs(fd)
+    u = np.random.default_rng(2).random(n)
+    fdm = rich(lambda h: L(pos, mass * (1 + h * u)))
+    assert abs(float((mb * mass * u).sum()) - fdm) <= 1e-8 * abs(fdm)
