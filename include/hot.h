@@ -169,9 +169,11 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
  * the far replicas with a uniform neutralising background (Ewald's split of
  * the lattice sum, no surface term) through their lattice sums: a local
  * expansion about the cube centre built from the root's moments, derivatives
- * of the far function to order 2p + 1, applied to order p. Potentials and
- * the adjoint are not available with periodic lists (HOT_E_INVALID,
- * HOT_E_STATE). theta: (0, 1); direct_max: >= 0. Synchronises the stream.
+ * of the far function to order 2p + 1, applied to order p. eval_forces_adjoint
+ * differentiates all of it, the far replicas included (through the sink
+ * positions and the root's moments). Potentials are not available with
+ * periodic lists (HOT_E_INVALID). theta: (0, 1); direct_max: >= 0.
+ * Synchronises the stream.
  */
 int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
 

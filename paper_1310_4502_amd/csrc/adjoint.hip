@@ -113,10 +113,12 @@ __global__ __launch_bounds__(kB) void k_srec_fill(
 }
 
 // key: the cell, followed by the entry's order in 4 low bits when the lists
-// carry orders (m2p_q not null)
+// carry orders (m2p_q not null), or by its image in 7 low bits when they
+// carry images (m2p_img not null)
 __global__ __launch_bounds__(kB) void k_mrec_fill(const int64_t* __restrict__ m2p_off,
                                                   const int32_t* __restrict__ m2p,
-                                                  const int8_t* __restrict__ m2p_q, int64_t G,
+                                                  const int8_t* __restrict__ m2p_q,
+                                                  const int8_t* __restrict__ m2p_img, int64_t G,
                                                   uint64_t* __restrict__ key,
                                                   uint32_t* __restrict__ val) {
   const int lane = threadIdx.x & 63;
@@ -124,7 +126,10 @@ __global__ __launch_bounds__(kB) void k_mrec_fill(const int64_t* __restrict__ m2
   if (g >= G) return;
   const int64_t e1 = m2p_off[g + 1];
   for (int64_t e = m2p_off[g] + lane; e < e1; e += 64) {
-    key[e] = m2p_q ? (((uint64_t)m2p[e] << 4) | (uint64_t)m2p_q[e]) : (uint64_t)m2p[e];
+    uint64_t k = (uint64_t)m2p[e];
+    if (m2p_q) k = (k << 4) | (uint64_t)m2p_q[e];
+    if (m2p_img) k = (k << 7) | (uint64_t)m2p_img[e];
+    key[e] = k;
     val[e] = (uint32_t)g;
   }
 }
@@ -232,12 +237,23 @@ __global__ void k_abar(const double* __restrict__ abar, const uint32_t* __restri
   ab[i] = v;
 }
 
+// Image index -> shift of the source replica (periodic lists): n L with
+// n_d = digit - 2 of the index in base 5 (x most significant).
+__device__ __forceinline__ void image_shift(int img, double side, double& sx, double& sy,
+                                           double& sz) {
+  sx = (double)(img / 25 - 2) * side;
+  sy = (double)((img / 5) % 5 - 2) * side;
+  sz = (double)(img % 5 - 2) * side;
+}
+constexpr int kCentreImage = 62;  // n = (0, 0, 0)
+
 // ------------------------------------------------------- pair terms, sink side
 // state per sorted particle: s_x s_y s_z - c_x c_y c_z -
-template <typename T, bool EPS0>
+template <typename T, bool EPS0, bool PER>
 __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
-    const int32_t* __restrict__ p2p, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
+    const int32_t* __restrict__ c_first,
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
@@ -266,14 +282,18 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
   while (e < e1) {
     // a run of consecutive entries with contiguous particle ranges
     int c = uniform_i32(p2p[e]);
+    const int im0 = PER ? uniform_i32(p2p_img[e]) : kCentreImage;
     const int f = uniform_i32(c_first[c]);
     int end = f + uniform_i32(c_count[c]);
     for (++e; e < e1; ++e) {
       c = uniform_i32(p2p[e]);
       const int f2 = uniform_i32(c_first[c]);
       if (f2 != end) break;
+      if (PER && uniform_i32(p2p_img[e]) != im0) break;
       end = f2 + uniform_i32(c_count[c]);
     }
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    if (PER) image_shift(im0, side, shx, shy, shz);
     T A = 0, Bx = 0, By = 0, Bz = 0;  // sum m inv3 ; sum 3 m (r.ab) inv5 r
     int j = f;
     while (j < end) {
@@ -282,9 +302,16 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
       const int jend = end < sgend ? end : sgend;
       if (jend <= j) break;
       const int sc = g_cell[sg];
-      const T tx = (T)(c_centre[3 * sc] - cgx) - me.x;
-      const T ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
-      const T tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+      T tx, ty, tz;
+      if (PER) {
+        tx = (T)((c_centre[3 * sc] + shx) - cgx) - me.x;
+        ty = (T)((c_centre[3 * sc + 1] + shy) - cgy) - me.y;
+        tz = (T)((c_centre[3 * sc + 2] + shz) - cgz) - me.z;
+      } else {
+        tx = (T)(c_centre[3 * sc] - cgx) - me.x;
+        ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
+        tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+      }
 #define HOT_SINK_PAIR(SELF)                                                          \
   {                                                                                  \
     const V4<T> s = off[jj];                                                         \
@@ -301,7 +328,7 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     By = hot_fma(q, ry, By);                                                         \
     Bz = hot_fma(q, rz, Bz);                                                         \
   }
-      if (sg == g) {
+      if (sg == g && im0 == kCentreImage) {
         for (int jj = j; jj < jend; ++jj) HOT_SINK_PAIR(true)
       } else {
 #pragma unroll 4
@@ -327,11 +354,12 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
 }
 
 // ------------------------------------------------- expansion terms, sink side
-// MIXQ: per-entry orders (error-bound lists)
-template <int P, typename T, bool MIXQ>
+// MIXQ: per-entry orders (error-bound lists); PER: per-entry images (periodic)
+template <int P, typename T, bool MIXQ, bool PER>
 __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
     const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_q,
+    const int8_t* __restrict__ m2p_img, double side,
     const int8_t* __restrict__ c_level,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
@@ -377,6 +405,13 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
     nx = c_centre[3 * cn];
     ny = c_centre[3 * cn + 1];
     nz = c_centre[3 * cn + 2];
+    if (PER) {
+      double sx, sy, sz;
+      image_shift(uniform_i32(m2p_img[e0]), side, sx, sy, sz);
+      nx += sx;
+      ny += sy;
+      nz += sz;
+    }
   }
   for (int64_t e = e0; e < e1; ++e) {
     const int c = cn;
@@ -394,6 +429,13 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
       nx = c_centre[3 * cn];
       ny = c_centre[3 * cn + 1];
       nz = c_centre[3 * cn + 2];
+      if (PER) {
+        double sx, sy, sz;
+        image_shift(uniform_i32(m2p_img[e + 1]), side, sx, sy, sz);
+        nx += sx;
+        ny += sy;
+        nz += sz;
+      }
     }
     const double es = eps * inv_s;
     T gx = 0, gy = 0, gz = 0;
@@ -423,11 +465,12 @@ __global__ __launch_bounds__(kB) void k_m2p_sink_adj(
 // one group are merged into a lane mask (the lanes whose particles lie in one
 // of that group's P2P cells), then the group's sinks are swept uniformly.
 // out per sorted particle: s_x s_y s_z s_m c_x c_y c_z c_m
-template <typename T, bool EPS0>
+template <typename T, bool EPS0, bool PER>
 __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     const int2* __restrict__ items, int64_t n_items, const uint64_t* __restrict__ skey,
     const uint32_t* __restrict__ sval, const uint32_t* __restrict__ soff, uint64_t gmask,
-    const int32_t* __restrict__ p2p, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
+    const int32_t* __restrict__ c_first,
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
     const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
@@ -450,17 +493,28 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
   while (r < rend) {
     const uint64_t k0 = skey[r];
     const int g = uniform_i32((int)(k0 & gmask));
+    // consecutive records of the same sink group (and, periodic, the same image)
+    const int im0 = PER ? uniform_i32(p2p_img[sval[r]]) : kCentreImage;
     bool mine = false;
-    while (r < rend && skey[r] == k0) {
+    while (r < rend && skey[r] == k0 && (!PER || uniform_i32(p2p_img[sval[r]]) == im0)) {
       const int c = p2p[sval[r]];
       const int f = c_first[c];
       mine |= (j >= f) && (j < f + c_count[c]);
       ++r;
     }
     const int gc = uniform_i32(g_cell[g]);
-    const T tx = (T)(csx - c_centre[3 * gc]) + me.x;  // r_ij = x_j - x_i = t - off_i
-    const T ty = (T)(csy - c_centre[3 * gc + 1]) + me.y;
-    const T tz = (T)(csz - c_centre[3 * gc + 2]) + me.z;
+    T tx, ty, tz;  // r_ij = x_j - x_i = t - off_i
+    if (PER) {
+      double shx, shy, shz;
+      image_shift(im0, side, shx, shy, shz);
+      tx = (T)((csx + shx) - c_centre[3 * gc]) + me.x;
+      ty = (T)((csy + shy) - c_centre[3 * gc + 1]) + me.y;
+      tz = (T)((csz + shz) - c_centre[3 * gc + 2]) + me.z;
+    } else {
+      tx = (T)(csx - c_centre[3 * gc]) + me.x;
+      ty = (T)(csy - c_centre[3 * gc + 1]) + me.y;
+      tz = (T)(csz - c_centre[3 * gc + 2]) + me.z;
+    }
     const int i0 = uniform_i32(g_first[g]);
     const int i1 = i0 + uniform_i32(g_count[g]);
     T gx = 0, gy = 0, gz = 0, gm = 0;
@@ -481,7 +535,7 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     gz = hot_fma(ab.z, inv3, hot_fma(-qq, rz, gz));                                  \
     gm = hot_fma(rd, inv3, gm);                                                      \
   }
-    if (g == gs) {
+    if (g == gs && im0 == kCentreImage) {
       for (int i = i0; i < i1; ++i) HOT_SRC_PAIR(true)
     } else {
 #pragma unroll 4
@@ -517,12 +571,12 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
 // orders): the block's item is qitems[qbase + block], its records end at
 // citem_end, and the row is written with stride out_stride, zero-filled from
 // nm(P) up to out_nm (the cell's full moment count).
-template <int P, typename T, bool MIXQ>
+template <int P, typename T, bool MIXQ, bool PER>
 __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     int64_t n_citems, const uint32_t* __restrict__ citem_rec, const int32_t* __restrict__ citem_cell,
     const uint32_t* __restrict__ crec_off, const uint32_t* __restrict__ qitems, int64_t qbase,
     const uint32_t* __restrict__ citem_end, int out_stride, int out_nm,
-    const uint32_t* __restrict__ mval,
+    const uint64_t* __restrict__ mkey, double side, const uint32_t* __restrict__ mval,
     const int8_t* __restrict__ c_level, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
     const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
@@ -553,9 +607,18 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
   auto group_centre = [&](uint32_t r, int& gf, int& ge, T& dx, T& dy, T& dz) {
     const int g = uniform_i32((int)mval[r]);
     const int gc = uniform_i32(g_cell[g]);
-    dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
-    dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
-    dz = (T)((c_centre[3 * gc + 2] - ccz) * inv_s);
+    if (PER) {
+      // the record's image of the cell sits at its centre + n L
+      double shx, shy, shz;
+      image_shift(uniform_i32((int)(mkey[r] & 127u)), side, shx, shy, shz);
+      dx = (T)((c_centre[3 * gc] - (ccx + shx)) * inv_s);
+      dy = (T)((c_centre[3 * gc + 1] - (ccy + shy)) * inv_s);
+      dz = (T)((c_centre[3 * gc + 2] - (ccz + shz)) * inv_s);
+    } else {
+      dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
+      dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
+      dz = (T)((c_centre[3 * gc + 2] - ccz) * inv_s);
+    }
     gf = uniform_i32(g_first[g]);
     ge = gf + uniform_i32(g_count[g]);
   };
@@ -779,13 +842,16 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     t->mcell_rec.alloc(ctx, (C + 1) * sizeof(uint32_t));
     t->mcell_item.alloc(ctx, (C + 1) * sizeof(uint32_t));
     const int qsh = t->list_p >= 0 ? 4 : 0;  // order bits below the cell id
+    const int ish = t->periodic ? 7 : 0;       // image bits below the cell id
     k_mrec_fill<<<grid_for(G, kWPB), kB, 0, st>>>(
         t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
-        t->list_p >= 0 ? t->m2p_q.as<int8_t>() : nullptr, G, t->mrec_key.as<uint64_t>(),
+        t->list_p >= 0 ? t->m2p_q.as<int8_t>() : nullptr,
+        t->periodic ? t->m2p_img.as<int8_t>() : nullptr, G, t->mrec_key.as<uint64_t>(),
         t->mrec_val.as<uint32_t>());
     HOT_CHECK_LAUNCH();
-    radix_sort(ctx, t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(), E, bits_for(C) + qsh);
-    k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, qsh, C,
+    radix_sort(ctx, t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(), E,
+               bits_for(C) + qsh + ish);
+    k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, qsh + ish, C,
                                                       t->mcell_rec.as<uint32_t>());
     HOT_CHECK_LAUNCH();
     if (qsh)
@@ -839,22 +905,25 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
 
 template <int P, typename T>
 void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<T>* ab,
-                          const T* momw, double eps, T* sink_state, double* mbar64) {
+                          const T* momw, double eps, T* sink_state, double* mbar64,
+                          const double* pos, const double* abar) {
   hipStream_t st = ctx->stream;
   const double inv_side = 1.0 / t->side;
   const bool mixq = t->list_p >= 0;
   auto sink = [&](auto kern) {
     kern<<<grid_for(t->n_items, kWPB), kB, 0, st>>>(
         t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
-        t->m2p_q.as<int8_t>(), t->c_level.as<int8_t>(), t->g_first.as<int32_t>(),
-        t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab,
-        momw, inv_side, eps, sink_state);
+        t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
+        t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
+        t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state);
     HOT_CHECK_LAUNCH();
   };
   if (mixq)
-    sink(k_m2p_sink_adj<P, T, true>);
+    sink(k_m2p_sink_adj<P, T, true, false>);
+  else if (t->periodic)
+    sink(k_m2p_sink_adj<P, T, false, true>);
   else
-    sink(k_m2p_sink_adj<P, T, false>);
+    sink(k_m2p_sink_adj<P, T, false, false>);
   const int64_t C = t->n_cells;
   DBuf part;
   part.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_citems) * nm_pad(P) * sizeof(T));
@@ -864,7 +933,7 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
       kern<<<(unsigned)n, 64, 0, st>>>(
           n, t->citem_rec.as<uint32_t>(), t->citem_cell.as<int32_t>(), t->mcell_rec.as<uint32_t>(),
           t->qitems.as<uint32_t>(), base, t->citem_end.as<uint32_t>(), nm_pad(P), nm(P),
-          t->mrec_val.as<uint32_t>(), t->c_level.as<int8_t>(), t->g_first.as<int32_t>(),
+          t->mrec_key.as<uint64_t>(), t->side, t->mrec_val.as<uint32_t>(), t->c_level.as<int8_t>(), t->g_first.as<int32_t>(),
           t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, ab,
           inv_side, eps, part.as<T>());
       HOT_CHECK_LAUNCH();
@@ -873,18 +942,23 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
       // one launch per order present: each kernel holds only its order's row
       const int64_t* qo = t->qitem_off;
 #define HOT_CELL_Q(Q) \
-  if constexpr (Q <= P) cell(k_m2p_cell_adj<Q, T, true>, qo[Q + 1] - qo[Q], qo[Q]);
+  if constexpr (Q <= P) cell(k_m2p_cell_adj<Q, T, true, false>, qo[Q + 1] - qo[Q], qo[Q]);
       HOT_CELL_Q(0) HOT_CELL_Q(1) HOT_CELL_Q(2) HOT_CELL_Q(3) HOT_CELL_Q(4) HOT_CELL_Q(5)
       HOT_CELL_Q(6) HOT_CELL_Q(7) HOT_CELL_Q(8)
 #undef HOT_CELL_Q
     } else {
-      cell(k_m2p_cell_adj<P, T, false>, t->n_citems, 0);
+      if (t->periodic)
+        cell(k_m2p_cell_adj<P, T, false, true>, t->n_citems, 0);
+      else
+        cell(k_m2p_cell_adj<P, T, false, false>, t->n_citems, 0);
     }
   }
   const int64_t tot = C * nm(P);
   k_mbar_final<T><<<grid_for(tot, kB), kB, 0, st>>>(part.as<T>(), t->mcell_item.as<uint32_t>(), C,
                                                     t->c_level.as<int8_t>(), inv_side, P, mbar64);
   HOT_CHECK_LAUNCH();
+  // far periodic replicas: their cotangent of the root's moments (cell 0)
+  if (t->periodic) far_replicas_mbar(ctx, t, pos, abar, mbar64);
   // down the tree: level L+1 cells take their parents' cotangents
   for (int L = 1; L <= t->max_level; ++L) {
     const int64_t c0 = t->level_off[L], c1 = t->level_off[L + 1];
@@ -932,19 +1006,26 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   const T e2 = (T)(eps * eps);
   const unsigned gi = grid_for(t->n_items, kWPB);
   // pair terms
-  auto sink_k = e2 > T(0) ? k_p2p_sink_adj<T, false> : k_p2p_sink_adj<T, true>;
+  auto sink_k = t->periodic ? (e2 > T(0) ? k_p2p_sink_adj<T, false, true>
+                                           : k_p2p_sink_adj<T, true, true>)
+                            : (e2 > T(0) ? k_p2p_sink_adj<T, false, false>
+                                         : k_p2p_sink_adj<T, true, false>);
   sink_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
-                            t->p2p.as<int32_t>(), t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+                            t->p2p.as<int32_t>(), t->p2p_img.as<int8_t>(), t->side,
+                            t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
                             t->group_of.as<int32_t>(), t->g_first.as<int32_t>(),
                             t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
                             t->c_centre.as<double>(), off.as<V4<T>>(), ab.as<V4<T>>(), e2,
                             sink.as<T>());
   HOT_CHECK_LAUNCH();
-  auto src_k = e2 > T(0) ? k_p2p_src_adj<T, false> : k_p2p_src_adj<T, true>;
+  auto src_k = t->periodic ? (e2 > T(0) ? k_p2p_src_adj<T, false, true>
+                                          : k_p2p_src_adj<T, true, true>)
+                           : (e2 > T(0) ? k_p2p_src_adj<T, false, false>
+                                        : k_p2p_src_adj<T, true, false>);
   src_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->srec_key.as<uint64_t>(),
                            t->srec_val.as<uint32_t>(), t->srec_off.as<uint32_t>(),
                            (1ull << t->srec_gbits) - 1ull, t->p2p.as<int32_t>(),
-                           t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+                           t->p2p_img.as<int8_t>(), t->side, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
                            t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
                            t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off.as<V4<T>>(),
                            ab.as<V4<T>>(), e2, src.as<T>());
@@ -962,15 +1043,15 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   double* M = mbar64.as<double>();
   T* S = sink.as<T>();
   switch (p) {
-    case 0: launch_expansion_adj<0, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 1: launch_expansion_adj<1, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 2: launch_expansion_adj<2, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 3: launch_expansion_adj<3, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 4: launch_expansion_adj<4, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 5: launch_expansion_adj<5, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 6: launch_expansion_adj<6, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 7: launch_expansion_adj<7, T>(ctx, t, o4, a4, momw, eps, S, M); break;
-    case 8: launch_expansion_adj<8, T>(ctx, t, o4, a4, momw, eps, S, M); break;
+    case 0: launch_expansion_adj<0, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 1: launch_expansion_adj<1, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 2: launch_expansion_adj<2, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 3: launch_expansion_adj<3, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 4: launch_expansion_adj<4, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 5: launch_expansion_adj<5, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 6: launch_expansion_adj<6, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 7: launch_expansion_adj<7, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 8: launch_expansion_adj<8, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
     default: invalid("p out of range");
   }
   const double* sp = spos.as<double>();
@@ -990,6 +1071,8 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
                                                     mb.as<double>(), t->perm.as<uint32_t>(), n,
                                                     xbar, mbar);
   HOT_CHECK_LAUNCH();
+  // far periodic replicas: their direct dependence on the sink position
+  if (t->periodic) far_replicas_xbar(ctx, t, pos, abar, xbar);
 }
 
 }  // namespace

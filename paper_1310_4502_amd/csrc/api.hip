@@ -291,7 +291,6 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
-    if (tree->periodic) hot::state("the adjoint of periodic lists is not available");
     hot::adjoint(ctx, tree, pos, mass, eps, precision, acc_bar, pos_bar, mass_bar);
   });
 }

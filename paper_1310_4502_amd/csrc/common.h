@@ -194,6 +194,10 @@ void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, 
 void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
 void lattice_tensor(hot_ctx* ctx, hot_tree* t);
 void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
+void far_replicas_mbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,
+                       double* mbar_root);
+void far_replicas_xbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,
+                       double* xbar);
 void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
             int precision, double* acc, double* pot, hot_stats* stats);
 void adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,

@@ -202,7 +202,180 @@ __global__ void k_far_l2p(const double* __restrict__ pos, int64_t n, const doubl
   acc[3 * i + 2] += az;
 }
 
+// Adjoint of the far replicas (u = x_i - c, b_i the acceleration cotangent):
+//   xbar_{i,l} += sum_k b_ik sum_{|beta| <= p-1} u^beta/beta! L_{beta+e_k+e_l},
+//   Mbar_alpha(root) += w_alpha sum_{|gamma| <= p+1} T_{alpha+gamma} D_gamma,
+//   D_gamma = sum_i sum_k b_ik u^(gamma-e_k)/(gamma-e_k)!   (gamma_k >= 1).
+__global__ void k_far_l2p_adj(const double* __restrict__ pos, const double* __restrict__ abar,
+                              int64_t n, const double* __restrict__ c, int p,
+                              const double* __restrict__ Lc, double* __restrict__ xbar) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double u0 = pos[3 * i] - c[0], u1 = pos[3 * i + 1] - c[1], u2 = pos[3 * i + 2] - c[2];
+  const double b0 = abar[3 * i], b1 = abar[3 * i + 1], b2 = abar[3 * i + 2];
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  double px = 1.0;
+  for (int a = 0; a < p; ++a) {
+    double py = 1.0;
+    for (int b = 0; a + b < p; ++b) {
+      double pz = 1.0;
+      for (int d = 0; a + b + d < p; ++d) {
+        const double m = (px * py) * pz;
+        // sum_k b_k L_{beta+e_k+e_l} for l = x, y, z
+        const double hx = b0 * Lc[slot3(a + 2, b, d)] + b1 * Lc[slot3(a + 1, b + 1, d)] +
+                          b2 * Lc[slot3(a + 1, b, d + 1)];
+        const double hy = b0 * Lc[slot3(a + 1, b + 1, d)] + b1 * Lc[slot3(a, b + 2, d)] +
+                          b2 * Lc[slot3(a, b + 1, d + 1)];
+        const double hz = b0 * Lc[slot3(a + 1, b, d + 1)] + b1 * Lc[slot3(a, b + 1, d + 1)] +
+                          b2 * Lc[slot3(a, b, d + 2)];
+        gx += m * hx;
+        gy += m * hy;
+        gz += m * hz;
+        pz *= u2 / (d + 1);
+      }
+      py *= u1 / (b + 1);
+    }
+    px *= u0 / (a + 1);
+  }
+  xbar[3 * i] += gx;
+  xbar[3 * i + 1] += gy;
+  xbar[3 * i + 2] += gz;
+}
+
+constexpr int kDChunk = 16;  // D entries per pass
+constexpr int kDBlocks = 1024;
+
+// per-block partial sums of D_gamma for gamma = g0 .. g0 + kDChunk - 1
+// (grid-stride over the particles; fixed order of the block reduction)
+__global__ __launch_bounds__(256) void k_far_dpart(const double* __restrict__ pos,
+                                                   const double* __restrict__ abar, int64_t n,
+                                                   const double* __restrict__ c, int g0, int ng,
+                                                   double* __restrict__ part) {
+  __shared__ double red[256];
+  int gi[kDChunk][3];
+  for (int q = 0; q < kDChunk; ++q) {
+    int b = g0 + q < ng ? g0 + q : 0;
+    int nn = 0;
+    while (tri(nn + 1) <= b) ++nn;
+    int r = b - tri(nn), ex = nn, ey = 0;
+    for (int a = nn; a >= 0; --a) {
+      if (r <= nn - a) {
+        ex = a;
+        ey = nn - a - r;
+        break;
+      }
+      r -= nn - a + 1;
+    }
+    gi[q][0] = ex;
+    gi[q][1] = ey;
+    gi[q][2] = nn - ex - ey;
+  }
+  double acc[kDChunk];
+  for (int q = 0; q < kDChunk; ++q) acc[q] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double u[3] = {pos[3 * i] - c[0], pos[3 * i + 1] - c[1], pos[3 * i + 2] - c[2]};
+    const double b[3] = {abar[3 * i], abar[3 * i + 1], abar[3 * i + 2]};
+    for (int q = 0; q < kDChunk; ++q) {
+      if (g0 + q >= ng) break;
+      double v = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        if (gi[q][k] == 0) continue;
+        double m = 1.0;
+        for (int d = 0; d < 3; ++d) {
+          const int e = gi[q][d] - (d == k);
+          for (int j = 1; j <= e; ++j) m *= u[d] / j;
+        }
+        v += b[k] * m;
+      }
+      acc[q] += v;
+    }
+  }
+  for (int q = 0; q < kDChunk && g0 + q < ng; ++q) {
+    red[threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ng + g0 + q] = red[0];
+    __syncthreads();
+  }
+}
+
+// Mbar(root)_alpha += w_alpha sum_gamma T_{alpha+gamma} D_gamma, D from the partials
+__global__ void k_far_mbar(const double* __restrict__ part, int nblocks, int ng, int p,
+                           const double* __restrict__ T, double* __restrict__ mbar_root) {
+  extern __shared__ double D[];
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * ng + g];
+    D[g] = s;
+  }
+  __syncthreads();
+  const int na = tri(p + 1);
+  for (int al = threadIdx.x; al < na; al += blockDim.x) {
+    int nn = 0;
+    while (tri(nn + 1) <= al) ++nn;
+    int r = al - tri(nn), ax = nn, ay = 0;
+    for (int a = nn; a >= 0; --a) {
+      if (r <= nn - a) {
+        ax = a;
+        ay = nn - a - r;
+        break;
+      }
+      r -= nn - a + 1;
+    }
+    const int az = nn - ax - ay;
+    double f = 1.0;
+    for (int q = 2; q <= ax; ++q) f *= q;
+    for (int q = 2; q <= ay; ++q) f *= q;
+    for (int q = 2; q <= az; ++q) f *= q;
+    const double w = ((nn & 1) ? -1.0 : 1.0) / f;
+    double acc = 0.0;
+    for (int s2 = 0; s2 <= p + 1; ++s2)
+      for (int g0 = s2; g0 >= 0; --g0)
+        for (int g1 = s2 - g0; g1 >= 0; --g1) {
+          const int g2 = s2 - g0 - g1;
+          acc += T[slot3(ax + g0, ay + g1, az + g2)] * D[slot3(g0, g1, g2)];
+        }
+    mbar_root[al] += w * acc;
+  }
+}
+
 }  // namespace
+
+void far_replicas_mbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,
+                       double* mbar_root) {
+  hipStream_t st = ctx->stream;
+  const int p = t->p, ng = tri(p + 2);
+  DBuf part;
+  part.alloc(ctx, (size_t)kDBlocks * ng * sizeof(double));
+  for (int g0 = 0; g0 < ng; g0 += kDChunk) {
+    k_far_dpart<<<kDBlocks, 256, 0, st>>>(pos, abar, t->n, t->c_centre.as<double>(), g0, ng,
+                                          part.as<double>());
+    HOT_CHECK_LAUNCH();
+  }
+  k_far_mbar<<<1, 256, ng * sizeof(double), st>>>(part.as<double>(), kDBlocks, ng, p,
+                                                  t->lattice.as<double>(), mbar_root);
+  HOT_CHECK_LAUNCH();
+}
+
+void far_replicas_xbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,
+                       double* xbar) {
+  hipStream_t st = ctx->stream;
+  const int p = t->p;
+  DBuf Lc;
+  Lc.alloc(ctx, tri(p + 2) * sizeof(double));
+  k_far_local<<<grid_for(tri(p + 2), 256), 256, 0, st>>>(t->mom64.as<double>(), p,
+                                                         t->lattice.as<double>(), Lc.as<double>());
+  HOT_CHECK_LAUNCH();
+  if (p >= 1) {
+    k_far_l2p_adj<<<grid_for(t->n, 256), 256, 0, st>>>(pos, abar, t->n, t->c_centre.as<double>(),
+                                                       p, Lc.as<double>(), xbar);
+    HOT_CHECK_LAUNCH();
+  }
+}
 
 void lattice_tensor(hot_ctx* ctx, hot_tree* t) {
   if (ctx->lattice_side != t->side) {

@@ -2,7 +2,8 @@
 cell; near replicas as image-tagged list entries, far replicas through
 lattice sums) against the oracle: lists and images bit-exact, forces against
 the oracle treecode on the same lists and against the Ewald direct sum,
-invariance under a periodic translation, and the entry point's checks."""
+invariance under a periodic translation, the adjoint against the oracle's VJP
+and against finite differences, and the entry point's checks."""
 import sys
 
 import numpy as np
@@ -95,6 +96,68 @@ def test_periodic_translation_invariance():
     assert e <= 1e-5  # two different trees: the treecode error, not rounding
 
 
+# small enough for the oracle's VJP (its expansion derivatives are generic and
+# periodic lists are long: every sink sees 125 images)
+ADJ_CASES = [
+    ("uniform", 4096, 4, 0.5, 0, 16, 64),
+    ("clustered", 1200, 6, 0.6, 16, 8, 32),
+    ("clustered", 700, 8, 0.5, 0, 8, 32),
+]
+
+
+@pytest.mark.parametrize("name,n,p,theta,dmax,n_leaf,n_group", ADJ_CASES)
+def test_periodic_adjoint_vs_oracle_vjp(name, n, p, theta, dmax, n_leaf, n_group):
+    pos_np, mass_np = _pos(name, n)
+    eps = 1e-3
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    gt = Tree(pos, n_leaf, n_group, BOX)
+    ot = oracle.Tree(pos_np, n_leaf, n_group, BOX)
+    gt.build_interaction_lists_periodic(theta, dmax)
+    ot.build_lists_periodic(theta, dmax)
+    gt.compute_moments(pos, mass, p)
+    ot.compute_moments(pos_np, mass_np, p)
+    abar_np = W.cotangent(n, 41)
+    ox, om = ot.vjp(pos_np, mass_np, eps, abar_np)
+    abar = torch.from_numpy(abar_np).cuda()
+    gx64, gm64 = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_FP64, with_mass=True)
+    gx, gm = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_MIXED, with_mass=True)
+    e64, m64 = rel_rms(gx64.cpu().numpy(), ox), rel_rms(gm64.cpu().numpy(), om)
+    e32, m32 = rel_rms(gx.cpu().numpy(), ox), rel_rms(gm.cpu().numpy(), om)
+    _log(name, n, "periodic adjoint fp64", e64, m64, "mixed", e32, m32)
+    assert e64 <= 1e-11 and m64 <= 1e-11
+    assert e32 <= 1e-5 and m32 <= 1e-5
+    gx2, _ = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_MIXED)
+    assert torch.equal(gx, gx2)
+
+
+def test_periodic_adjoint_directional_fd():
+    pos_np, mass_np = _clustered(10000, 13)
+    eps, p = 1e-3, 6
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    t = Tree(pos, 16, 64, BOX)
+    t.build_interaction_lists_periodic(0.5, 0)
+    t.compute_moments(pos, mass, p)
+    abar = torch.from_numpy(W.cotangent(pos_np.shape[0], 17)).cuda()
+    v = torch.from_numpy(np.random.default_rng(18).normal(size=pos_np.shape)).cuda()
+    xbar, _ = t.eval_forces_adjoint(pos, mass, eps, abar, HOT_FP64)
+
+    def L(x):
+        t.compute_moments(x, mass, p)
+        a, _, _ = t.eval_forces(x, mass, eps, HOT_FP64)
+        return float((a * abar).sum())
+
+    def cd(h):
+        return (L(pos + h * v) - L(pos - h * v)) / (2 * h)
+
+    h = 1e-6
+    fd = (4 * cd(h) - cd(2 * h)) / 3
+    an = float((xbar * v).sum())
+    _log("periodic directional", an, fd)
+    assert abs(an - fd) <= 1e-6 * abs(fd)
+
+
 def test_periodic_checks():
     w = W.make("uniform4k")
     pos = torch.from_numpy(w.pos).cuda()
@@ -110,7 +173,7 @@ def test_periodic_checks():
     t.compute_moments(pos, mass, 4)
     with pytest.raises(HotError):
         t.eval_forces(pos, mass, w.eps, HOT_MIXED, with_pot=True)
-    with pytest.raises(HotError):
-        t.eval_forces_adjoint(pos, mass, w.eps, torch.zeros_like(pos), HOT_MIXED)
     a, _, _ = t.eval_forces(pos, mass, w.eps, HOT_MIXED)
     assert torch.isfinite(a).all()
+    xb, _ = t.eval_forces_adjoint(pos, mass, w.eps, torch.zeros_like(pos), HOT_MIXED)
+    assert torch.all(xb == 0)
