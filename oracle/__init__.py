@@ -163,6 +163,29 @@ class Tree:
         _chk(lib().oracle_build_lists_periodic(self.h, ctypes.c_double(theta), int(direct_max),
                                                ctypes.c_int64(ns), _p(sel)))
 
+    def build_lists_periodic_bs(self, theta, direct_max=0, groups=None):
+        """Periodic lists with background subtraction: outside each group's
+        neighbourhood (the cube of three times its side) the sources are
+        matter minus the uniform mean density; evaluation adds the exact
+        fields of the listed boxes, takes off the neighbourhood's and adds
+        back the near zone's."""
+        sel = _i64(groups)
+        ns = 0 if sel is None else sel.shape[0]
+        _chk(lib().oracle_build_lists_periodic_bs(self.h, ctypes.c_double(theta), int(direct_max),
+                                                  ctypes.c_int64(ns), _p(sel)))
+
+    def background(self):
+        """(box_off (G+1), boxes (B, 6) lo|hi, sign (B,), m2p_sub (M2P entries,))."""
+        c = self.counts()
+        off = np.empty(c["n_groups"] + 1, np.int64)
+        _chk(lib().oracle_get_background(self.h, _p(off), None, None, None))
+        nb = int(off[-1])
+        boxes = np.empty((nb, 6))
+        sign = np.empty(nb, np.int8)
+        sub = np.empty(c["n_m2p"], np.int8)
+        _chk(lib().oracle_get_background(self.h, _p(off), _p(boxes), _p(sign), _p(sub)))
+        return off, boxes, sign, sub
+
     def list_images(self):
         c = self.counts()
         pi = np.empty(c["n_p2p"], np.int8)
@@ -256,6 +279,23 @@ def direct_vjp(pos, mass, eps, abar, rows=None):
                                  _p(abar), ctypes.c_int64(0 if r is None else T), _p(r),
                                  _p(xbar), _p(mbar)))
     return xbar, mbar
+
+
+def box_field(lo, hi, x):
+    """Field at points x (n, 3) of unit density filling the box [lo, hi]."""
+    lo = _f64(np.asarray(lo, dtype=np.float64))
+    hi = _f64(np.asarray(hi, dtype=np.float64))
+    x = _f64(np.atleast_2d(x))
+    out = np.empty_like(x)
+    _chk(lib().oracle_box_field(_p(lo), _p(hi), ctypes.c_int64(x.shape[0]), _p(x), _p(out)))
+    return out
+
+
+def cube_moments(p, s):
+    """Raw moments (slot order) of unit density filling a cube of side s."""
+    out = np.empty((p + 1) * (p + 2) * (p + 3) // 6)
+    _chk(lib().oracle_cube_moments(int(p), ctypes.c_double(s), _p(out)))
+    return out
 
 
 def lattice_tensor(L, K, split=2.0):

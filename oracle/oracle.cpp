@@ -18,6 +18,12 @@
 //     Improving instruction-level parallelism section) and the Cartesian
 //     cell-body multipole expansion with Delta = 0 (Multipole Error Bounds
 //     section), evaluated with the softened Green's function.
+//   * Variants of the lists: an absolute-error acceptance test choosing the
+//     order per interaction (Multipole Error Bounds section), periodic
+//     boundaries with far replicas by lattice sums (Boundary Conditions
+//     section), and on top of the periodic lists background subtraction
+//     (Background Subtraction section: density contrasts, cube moments
+//     subtracted to the matter's order, exact uniform-box fields).
 //   * The VJP (reverse derivative) of O-D and of O-T with the tree topology
 //     held fixed.
 //
@@ -154,6 +160,15 @@ struct Tree {
   // periodic lists: the image (0 .. 124) of every entry; empty otherwise
   std::vector<int8_t> p2p_img, m2p_img;
   bool periodic = false;
+  // background subtraction (periodic lists only): M2P entries whose cell lies
+  // outside the group's neighbourhood (1: the cell's uniform cube is taken
+  // off its moments), and per group the boxes whose uniform field is added
+  // exactly, with sign +1 or -1 (CSR, 6 doubles lo[3], hi[3] per box)
+  bool bg = false;
+  std::vector<int8_t> m2p_sub;
+  std::vector<int64_t> box_off;
+  std::vector<double> boxes;
+  std::vector<int8_t> box_sign;
   // moments
   int p = -1;
   std::vector<double> mom;        // n_cells x nm(p)
@@ -448,6 +463,11 @@ int build_lists(Tree& t, double theta, int direct_max, const std::vector<char>& 
   t.p2p_img.clear();
   t.m2p_img.clear();
   t.periodic = false;
+  t.bg = false;
+  t.m2p_sub.clear();
+  t.box_off.clear();
+  t.boxes.clear();
+  t.box_sign.clear();
   if (err) {
     t.m2p_q.resize(t.m2p_off[G]);
     for (int64_t g = 0; g < G; ++g) std::copy(lq[g].begin(), lq[g].end(), t.m2p_q.begin() + t.m2p_off[g]);
@@ -803,6 +823,177 @@ void walk_image(const Tree& t, const Cell& g, int64_t ci, const double sh[3], do
     walk_image(t, g, c.child_first + k, sh, theta, direct_max, img, p2p, pimg, m2p, mimg);
 }
 
+// ---------------------------------------------------------------------------
+// Background subtraction (Background Subtraction section and its figure).
+// The sources become density contrasts: from every source region the uniform
+// mean density rho = M_total / L^3 is taken off, and the total taken off over
+// the near zone (the 5L cube of the 125 images) is added back exactly, so
+// with nothing truncated the result is that of the lists without subtraction.
+// For a sink group g of side s_g its neighbourhood N(g) is the cube of side
+// 3 s_g about its centre. Source cells inside N(g) interact as usual (matter
+// only); the uniform background of N(g) is removed for all its sinks by the
+// exact field of that cube. Outside N(g) every region of space interacts as
+// matter minus background: an M2P cell through its moments minus those of its
+// uniform cube (to the same order as the matter), a P2P cell through its
+// pairs plus the exact field of its negative cube, an empty octant of an
+// opened cell through the exact field of its negative cube. A cell straddling
+// the border of N(g) is opened whatever the theta test says; if it is a leaf,
+// or for an empty octant that straddles, the part outside N(g) is the box
+// minus its intersection with N(g) (two exact box fields).
+// ---------------------------------------------------------------------------
+
+// ln(b + R) with R = sqrt(a^2 + b^2 + c^2), a^2 + c^2 > 0; for b < 0 written
+// as ln((a^2 + c^2) / (R - b)) to avoid the cancellation.
+double log_b_plus_r(double a, double b, double c, double R) {
+  if (b >= 0.0) return std::log(b + R);
+  return std::log(((a * a) + (c * c)) / (R - b));
+}
+
+// Phi(a, b, c) = a ln(b + R) + b ln(a + R) - c atan(a b / (c R)): a function
+// whose mixed derivative d^2/da db is 1/R (terms that vanish with their
+// factor are dropped, which is their limit).
+double box_phi(double a, double b, double c) {
+  const double R = std::sqrt((a * a + b * b) + c * c);
+  double t = 0.0;
+  if (a != 0.0) t += a * log_b_plus_r(a, b, c, R);
+  if (b != 0.0) t += b * log_b_plus_r(b, a, c, R);
+  if (c != 0.0) t -= c * std::atan((a * b) / (c * R));
+  return t;
+}
+
+// Field at x of unit density filling the box [lo, hi] (G = 1, unsoftened):
+//   a(x) = integral over the box of (y - x) / |y - x|^3 dy.
+// Along z the w-integral of w / R^3 is -1/R at the end points and the u, v
+// integrals of 1/R are double differences of Phi, so
+//   a_z = - sum over the 8 corners of s_u s_v s_w Phi(u, v, w),
+// u, v, w the corner's offsets from x and s = +1 at hi, -1 at lo; x and y
+// follow by symmetry.
+void box_field(const double lo[3], const double hi[3], const double x[3], double a[3]) {
+  const double u[2] = {lo[0] - x[0], hi[0] - x[0]};
+  const double v[2] = {lo[1] - x[1], hi[1] - x[1]};
+  const double w[2] = {lo[2] - x[2], hi[2] - x[2]};
+  a[0] = a[1] = a[2] = 0.0;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k) {
+        const double s = ((i ^ j ^ k) & 1) ? 1.0 : -1.0;  // s_u s_v s_w: -1 x (-1)^(#lo)
+        a[0] -= s * box_phi(v[j], w[k], u[i]);
+        a[1] -= s * box_phi(u[i], w[k], v[j]);
+        a[2] -= s * box_phi(u[i], v[j], w[k]);
+      }
+}
+
+// Raw moments of unit density filling a cube of side s about its centre:
+// prod_d 2 (s/2)^(alpha_d + 1) / (alpha_d + 1) for all alpha_d even, else 0.
+double cube_moment(int a, int b, int c, double s) {
+  if ((a & 1) || (b & 1) || (c & 1)) return 0.0;
+  const int al[3] = {a, b, c};
+  double m = 1.0;
+  for (int d = 0; d < 3; ++d) m *= 2.0 * ipow(0.5 * s, al[d] + 1) / (double)(al[d] + 1);
+  return m;
+}
+
+enum Rel { kInside = 0, kOutside = 1, kStraddle = 2 };
+
+// Relation of the box [blo, bhi] to N = [nlo, nhi].
+int box_rel(const double blo[3], const double bhi[3], const double nlo[3], const double nhi[3]) {
+  bool inside = true, outside = false;
+  for (int d = 0; d < 3; ++d) {
+    inside = inside && blo[d] >= nlo[d] && bhi[d] <= nhi[d];
+    outside = outside || bhi[d] <= nlo[d] || blo[d] >= nhi[d];
+  }
+  return inside ? kInside : (outside ? kOutside : kStraddle);
+}
+
+struct BgLists {
+  std::vector<int8_t> msub;
+  std::vector<double> boxes;
+  std::vector<int8_t> sign;
+  void push(const double lo[3], const double hi[3], int sg) {
+    for (int d = 0; d < 3; ++d) boxes.push_back(lo[d]);
+    for (int d = 0; d < 3; ++d) boxes.push_back(hi[d]);
+    sign.push_back((int8_t)sg);
+  }
+  // negative background over [lo, hi] minus N
+  void push_outside(const double lo[3], const double hi[3], int rel, const double nlo[3],
+                    const double nhi[3]) {
+    if (rel == kInside) return;
+    push(lo, hi, -1);
+    if (rel == kStraddle) {
+      double ilo[3], ihi[3];
+      for (int d = 0; d < 3; ++d) {
+        ilo[d] = std::max(lo[d], nlo[d]);
+        ihi[d] = std::min(hi[d], nhi[d]);
+      }
+      push(ilo, ihi, +1);
+    }
+  }
+};
+
+// periodic walk with background subtraction; N = [nlo, nhi] is N(g)
+void walk_image_bs(const Tree& t, const Cell& g, const double nlo[3], const double nhi[3],
+                   int64_t ci, const double sh[3], double theta, int direct_max, int img,
+                   std::vector<int32_t>& p2p, std::vector<int8_t>& pimg,
+                   std::vector<int32_t>& m2p, std::vector<int8_t>& mimg, BgLists& bl) {
+  const Cell& c = t.cells[ci];
+  const double cx[3] = {c.centre[0] + sh[0], c.centre[1] + sh[1], c.centre[2] + sh[2]};
+  const double h = std::ldexp(t.side, -(c.level + 1));
+  const double blo[3] = {cx[0] - h, cx[1] - h, cx[2] - h};
+  const double bhi[3] = {cx[0] + h, cx[1] + h, cx[2] + h};
+  const int rel = box_rel(blo, bhi, nlo, nhi);
+  double dx = g.centre[0] - cx[0];
+  double dy = g.centre[1] - cx[1];
+  double dz = g.centre[2] - cx[2];
+  double d2 = (dx * dx + dy * dy) + dz * dz;
+  double rr = c.bmax / theta + g.bmax;
+  if (rel != kStraddle && d2 > rr * rr) {
+    if (c.count <= direct_max) {
+      p2p.push_back((int32_t)ci);
+      pimg.push_back((int8_t)img);
+      bl.push_outside(blo, bhi, rel, nlo, nhi);
+    } else {
+      m2p.push_back((int32_t)ci);
+      mimg.push_back((int8_t)img);
+      bl.msub.push_back((int8_t)(rel == kOutside));
+    }
+    return;
+  }
+  if (c.is_leaf) {
+    p2p.push_back((int32_t)ci);
+    pimg.push_back((int8_t)img);
+    bl.push_outside(blo, bhi, rel, nlo, nhi);
+    return;
+  }
+  // opened: its empty octants first (octant o = 4 x + 2 y + z, key order),
+  // then its children
+  if (rel != kInside) {
+    bool has[8] = {false, false, false, false, false, false, false, false};
+    for (int k = 0; k < c.n_child; ++k) has[t.cells[c.child_first + k].key & 7u] = true;
+    for (int o = 0; o < 8; ++o) {
+      if (has[o]) continue;
+      const int bit[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
+      double olo[3], ohi[3];
+      for (int d = 0; d < 3; ++d) {
+        olo[d] = bit[d] ? cx[d] : blo[d];
+        ohi[d] = bit[d] ? bhi[d] : cx[d];
+      }
+      bl.push_outside(olo, ohi, box_rel(olo, ohi, nlo, nhi), nlo, nhi);
+    }
+  }
+  for (int k = 0; k < c.n_child; ++k)
+    walk_image_bs(t, g, nlo, nhi, c.child_first + k, sh, theta, direct_max, img, p2p, pimg, m2p,
+                  mimg, bl);
+}
+
+// N(g): the cube of side 3 s_g about the group's centre
+void neighbourhood(const Tree& t, const Cell& g, double nlo[3], double nhi[3]) {
+  const double h3 = 3.0 * std::ldexp(t.side, -(g.level + 1));
+  for (int d = 0; d < 3; ++d) {
+    nlo[d] = g.centre[d] - h3;
+    nhi[d] = g.centre[d] + h3;
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -968,9 +1159,22 @@ int oracle_build_lists_err(void* h, const double* mass, double tol, int pmax, in
 // tree (the cube and its neighbours, image = 25 (n_x + 2) + 5 (n_y + 2) +
 // (n_z + 2)), images in that order, each a depth-first walk; the root cube is
 // the periodic cell. The tree must have been built with a given box.
+int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
+                         const int64_t* sel, bool bs);
+
 int oracle_build_lists_periodic(void* h, double theta, int direct_max, int64_t n_sel,
                                 const int64_t* sel) {
-  Tree* t = (Tree*)h;
+  return build_lists_periodic((Tree*)h, theta, direct_max, n_sel, sel, false);
+}
+
+// Periodic lists with background subtraction (see walk_image_bs).
+int oracle_build_lists_periodic_bs(void* h, double theta, int direct_max, int64_t n_sel,
+                                   const int64_t* sel) {
+  return build_lists_periodic((Tree*)h, theta, direct_max, n_sel, sel, true);
+}
+
+int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
+                         const int64_t* sel, bool bs) {
   if (!(theta > 0 && theta < 1)) return fail("theta must lie in (0, 1)");
   if (direct_max < 0) return fail("direct_max must be >= 0");
   std::vector<char> want;
@@ -984,14 +1188,35 @@ int oracle_build_lists_periodic(void* h, double theta, int direct_max, int64_t n
   const int64_t G = (int64_t)t->groups.size();
   std::vector<std::vector<int32_t>> lp(G), lm(G);
   std::vector<std::vector<int8_t>> ip(G), im(G);
+  std::vector<BgLists> bl(bs ? G : 0);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t g = 0; g < G; ++g) {
     if (!(want.empty() || want[g])) continue;
+    const Cell& gc = t->cells[t->groups[g]];
+    double nlo[3], nhi[3];
+    neighbourhood(*t, gc, nlo, nhi);
     for (int img = 0; img < kImages; ++img) {
       double sh[3];
       image_shift(img, t->side, sh);
-      walk_image(*t, t->cells[t->groups[g]], 0, sh, theta, direct_max, img, lp[g], ip[g], lm[g],
-                 im[g]);
+      if (bs)
+        walk_image_bs(*t, gc, nlo, nhi, 0, sh, theta, direct_max, img, lp[g], ip[g], lm[g], im[g],
+                      bl[g]);
+      else
+        walk_image(*t, gc, 0, sh, theta, direct_max, img, lp[g], ip[g], lm[g], im[g]);
+    }
+  }
+  t->bg = bs;
+  t->m2p_sub.clear();
+  t->box_off.clear();
+  t->boxes.clear();
+  t->box_sign.clear();
+  if (bs) {
+    t->box_off.assign(G + 1, 0);
+    for (int64_t g = 0; g < G; ++g) {
+      t->box_off[g + 1] = t->box_off[g] + (int64_t)bl[g].sign.size();
+      t->m2p_sub.insert(t->m2p_sub.end(), bl[g].msub.begin(), bl[g].msub.end());
+      t->boxes.insert(t->boxes.end(), bl[g].boxes.begin(), bl[g].boxes.end());
+      t->box_sign.insert(t->box_sign.end(), bl[g].sign.begin(), bl[g].sign.end());
     }
   }
   t->p2p_off.assign(G + 1, 0);
@@ -1017,6 +1242,35 @@ int oracle_build_lists_periodic(void* h, double theta, int direct_max, int64_t n
   t->periodic = true;
   t->theta = theta;
   t->direct_max = direct_max;
+  return 0;
+}
+
+// Background-subtracted lists: box CSR offsets (G + 1), boxes (6 per box:
+// lo[3], hi[3]), their signs, and the subtraction flag of every M2P entry.
+int oracle_get_background(void* h, int64_t* box_off, double* boxes, int8_t* box_sign,
+                          int8_t* m2p_sub) {
+  Tree* t = (Tree*)h;
+  if (!t->has_lists || !t->bg) return fail("no background-subtracted lists");
+  if (box_off) std::copy(t->box_off.begin(), t->box_off.end(), box_off);
+  if (boxes) std::copy(t->boxes.begin(), t->boxes.end(), boxes);
+  if (box_sign) std::copy(t->box_sign.begin(), t->box_sign.end(), box_sign);
+  if (m2p_sub) std::copy(t->m2p_sub.begin(), t->m2p_sub.end(), m2p_sub);
+  return 0;
+}
+
+// Raw moments, slots 0 .. nm(p) - 1, of unit density filling a cube of side s
+// about its centre (for the pins).
+int oracle_cube_moments(int p, double s, double* out) {
+  ensure_alpha();
+  if (p < 0 || p > 12) return fail("p must lie in [0, 12]");
+  for (int sl = 0; sl < nm(p); ++sl)
+    out[sl] = cube_moment(g_alpha[3 * sl], g_alpha[3 * sl + 1], g_alpha[3 * sl + 2], s);
+  return 0;
+}
+
+// Field of unit density filling [lo, hi] at n points (for the pins).
+int oracle_box_field(const double* lo, const double* hi, int64_t n, const double* x, double* a) {
+  for (int64_t i = 0; i < n; ++i) box_field(lo, hi, &x[3 * i], &a[3 * i]);
   return 0;
 }
 
@@ -1196,6 +1450,13 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
         far_L[b] += w * M[sl] * Tg[slot_of(gsum)];
       }
   }
+  // background subtraction: the mean density, total mass (the root's
+  // monopole) over the cube's volume
+  double bg_rho = 0.0;
+  if (t->bg) {
+    if (!t->mom_valid[0]) return fail("moments of the root are needed for the background");
+    bg_rho = t->mom[0] / (t->side * t->side * t->side);
+  }
   int64_t c_p2p = 0, c_m2p = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : c_p2p, c_m2p)
   for (int64_t k = 0; k < T; ++k) {
@@ -1217,6 +1478,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
         p2p_pair(mass[t->perm[j]], r, eps, a, &ph);
       }
     }
+    std::vector<double> msub(t->bg ? K : 0);
     for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e) {
       const int64_t cid = t->m2p[e];
       const Cell& c = t->cells[cid];
@@ -1226,10 +1488,41 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
                      xi[2] - (c.centre[2] + sh[2])};
       double da[3], dphi;
       const int q = t->list_p >= 0 ? (int)t->m2p_q[e] : t->p;
-      m2p_one(&t->mom[cid * K], q, R, eps, da, &dphi);
+      const double* Mc = &t->mom[cid * K];
+      if (t->bg && t->m2p_sub[e]) {
+        // matter minus the uniform cube of the cell, order by order up to p
+        const double s = std::ldexp(t->side, -c.level);
+        for (int sl = 0; sl < K; ++sl) {
+          const int* al = &g_alpha[3 * sl];
+          msub[sl] = Mc[sl] - bg_rho * cube_moment(al[0], al[1], al[2], s);
+        }
+        Mc = msub.data();
+      }
+      m2p_one(Mc, q, R, eps, da, &dphi);
       a[0] += da[0], a[1] += da[1], a[2] += da[2];
       ph += dphi;
       c_m2p += 1;
+    }
+    if (t->bg) {
+      // background: the listed boxes, minus N(g), plus the 5L cube of the
+      // near zone (exact fields, FP64)
+      double f[3];
+      for (int64_t b = t->box_off[g]; b < t->box_off[g + 1]; ++b) {
+        box_field(&t->boxes[6 * b], &t->boxes[6 * b + 3], xi, f);
+        const double sg = (double)t->box_sign[b];
+        for (int d = 0; d < 3; ++d) a[d] += sg * bg_rho * f[d];
+      }
+      double nlo[3], nhi[3];
+      neighbourhood(*t, t->cells[t->groups[g]], nlo, nhi);
+      box_field(nlo, nhi, xi, f);
+      for (int d = 0; d < 3; ++d) a[d] -= bg_rho * f[d];
+      double zlo[3], zhi[3];
+      for (int d = 0; d < 3; ++d) {
+        zlo[d] = t->lo[d] - (double)kWs * t->side;
+        zhi[d] = t->lo[d] + (double)(kWs + 1) * t->side;
+      }
+      box_field(zlo, zhi, xi, f);
+      for (int d = 0; d < 3; ++d) a[d] += bg_rho * f[d];
     }
     if (t->periodic) {
       // far replicas: a_k = sum_{|beta| <= p} u^beta/beta! L_{beta+e_k}
@@ -1330,6 +1623,7 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
   if (!t->list_sel.empty()) return fail("the VJP needs the lists of every group");
   if (t->p < 0) return fail("moments not computed");
   if (t->p < t->list_p) return fail("moments of lower order than the lists");
+  if (t->bg) return fail("the VJP of background-subtracted lists is not provided");
   const int64_t n = t->n;
   const int p = t->p;
   const int K = nm(p);
