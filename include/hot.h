@@ -178,6 +178,30 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
 int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
 
 /*
+ * build_interaction_lists_periodic_bs -- the periodic lists above with
+ * background subtraction (Background Subtraction section and its figure):
+ * the sources become density contrasts, matter minus the mean density
+ * rho = M_total / L^3 (M_total the root's monopole at evaluation). For a
+ * sink group of side s, N(g) is the cube of side 3 s about its centre.
+ * Source cells inside N(g) interact as usual. Outside it every M2P entry
+ * uses its cell's moments minus those of its uniform cube, to the same
+ * order as the matter (flagged per entry, tree_get_background), and P2P
+ * cells and empty octants of opened cells contribute the exact field of
+ * their negative uniform cube, listed per group as boxes with sign -1; a
+ * cell straddling the border of N(g) is opened whatever the theta test
+ * says, and where a straddling leaf or empty octant remains, its
+ * intersection with N(g) is listed with sign +1. eval_forces then adds, per
+ * sink, rho times the exact fields of its group's boxes, minus N(g)'s, plus
+ * that of the whole 5L cube of the near zone (unsoftened, FP64), so that
+ * with no truncation the result equals that of the periodic lists without
+ * subtraction. Potentials and the adjoint are not available with these
+ * lists (HOT_E_INVALID, HOT_E_STATE). theta: (0, 1); direct_max: >= 0.
+ * Synchronises the stream.
+ */
+int build_interaction_lists_periodic_bs(hot_ctx* ctx, hot_tree* tree, double theta,
+                                        int direct_max);
+
+/*
  * eval_forces -- accelerations (and optionally potentials) of all particles:
  *   a_i = sum over P2P cells, j != i:  m_j (x_j - x_i) (|x_j - x_i|^2 + eps^2)^(-3/2)
  *       + sum over M2P cells c:  -sum_{|alpha|<=p} (-1)^|alpha|/alpha! M_alpha
@@ -211,8 +235,8 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
 /* ---- host-copy getters (synchronise; for tests and diagnostics) ---------- */
 
 /* out[16]: n, n_cells, n_groups, n_leaves, max_level, n_p2p_entries,
- * n_m2p_entries, p (or -1), n_work_items, hash_slots, 0... (-1 where not yet
- * built). */
+ * n_m2p_entries, p (or -1), n_work_items, hash_slots, p2p_pairs, m2p_pairs,
+ * n_background_boxes, 0... (-1 where not yet built or not applicable). */
 int tree_get_counts(hot_ctx* ctx, hot_tree* tree, int64_t* out);
 /* HOST: lo_side[4] = root cube lo[3], side. */
 int tree_get_root(hot_ctx* ctx, hot_tree* tree, double* lo_side);
@@ -235,6 +259,14 @@ int tree_get_lists(hot_ctx* ctx, hot_tree* tree, int64_t* p2p_off, int32_t* p2p,
 /* Expansion order of every M2P entry (host out, n_m2p int8, list order);
  * HOT_E_STATE unless the lists came from build_interaction_lists_err. */
 int tree_get_m2p_orders(hot_ctx* ctx, hot_tree* tree, int8_t* orders);
+
+/* Background-subtracted lists (host outs, each may be NULL): box_off
+ * n_groups + 1 (CSR offsets), boxes 6 per box (lo[3], hi[3]), box_sign one
+ * per box (+1 / -1), m2p_sub one per M2P entry (1: the cell's uniform cube is
+ * subtracted). HOT_E_STATE unless the lists came from
+ * build_interaction_lists_periodic_bs. */
+int tree_get_background(hot_ctx* ctx, hot_tree* tree, int64_t* box_off, double* boxes,
+                        int8_t* box_sign, int8_t* m2p_sub);
 
 /* Image (0 .. 124) of every P2P and M2P entry of periodic lists (host out,
  * n_p2p and n_m2p int8, list order; either may be NULL); HOT_E_STATE unless

@@ -27,7 +27,8 @@ EXPORTS = ["hot_ctx_create", "hot_ctx_destroy", "hot_last_error", "hot_sync", "t
            "eval_forces_adjoint", "tree_get_counts", "tree_get_root", "tree_get_keys",
            "tree_get_cells", "tree_get_groups", "tree_get_lists", "tree_get_moments",
            "tree_lookup", "build_interaction_lists_err", "tree_get_m2p_orders",
-           "build_interaction_lists_periodic", "tree_get_list_images"]
+           "build_interaction_lists_periodic", "tree_get_list_images",
+           "build_interaction_lists_periodic_bs", "tree_get_background"]
 
 
 class HotError(RuntimeError):
@@ -81,6 +82,8 @@ def load(path: Optional[str] = None):
     L.tree_get_m2p_orders.argtypes = [vp, vp, vp]
     L.build_interaction_lists_periodic.argtypes = [vp, vp, dbl, i32]
     L.tree_get_list_images.argtypes = [vp, vp, vp, vp]
+    L.build_interaction_lists_periodic_bs.argtypes = [vp, vp, dbl, i32]
+    L.tree_get_background.argtypes = [vp, vp, vp, vp, vp, vp]
     L.eval_forces.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     L.eval_forces_adjoint.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, vp]
     L.tree_get_counts.argtypes = [vp, vp, vp]
@@ -237,6 +240,25 @@ class Tree:
         self.ctx.check(load().build_interaction_lists_periodic(self.ctx.h, self.h, float(theta),
                                                                int(direct_max)))
 
+    def build_interaction_lists_periodic_bs(self, theta, direct_max=0):
+        """Periodic lists with background subtraction: outside each group's
+        neighbourhood (three group sides) the sources are matter minus the
+        mean density; eval_forces adds the exact uniform-box fields."""
+        self.ctx.check(load().build_interaction_lists_periodic_bs(
+            self.ctx.h, self.h, float(theta), int(direct_max)))
+
+    def background(self):
+        """(box_off (G+1), boxes (B, 6) lo|hi, sign (B,), m2p_sub (M2P entries,))."""
+        c = self.counts()
+        off = np.empty(c["n_groups"] + 1, np.int64)
+        nb = max(c["n_boxes"], 0)
+        boxes = np.empty((nb, 6))
+        sign = np.empty(nb, np.int8)
+        sub = np.empty(max(c["n_m2p"], 0), np.int8)
+        self.ctx.check(load().tree_get_background(self.ctx.h, self.h, _np(off), _np(boxes),
+                                                  _np(sign), _np(sub)))
+        return off, boxes, sign, sub
+
     def list_images(self):
         c = self.counts()
         pi = np.empty(max(c["n_p2p"], 0), np.int8)
@@ -277,7 +299,7 @@ class Tree:
         out = np.zeros(16, np.int64)
         self.ctx.check(load().tree_get_counts(self.ctx.h, self.h, _np(out)))
         keys = ["n", "n_cells", "n_groups", "n_leaves", "max_level", "n_p2p", "n_m2p", "p",
-                "n_items", "hash_slots", "p2p_pairs", "m2p_pairs"]
+                "n_items", "hash_slots", "p2p_pairs", "m2p_pairs", "n_boxes"]
         return {k: int(out[i]) for i, k in enumerate(keys)}
 
     def root(self):

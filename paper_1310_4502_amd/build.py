@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libhot.so")
 SOURCES = ["api.hip", "scan_sort.hip", "tree.hip", "moments.hip", "walk.hip", "eval.hip",
-           "adjoint.hip", "periodic.hip"]
+           "adjoint.hip", "periodic.hip", "background.hip"]
 ARCH = os.environ.get("HOT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

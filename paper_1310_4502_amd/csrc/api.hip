@@ -264,6 +264,24 @@ int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta,
   });
 }
 
+int build_interaction_lists_periodic_bs(hot_ctx* ctx, hot_tree* tree, double theta,
+                                        int direct_max) {
+  return guard(ctx, [&] {
+    need_tree(ctx, tree);
+    if (!tree->box_given) hot::state("periodic lists need a tree built with a given box");
+    if (!(theta > 0.0 && theta < 1.0)) hot::invalid("theta must lie in (0, 1)");
+    if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    try {
+      hot::build_lists_periodic_bs(ctx, tree, theta, direct_max);
+    } catch (...) {
+      tree->has_lists = false;
+      tree->periodic = false;
+      tree->bg = false;
+      throw;
+    }
+  });
+}
+
 int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass, double eps,
                 int precision, double* acc, double* pot, hot_stats* stats) {
   return guard(ctx, [&] {
@@ -277,6 +295,7 @@ int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* m
     if (tree->periodic && pot) hot::invalid("potentials are not available with periodic lists");
     hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats);
     if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc);
+    if (tree->bg) hot::background_boxes(ctx, tree, pos, acc);
   });
 }
 
@@ -289,6 +308,7 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     if (!(eps >= 0.0) || !std::isfinite(eps)) hot::invalid("eps must be finite and >= 0");
     if (precision != HOT_MIXED && precision != HOT_FP64) hot::invalid("unknown precision");
     if (!tree->has_lists) hot::state("build_interaction_lists first");
+    if (tree->bg) hot::state("the adjoint of background-subtracted lists is not provided");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
     hot::adjoint(ctx, tree, pos, mass, eps, precision, acc_bar, pos_bar, mass_bar);
@@ -317,6 +337,7 @@ int tree_get_counts(hot_ctx* ctx, hot_tree* t, int64_t* out) {
     out[9] = (int64_t)t->hash_slots;
     out[10] = t->has_lists ? t->p2p_pairs : -1;
     out[11] = t->has_lists ? t->m2p_pairs : -1;
+    out[12] = t->has_lists && t->bg ? t->n_boxes : -1;
   });
 }
 
@@ -390,6 +411,19 @@ int tree_get_list_images(hot_ctx* ctx, hot_tree* t, int8_t* p2p_img, int8_t* m2p
     if (!t->has_lists || !t->periodic) hot::state("no periodic lists");
     d2h<int8_t>(ctx, p2p_img, t->p2p_img.p, t->n_p2p);
     d2h<int8_t>(ctx, m2p_img, t->m2p_img.p, t->n_m2p);
+    HOT_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tree_get_background(hot_ctx* ctx, hot_tree* t, int64_t* box_off, double* boxes,
+                        int8_t* box_sign, int8_t* m2p_sub) {
+  return guard(ctx, [&] {
+    need_tree(ctx, t);
+    if (!t->has_lists || !t->bg) hot::state("no background-subtracted lists");
+    if (box_off) d2h<int64_t>(ctx, box_off, t->box_off.p, t->n_groups + 1);
+    if (boxes) d2h<double>(ctx, boxes, t->boxes.p, 6 * t->n_boxes);
+    if (box_sign) d2h<int8_t>(ctx, box_sign, t->box_sign.p, t->n_boxes);
+    if (m2p_sub) d2h<int8_t>(ctx, m2p_sub, t->m2p_sub.p, t->n_m2p);
     HOT_HIP(hipStreamSynchronize(ctx->stream));
   });
 }

@@ -149,6 +149,13 @@ struct hot_tree {
   bool box_given = false;
   bool periodic = false;
   hot::DBuf p2p_img, m2p_img, lattice;
+  // background subtraction (periodic lists only): per M2P entry 1 if its
+  // cell's uniform cube is subtracted; per group (CSR) the boxes whose exact
+  // uniform field enters with sign +1 / -1 (lo[3], hi[3] each); the
+  // subtracted weighted moments built at evaluation
+  bool bg = false;
+  int64_t n_boxes = 0;
+  hot::DBuf m2p_sub, box_off, boxes, box_sign, momsub;
   // eval work items: (group, first sink) per wave
   int64_t n_items = 0;
   hot::DBuf items;
@@ -192,6 +199,12 @@ void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
                      int direct_max);
 void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
+void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
+// weighted scaled moments minus those of each cell's uniform cube of the mean
+// density (into t->momsub, FP32 or FP64 as asked)
+void weighted_sub(hot_ctx* ctx, hot_tree* t, bool fp64);
+// exact background fields of the listed boxes, minus N(g), plus the near zone
+void background_boxes(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
 void lattice_tensor(hot_ctx* ctx, hot_tree* t);
 void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
 void far_replicas_mbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,

@@ -153,12 +153,15 @@ constexpr int m2p_waves_per_simd() { return (sizeof(T) == 4 && P >= 7) ? 4 : 1; 
 
 // MIXQ: every entry carries its own order q <= P (m2p_q), error-bound lists.
 // PER: every entry carries the image of its cell (periodic lists).
-template <int P, typename T, bool POT, bool MIXQ, bool PER>
+// BG: background subtraction; an entry flagged in m2p_sub takes its cell's
+// moments minus those of its uniform cube (momsub) instead of momw.
+template <int P, typename T, bool POT, bool MIXQ, bool PER, bool BG>
 __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(m2p_waves_per_simd<P, T>())))
 void k_m2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
     const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_q,
-    const int8_t* __restrict__ m2p_img, double side,
+    const int8_t* __restrict__ m2p_img, double side, const int8_t* __restrict__ m2p_sub,
+    const T* __restrict__ momsub,
     const int8_t* __restrict__ c_level,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
@@ -194,12 +197,13 @@ void k_m2p(
   const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
   T* slot = smom + (Stage::kLds ? w * Stage::kStride : 0);
   typename Stage::Regs pre;
-  int cn = 0, ln = 0, qn = P;
+  int cn = 0, ln = 0, qn = P, sn = 0;
   double nx = 0, ny = 0, nz = 0;
   if (e0 < e1) {
     cn = uniform_i32(m2p[e0]);
     if (MIXQ) qn = uniform_i32(m2p_q[e0]);
-    Stage::prefetch(pre, momw, cn, lane);
+    if (BG) sn = uniform_i32(m2p_sub[e0]);
+    Stage::prefetch(pre, (BG && sn) ? momsub : momw, cn, lane);
     ln = c_level[cn];
     nx = c_centre[3 * cn];
     ny = c_centre[3 * cn + 1];
@@ -219,11 +223,12 @@ void k_m2p(
     const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
     const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
     const T Z = (T)((cgz - nz) * inv_s) + me.z * (T)inv_s;
-    const T* M = Stage::commit(pre, momw, c, slot, lane);
+    const T* M = Stage::commit(pre, (BG && sn) ? momsub : momw, c, slot, lane);
     if (e + 1 < e1) {
       cn = uniform_i32(m2p[e + 1]);
       if (MIXQ) qn = uniform_i32(m2p_q[e + 1]);
-      Stage::prefetch(pre, momw, cn, lane);
+      if (BG) sn = uniform_i32(m2p_sub[e + 1]);
+      Stage::prefetch(pre, (BG && sn) ? momsub : momw, cn, lane);
       ln = c_level[cn];
       nx = c_centre[3 * cn];
       ny = c_centre[3 * cn + 1];
@@ -303,38 +308,46 @@ void launch_p2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, double eps, T* stat
 }
 
 template <int P, typename T, bool POT>
-void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, double eps,
-                  T* state) {
+void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, const T* momsub,
+                  double eps, T* state) {
   const unsigned grid = grid_for(t->n_items, kWavesPerBlock);
   auto go = [&](auto kern) {
     kern<<<grid, kB, 0, ctx->stream>>>(
         t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
-        t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
-        t->g_first.as<int32_t>(),
-        t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, momw,
-        1.0 / t->side, eps, state);
+        t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->m2p_sub.as<int8_t>(), momsub,
+        t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+        t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, momw, 1.0 / t->side, eps, state);
     HOT_CHECK_LAUNCH();
   };
-  if (t->list_p >= 0)
-    go(k_m2p<P, T, POT, true, false>);
-  else if (t->periodic)
-    go(k_m2p<P, T, POT, false, true>);
-  else
-    go(k_m2p<P, T, POT, false, false>);
+  if (t->list_p >= 0) {
+    go(k_m2p<P, T, POT, true, false, false>);
+  } else if (t->periodic) {
+    // potentials are refused with periodic lists: no subtracted variant for them
+    if constexpr (!POT) {
+      if (t->bg) {
+        go(k_m2p<P, T, POT, false, true, true>);
+        return;
+      }
+    }
+    go(k_m2p<P, T, POT, false, true, false>);
+  } else {
+    go(k_m2p<P, T, POT, false, false, false>);
+  }
 }
 
 template <typename T, bool POT>
-void launch_m2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, double eps, T* state) {
+void launch_m2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, const T* momsub,
+                double eps, T* state) {
   switch (t->p) {
-    case 0: launch_m2p_p<0, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 1: launch_m2p_p<1, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 2: launch_m2p_p<2, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 3: launch_m2p_p<3, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 4: launch_m2p_p<4, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 5: launch_m2p_p<5, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 6: launch_m2p_p<6, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 7: launch_m2p_p<7, T, POT>(ctx, t, off, momw, eps, state); break;
-    case 8: launch_m2p_p<8, T, POT>(ctx, t, off, momw, eps, state); break;
+    case 0: launch_m2p_p<0, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 1: launch_m2p_p<1, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 2: launch_m2p_p<2, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 3: launch_m2p_p<3, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 4: launch_m2p_p<4, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 5: launch_m2p_p<5, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 6: launch_m2p_p<6, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 7: launch_m2p_p<7, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 8: launch_m2p_p<8, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
     default: invalid("p out of range");
   }
 }
@@ -359,6 +372,11 @@ void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, 
     weighted_fp64(ctx, t);
     momw = t->momw64.as<T>();
   }
+  const T* momsub = nullptr;
+  if (t->bg) {
+    weighted_sub(ctx, t, sizeof(T) == 8);
+    momsub = t->momsub.as<T>();
+  }
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[0], st));
   if (pot)
     launch_p2p<T, true>(ctx, t, off.as<V4<T>>(), eps, state.as<T>());
@@ -366,9 +384,9 @@ void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, 
     launch_p2p<T, false>(ctx, t, off.as<V4<T>>(), eps, state.as<T>());
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[1], st));
   if (pot)
-    launch_m2p<T, true>(ctx, t, off.as<V4<T>>(), momw, eps, state.as<T>());
+    launch_m2p<T, true>(ctx, t, off.as<V4<T>>(), momw, momsub, eps, state.as<T>());
   else
-    launch_m2p<T, false>(ctx, t, off.as<V4<T>>(), momw, eps, state.as<T>());
+    launch_m2p<T, false>(ctx, t, off.as<V4<T>>(), momw, momsub, eps, state.as<T>());
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[2], st));
   k_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(state.as<T>(), t->perm.as<uint32_t>(), n, acc, pot);
   HOT_CHECK_LAUNCH();

@@ -163,7 +163,56 @@ __global__ void k_weighted(const double* __restrict__ mom, int64_t C,
   out[c * stride + s] = (T)(kAlpha.w[s] * (mom[c * nmv + s] * sc));
 }
 
+// The same weighted scaled moments with each cell's uniform cube of the mean
+// density taken off (background subtraction). Scaled by the cell side s, the
+// raw moments of a cube of mass m_c are m_c prod_d 2^(-alpha_d) / (alpha_d + 1)
+// for all alpha_d even (zero otherwise), and m_c = M_total 2^(-3 level): the
+// mean density M_total / L^3 (M_total the root's monopole) times s^3.
+template <typename T>
+__global__ void k_weighted_sub(const double* __restrict__ mom, int64_t C,
+                               const int8_t* __restrict__ c_level, double inv_side, int p,
+                               T* __restrict__ out) {
+  const int nmv = nm(p), stride = nm_pad(p);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = t / stride;
+  const int s = (int)(t - c * stride);
+  if (c >= C) return;
+  if (s >= nmv) {
+    out[c * stride + s] = T(0);
+    return;
+  }
+  const int a = kAlpha.a[s], b = kAlpha.b[s], cc = kAlpha.c[s];
+  const int order = a + b + cc;
+  const int lev = (int)c_level[c];
+  const double inv_s = ldexp(inv_side, lev);
+  double sc = 1.0;
+  for (int k = 0; k < order; ++k) sc *= inv_s;
+  double v = mom[c * nmv + s] * sc;
+  if (!((a | b | cc) & 1)) {
+    const double cube = ldexp(mom[0], -3 * lev - order) /
+                        ((double)(a + 1) * (double)(b + 1) * (double)(cc + 1));
+    v -= cube;
+  }
+  out[c * stride + s] = (T)(kAlpha.w[s] * v);
+}
+
 }  // namespace
+
+void weighted_sub(hot_ctx* ctx, hot_tree* t, bool fp64) {
+  const int64_t C = t->n_cells;
+  const int p = t->p;
+  const int64_t tot = C * nm_pad(p);
+  t->momsub.alloc(ctx, (size_t)tot * (fp64 ? sizeof(double) : sizeof(float)));
+  if (fp64)
+    k_weighted_sub<double><<<grid_for(tot, kB), kB, 0, ctx->stream>>>(
+        t->mom64.as<double>(), C, t->c_level.as<int8_t>(), 1.0 / t->side, p,
+        t->momsub.as<double>());
+  else
+    k_weighted_sub<float><<<grid_for(tot, kB), kB, 0, ctx->stream>>>(
+        t->mom64.as<double>(), C, t->c_level.as<int8_t>(), 1.0 / t->side, p,
+        t->momsub.as<float>());
+  HOT_CHECK_LAUNCH();
+}
 
 void gather_sorted(hot_ctx* ctx, const hot_tree* t, const double* pos, const double* mass,
                    double* spos, double* smass, int check_mass) {

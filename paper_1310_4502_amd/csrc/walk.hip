@@ -48,6 +48,65 @@ struct Images {
   int8_t* m2p_img;
 };
 
+// Background subtraction on periodic lists (Background Subtraction section
+// and its figure). N(g), the cube of three group sides about the group's
+// centre, splits the sources: cells inside it interact as usual; outside it
+// every region is matter minus the uniform mean density -- M2P cells through
+// their moments minus their cube's (flagged per entry), P2P cells and the
+// empty octants of opened cells through the exact field of their negative
+// cube (listed as boxes). A cell straddling the border of N(g) is opened
+// whatever the theta test says; the part of a straddling leaf or empty
+// octant outside N(g) is its box (sign -1) minus its intersection with N(g)
+// (sign +1). Empty octants are listed when their cell is opened, in octant
+// order, before its children are walked.
+struct Background {
+  const int8_t* c_level;
+  const uint64_t* c_key;
+  int64_t* cnt_box;        // count pass: boxes per group
+  const int64_t* off_box;  // fill pass: first box of each group
+  double* boxes;           // fill pass: lo[3], hi[3] per box
+  int8_t* box_sign;
+  int8_t* m2p_sub;         // fill pass: 1 = the entry's cell lies outside N(g)
+};
+
+enum { REL_IN = 0, REL_OUT = 1, REL_STRADDLE = 2 };
+
+__device__ __forceinline__ int box_rel(const double lo[3], const double hi[3],
+                                       const double nlo[3], const double nhi[3]) {
+  bool inside = true, outside = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    inside = inside && lo[d] >= nlo[d] && hi[d] <= nhi[d];
+    outside = outside || hi[d] <= nlo[d] || lo[d] >= nhi[d];
+  }
+  return inside ? REL_IN : (outside ? REL_OUT : REL_STRADDLE);
+}
+
+// the box pieces of a region outside or straddling N(g), from slot `at`
+__device__ __forceinline__ void put_pieces(const Background& bg, int64_t at, const double lo[3],
+                                           const double hi[3], int rel, const double nlo[3],
+                                           const double nhi[3]) {
+  double* b = bg.boxes + 6 * at;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b[d] = lo[d];
+    b[3 + d] = hi[d];
+  }
+  bg.box_sign[at] = -1;
+  if (rel == REL_STRADDLE) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      b[6 + d] = fmax(lo[d], nlo[d]);
+      b[9 + d] = fmin(hi[d], nhi[d]);
+    }
+    bg.box_sign[at + 1] = 1;
+  }
+}
+
+__device__ __forceinline__ int n_pieces(int rel) {
+  return rel == REL_IN ? 0 : (rel == REL_OUT ? 1 : 2);
+}
+
 // Order accepted for cell c (-1: not acceptable). FP64, no FMA; the same
 // operations in the same order as the oracle's test.
 __device__ __forceinline__ int accept_order(double dx, double dy, double dz, double gb, double b,
@@ -66,12 +125,13 @@ __device__ __forceinline__ int accept_order(double dx, double dy, double dz, dou
   return -1;
 }
 
-template <bool FILL, bool ERR, bool PER>
+template <bool FILL, bool ERR, bool PER, bool BG>
 __global__ __launch_bounds__(kB) void k_walk(
     const int32_t* __restrict__ g_cell, int64_t G, const double* __restrict__ c_centre,
     const double* __restrict__ c_bmax, const int32_t* __restrict__ c_count,
     const uint8_t* __restrict__ c_leaf, const int32_t* __restrict__ c_child,
-    const int32_t* __restrict__ c_nchild, double theta, ErrMac em, Images im, int direct_max,
+    const int32_t* __restrict__ c_nchild, double theta, ErrMac em, Images im, Background bg,
+    int direct_max,
     int64_t* __restrict__ cnt_p2p, int64_t* __restrict__ cnt_m2p, int64_t* __restrict__ pairs_p2p,
     const int64_t* __restrict__ off_p2p, const int64_t* __restrict__ off_m2p,
     int32_t* __restrict__ p2p, int32_t* __restrict__ m2p, int64_t C, unsigned* __restrict__ flags) {
@@ -84,11 +144,18 @@ __global__ __launch_bounds__(kB) void k_walk(
   const double gb = c_bmax[gc];
   const double mmax = ERR ? *em.mmax : 0.0;
   const uint64_t lt = lanemask_lt();
-  int64_t np = 0, nmm = 0, npairs = 0;
-  int64_t bp = 0, bm = 0;
+  int64_t np = 0, nmm = 0, npairs = 0, nbox = 0;
+  int64_t bp = 0, bm = 0, bb = 0;
   if (FILL) {
     bp = off_p2p[g];
     bm = off_m2p[g];
+    if (BG) bb = bg.off_box[g];
+  }
+  double nlo[3] = {0.0, 0.0, 0.0}, nhi[3] = {0.0, 0.0, 0.0};
+  if (BG) {
+    const double h3 = 3.0 * ldexp(im.side, -((int)bg.c_level[gc] + 1));
+    nlo[0] = gx - h3, nlo[1] = gy - h3, nlo[2] = gz - h3;
+    nhi[0] = gx + h3, nhi[1] = gy + h3, nhi[2] = gz + h3;
   }
   bool bad = false;
   for (int img = 0; img < (PER ? 125 : 1) && !bad; ++img) {
@@ -114,12 +181,23 @@ __global__ __launch_bounds__(kB) void k_walk(
     int cls = CLS_NONE;
     int cnt = 0;
     int q = -1;
+    int rel = REL_IN;
+    double blo[3], bhi[3];
     if (c < hi) {
       double dx, dy, dz;
       if (PER) {
-        dx = gx - (c_centre[3 * c] + shx);
-        dy = gy - (c_centre[3 * c + 1] + shy);
-        dz = gz - (c_centre[3 * c + 2] + shz);
+        const double cx = c_centre[3 * c] + shx;
+        const double cy = c_centre[3 * c + 1] + shy;
+        const double cz = c_centre[3 * c + 2] + shz;
+        dx = gx - cx;
+        dy = gy - cy;
+        dz = gz - cz;
+        if (BG) {
+          const double h = ldexp(im.side, -((int)bg.c_level[c] + 1));
+          blo[0] = cx - h, blo[1] = cy - h, blo[2] = cz - h;
+          bhi[0] = cx + h, bhi[1] = cy + h, bhi[2] = cz + h;
+          rel = box_rel(blo, bhi, nlo, nhi);
+        }
       } else {
         dx = gx - c_centre[3 * c];
         dy = gy - c_centre[3 * c + 1];
@@ -135,6 +213,7 @@ __global__ __launch_bounds__(kB) void k_walk(
         const double rr = c_bmax[c] / theta + gb;
         acc = d2 > rr * rr;
       }
+      if (BG && rel == REL_STRADDLE) acc = false;
       if (acc)
         cls = cnt <= direct_max ? CLS_P2P : CLS_M2P;
       else
@@ -145,29 +224,74 @@ __global__ __launch_bounds__(kB) void k_walk(
     const uint64_t before = k >= 64 ? ~0ull : ((1ull << k) - 1ull);
     const uint64_t pm = __ballot(cls == CLS_P2P) & before;
     const uint64_t mm = __ballot(cls == CLS_M2P) & before;
+    // boxes of the emitted P2P cells, in lane order (one or two per cell)
+    uint64_t b1 = 0, b2 = 0;
+    if (BG) {
+      const bool mine = (pm >> lane) & 1ull;
+      b1 = __ballot(mine && rel != REL_IN);
+      b2 = __ballot(mine && rel == REL_STRADDLE);
+    }
     if (FILL) {
       if ((pm >> lane) & 1ull) {
         p2p[bp + np + __popcll(pm & lt)] = c;
         if (PER) im.p2p_img[bp + np + __popcll(pm & lt)] = (int8_t)img;
+        if (BG && rel != REL_IN)
+          put_pieces(bg, bb + nbox + __popcll(b1 & lt) + __popcll(b2 & lt), blo, bhi, rel, nlo,
+                     nhi);
       }
       if ((mm >> lane) & 1ull) {
         m2p[bm + nmm + __popcll(mm & lt)] = c;
         if (ERR) em.m2p_q[bm + nmm + __popcll(mm & lt)] = (int8_t)q;
         if (PER) im.m2p_img[bm + nmm + __popcll(mm & lt)] = (int8_t)img;
+        if (BG) bg.m2p_sub[bm + nmm + __popcll(mm & lt)] = (int8_t)(rel == REL_OUT);
       }
     } else {
       if ((pm >> lane) & 1ull) npairs += cnt;
     }
     np += __popcll(pm);
     nmm += __popcll(mm);
+    if (BG) nbox += __popcll(b1) + __popcll(b2);
     if (om) {
       const int oc = lo + k;
       const int cf = c_child[oc], nc = c_nchild[oc];
       int nt = top;
-      if (nc < 1 || cf < 0 || top + 2 >= kStack) {  // never true for a valid tree
+      if (nc < 1 || nc > 8 || cf < 0 || top + 2 >= kStack) {  // never true for a valid tree
         if (lane == 0) atomicOr(flags, FLAG_INTERNAL);
         bad = true;
         break;
+      }
+      if (BG) {
+        // the opened cell's empty octants (octant = the key's last digit,
+        // 4 x + 2 y + z), one lane each
+        const double ocx = c_centre[3 * oc] + shx;
+        const double ocy = c_centre[3 * oc + 1] + shy;
+        const double ocz = c_centre[3 * oc + 2] + shz;
+        const double h = ldexp(im.side, -((int)bg.c_level[oc] + 1));
+        const double plo[3] = {ocx - h, ocy - h, ocz - h};
+        const double phi[3] = {ocx + h, ocy + h, ocz + h};
+        const double pc[3] = {ocx, ocy, ocz};
+        if (box_rel(plo, phi, nlo, nhi) != REL_IN) {
+          const int oct = lane < nc ? (int)(bg.c_key[cf + lane] & 7ull) : -1;
+          unsigned present = 0u;
+          for (int j = 0; j < nc; ++j) present |= 1u << __shfl(oct, j);
+          int orel = REL_IN;
+          double olo[3], ohi[3];
+          if (lane < 8 && !((present >> lane) & 1u)) {
+            const int bit[3] = {(lane >> 2) & 1, (lane >> 1) & 1, lane & 1};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              olo[d] = bit[d] ? pc[d] : plo[d];
+              ohi[d] = bit[d] ? phi[d] : pc[d];
+            }
+            orel = box_rel(olo, ohi, nlo, nhi);
+          }
+          const uint64_t e1 = __ballot(orel != REL_IN);
+          const uint64_t e2 = __ballot(orel == REL_STRADDLE);
+          if (FILL && orel != REL_IN)
+            put_pieces(bg, bb + nbox + __popcll(e1 & lt) + __popcll(e2 & lt), olo, ohi, orel, nlo,
+                       nhi);
+          nbox += __popcll(e1) + __popcll(e2);
+        }
       }
       if (oc + 1 < hi) {
         if (lane == 0) stk[w][top] = make_int2(oc + 1, hi);
@@ -188,6 +312,7 @@ __global__ __launch_bounds__(kB) void k_walk(
       cnt_p2p[g] = np;
       cnt_m2p[g] = nmm;
       pairs_p2p[g] = npairs;
+      if (BG) bg.cnt_box[g] = nbox;
     }
   }
 }
@@ -224,26 +349,33 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
 namespace {
 
-template <bool ERR, bool PER>
+template <bool ERR, bool PER, bool BG = false>
 void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_max) {
   Images im{t->side, nullptr, nullptr};
+  Background bg{t->c_level.as<int8_t>(), t->c_key.as<uint64_t>(), nullptr, nullptr, nullptr,
+                nullptr, nullptr};
   hipStream_t st = ctx->stream;
   const int64_t G = t->n_groups;
   t->has_lists = false;
   t->has_transpose = false;
   t->list_p = -1;
   t->periodic = false;
+  t->bg = false;
   t->p2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
+  if (BG) {
+    t->box_off.alloc(ctx, (G + 1) * sizeof(int64_t));
+    bg.cnt_box = t->box_off.as<int64_t>();
+  }
   t->m2p_off.alloc(ctx, (G + 1) * sizeof(int64_t));
   DBuf pairs, mcount, totals;
   pairs.alloc(ctx, (G + 1) * sizeof(int64_t));
   mcount.alloc(ctx, (G + 1) * sizeof(int64_t));
   totals.alloc(ctx, 4 * sizeof(int64_t));
   const unsigned grid = grid_for(G, kWavesPerBlock);
-  k_walk<false, ERR, PER><<<grid, kB, 0, st>>>(
+  k_walk<false, ERR, PER, BG><<<grid, kB, 0, st>>>(
       t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
-      t->c_nchild.as<int32_t>(), theta, em, im, direct_max, t->p2p_off.as<int64_t>(),
+      t->c_nchild.as<int32_t>(), theta, em, im, bg, direct_max, t->p2p_off.as<int64_t>(),
       t->m2p_off.as<int64_t>(), pairs.as<int64_t>(), nullptr, nullptr, nullptr, nullptr,
       t->n_cells, ctx->d_flags);
   HOT_CHECK_LAUNCH();
@@ -257,12 +389,18 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
   scan_i64(ctx, mcount.as<int64_t>(), mcount.as<int64_t>(), G, tot + 3);
   scan_i64(ctx, t->p2p_off.as<int64_t>(), t->p2p_off.as<int64_t>(), G, t->p2p_off.as<int64_t>() + G);
   scan_i64(ctx, t->m2p_off.as<int64_t>(), t->m2p_off.as<int64_t>(), G, t->m2p_off.as<int64_t>() + G);
-  int64_t h[4];
+  if (BG)
+    scan_i64(ctx, t->box_off.as<int64_t>(), t->box_off.as<int64_t>(), G,
+             t->box_off.as<int64_t>() + G);
+  int64_t h[5] = {0, 0, 0, 0, 0};
   unsigned flags = 0;
   HOT_HIP(hipMemcpyAsync(&flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipMemcpyAsync(&h[0], t->p2p_off.as<int64_t>() + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipMemcpyAsync(&h[1], t->m2p_off.as<int64_t>() + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipMemcpyAsync(&h[2], tot + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  if (BG)
+    HOT_HIP(hipMemcpyAsync(&h[4], t->box_off.as<int64_t>() + G, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, st));
   HOT_HIP(hipStreamSynchronize(st));
   if (flags & FLAG_INTERNAL) throw Error{HOT_E_DEVICE, "walk consistency check failed"};
   if (ERR && (flags & FLAG_BAD_MASS)) throw Error{HOT_E_INVALID, "non-finite or negative mass"};
@@ -287,10 +425,26 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
     t->p2p_img.release();
     t->m2p_img.release();
   }
-  k_walk<true, ERR, PER><<<grid, kB, 0, st>>>(
+  t->n_boxes = h[4];
+  if (BG) {
+    t->boxes.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_boxes) * 6 * sizeof(double));
+    t->box_sign.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_boxes) * sizeof(int8_t));
+    t->m2p_sub.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_m2p) * sizeof(int8_t));
+    bg.cnt_box = nullptr;
+    bg.off_box = t->box_off.as<int64_t>();
+    bg.boxes = t->boxes.as<double>();
+    bg.box_sign = t->box_sign.as<int8_t>();
+    bg.m2p_sub = t->m2p_sub.as<int8_t>();
+  } else {
+    t->box_off.release();
+    t->boxes.release();
+    t->box_sign.release();
+    t->m2p_sub.release();
+  }
+  k_walk<true, ERR, PER, BG><<<grid, kB, 0, st>>>(
       t->g_cell.as<int32_t>(), G, t->c_centre.as<double>(), t->c_bmax.as<double>(),
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
-      t->c_nchild.as<int32_t>(), theta, em, im, direct_max, nullptr, nullptr, nullptr,
+      t->c_nchild.as<int32_t>(), theta, em, im, bg, direct_max, nullptr, nullptr, nullptr,
       t->p2p_off.as<int64_t>(), t->m2p_off.as<int64_t>(), t->p2p.as<int32_t>(),
       t->m2p.as<int32_t>(), t->n_cells, ctx->d_flags);
   HOT_CHECK_LAUNCH();
@@ -298,6 +452,7 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
   t->direct_max = direct_max;
   t->list_p = ERR ? em.pmax : -1;
   t->periodic = PER;
+  t->bg = BG;
   t->has_lists = true;
 }
 
@@ -312,6 +467,12 @@ void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_ma
   ErrMac em{0.0, nullptr, 0, nullptr};
   lattice_tensor(ctx, t);
   walk_lists<false, true>(ctx, t, theta, em, direct_max);
+}
+
+void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+  ErrMac em{0.0, nullptr, 0, nullptr};
+  lattice_tensor(ctx, t);
+  walk_lists<false, true, true>(ctx, t, theta, em, direct_max);
 }
 
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,

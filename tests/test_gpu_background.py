@@ -1,0 +1,143 @@
+"""GPU background subtraction on periodic lists against the oracle: lists,
+images, subtraction flags and boxes bit-exact; forces against the oracle
+treecode on the same lists (FP64 and mixed precision) and against the Ewald
+direct sum; the gain the method is for (more accurate than the unsubtracted
+lists at the same order in near-uniform volumes, and far less FP32 rounding
+there); and the entry point's checks."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
+from gpu_util import assert_lists_equal, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+BOX = np.array([0.0, 0.0, 0.0, 1.0])
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _lattice(n1, amp, seed):
+    g = (np.arange(n1) + 0.5) / n1
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    x = (x + amp / n1 * np.random.default_rng(seed).standard_normal(x.shape)) % 1.0
+    return x, np.full(x.shape[0], 1.0 / x.shape[0])
+
+
+def _clustered(n, width, seed):
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([rng.random((n // 2, 3)),
+                        (0.3 + width * rng.standard_normal((n - n // 2, 3))) % 1.0])
+    return x, np.full(n, 1.0 / n)
+
+
+CASES = [
+    # kind, size, amplitude / width, p, theta, direct_max, n_leaf, n_group
+    ("lattice", 16, 0.05, 6, 0.6, 0, 16, 64),
+    ("lattice", 24, 0.3, 4, 0.5, 8, 8, 32),
+    ("clustered", 12000, 0.04, 6, 0.5, 0, 8, 32),  # straddling leaves and octants
+    ("clustered", 6000, 0.02, 8, 0.6, 16, 4, 16),
+]
+
+
+def _pos(kind, size, a):
+    return _lattice(size, a, 3) if kind == "lattice" else _clustered(size, a, 11)
+
+
+@pytest.mark.parametrize("kind,size,a,p,theta,dmax,n_leaf,n_group", CASES)
+def test_bs_lists_boxes_and_forces(kind, size, a, p, theta, dmax, n_leaf, n_group):
+    pos_np, mass_np = _pos(kind, size, a)
+    n = pos_np.shape[0]
+    eps = 1e-3
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    gt = Tree(pos, n_leaf, n_group, BOX)
+    ot = oracle.Tree(pos_np, n_leaf, n_group, BOX)
+    gt.build_interaction_lists_periodic_bs(theta, dmax)
+    ot.build_lists_periodic_bs(theta, dmax)
+    assert_lists_equal(gt, ot)
+    gpi, gmi = gt.list_images()
+    opi, omi = ot.list_images()
+    assert np.array_equal(gpi, opi) and np.array_equal(gmi, omi), "images differ"
+    goff, gbox, gsg, gsub = gt.background()
+    ooff, obox, osg, osub = ot.background()
+    assert np.array_equal(goff, ooff), "box offsets differ"
+    assert np.array_equal(gbox, obox), "boxes differ"
+    assert np.array_equal(gsg, osg) and np.array_equal(gsub, osub), "signs or flags differ"
+    _log(kind, n, "M2P", len(gmi), "subtracted", int(gsub.sum()), "boxes", len(gsg),
+         "with +1", int((gsg > 0).sum()))
+    if kind == "clustered":
+        assert (gsg > 0).any()
+    gt.compute_moments(pos, mass, p)
+    ot.compute_moments(pos_np, mass_np, p)
+    ts = np.sort(np.random.default_rng(2).choice(n, 512, replace=False))
+    oa, _, _ = ot.eval(pos_np, mass_np, eps, sinks=ts, with_pot=False)
+    g64, _, _ = gt.eval_forces(pos, mass, eps, HOT_FP64)
+    g32, _, _ = gt.eval_forces(pos, mass, eps, HOT_MIXED)
+    e64 = rel_rms(g64.cpu().numpy()[ts], oa)
+    e32 = rel_rms(g32.cpu().numpy()[ts], oa)
+    _log("vs oracle treecode: fp64", e64, "mixed", e32)
+    assert e64 <= 1e-11 and e32 <= 1e-5
+
+
+def test_bs_gain_in_near_uniform_volume():
+    """A perturbed lattice: at the same theta and order the subtracted lists
+    are closer to the Ewald direct sum, and their mixed-precision result is
+    far closer to their FP64 one (the large cancelling cell fields are gone
+    before the FP32 arithmetic)."""
+    pos_np, mass_np = _lattice(32, 0.05, 7)
+    n = pos_np.shape[0]
+    eps, p = 1e-3, 6
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    sinks = np.sort(np.random.default_rng(4).choice(n, 48, replace=False))
+    ad = oracle.ewald_direct(pos_np, mass_np, 1.0, eps, sinks=sinks)
+    res = {}
+    for bs in (False, True):
+        t = Tree(pos, 16, 64, BOX)
+        if bs:
+            t.build_interaction_lists_periodic_bs(0.6, 0)
+        else:
+            t.build_interaction_lists_periodic(0.6, 0)
+        t.compute_moments(pos, mass, p)
+        a64 = t.eval_forces(pos, mass, eps, HOT_FP64)[0].cpu().numpy()
+        a32 = t.eval_forces(pos, mass, eps, HOT_MIXED)[0].cpu().numpy()
+        res[bs] = (rel_rms(a64[sinks], ad), rel_rms(a32, a64))
+    _log("unsubtracted: vs Ewald", res[False][0], "mixed vs fp64", res[False][1])
+    _log("subtracted:   vs Ewald", res[True][0], "mixed vs fp64", res[True][1])
+    assert res[True][0] <= res[False][0] / 3
+    assert res[True][1] <= res[False][1] / 3
+
+
+def test_bs_checks():
+    pos_np, mass_np = _lattice(8, 0.2, 1)
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    t = Tree(pos, 16, 64)  # no box given
+    with pytest.raises(HotError):
+        t.build_interaction_lists_periodic_bs(0.5, 0)
+    t = Tree(pos, 16, 64, BOX)
+    t.build_interaction_lists_periodic(0.5, 0)
+    with pytest.raises(HotError):
+        t.background()
+    with pytest.raises(HotError):
+        t.build_interaction_lists_periodic_bs(1.5, 0)
+    t.build_interaction_lists_periodic_bs(0.5, 0)
+    assert t.counts()["n_boxes"] >= 0
+    t.compute_moments(pos, mass, 4)
+    with pytest.raises(HotError):
+        t.eval_forces(pos, mass, 1e-3, HOT_MIXED, with_pot=True)
+    with pytest.raises(HotError):
+        t.eval_forces_adjoint(pos, mass, 1e-3, torch.zeros_like(pos), HOT_MIXED)
+    a, _, _ = t.eval_forces(pos, mass, 1e-3, HOT_MIXED)
+    assert torch.isfinite(a).all()
+    # back to plain periodic lists: the adjoint is available again
+    t.build_interaction_lists_periodic(0.5, 0)
+    xb, _ = t.eval_forces_adjoint(pos, mass, 1e-3, torch.zeros_like(pos), HOT_MIXED)
+    assert torch.all(xb == 0)
