@@ -92,7 +92,13 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--periodic", action="store_true",
                     help="periodic boundaries: positions wrapped into the unit cube, which is "
-                         "the periodic cell (no adjoint: not available with periodic lists)")
+                         "the periodic cell")
+    ap.add_argument("--background", action="store_true",
+                    help="periodic boundaries with background subtraction (implies "
+                         "--periodic; forward only: the adjoint is not provided for these lists)")
+    ap.add_argument("--bg-width", type=int, default=3,
+                    help="background subtraction: side of each group's neighbourhood in group "
+                         "sides (odd, 3 .. 9)")
     ap.add_argument("--err-tol", type=float, default=None,
                     help="error-bound lists with this absolute acceleration tolerance per "
                          "interaction (orders up to the workload's p) instead of theta lists")
@@ -135,8 +141,14 @@ def main():
     n_leaf = args.n_leaf or n_leaf
     n_group = args.n_group or n_group
     direct_max = direct_max if args.direct_max is None else args.direct_max
+    if args.background and args.direct_max is None:
+        # accepted cells summed pair by pair outside the neighbourhood would
+        # each need an exact box field: with subtraction they stay expansions
+        direct_max = 0
     prec = HOT_FP64 if args.precision == "fp64" else HOT_MIXED
 
+    if args.background:
+        args.periodic = True
     t0 = time.time()
     w = W.make(args.workload)
     log(f"workload {args.workload}: N={w.n} generated in {time.time() - t0:.1f}s")
@@ -156,7 +168,9 @@ def main():
         evs[3].record()
         t = Tree(pos, n_leaf, n_group, w.box)
         t.compute_moments(pos, mass, w.p)
-        if args.periodic:
+        if args.background:
+            t.build_interaction_lists_periodic_bs(w.theta, direct_max, args.bg_width)
+        elif args.periodic:
             t.build_interaction_lists_periodic(w.theta, direct_max)
         elif args.err_tol is None:
             t.build_interaction_lists(w.theta, direct_max)
@@ -167,7 +181,7 @@ def main():
         acc, _, st = t.eval_forces(pos, mass, w.eps, prec, stats=True)
         ev1.record()
         xbar = None
-        if not args.periodic:
+        if not args.background:
             xbar, _ = t.eval_forces_adjoint(pos, mass, w.eps, abar, prec)
         ev2.record()
         return t, acc, xbar, st, evs
@@ -192,7 +206,7 @@ def main():
     ms_p2p = float(np.mean([r[0] for r in recs]))
     ms_m2p = float(np.mean([r[1] for r in recs]))
     ms_fwd_eval = float(np.mean([r[2] for r in recs]))
-    ms_adj = (None if args.periodic else
+    ms_adj = (None if args.background else
               float(np.mean([r[5][1].elapsed_time(r[5][2]) for r in recs])))
     step_ms = [r[5][3].elapsed_time(r[5][2]) for r in recs]
     p2p_pairs, m2p_pairs = recs[-1][3], recs[-1][4]
@@ -268,7 +282,10 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n": w.n, "p": w.p,
                    "theta": w.theta if args.err_tol is None else None,
                    "err_tol": args.err_tol, "eps": w.eps, "n_leaf": n_leaf,
-                   "n_group": n_group, "direct_max": direct_max, "precision": args.precision},
+                   "n_group": n_group, "direct_max": direct_max, "precision": args.precision,
+                   "boundary": (f"periodic, background subtracted (neighbourhood "
+                                f"{args.bg_width} group sides)" if args.background else
+                                "periodic" if args.periodic else "open")},
         "forces_per_s": w.n / (ms_step * 1e-3),
         "p2p_pairs": p2p_pairs,
         "m2p_pairs": m2p_pairs,
@@ -285,7 +302,7 @@ def main():
         "interactions_per_s_eval": inter / (ms_fwd_eval * 1e-3),
         "p2p_gflops_28flop_convention": p2p_pairs * 28 / (ms_p2p * 1e-3) / 1e9,
         "tree": {k: counts[k] for k in ("n_cells", "n_groups", "n_leaves", "max_level",
-                                        "n_p2p", "n_m2p", "n_items")},
+                                        "n_p2p", "n_m2p", "n_items", "n_boxes")},
         "roofline": roofline,
         "m2p_orders": orders,
         "cpu_baseline": None,
@@ -294,7 +311,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], errs = cpu_baseline(
             w, {"mixed": acc, "fp64": acc64}, n_leaf, n_group, direct_max, args.cpu_groups,
-            args.err_sinks, args.err_tol, args.periodic)
+            args.err_sinks, args.err_tol, args.periodic,
+            args.bg_width if args.background else None)
         key = "rms_err_vs_oracle_treecode" if args.periodic else "rms_err_vs_direct"
         out[key] = errs.get("mixed" if prec == HOT_MIXED else "fp64")
         if acc64 is not None:
@@ -303,7 +321,7 @@ def main():
 
 
 def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err, err_tol=None,
-                 periodic=False):
+                 periodic=False, bg_width=None):
     """The CPU oracle (FP64 scalar treecode, OpenMP) on a bounded sample of the
     same workload: its interaction rate over the sampled sinks' evaluation
     (tree build and moments excluded), plus the relative RMS error of each GPU
@@ -318,7 +336,9 @@ def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err, e
     gof = ot.group_of()
     G = ot.counts()["n_groups"]
     groups = W.sample_indices(G, n_groups_sample, 77)
-    if periodic:
+    if bg_width is not None:
+        ot.build_lists_periodic_bs(w.theta, direct_max, width=bg_width, groups=groups)
+    elif periodic:
         ot.build_lists_periodic(w.theta, direct_max, groups=groups)
     elif err_tol is None:
         ot.build_lists(w.theta, direct_max, groups=groups)

@@ -182,7 +182,9 @@ int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta,
  * background subtraction (Background Subtraction section and its figure):
  * the sources become density contrasts, matter minus the mean density
  * rho = M_total / L^3 (M_total the root's monopole at evaluation). For a
- * sink group of side s, N(g) is the cube of side 3 s about its centre.
+ * sink group of side s, N(g) is the cube of side width * s about its centre
+ * (width odd, 3 .. 9; the section's figure draws 3: a region that roughly
+ * surrounds the pair-summed cells keeps their exact box fields few).
  * Source cells inside N(g) interact as usual. Outside it every M2P entry
  * uses its cell's moments minus those of its uniform cube, to the same
  * order as the matter (flagged per entry, tree_get_background), and P2P
@@ -199,7 +201,7 @@ int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta,
  * Synchronises the stream.
  */
 int build_interaction_lists_periodic_bs(hot_ctx* ctx, hot_tree* tree, double theta,
-                                        int direct_max);
+                                        int direct_max, int width);
 
 /*
  * eval_forces -- accelerations (and optionally potentials) of all particles:

@@ -163,16 +163,16 @@ class Tree:
         _chk(lib().oracle_build_lists_periodic(self.h, ctypes.c_double(theta), int(direct_max),
                                                ctypes.c_int64(ns), _p(sel)))
 
-    def build_lists_periodic_bs(self, theta, direct_max=0, groups=None):
+    def build_lists_periodic_bs(self, theta, direct_max=0, width=3, groups=None):
         """Periodic lists with background subtraction: outside each group's
-        neighbourhood (the cube of three times its side) the sources are
+        neighbourhood (the cube of `width` times its side) the sources are
         matter minus the uniform mean density; evaluation adds the exact
         fields of the listed boxes, takes off the neighbourhood's and adds
         back the near zone's."""
         sel = _i64(groups)
         ns = 0 if sel is None else sel.shape[0]
         _chk(lib().oracle_build_lists_periodic_bs(self.h, ctypes.c_double(theta), int(direct_max),
-                                                  ctypes.c_int64(ns), _p(sel)))
+                                                  int(width), ctypes.c_int64(ns), _p(sel)))
 
     def background(self):
         """(box_off (G+1), boxes (B, 6) lo|hi, sign (B,), m2p_sub (M2P entries,))."""

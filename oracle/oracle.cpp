@@ -165,6 +165,7 @@ struct Tree {
   // off its moments), and per group the boxes whose uniform field is added
   // exactly, with sign +1 or -1 (CSR, 6 doubles lo[3], hi[3] per box)
   bool bg = false;
+  int bg_width = 3;  // side of N(g) in group sides (odd)
   std::vector<int8_t> m2p_sub;
   std::vector<int64_t> box_off;
   std::vector<double> boxes;
@@ -830,7 +831,9 @@ void walk_image(const Tree& t, const Cell& g, int64_t ci, const double sh[3], do
 // the near zone (the 5L cube of the 125 images) is added back exactly, so
 // with nothing truncated the result is that of the lists without subtraction.
 // For a sink group g of side s_g its neighbourhood N(g) is the cube of side
-// 3 s_g about its centre. Source cells inside N(g) interact as usual (matter
+// width * s_g about its centre (width odd; the section's figure draws 3, and
+// the text asks for a region that roughly surrounds the nearby cells summed
+// pair by pair, which a wider cube does when cells are pair-summed far out). Source cells inside N(g) interact as usual (matter
 // only); the uniform background of N(g) is removed for all its sinks by the
 // exact field of that cube. Outside N(g) every region of space interacts as
 // matter minus background: an M2P cell through its moments minus those of its
@@ -985,9 +988,9 @@ void walk_image_bs(const Tree& t, const Cell& g, const double nlo[3], const doub
                   mimg, bl);
 }
 
-// N(g): the cube of side 3 s_g about the group's centre
-void neighbourhood(const Tree& t, const Cell& g, double nlo[3], double nhi[3]) {
-  const double h3 = 3.0 * std::ldexp(t.side, -(g.level + 1));
+// N(g): the cube of side width * s_g about the group's centre
+void neighbourhood(const Tree& t, const Cell& g, int width, double nlo[3], double nhi[3]) {
+  const double h3 = (double)width * std::ldexp(t.side, -(g.level + 1));
   for (int d = 0; d < 3; ++d) {
     nlo[d] = g.centre[d] - h3;
     nhi[d] = g.centre[d] + h3;
@@ -1160,21 +1163,23 @@ int oracle_build_lists_err(void* h, const double* mass, double tol, int pmax, in
 // (n_z + 2)), images in that order, each a depth-first walk; the root cube is
 // the periodic cell. The tree must have been built with a given box.
 int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
-                         const int64_t* sel, bool bs);
+                         const int64_t* sel, bool bs, int width);
 
 int oracle_build_lists_periodic(void* h, double theta, int direct_max, int64_t n_sel,
                                 const int64_t* sel) {
-  return build_lists_periodic((Tree*)h, theta, direct_max, n_sel, sel, false);
+  return build_lists_periodic((Tree*)h, theta, direct_max, n_sel, sel, false, 3);
 }
 
-// Periodic lists with background subtraction (see walk_image_bs).
-int oracle_build_lists_periodic_bs(void* h, double theta, int direct_max, int64_t n_sel,
-                                   const int64_t* sel) {
-  return build_lists_periodic((Tree*)h, theta, direct_max, n_sel, sel, true);
+// Periodic lists with background subtraction (see walk_image_bs); N(g) of
+// side width (odd, 3 .. 9) group sides.
+int oracle_build_lists_periodic_bs(void* h, double theta, int direct_max, int width,
+                                   int64_t n_sel, const int64_t* sel) {
+  if (width < 3 || width > 9 || !(width & 1)) return fail("width must be odd, in [3, 9]");
+  return build_lists_periodic((Tree*)h, theta, direct_max, n_sel, sel, true, width);
 }
 
 int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
-                         const int64_t* sel, bool bs) {
+                         const int64_t* sel, bool bs, int width) {
   if (!(theta > 0 && theta < 1)) return fail("theta must lie in (0, 1)");
   if (direct_max < 0) return fail("direct_max must be >= 0");
   std::vector<char> want;
@@ -1194,7 +1199,7 @@ int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
     if (!(want.empty() || want[g])) continue;
     const Cell& gc = t->cells[t->groups[g]];
     double nlo[3], nhi[3];
-    neighbourhood(*t, gc, nlo, nhi);
+    neighbourhood(*t, gc, width, nlo, nhi);
     for (int img = 0; img < kImages; ++img) {
       double sh[3];
       image_shift(img, t->side, sh);
@@ -1206,6 +1211,7 @@ int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
     }
   }
   t->bg = bs;
+  t->bg_width = width;
   t->m2p_sub.clear();
   t->box_off.clear();
   t->boxes.clear();
@@ -1513,7 +1519,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
         for (int d = 0; d < 3; ++d) a[d] += sg * bg_rho * f[d];
       }
       double nlo[3], nhi[3];
-      neighbourhood(*t, t->cells[t->groups[g]], nlo, nhi);
+      neighbourhood(*t, t->cells[t->groups[g]], t->bg_width, nlo, nhi);
       box_field(nlo, nhi, xi, f);
       for (int d = 0; d < 3; ++d) a[d] -= bg_rho * f[d];
       double zlo[3], zhi[3];

@@ -82,7 +82,7 @@ def load(path: Optional[str] = None):
     L.tree_get_m2p_orders.argtypes = [vp, vp, vp]
     L.build_interaction_lists_periodic.argtypes = [vp, vp, dbl, i32]
     L.tree_get_list_images.argtypes = [vp, vp, vp, vp]
-    L.build_interaction_lists_periodic_bs.argtypes = [vp, vp, dbl, i32]
+    L.build_interaction_lists_periodic_bs.argtypes = [vp, vp, dbl, i32, i32]
     L.tree_get_background.argtypes = [vp, vp, vp, vp, vp, vp]
     L.eval_forces.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     L.eval_forces_adjoint.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, vp]
@@ -240,12 +240,12 @@ class Tree:
         self.ctx.check(load().build_interaction_lists_periodic(self.ctx.h, self.h, float(theta),
                                                                int(direct_max)))
 
-    def build_interaction_lists_periodic_bs(self, theta, direct_max=0):
+    def build_interaction_lists_periodic_bs(self, theta, direct_max=0, width=3):
         """Periodic lists with background subtraction: outside each group's
-        neighbourhood (three group sides) the sources are matter minus the
+        neighbourhood (`width` group sides) the sources are matter minus the
         mean density; eval_forces adds the exact uniform-box fields."""
         self.ctx.check(load().build_interaction_lists_periodic_bs(
-            self.ctx.h, self.h, float(theta), int(direct_max)))
+            self.ctx.h, self.h, float(theta), int(direct_max), int(width)))
 
     def background(self):
         """(box_off (G+1), boxes (B, 6) lo|hi, sign (B,), m2p_sub (M2P entries,))."""

@@ -265,14 +265,15 @@ int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta,
 }
 
 int build_interaction_lists_periodic_bs(hot_ctx* ctx, hot_tree* tree, double theta,
-                                        int direct_max) {
+                                        int direct_max, int width) {
   return guard(ctx, [&] {
     need_tree(ctx, tree);
     if (!tree->box_given) hot::state("periodic lists need a tree built with a given box");
     if (!(theta > 0.0 && theta < 1.0)) hot::invalid("theta must lie in (0, 1)");
     if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    if (width < 3 || width > 9 || !(width & 1)) hot::invalid("width must be odd, in [3, 9]");
     try {
-      hot::build_lists_periodic_bs(ctx, tree, theta, direct_max);
+      hot::build_lists_periodic_bs(ctx, tree, theta, direct_max, width);
     } catch (...) {
       tree->has_lists = false;
       tree->periodic = false;

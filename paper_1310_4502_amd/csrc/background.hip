@@ -5,7 +5,7 @@
 // For periodic lists built with background subtraction, every sink gets
 //   rho * ( sum over its group's listed boxes of sign * F_box(x)
 //           - F_N(g)(x) + F_near-zone(x) ),
-// rho = M_total / L^3 the mean density, N(g) the cube of three group sides
+// rho = M_total / L^3 the mean density, N(g) the cube of `width` group sides
 // about the group's centre and the near zone the 5L cube covered by the 125
 // images. F_box is the unsoftened field of unit density filling a box:
 //   F(x) = integral over the box of (y - x) / |y - x|^3 dy.
@@ -66,8 +66,8 @@ __global__ __launch_bounds__(kB) void k_bg_boxes(
     const double* __restrict__ c_centre, const int8_t* __restrict__ c_level,
     const int64_t* __restrict__ box_off, const double* __restrict__ boxes,
     const int8_t* __restrict__ box_sign, const uint32_t* __restrict__ perm,
-    const double* __restrict__ pos, const double* __restrict__ mom64, double side, double lo0,
-    double lo1, double lo2, double* __restrict__ acc) {
+    const double* __restrict__ pos, const double* __restrict__ mom64, double side, int width,
+    double lo0, double lo1, double lo2, double* __restrict__ acc) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (it >= n_items) return;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kB) void k_bg_boxes(
   {
     // minus N(g)
     const int gc = g_cell[g];
-    const double h3 = 3.0 * ldexp(side, -((int)c_level[gc] + 1));
+    const double h3 = (double)width * ldexp(side, -((int)c_level[gc] + 1));
     const double nlo[3] = {c_centre[3 * gc] - h3, c_centre[3 * gc + 1] - h3,
                            c_centre[3 * gc + 2] - h3};
     const double nhi[3] = {c_centre[3 * gc] + h3, c_centre[3 * gc + 1] + h3,
@@ -120,8 +120,8 @@ void background_boxes(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc)
       t->items.as<int2>(), t->n_items, t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
       t->g_cell.as<int32_t>(), t->c_centre.as<double>(), t->c_level.as<int8_t>(),
       t->box_off.as<int64_t>(), t->boxes.as<double>(), t->box_sign.as<int8_t>(),
-      t->perm.as<uint32_t>(), pos, t->mom64.as<double>(), t->side, t->lo[0], t->lo[1], t->lo[2],
-      acc);
+      t->perm.as<uint32_t>(), pos, t->mom64.as<double>(), t->side, t->bg_width, t->lo[0],
+      t->lo[1], t->lo[2], acc);
   HOT_CHECK_LAUNCH();
 }
 

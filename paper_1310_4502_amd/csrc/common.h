@@ -154,6 +154,7 @@ struct hot_tree {
   // uniform field enters with sign +1 / -1 (lo[3], hi[3] each); the
   // subtracted weighted moments built at evaluation
   bool bg = false;
+  int bg_width = 3;  // side of N(g) in group sides
   int64_t n_boxes = 0;
   hot::DBuf m2p_sub, box_off, boxes, box_sign, momsub;
   // eval work items: (group, first sink) per wave
@@ -199,7 +200,7 @@ void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
                      int direct_max);
 void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
-void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
+void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max, int width);
 // weighted scaled moments minus those of each cell's uniform cube of the mean
 // density (into t->momsub, FP32 or FP64 as asked)
 void weighted_sub(hot_ctx* ctx, hot_tree* t, bool fp64);

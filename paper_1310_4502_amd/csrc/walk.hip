@@ -49,8 +49,8 @@ struct Images {
 };
 
 // Background subtraction on periodic lists (Background Subtraction section
-// and its figure). N(g), the cube of three group sides about the group's
-// centre, splits the sources: cells inside it interact as usual; outside it
+// and its figure). N(g), the cube of `width` (odd, 3 in the figure) group
+// sides about the group's centre, splits the sources: cells inside it interact as usual; outside it
 // every region is matter minus the uniform mean density -- M2P cells through
 // their moments minus their cube's (flagged per entry), P2P cells and the
 // empty octants of opened cells through the exact field of their negative
@@ -60,6 +60,7 @@ struct Images {
 // (sign +1). Empty octants are listed when their cell is opened, in octant
 // order, before its children are walked.
 struct Background {
+  int width;               // side of N(g) in group sides (odd)
   const int8_t* c_level;
   const uint64_t* c_key;
   int64_t* cnt_box;        // count pass: boxes per group
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(kB) void k_walk(
   }
   double nlo[3] = {0.0, 0.0, 0.0}, nhi[3] = {0.0, 0.0, 0.0};
   if (BG) {
-    const double h3 = 3.0 * ldexp(im.side, -((int)bg.c_level[gc] + 1));
+    const double h3 = (double)bg.width * ldexp(im.side, -((int)bg.c_level[gc] + 1));
     nlo[0] = gx - h3, nlo[1] = gy - h3, nlo[2] = gz - h3;
     nhi[0] = gx + h3, nhi[1] = gy + h3, nhi[2] = gz + h3;
   }
@@ -350,10 +351,11 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 namespace {
 
 template <bool ERR, bool PER, bool BG = false>
-void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_max) {
+void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_max,
+                int width = 3) {
   Images im{t->side, nullptr, nullptr};
-  Background bg{t->c_level.as<int8_t>(), t->c_key.as<uint64_t>(), nullptr, nullptr, nullptr,
-                nullptr, nullptr};
+  Background bg{width, t->c_level.as<int8_t>(), t->c_key.as<uint64_t>(), nullptr, nullptr,
+                nullptr, nullptr, nullptr};
   hipStream_t st = ctx->stream;
   const int64_t G = t->n_groups;
   t->has_lists = false;
@@ -453,6 +455,7 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
   t->list_p = ERR ? em.pmax : -1;
   t->periodic = PER;
   t->bg = BG;
+  t->bg_width = width;
   t->has_lists = true;
 }
 
@@ -469,10 +472,10 @@ void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_ma
   walk_lists<false, true>(ctx, t, theta, em, direct_max);
 }
 
-void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max, int width) {
   ErrMac em{0.0, nullptr, 0, nullptr};
   lattice_tensor(ctx, t);
-  walk_lists<false, true, true>(ctx, t, theta, em, direct_max);
+  walk_lists<false, true, true>(ctx, t, theta, em, direct_max, width);
 }
 
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,

@@ -38,11 +38,11 @@ def _clustered(n, width, seed):
 
 
 CASES = [
-    # kind, size, amplitude / width, p, theta, direct_max, n_leaf, n_group
-    ("lattice", 16, 0.05, 6, 0.6, 0, 16, 64),
-    ("lattice", 24, 0.3, 4, 0.5, 8, 8, 32),
-    ("clustered", 12000, 0.04, 6, 0.5, 0, 8, 32),  # straddling leaves and octants
-    ("clustered", 6000, 0.02, 8, 0.6, 16, 4, 16),
+    # kind, size, amplitude / width, p, theta, direct_max, n_leaf, n_group, neighbourhood
+    ("lattice", 16, 0.05, 6, 0.6, 0, 16, 64, 3),
+    ("lattice", 24, 0.3, 4, 0.5, 8, 8, 32, 5),
+    ("clustered", 12000, 0.04, 6, 0.5, 0, 8, 32, 3),  # straddling leaves and octants
+    ("clustered", 6000, 0.02, 8, 0.6, 16, 4, 16, 7),
 ]
 
 
@@ -50,8 +50,8 @@ def _pos(kind, size, a):
     return _lattice(size, a, 3) if kind == "lattice" else _clustered(size, a, 11)
 
 
-@pytest.mark.parametrize("kind,size,a,p,theta,dmax,n_leaf,n_group", CASES)
-def test_bs_lists_boxes_and_forces(kind, size, a, p, theta, dmax, n_leaf, n_group):
+@pytest.mark.parametrize("kind,size,a,p,theta,dmax,n_leaf,n_group,width", CASES)
+def test_bs_lists_boxes_and_forces(kind, size, a, p, theta, dmax, n_leaf, n_group, width):
     pos_np, mass_np = _pos(kind, size, a)
     n = pos_np.shape[0]
     eps = 1e-3
@@ -59,8 +59,8 @@ def test_bs_lists_boxes_and_forces(kind, size, a, p, theta, dmax, n_leaf, n_grou
     mass = torch.from_numpy(mass_np).cuda()
     gt = Tree(pos, n_leaf, n_group, BOX)
     ot = oracle.Tree(pos_np, n_leaf, n_group, BOX)
-    gt.build_interaction_lists_periodic_bs(theta, dmax)
-    ot.build_lists_periodic_bs(theta, dmax)
+    gt.build_interaction_lists_periodic_bs(theta, dmax, width)
+    ot.build_lists_periodic_bs(theta, dmax, width=width)
     assert_lists_equal(gt, ot)
     gpi, gmi = gt.list_images()
     opi, omi = ot.list_images()
@@ -72,7 +72,7 @@ def test_bs_lists_boxes_and_forces(kind, size, a, p, theta, dmax, n_leaf, n_grou
     assert np.array_equal(gsg, osg) and np.array_equal(gsub, osub), "signs or flags differ"
     _log(kind, n, "M2P", len(gmi), "subtracted", int(gsub.sum()), "boxes", len(gsg),
          "with +1", int((gsg > 0).sum()))
-    if kind == "clustered":
+    if kind == "clustered" and width == 3:
         assert (gsg > 0).any()
     gt.compute_moments(pos, mass, p)
     ot.compute_moments(pos_np, mass_np, p)
@@ -128,6 +128,9 @@ def test_bs_checks():
         t.background()
     with pytest.raises(HotError):
         t.build_interaction_lists_periodic_bs(1.5, 0)
+    for bad_width in (1, 4, 11):
+        with pytest.raises(HotError):
+            t.build_interaction_lists_periodic_bs(0.5, 0, bad_width)
     t.build_interaction_lists_periodic_bs(0.5, 0)
     assert t.counts()["n_boxes"] >= 0
     t.compute_moments(pos, mass, 4)

@@ -126,10 +126,10 @@ def _bs_tree(orc, pos, mass, theta, n_leaf, n_group, p=None):
     return t
 
 
-def _neigh(cells, gc):
+def _neigh(cells, gc, width):
     h = 0.5 ** (int(cells["level"][gc]) + 1)
     c = cells["centre"][gc]
-    return c - 3 * h, c + 3 * h
+    return c - width * h, c + width * h
 
 
 def _clustered(n, width, seed):
@@ -139,13 +139,15 @@ def _clustered(n, width, seed):
     return x, np.full(n, 1.0 / n)
 
 
-@pytest.mark.parametrize("kind,n,a,n_leaf,n_group", [
-    ("lattice", 12, 0.2, 8, 32), ("lattice", 16, 0.6, 16, 64),
-    ("clustered", 3000, 0.04, 8, 32),  # coarse leaves straddle fine neighbourhoods
+@pytest.mark.parametrize("kind,n,a,n_leaf,n_group,width", [
+    ("lattice", 12, 0.2, 8, 32, 3), ("lattice", 16, 0.6, 16, 64, 3),
+    ("clustered", 3000, 0.04, 8, 32, 3),  # coarse leaves straddle fine neighbourhoods
+    ("clustered", 3000, 0.1, 16, 64, 5),
 ])
-def test_bs_pieces_tile_the_near_zone(orc, kind, n, a, n_leaf, n_group):
+def test_bs_pieces_tile_the_near_zone(orc, kind, n, a, n_leaf, n_group, width):
     pos, mass = _lattice(n, a, 5) if kind == "lattice" else _clustered(n, a, 11)
-    t = _bs_tree(orc, pos, mass, 0.6, n_leaf, n_group)
+    t = orc.Tree(pos, n_leaf, n_group, BOX)
+    t.build_lists_periodic_bs(0.6, 0, width=width)
     cells, groups = t.cells(), t.groups()
     po, pl, mo, ml = t.lists()
     pi, mi = t.list_images()
@@ -160,12 +162,12 @@ def test_bs_pieces_tile_the_near_zone(orc, kind, n, a, n_leaf, n_group):
         vol = sum(0.5 ** (3 * int(lev[ml[e]])) for e in range(mo[g], mo[g + 1]) if sub[e])
         bx = boxes[off[g]:off[g + 1]]
         vol += float((-sign[off[g]:off[g + 1]] * np.prod(bx[:, 3:] - bx[:, :3], axis=1)).sum())
-        vol += (3 * 0.5 ** int(lev[groups[g]])) ** 3
+        vol += (width * 0.5 ** int(lev[groups[g]])) ** 3
         assert vol == 125.0
         if g % 7:
             continue
         # coverage: random points of the 5L cube are covered exactly once
-        nlo, nhi = _neigh(cells, groups[g])
+        nlo, nhi = _neigh(cells, groups[g], width)
         pieces = [(cells["centre"][ml[e]] + _shift(mi[e]) - 0.5 ** (lev[ml[e]] + 1),
                    cells["centre"][ml[e]] + _shift(mi[e]) + 0.5 ** (lev[ml[e]] + 1), -1)
                   for e in range(mo[g], mo[g + 1]) if sub[e]]
