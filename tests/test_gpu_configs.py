@@ -4,7 +4,9 @@ against the oracle; lists bit-exact and moments close on sampled groups;
 accelerations on every sink of the sampled groups against the oracle
 treecode, and on sampled sinks against direct summation; for the 2^24
 Zel'dovich field also the adjoint (directional FD of the FP64 forward with
-the topology frozen, and direct-sum VJP rows)."""
+the topology frozen, and direct-sum VJP rows), error-bound lists, and the
+field wrapped into a periodic cube with and without background
+subtraction."""
 import sys
 import time
 
@@ -138,3 +140,83 @@ def test_error_bound_lists_full_size(name, tol):
     _log(f"{name} err lists: vs oracle treecode {e_tree:.3e} ({len(sinks)} sinks) "
          f"{time.time() - t0:.1f}s")
     assert e_tree <= 1e-5
+
+
+@pytest.mark.parametrize("bs", [False, True])
+def test_periodic_full_size(bs):
+    """The 2^24 Zel'dovich field wrapped into the unit cube, which is the
+    periodic cell (with and without background subtraction; direct_max as
+    bench.py uses for each): lists, images, and for background subtraction
+    the flags and boxes, bit-exact on sampled groups; accelerations on their
+    sinks against the oracle treecode on the same lists (FP64 and mixed);
+    for the plain periodic lists the adjoint against a directional finite
+    difference of the FP64 forward with the topology frozen."""
+    t0 = time.time()
+    w = W.make("zeldovich16m")
+    n_leaf, n_group, dmax = BENCH["zeldovich16m"]
+    if bs:
+        dmax = 0
+    w.pos = np.ascontiguousarray(w.pos % 1.0)
+    w.box = (0.0, 0.0, 0.0, 1.0)
+    pos, mass = to_dev(w)
+    gt = Tree(pos, n_leaf, n_group, w.box)
+    if bs:
+        gt.build_interaction_lists_periodic_bs(w.theta, dmax, 3)
+    else:
+        gt.build_interaction_lists_periodic(w.theta, dmax)
+    gt.compute_moments(pos, mass, w.p)
+    g32 = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)[0].cpu().numpy()
+    g64 = gt.eval_forces(pos, mass, w.eps, HOT_FP64)[0].cpu().numpy()
+    _log(f"periodic bs={bs}: gpu done {time.time() - t0:.1f}s")
+    ot = oracle.Tree(w.pos, n_leaf, n_group, w.box)
+    G = ot.counts()["n_groups"]
+    groups = W.sample_indices(G, 16, 79)
+    if bs:
+        ot.build_lists_periodic_bs(w.theta, dmax, width=3, groups=groups)
+    else:
+        ot.build_lists_periodic(w.theta, dmax, groups=groups)
+    assert_lists_equal(gt, ot, groups=groups)
+    gpo, _, gmo, _ = gt.lists()
+    opo, _, omo, oml = ot.lists()
+    gpi, gmi = gt.list_images()
+    opi, omi = ot.list_images()
+    if bs:
+        gboff, gbox, gsg, gsub = gt.background()
+        oboff, obox, osg, osub = ot.background()
+    for g in groups:
+        assert np.array_equal(gpi[gpo[g]:gpo[g + 1]], opi[opo[g]:opo[g + 1]]), g
+        assert np.array_equal(gmi[gmo[g]:gmo[g + 1]], omi[omo[g]:omo[g + 1]]), g
+        if bs:
+            assert np.array_equal(gsub[gmo[g]:gmo[g + 1]], osub[omo[g]:omo[g + 1]]), g
+            assert np.array_equal(gbox[gboff[g]:gboff[g + 1]], obox[oboff[g]:oboff[g + 1]]), g
+            assert np.array_equal(gsg[gboff[g]:gboff[g + 1]], osg[oboff[g]:oboff[g + 1]]), g
+    cells = np.unique(np.concatenate([oml[omo[g]:omo[g + 1]] for g in groups] + [np.zeros(1, int)]))
+    ot.compute_moments(w.pos, w.mass, w.p, cells=cells)
+    _, perm = ot.keys()
+    sinks = np.sort(perm[np.isin(ot.group_of(), groups)])
+    oa, _, _ = ot.eval(w.pos, w.mass, w.eps, sinks=sinks, with_pot=False)
+    e64, e32 = rel_rms(g64[sinks], oa), rel_rms(g32[sinks], oa)
+    _log(f"periodic bs={bs}: vs oracle treecode fp64 {e64:.3e} mixed {e32:.3e} ({len(sinks)} sinks) "
+         f"{time.time() - t0:.1f}s")
+    assert e64 <= 1e-10
+    # without subtraction the near-uniform field's net force is a small remainder
+    # of large FP32 contributions; with it the FP32 terms are perturbations
+    assert e32 <= (1e-5 if bs else 1e-4)
+    if bs:
+        return
+    abar = torch.from_numpy(W.cotangent(w.n, 406)).cuda()
+    xbar, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64)
+    v = torch.from_numpy(np.random.default_rng(9).normal(size=(w.n, 3))).cuda() * 1e-3
+
+    def L(x):
+        gt.compute_moments(x, mass, w.p)
+        a, _, _ = gt.eval_forces(x, mass, w.eps, HOT_FP64)
+        return (a * abar).sum().item()
+
+    h = 1e-4
+    d1 = (L(pos + h * v) - L(pos - h * v)) / (2 * h)
+    d2 = (L(pos + 2 * h * v) - L(pos - 2 * h * v)) / (4 * h)
+    fd = (4 * d1 - d2) / 3
+    an = float((xbar * v).sum())
+    _log(f"periodic adjoint at 2^24: directional {an:.9e} vs FD {fd:.9e}")
+    assert abs(an - fd) <= 1e-4 * abs(fd)
