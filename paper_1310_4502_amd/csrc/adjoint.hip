@@ -158,16 +158,62 @@ __global__ void k_items_from_off(const uint32_t* __restrict__ rec_off, int64_t C
   if (c < C) nit[c] = (rec_off[c + 1] - rec_off[c] + kCellItemGroups - 1) / kCellItemGroups;
 }
 
+// cell owning entry k of a CSR with offsets off[0 .. C]: the largest c with
+// off[c] <= k (cells without entries are skipped by taking the largest)
+__device__ __forceinline__ int64_t owner_of(const uint32_t* __restrict__ off, int64_t C,
+                                            uint32_t k) {
+  int64_t lo = 0, hi = C;  // off[lo] <= k < off[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// one thread per item (a cell may own very many items under periodic lists)
 __global__ void k_cell_items(const uint32_t* __restrict__ rec_off, const uint32_t* __restrict__ it_off,
-                             int64_t C, uint32_t* __restrict__ citem_rec,
+                             int64_t C, int64_t n_items, uint32_t* __restrict__ citem_rec,
                              int32_t* __restrict__ citem_cell) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_items) return;
+  const int64_t c = owner_of(it_off, C, (uint32_t)k);
+  citem_rec[k] = rec_off[c] + ((uint32_t)k - it_off[c]) * kCellItemGroups;
+  citem_cell[k] = (int32_t)c;
+}
+
+// Reduction of the item partials of each cell in rounds: per cell, chunks of
+// at most kSegChunk consecutive values; one thread per (chunk, slot).
+constexpr int kSegChunk = 64;
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+__global__ void k_seg_count(const uint32_t* __restrict__ off, int64_t C,
+                            uint32_t* __restrict__ cnt, unsigned* __restrict__ maxlen) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
-  const uint32_t r0 = rec_off[c], i0 = it_off[c], i1 = it_off[c + 1];
-  for (uint32_t k = i0; k < i1; ++k) {
-    citem_rec[k] = r0 + (k - i0) * kCellItemGroups;
-    citem_cell[k] = (int32_t)c;
-  }
+  const uint32_t len = off[c + 1] - off[c];
+  cnt[c] = (len + kSegChunk - 1) / kSegChunk;
+  if (maxlen) atomicMax(maxlen, len);
+}
+
+template <typename Tin>
+__global__ void k_seg_chunk_sum(const Tin* __restrict__ in, int in_stride,
+                                const uint32_t* __restrict__ off_in,
+                                const uint32_t* __restrict__ off_out, int64_t C, int64_t n_out,
+                                int nmv, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = t / nmv;
+  const int a = (int)(t - j * nmv);
+  if (j >= n_out) return;
+  const int64_t c = owner_of(off_out, C, (uint32_t)j);
+  const uint32_t k0 = off_in[c] + ((uint32_t)j - off_out[c]) * kSegChunk;
+  const uint32_t k1 = min(off_in[c + 1], k0 + kSegChunk);
+  double s = 0.0;
+  for (uint32_t k = k0; k < k1; ++k) s += (double)in[(int64_t)k * in_stride + a];
+  out[j * nmv + a] = s;
 }
 
 // Lists with per-entry orders: the records of a cell are sorted by order
@@ -670,10 +716,11 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
 
 // Mbar_alpha(c) = -w_alpha s^(-2-|alpha|) * sum over the cell's items (in order).
 template <typename T>
-__global__ void k_mbar_final(const T* __restrict__ part, const uint32_t* __restrict__ it_off,
-                             int64_t C, const int8_t* __restrict__ c_level, double inv_side, int p,
+__global__ void k_mbar_final(const T* __restrict__ part, int stride,
+                             const uint32_t* __restrict__ it_off, int64_t C,
+                             const int8_t* __restrict__ c_level, double inv_side, int p,
                              double* __restrict__ mbar) {
-  const int nmv = nm(p), stride = nm_pad(p);
+  const int nmv = nm(p);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = t / nmv;
   const int a = (int)(t - c * nmv);
@@ -893,11 +940,40 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     } else {
       t->citem_end.release();
       t->qitems.release();
-      k_cell_items<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(),
-                                                   t->mcell_item.as<uint32_t>(), C,
-                                                   t->citem_rec.as<uint32_t>(),
-                                                   t->citem_cell.as<int32_t>());
+      if (nci > 0) {
+        k_cell_items<<<grid_for(nci, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(),
+                                                       t->mcell_item.as<uint32_t>(), C, nci,
+                                                       t->citem_rec.as<uint32_t>(),
+                                                       t->citem_cell.as<int32_t>());
+        HOT_CHECK_LAUNCH();
+      }
+    }
+    // rounds of the cells' partial sums: while some cell has more than
+    // kSegChunk values, chunk offsets for the next round
+    t->mred_levels = 0;
+    const uint32_t* off = t->mcell_item.as<uint32_t>();
+    DBuf dmax;
+    dmax.alloc(ctx, sizeof(unsigned));
+    for (int lev = 0; lev < 3; ++lev) {
+      k_zero_u32<<<1, 1, 0, st>>>(dmax.as<unsigned>());
       HOT_CHECK_LAUNCH();
+      t->mred_off[lev].alloc(ctx, (C + 1) * sizeof(uint32_t));
+      k_seg_count<<<grid_for(C, kB), kB, 0, st>>>(off, C, t->mred_off[lev].as<uint32_t>(),
+                                                  dmax.as<unsigned>());
+      HOT_CHECK_LAUNCH();
+      unsigned mx = 0;
+      HOT_HIP(hipMemcpyAsync(&mx, dmax.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+      HOT_HIP(hipStreamSynchronize(st));
+      if (mx <= (unsigned)kSegChunk) break;
+      scan_u32(ctx, t->mred_off[lev].as<uint32_t>(), t->mred_off[lev].as<uint32_t>(), C,
+               t->mred_off[lev].as<uint32_t>() + C);
+      uint32_t n_out = 0;
+      HOT_HIP(hipMemcpyAsync(&n_out, t->mred_off[lev].as<uint32_t>() + C, sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, st));
+      HOT_HIP(hipStreamSynchronize(st));
+      t->mred_n[lev] = n_out;
+      t->mred_levels = lev + 1;
+      off = t->mred_off[lev].as<uint32_t>();
     }
   }
   t->has_transpose = true;
@@ -954,9 +1030,38 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
     }
   }
   const int64_t tot = C * nm(P);
-  k_mbar_final<T><<<grid_for(tot, kB), kB, 0, st>>>(part.as<T>(), t->mcell_item.as<uint32_t>(), C,
-                                                    t->c_level.as<int8_t>(), inv_side, P, mbar64);
-  HOT_CHECK_LAUNCH();
+  if (t->mred_levels == 0) {
+    k_mbar_final<T><<<grid_for(tot, kB), kB, 0, st>>>(part.as<T>(), nm_pad(P),
+                                                      t->mcell_item.as<uint32_t>(), C,
+                                                      t->c_level.as<int8_t>(), inv_side, P, mbar64);
+    HOT_CHECK_LAUNCH();
+  } else {
+    // cells with many items: chunked rounds, then the final sum per cell
+    DBuf red[2];
+    const uint32_t* off_in = t->mcell_item.as<uint32_t>();
+    const double* in64 = nullptr;
+    for (int lev = 0; lev < t->mred_levels; ++lev) {
+      const int64_t n_out = t->mred_n[lev];
+      DBuf& out = red[lev & 1];
+      out.alloc(ctx, (size_t)std::max<int64_t>(1, n_out) * nm(P) * sizeof(double));
+      const unsigned grid = grid_for(n_out * nm(P), kB);
+      if (lev == 0)
+        k_seg_chunk_sum<T><<<grid, kB, 0, st>>>(part.as<T>(), nm_pad(P), off_in,
+                                                t->mred_off[lev].as<uint32_t>(), C, n_out, nm(P),
+                                                out.as<double>());
+      else
+        k_seg_chunk_sum<double><<<grid, kB, 0, st>>>(in64, nm(P), off_in,
+                                                     t->mred_off[lev].as<uint32_t>(), C, n_out,
+                                                     nm(P), out.as<double>());
+      HOT_CHECK_LAUNCH();
+      off_in = t->mred_off[lev].as<uint32_t>();
+      in64 = out.as<double>();
+    }
+    k_mbar_final<double><<<grid_for(tot, kB), kB, 0, st>>>(in64, nm(P), off_in, C,
+                                                           t->c_level.as<int8_t>(), inv_side, P,
+                                                           mbar64);
+    HOT_CHECK_LAUNCH();
+  }
   // far periodic replicas: their cotangent of the root's moments (cell 0)
   if (t->periodic) far_replicas_mbar(ctx, t, pos, abar, mbar64);
   // down the tree: level L+1 cells take their parents' cotangents

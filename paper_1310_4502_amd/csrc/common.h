@@ -175,6 +175,12 @@ struct hot_tree {
   // order, qitem_off[q] .. qitem_off[q + 1] those of order q (host copy)
   hot::DBuf citem_end, qitems;
   int64_t qitem_off[hot::kMaxP + 2] = {};
+  // a cell's item partials are summed in rounds of at most 64 values when it
+  // has more items than that: per round, chunk offsets per cell (C + 1) and
+  // the number of chunks
+  int mred_levels = 0;
+  int64_t mred_n[3] = {};
+  hot::DBuf mred_off[3];
 };
 
 namespace hot {

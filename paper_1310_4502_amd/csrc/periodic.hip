@@ -242,19 +242,25 @@ __global__ void k_far_l2p_adj(const double* __restrict__ pos, const double* __re
   xbar[3 * i + 2] += gz;
 }
 
-constexpr int kDChunk = 16;  // D entries per pass
+constexpr int kDTile = 128;  // particles staged per round
 constexpr int kDBlocks = 1024;
 
-// per-block partial sums of D_gamma for gamma = g0 .. g0 + kDChunk - 1
-// (grid-stride over the particles; fixed order of the block reduction)
+// Per-block partial sums of D_gamma for every gamma of order <= p + 1 (one
+// thread each, slot order; at most nm(kMaxP + 1) = 220 <= 256). A round
+// stages a tile of particles in LDS as the scaled powers u_d^e / e! (e <= p)
+// and their cotangents; thread gamma then adds, particle by particle,
+// sum_k abar_k u^(gamma - e_k) / (gamma - e_k)!. Grid-stride over the tiles,
+// fixed order: deterministic.
 __global__ __launch_bounds__(256) void k_far_dpart(const double* __restrict__ pos,
                                                    const double* __restrict__ abar, int64_t n,
-                                                   const double* __restrict__ c, int g0, int ng,
+                                                   const double* __restrict__ c, int p, int ng,
                                                    double* __restrict__ part) {
-  __shared__ double red[256];
-  int gi[kDChunk][3];
-  for (int q = 0; q < kDChunk; ++q) {
-    int b = g0 + q < ng ? g0 + q : 0;
+  __shared__ double pw[kDTile][3][kMaxP + 1];
+  __shared__ double bb[kDTile][3];
+  const bool valid = (int)threadIdx.x < ng;
+  int gx = 0, gy = 0, gz = 0;
+  if (valid) {
+    const int b = threadIdx.x;
     int nn = 0;
     while (tri(nn + 1) <= b) ++nn;
     int r = b - tri(nn), ex = nn, ey = 0;
@@ -266,41 +272,44 @@ __global__ __launch_bounds__(256) void k_far_dpart(const double* __restrict__ po
       }
       r -= nn - a + 1;
     }
-    gi[q][0] = ex;
-    gi[q][1] = ey;
-    gi[q][2] = nn - ex - ey;
+    gx = ex;
+    gy = ey;
+    gz = nn - ex - ey;
   }
-  double acc[kDChunk];
-  for (int q = 0; q < kDChunk; ++q) acc[q] = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double u[3] = {pos[3 * i] - c[0], pos[3 * i + 1] - c[1], pos[3 * i + 2] - c[2]};
-    const double b[3] = {abar[3 * i], abar[3 * i + 1], abar[3 * i + 2]};
-    for (int q = 0; q < kDChunk; ++q) {
-      if (g0 + q >= ng) break;
-      double v = 0.0;
-      for (int k = 0; k < 3; ++k) {
-        if (gi[q][k] == 0) continue;
-        double m = 1.0;
-        for (int d = 0; d < 3; ++d) {
-          const int e = gi[q][d] - (d == k);
-          for (int j = 1; j <= e; ++j) m *= u[d] / j;
+  const double c0 = c[0], c1 = c[1], c2 = c[2];
+  double acc = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * kDTile; base < n;
+       base += (int64_t)gridDim.x * kDTile) {
+    __syncthreads();
+    if (threadIdx.x < kDTile) {
+      const int j = threadIdx.x;
+      const int64_t i = base + j;
+      const bool in = i < n;
+      const double u[3] = {in ? pos[3 * i] - c0 : 0.0, in ? pos[3 * i + 1] - c1 : 0.0,
+                           in ? pos[3 * i + 2] - c2 : 0.0};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        bb[j][d] = in ? abar[3 * i + d] : 0.0;
+        double v = 1.0;
+        pw[j][d][0] = 1.0;
+        for (int e = 1; e <= p; ++e) {
+          v = v * u[d] / (double)e;
+          pw[j][d][e] = v;
         }
-        v += b[k] * m;
       }
-      acc[q] += v;
+    }
+    __syncthreads();
+    if (valid) {
+      for (int j = 0; j < kDTile; ++j) {
+        double v = 0.0;
+        if (gx > 0) v += bb[j][0] * ((pw[j][0][gx - 1] * pw[j][1][gy]) * pw[j][2][gz]);
+        if (gy > 0) v += bb[j][1] * ((pw[j][0][gx] * pw[j][1][gy - 1]) * pw[j][2][gz]);
+        if (gz > 0) v += bb[j][2] * ((pw[j][0][gx] * pw[j][1][gy]) * pw[j][2][gz - 1]);
+        acc += v;
+      }
     }
   }
-  for (int q = 0; q < kDChunk && g0 + q < ng; ++q) {
-    red[threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ng + g0 + q] = red[0];
-    __syncthreads();
-  }
+  if (valid) part[(int64_t)blockIdx.x * ng + threadIdx.x] = acc;
 }
 
 // Mbar(root)_alpha += w_alpha sum_gamma T_{alpha+gamma} D_gamma, D from the partials
@@ -351,11 +360,9 @@ void far_replicas_mbar(hot_ctx* ctx, hot_tree* t, const double* pos, const doubl
   const int p = t->p, ng = tri(p + 2);
   DBuf part;
   part.alloc(ctx, (size_t)kDBlocks * ng * sizeof(double));
-  for (int g0 = 0; g0 < ng; g0 += kDChunk) {
-    k_far_dpart<<<kDBlocks, 256, 0, st>>>(pos, abar, t->n, t->c_centre.as<double>(), g0, ng,
-                                          part.as<double>());
-    HOT_CHECK_LAUNCH();
-  }
+  k_far_dpart<<<kDBlocks, 256, 0, st>>>(pos, abar, t->n, t->c_centre.as<double>(), p, ng,
+                                        part.as<double>());
+  HOT_CHECK_LAUNCH();
   k_far_mbar<<<1, 256, ng * sizeof(double), st>>>(part.as<double>(), kDBlocks, ng, p,
                                                   t->lattice.as<double>(), mbar_root);
   HOT_CHECK_LAUNCH();
