@@ -177,3 +177,52 @@ def test_periodic_checks():
     assert torch.isfinite(a).all()
     xb, _ = t.eval_forces_adjoint(pos, mass, w.eps, torch.zeros_like(pos), HOT_MIXED)
     assert torch.all(xb == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65])
+@pytest.mark.parametrize("bs", [False, True])
+def test_periodic_tiny(n, bs):
+    """Degenerate sizes (one particle: the root is the only group and its own
+    leaf; a ragged 65 = one full wave plus one): forces against the oracle on
+    the same lists, the adjoint (plain periodic lists) against its VJP; a lone
+    particle at the cube centre feels no force (its lattice is symmetric)."""
+    pos_np = np.random.default_rng(100 + n).random((n, 3))
+    mass_np = np.full(n, 1.0 / n)
+    eps, p = 1e-3, 4
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    gt = Tree(pos, 16, 64, BOX)
+    ot = oracle.Tree(pos_np, 16, 64, BOX)
+    if bs:
+        gt.build_interaction_lists_periodic_bs(0.5, 0)
+        ot.build_lists_periodic_bs(0.5, 0)
+    else:
+        gt.build_interaction_lists_periodic(0.5, 0)
+        ot.build_lists_periodic(0.5, 0)
+    assert_lists_equal(gt, ot)
+    gt.compute_moments(pos, mass, p)
+    ot.compute_moments(pos_np, mass_np, p)
+    oa, _, _ = ot.eval(pos_np, mass_np, eps, with_pot=False)
+    ga = gt.eval_forces(pos, mass, eps, HOT_FP64)[0].cpu().numpy()
+    scale = max(np.abs(oa).max(), 1e-3)
+    assert np.abs(ga - oa).max() <= 1e-12 * scale
+    if not bs:
+        abar_np = W.cotangent(n, 43)
+        ox, om = ot.vjp(pos_np, mass_np, eps, abar_np)
+        gx, gm = gt.eval_forces_adjoint(pos, mass, eps, torch.from_numpy(abar_np).cuda(),
+                                        HOT_FP64, with_mass=True)
+        assert np.abs(gx.cpu().numpy() - ox).max() <= 1e-11 * max(np.abs(ox).max(), 1e-3)
+        assert np.abs(gm.cpu().numpy() - om).max() <= 1e-11 * max(np.abs(om).max(), 1e-3)
+    if n == 1:
+        c = torch.full((1, 3), 0.5, dtype=torch.float64).cuda()
+        t = Tree(c, 16, 64, BOX)
+        if bs:
+            t.build_interaction_lists_periodic_bs(0.5, 0)
+        else:
+            t.build_interaction_lists_periodic(0.5, 0)
+        t.compute_moments(c, mass, p)
+        # mixed: the FP32 terms of opposite images cancel to FP32 rounding of
+        # the unit-scale image fields
+        for prec, tol in ((HOT_FP64, 1e-12), (HOT_MIXED, 1e-6)):
+            a = t.eval_forces(c, mass, eps, prec)[0].cpu().numpy()
+            assert np.abs(a).max() <= tol
