@@ -2,8 +2,9 @@
 images, subtraction flags and boxes bit-exact; forces against the oracle
 treecode on the same lists (FP64 and mixed precision) and against the Ewald
 direct sum; the gain the method is for (more accurate than the unsubtracted
-lists at the same order in near-uniform volumes, and far less FP32 rounding
-there); and the entry point's checks."""
+lists at the same order in near-uniform volumes, far less FP32 rounding
+there, and so fewer interactions at equal accuracy); and the entry point's
+checks."""
 import sys
 
 import numpy as np
@@ -144,3 +145,38 @@ def test_bs_checks():
     t.build_interaction_lists_periodic(0.5, 0)
     xb, _ = t.eval_forces_adjoint(pos, mass, 1e-3, torch.zeros_like(pos), HOT_MIXED)
     assert torch.all(xb == 0)
+
+
+def test_bs_fewer_interactions_at_equal_accuracy():
+    """The efficiency the method is for, on a near-uniform periodic field (the
+    Zel'dovich recipe at 128^3, p = 8): with subtraction a larger opening
+    angle reaches the accuracy that the unsubtracted lists need a smaller one
+    for, so fewer interactions are evaluated. Errors against the
+    unsubtracted lists at theta = 0.25 (FP64)."""
+    from paper_1310_4502_amd import workloads as W
+    w = W.make("zeldovich16m", n=128 ** 3)
+    pos = torch.from_numpy(np.ascontiguousarray(w.pos % 1.0)).cuda()
+    mass = torch.from_numpy(w.mass).cuda()
+
+    def run(theta, bs):
+        t = Tree(pos, 16, 96, BOX)
+        if bs:
+            t.build_interaction_lists_periodic_bs(theta, 0, 3)
+        else:
+            t.build_interaction_lists_periodic(theta, 0)
+        t.compute_moments(pos, mass, 8)
+        a, _, st = t.eval_forces(pos, mass, w.eps, HOT_FP64, stats=True)
+        return a, st.p2p_pairs + st.m2p_pairs
+
+    ref, _ = run(0.25, False)
+    res = {}
+    for theta, bs in ((0.4, False), (0.5, True), (0.5, False), (0.6, True)):
+        a, inter = run(theta, bs)
+        res[theta, bs] = (float((a - ref).norm() / ref.norm()), inter)
+        _log(f"theta {theta} subtracted {bs}: rel err {res[theta, bs][0]:.3e}, "
+             f"{inter:.3e} interactions")
+    # same accuracy class with 1.5x - 1.7x fewer interactions
+    assert res[0.5, True][0] <= 1.5 * res[0.4, False][0]
+    assert res[0.5, True][1] <= 0.65 * res[0.4, False][1]
+    assert res[0.6, True][0] <= res[0.5, False][0]
+    assert res[0.6, True][1] <= 0.75 * res[0.5, False][1]
