@@ -163,6 +163,15 @@ class Tree:
         _chk(lib().oracle_build_lists_periodic(self.h, ctypes.c_double(theta), int(direct_max),
                                                ctypes.c_int64(ns), _p(sel)))
 
+    def build_lists_periodic_err(self, mass, tol, p_max, direct_max=0, groups=None):
+        """Periodic lists (as build_lists_periodic) with the error-bound test
+        of build_lists_err: every M2P entry carries its order."""
+        sel = _i64(groups)
+        ns = 0 if sel is None else sel.shape[0]
+        _chk(lib().oracle_build_lists_periodic_err(self.h, _p(_f64(mass)), ctypes.c_double(tol),
+                                                   int(p_max), int(direct_max),
+                                                   ctypes.c_int64(ns), _p(sel)))
+
     def build_lists_periodic_bs(self, theta, direct_max=0, width=3, groups=None):
         """Periodic lists with background subtraction: outside each group's
         neighbourhood (the cube of `width` times its side) the sources are

@@ -392,10 +392,8 @@ void walk(const Tree& t, const Cell& g, int64_t ci, double theta, int direct_max
 // at most tol is taken; if there is none (or d <= b), the cell is opened.
 // FP64, no FMA, this exact order of operations.
 // ---------------------------------------------------------------------------
-int accept_order(const Cell& g, const Cell& c, double tol, double mmax, int pmax) {
-  double dx = g.centre[0] - c.centre[0];
-  double dy = g.centre[1] - c.centre[1];
-  double dz = g.centre[2] - c.centre[2];
+int accept_order_d(double dx, double dy, double dz, const Cell& g, const Cell& c, double tol,
+                   double mmax, int pmax) {
   double d = std::sqrt((dx * dx + dy * dy) + dz * dz) - g.bmax;
   double b = c.bmax;
   if (!(d > b)) return -1;
@@ -409,6 +407,13 @@ int accept_order(const Cell& g, const Cell& c, double tol, double mmax, int pmax
     tp = tp * t;
   }
   return -1;
+}
+
+int accept_order(const Cell& g, const Cell& c, double tol, double mmax, int pmax) {
+  double dx = g.centre[0] - c.centre[0];
+  double dy = g.centre[1] - c.centre[1];
+  double dz = g.centre[2] - c.centre[2];
+  return accept_order_d(dx, dy, dz, g, c, tol, mmax, pmax);
 }
 
 void walk_err(const Tree& t, const Cell& g, int64_t ci, double tol, double mmax, int pmax,
@@ -824,6 +829,37 @@ void walk_image(const Tree& t, const Cell& g, int64_t ci, const double sh[3], do
     walk_image(t, g, c.child_first + k, sh, theta, direct_max, img, p2p, pimg, m2p, mimg);
 }
 
+// periodic walk with the error-bound test (image img, centres shifted)
+void walk_image_err(const Tree& t, const Cell& g, int64_t ci, const double sh[3], double tol,
+                    double mmax, int pmax, int direct_max, int img, std::vector<int32_t>& p2p,
+                    std::vector<int8_t>& pimg, std::vector<int32_t>& m2p,
+                    std::vector<int8_t>& mimg, std::vector<int8_t>& m2p_q) {
+  const Cell& c = t.cells[ci];
+  double dx = g.centre[0] - (c.centre[0] + sh[0]);
+  double dy = g.centre[1] - (c.centre[1] + sh[1]);
+  double dz = g.centre[2] - (c.centre[2] + sh[2]);
+  const int q = accept_order_d(dx, dy, dz, g, c, tol, mmax, pmax);
+  if (q >= 0) {
+    if (c.count <= direct_max) {
+      p2p.push_back((int32_t)ci);
+      pimg.push_back((int8_t)img);
+    } else {
+      m2p.push_back((int32_t)ci);
+      mimg.push_back((int8_t)img);
+      m2p_q.push_back((int8_t)q);
+    }
+    return;
+  }
+  if (c.is_leaf) {
+    p2p.push_back((int32_t)ci);
+    pimg.push_back((int8_t)img);
+    return;
+  }
+  for (int k = 0; k < c.n_child; ++k)
+    walk_image_err(t, g, c.child_first + k, sh, tol, mmax, pmax, direct_max, img, p2p, pimg, m2p,
+                   mimg, m2p_q);
+}
+
 // ---------------------------------------------------------------------------
 // Background subtraction (Background Subtraction section and its figure).
 // The sources become density contrasts: from every source region the uniform
@@ -1163,7 +1199,8 @@ int oracle_build_lists_err(void* h, const double* mass, double tol, int pmax, in
 // (n_z + 2)), images in that order, each a depth-first walk; the root cube is
 // the periodic cell. The tree must have been built with a given box.
 int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
-                         const int64_t* sel, bool bs, int width);
+                         const int64_t* sel, bool bs, int width, double tol = 0.0,
+                         double mmax = 0.0, int pmax = -1);
 
 int oracle_build_lists_periodic(void* h, double theta, int direct_max, int64_t n_sel,
                                 const int64_t* sel) {
@@ -1178,9 +1215,24 @@ int oracle_build_lists_periodic_bs(void* h, double theta, int direct_max, int wi
   return build_lists_periodic((Tree*)h, theta, direct_max, n_sel, sel, true, width);
 }
 
+// Periodic lists with the error-bound test of accept_order (orders up to
+// pmax per entry); mass in caller order (only its largest value is used).
+int oracle_build_lists_periodic_err(void* h, const double* mass, double tol, int pmax,
+                                    int direct_max, int64_t n_sel, const int64_t* sel) {
+  Tree* t = (Tree*)h;
+  if (!mass) return fail("bad arguments");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail("tol must be finite and > 0");
+  if (pmax < 0 || pmax > 8) return fail("pmax must lie in [0, 8]");
+  double mmax = 0.0;
+  for (int64_t i = 0; i < t->n; ++i) mmax = std::max(mmax, mass[i]);
+  return build_lists_periodic(t, -1.0, direct_max, n_sel, sel, false, 3, tol, mmax, pmax);
+}
+
 int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
-                         const int64_t* sel, bool bs, int width) {
-  if (!(theta > 0 && theta < 1)) return fail("theta must lie in (0, 1)");
+                         const int64_t* sel, bool bs, int width, double tol, double mmax,
+                         int pmax) {
+  const bool err = theta < 0;
+  if (!err && !(theta > 0 && theta < 1)) return fail("theta must lie in (0, 1)");
   if (direct_max < 0) return fail("direct_max must be >= 0");
   std::vector<char> want;
   if (sel) {
@@ -1192,7 +1244,7 @@ int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
   }
   const int64_t G = (int64_t)t->groups.size();
   std::vector<std::vector<int32_t>> lp(G), lm(G);
-  std::vector<std::vector<int8_t>> ip(G), im(G);
+  std::vector<std::vector<int8_t>> ip(G), im(G), iq(G);
   std::vector<BgLists> bl(bs ? G : 0);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t g = 0; g < G; ++g) {
@@ -1206,6 +1258,9 @@ int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
       if (bs)
         walk_image_bs(*t, gc, nlo, nhi, 0, sh, theta, direct_max, img, lp[g], ip[g], lm[g], im[g],
                       bl[g]);
+      else if (err)
+        walk_image_err(*t, gc, 0, sh, tol, mmax, pmax, direct_max, img, lp[g], ip[g], lm[g], im[g],
+                       iq[g]);
       else
         walk_image(*t, gc, 0, sh, theta, direct_max, img, lp[g], ip[g], lm[g], im[g]);
     }
@@ -1243,6 +1298,12 @@ int build_lists_periodic(Tree* t, double theta, int direct_max, int64_t n_sel,
   }
   t->m2p_q.clear();
   t->list_p = -1;
+  if (err) {
+    t->m2p_q.resize(t->m2p_off[G]);
+    for (int64_t g = 0; g < G; ++g)
+      std::copy(iq[g].begin(), iq[g].end(), t->m2p_q.begin() + t->m2p_off[g]);
+    t->list_p = pmax;
+  }
   t->list_sel = want;
   t->has_lists = true;
   t->periodic = true;

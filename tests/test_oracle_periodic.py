@@ -10,7 +10,9 @@ second derivatives set by the background (4 pi / 3 L^3 per axis), harmonicity
 of the higher derivatives, the scaling with L, the Taylor series of the far
 function against its direct gradient, and for the periodic forces: zero net
 force, invariance under a periodic translation, zero force in a perfect
-lattice, the large-box limit, and the treecode against the direct sum."""
+lattice, the large-box limit, and the treecode against the direct sum; with
+the error-bound test, every accepted image interaction within the tolerance
+of its exact field."""
 import numpy as np
 import pytest
 
@@ -210,3 +212,63 @@ def test_periodic_vjp_matches_fd(orc):
     u = np.random.default_rng(2).random(n)
     fdm = rich(lambda h: L(pos, mass * (1 + h * u)))
     assert abs(float((mb * mass * u).sum()) - fdm) <= 1e-8 * abs(fdm)
+
+
+def test_periodic_error_bound_lists(orc):
+    """Periodic lists with the error-bound test: every accepted (group, cell
+    image, order q) meets the tolerance at every sink of the group, checked
+    against the exact field of the image's particles (eps = 0); the VJP on
+    these lists against Richardson-extrapolated central differences."""
+    rng = np.random.default_rng(21)
+    n = 1500
+    pos = np.concatenate([rng.random((n // 2, 3)),
+                          (0.4 + 0.05 * rng.standard_normal((n - n // 2, 3))) % 1.0])
+    mass = np.full(n, 1.0 / n)
+    box = np.array([0.0, 0.0, 0.0, 1.0])
+    tol, pmax = 3e-3, 6
+    ot = orc.Tree(pos, 8, 32, box)
+    ot.build_lists_periodic_err(mass, tol, pmax, 0)
+    ot.compute_moments(pos, mass, pmax)
+    po, pl, mo, ml = ot.lists()
+    q = ot.m2p_orders()
+    _, mi = ot.list_images()
+    assert q.shape == ml.shape and np.unique(q).size >= 2 and np.unique(mi).size > 60
+    cells, groups = ot.cells(), ot.groups()
+    _, perm = ot.keys()
+    M = ot.moments()
+    checked = 0
+    for g in np.random.default_rng(1).choice(len(groups), 12, replace=False):
+        gc = groups[g]
+        xs = pos[perm[cells["first"][gc]:cells["first"][gc] + cells["count"][gc]]]
+        for e in range(mo[g], mo[g + 1]):
+            c, qq, im = int(ml[e]), int(q[e]), int(mi[e])
+            sh = np.array([im // 25 - 2, (im // 5) % 5 - 2, im % 5 - 2], dtype=np.float64)
+            src = perm[cells["first"][c]:cells["first"][c] + cells["count"][c]]
+            y = pos[src] + sh
+            r = y[None, :, :] - xs[:, None, :]
+            d = np.sqrt(np.einsum("ijk,ijk->ij", r, r))
+            exact = np.einsum("ij,ijk->ik", mass[src][None, :] / d ** 3, r)
+            cc = cells["centre"][c] + sh
+            approx = np.stack([orc.m2p(qq, M[c][:orc.nm(qq)], x - cc, 0.0)[0] for x in xs])
+            err = np.linalg.norm(approx - exact, axis=1).max()
+            assert err <= tol * (1 + 1e-9) + 1e-12 * np.abs(exact).max()
+            checked += 1
+    assert checked > 500
+    # VJP
+    eps = 1e-2
+    abar = W.cotangent(n, 5)
+    xb, _ = ot.vjp(pos, mass, eps, abar)
+    v = np.random.default_rng(6).normal(size=pos.shape)
+
+    def L(x):
+        ot.compute_moments(x, mass, pmax)
+        a, _, _ = ot.eval(x, mass, eps, with_pot=False)
+        return float((a * abar).sum())
+
+    def cd(h):
+        return (L(pos + h * v) - L(pos - h * v)) / (2 * h)
+
+    h = 1e-6
+    fd = (4 * cd(h) - cd(2 * h)) / 3
+    an = float((xb * v).sum())
+    assert abs(an - fd) <= 1e-8 * abs(fd)
