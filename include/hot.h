@@ -178,6 +178,18 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
 int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
 
 /*
+ * build_interaction_lists_periodic_err -- the periodic lists above with the
+ * error-bound test of build_interaction_lists_err in place of the theta test
+ * (per image entry, on the shifted centre; every M2P entry carries its order,
+ * tree_get_m2p_orders, and its image, tree_get_list_images). Evaluation and
+ * adjoint as for periodic lists; moments of order >= p_max are needed.
+ * mass: N (device; only its maximum is used). err_tol: finite, > 0.
+ * p_max: 0 .. 8. direct_max: >= 0. Synchronises the stream.
+ */
+int build_interaction_lists_periodic_err(hot_ctx* ctx, hot_tree* tree, const double* mass,
+                                         double err_tol, int p_max, int direct_max);
+
+/*
  * build_interaction_lists_periodic_bs -- the periodic lists above with
  * background subtraction (Background Subtraction section and its figure):
  * the sources become density contrasts, matter minus the mean density

@@ -28,7 +28,8 @@ EXPORTS = ["hot_ctx_create", "hot_ctx_destroy", "hot_last_error", "hot_sync", "t
            "tree_get_cells", "tree_get_groups", "tree_get_lists", "tree_get_moments",
            "tree_lookup", "build_interaction_lists_err", "tree_get_m2p_orders",
            "build_interaction_lists_periodic", "tree_get_list_images",
-           "build_interaction_lists_periodic_bs", "tree_get_background"]
+           "build_interaction_lists_periodic_bs", "tree_get_background",
+           "build_interaction_lists_periodic_err"]
 
 
 class HotError(RuntimeError):
@@ -83,6 +84,7 @@ def load(path: Optional[str] = None):
     L.build_interaction_lists_periodic.argtypes = [vp, vp, dbl, i32]
     L.tree_get_list_images.argtypes = [vp, vp, vp, vp]
     L.build_interaction_lists_periodic_bs.argtypes = [vp, vp, dbl, i32, i32]
+    L.build_interaction_lists_periodic_err.argtypes = [vp, vp, vp, dbl, i32, i32]
     L.tree_get_background.argtypes = [vp, vp, vp, vp, vp, vp]
     L.eval_forces.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     L.eval_forces_adjoint.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, vp]
@@ -239,6 +241,12 @@ class Tree:
         periodic cell; eval_forces adds the far replicas."""
         self.ctx.check(load().build_interaction_lists_periodic(self.ctx.h, self.h, float(theta),
                                                                int(direct_max)))
+
+    def build_interaction_lists_periodic_err(self, mass, err_tol, p_max, direct_max=0):
+        """Periodic lists with the error-bound test (per-entry orders)."""
+        mass = _as_vec(mass, self.n)
+        self.ctx.check(load().build_interaction_lists_periodic_err(
+            self.ctx.h, self.h, _dev(mass), float(err_tol), int(p_max), int(direct_max)))
 
     def build_interaction_lists_periodic_bs(self, theta, direct_max=0, width=3):
         """Periodic lists with background subtraction: outside each group's

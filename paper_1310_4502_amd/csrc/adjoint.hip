@@ -232,14 +232,15 @@ __device__ __forceinline__ uint32_t order_end(const uint64_t* __restrict__ key, 
   return lo;
 }
 
+// (ish: image bits below the order when the lists are periodic)
 __global__ void k_cq_count(const uint64_t* __restrict__ key, const uint32_t* __restrict__ rec_off,
-                           int64_t C, uint32_t* __restrict__ nit) {
+                           int64_t C, int ish, uint32_t* __restrict__ nit) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
   const uint32_t hi = rec_off[c + 1];
   uint32_t b = rec_off[c], n = 0;
   for (int q = 0; q <= kMaxP; ++q) {
-    const uint32_t e = order_end(key, b, hi, ((uint64_t)c << 4) | (uint64_t)(q + 1));
+    const uint32_t e = order_end(key, b, hi, (((uint64_t)c << 4) | (uint64_t)(q + 1)) << ish);
     n += (e - b + kCellItemGroups - 1) / kCellItemGroups;
     b = e;
   }
@@ -247,7 +248,7 @@ __global__ void k_cq_count(const uint64_t* __restrict__ key, const uint32_t* __r
 }
 
 __global__ void k_cq_items(const uint64_t* __restrict__ key, const uint32_t* __restrict__ rec_off,
-                           const uint32_t* __restrict__ it_off, int64_t C,
+                           const uint32_t* __restrict__ it_off, int64_t C, int ish,
                            uint32_t* __restrict__ citem_rec, uint32_t* __restrict__ citem_end,
                            int32_t* __restrict__ citem_cell, uint64_t* __restrict__ qkey,
                            uint32_t* __restrict__ qval) {
@@ -256,7 +257,7 @@ __global__ void k_cq_items(const uint64_t* __restrict__ key, const uint32_t* __r
   const uint32_t hi = rec_off[c + 1];
   uint32_t b = rec_off[c], k = it_off[c];
   for (int q = 0; q <= kMaxP; ++q) {
-    const uint32_t e = order_end(key, b, hi, ((uint64_t)c << 4) | (uint64_t)(q + 1));
+    const uint32_t e = order_end(key, b, hi, (((uint64_t)c << 4) | (uint64_t)(q + 1)) << ish);
     for (uint32_t r = b; r < e; r += kCellItemGroups, ++k) {
       citem_rec[k] = r;
       citem_end[k] = r + kCellItemGroups < e ? r + kCellItemGroups : e;
@@ -903,7 +904,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     HOT_CHECK_LAUNCH();
     if (qsh)
       k_cq_count<<<grid_for(C, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(),
-                                                 t->mcell_rec.as<uint32_t>(), C,
+                                                 t->mcell_rec.as<uint32_t>(), C, ish,
                                                  t->mcell_item.as<uint32_t>());
     else
       k_items_from_off<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
@@ -927,7 +928,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
       qoff.alloc(ctx, (kMaxP + 2) * sizeof(uint32_t));
       k_cq_items<<<grid_for(C, kB), kB, 0, st>>>(
           t->mrec_key.as<uint64_t>(), t->mcell_rec.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C,
-          t->citem_rec.as<uint32_t>(), t->citem_end.as<uint32_t>(), t->citem_cell.as<int32_t>(),
+          ish, t->citem_rec.as<uint32_t>(), t->citem_end.as<uint32_t>(), t->citem_cell.as<int32_t>(),
           qkey.as<uint64_t>(), t->qitems.as<uint32_t>());
       HOT_CHECK_LAUNCH();
       radix_sort(ctx, qkey.as<uint64_t>(), t->qitems.as<uint32_t>(), nci, 4);
@@ -994,7 +995,9 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
         t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state);
     HOT_CHECK_LAUNCH();
   };
-  if (mixq)
+  if (mixq && t->periodic)
+    sink(k_m2p_sink_adj<P, T, true, true>);
+  else if (mixq)
     sink(k_m2p_sink_adj<P, T, true, false>);
   else if (t->periodic)
     sink(k_m2p_sink_adj<P, T, false, true>);
@@ -1018,7 +1021,12 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
       // one launch per order present: each kernel holds only its order's row
       const int64_t* qo = t->qitem_off;
 #define HOT_CELL_Q(Q) \
-  if constexpr (Q <= P) cell(k_m2p_cell_adj<Q, T, true, false>, qo[Q + 1] - qo[Q], qo[Q]);
+  if constexpr (Q <= P) {                                                       \
+    if (t->periodic)                                                            \
+      cell(k_m2p_cell_adj<Q, T, true, true>, qo[Q + 1] - qo[Q], qo[Q]);         \
+    else                                                                        \
+      cell(k_m2p_cell_adj<Q, T, true, false>, qo[Q + 1] - qo[Q], qo[Q]);        \
+  }
       HOT_CELL_Q(0) HOT_CELL_Q(1) HOT_CELL_Q(2) HOT_CELL_Q(3) HOT_CELL_Q(4) HOT_CELL_Q(5)
       HOT_CELL_Q(6) HOT_CELL_Q(7) HOT_CELL_Q(8)
 #undef HOT_CELL_Q

@@ -248,6 +248,25 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
   });
 }
 
+int build_interaction_lists_periodic_err(hot_ctx* ctx, hot_tree* tree, const double* mass,
+                                         double err_tol, int p_max, int direct_max) {
+  return guard(ctx, [&] {
+    need_tree(ctx, tree);
+    if (!tree->box_given) hot::state("periodic lists need a tree built with a given box");
+    if (!mass) hot::invalid("null masses");
+    if (!(err_tol > 0.0) || !std::isfinite(err_tol)) hot::invalid("err_tol must be finite and > 0");
+    if (p_max < 0 || p_max > 8) hot::invalid("p_max must lie in [0, 8]");
+    if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    try {
+      hot::build_lists_periodic_err(ctx, tree, mass, err_tol, p_max, direct_max);
+    } catch (...) {
+      tree->has_lists = false;
+      tree->periodic = false;
+      throw;
+    }
+  });
+}
+
 int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max) {
   return guard(ctx, [&] {
     need_tree(ctx, tree);

@@ -207,6 +207,8 @@ void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, 
                      int direct_max);
 void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_max);
 void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max, int width);
+void build_lists_periodic_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol,
+                              int p_max, int direct_max);
 // weighted scaled moments minus those of each cell's uniform cube of the mean
 // density (into t->momsub, FP32 or FP64 as asked)
 void weighted_sub(hot_ctx* ctx, hot_tree* t, bool fp64);

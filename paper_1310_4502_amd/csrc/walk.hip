@@ -478,6 +478,27 @@ void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct
   walk_lists<false, true, true>(ctx, t, theta, em, direct_max, width);
 }
 
+namespace {
+// the largest particle mass on the device, for the error-bound test
+void mass_max(hot_ctx* ctx, hot_tree* t, const double* mass, DBuf& mm) {
+  mm.alloc(ctx, sizeof(unsigned long long));
+  k_zero_u64<<<1, 1, 0, ctx->stream>>>(mm.as<unsigned long long>());
+  HOT_CHECK_LAUNCH();
+  k_mass_max<<<grid_for(t->n, kB), kB, 0, ctx->stream>>>(mass, t->n, mm.as<unsigned long long>(),
+                                                         ctx->d_flags);
+  HOT_CHECK_LAUNCH();
+}
+}  // namespace
+
+void build_lists_periodic_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol,
+                              int p_max, int direct_max) {
+  DBuf mm;
+  mass_max(ctx, t, mass, mm);
+  ErrMac em{tol, mm.as<double>(), p_max, nullptr};
+  lattice_tensor(ctx, t);
+  walk_lists<true, true>(ctx, t, 0.0, em, direct_max);
+}
+
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
                      int direct_max) {
   DBuf mm;

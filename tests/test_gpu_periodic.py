@@ -226,3 +226,66 @@ def test_periodic_tiny(n, bs):
         for prec, tol in ((HOT_FP64, 1e-12), (HOT_MIXED, 1e-6)):
             a = t.eval_forces(c, mass, eps, prec)[0].cpu().numpy()
             assert np.abs(a).max() <= tol
+
+
+ERR_CASES = [
+    # name, n, tol, p_max, direct_max, n_leaf, n_group
+    ("uniform", 4096, 1e-3, 6, 0, 16, 64),
+    ("clustered", 12000, 1e-4, 8, 16, 8, 32),
+]
+
+
+@pytest.mark.parametrize("name,n,tol,p_max,dmax,n_leaf,n_group", ERR_CASES)
+def test_periodic_error_bound_lists(name, n, tol, p_max, dmax, n_leaf, n_group):
+    """Periodic lists with the error-bound test: lists, images and orders
+    bit-exact; forces against the oracle treecode on the same lists; the
+    adjoint against the oracle's VJP (small case) and a directional finite
+    difference."""
+    pos_np, mass_np = _pos(name, n)
+    eps = 1e-3
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    gt = Tree(pos, n_leaf, n_group, BOX)
+    ot = oracle.Tree(pos_np, n_leaf, n_group, BOX)
+    gt.build_interaction_lists_periodic_err(mass, tol, p_max, dmax)
+    ot.build_lists_periodic_err(mass_np, tol, p_max, dmax)
+    assert_lists_equal(gt, ot)
+    assert all(np.array_equal(a, b) for a, b in zip(gt.list_images(), ot.list_images()))
+    gq, oq = gt.m2p_orders(), ot.m2p_orders()
+    assert np.array_equal(gq, oq), "orders differ"
+    _log(name, n, "orders", np.bincount(gq, minlength=p_max + 1).tolist())
+    gt.compute_moments(pos, mass, p_max)
+    ot.compute_moments(pos_np, mass_np, p_max)
+    ts = np.sort(np.random.default_rng(2).choice(n, 512, replace=False))
+    oa, _, _ = ot.eval(pos_np, mass_np, eps, sinks=ts, with_pot=False)
+    g64 = gt.eval_forces(pos, mass, eps, HOT_FP64)[0].cpu().numpy()
+    g32 = gt.eval_forces(pos, mass, eps, HOT_MIXED)[0].cpu().numpy()
+    e64, e32 = rel_rms(g64[ts], oa), rel_rms(g32[ts], oa)
+    _log("vs oracle treecode: fp64", e64, "mixed", e32)
+    assert e64 <= 1e-11 and e32 <= 1e-5
+    abar_np = W.cotangent(n, 44)
+    abar = torch.from_numpy(abar_np).cuda()
+    if n <= 4096:
+        ox, om = ot.vjp(pos_np, mass_np, eps, abar_np)
+        gx64, gm64 = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_FP64, with_mass=True)
+        gx, gm = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_MIXED, with_mass=True)
+        r = [rel_rms(gx64.cpu().numpy(), ox), rel_rms(gm64.cpu().numpy(), om),
+             rel_rms(gx.cpu().numpy(), ox), rel_rms(gm.cpu().numpy(), om)]
+        _log("adjoint vs oracle VJP: fp64", r[:2], "mixed", r[2:])
+        assert max(r[:2]) <= 1e-11 and max(r[2:]) <= 1e-5
+    xbar, _ = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_FP64)
+    v = torch.from_numpy(np.random.default_rng(45).normal(size=pos_np.shape)).cuda()
+
+    def L(x):
+        gt.compute_moments(x, mass, p_max)
+        a, _, _ = gt.eval_forces(x, mass, eps, HOT_FP64)
+        return float((a * abar).sum())
+
+    def cd(h):
+        return (L(pos + h * v) - L(pos - h * v)) / (2 * h)
+
+    h = 1e-6
+    fd = (4 * cd(h) - cd(2 * h)) / 3
+    an = float((xbar * v).sum())
+    _log("directional", an, fd)
+    assert abs(an - fd) <= 1e-6 * abs(fd)
