@@ -142,18 +142,21 @@ def test_error_bound_lists_full_size(name, tol):
     assert e_tree <= 1e-5
 
 
-@pytest.mark.parametrize("bs", [False, True])
-def test_periodic_full_size(bs):
+@pytest.mark.parametrize("mode", ["theta", "bs", "err"])
+def test_periodic_full_size(mode):
     """The 2^24 Zel'dovich field wrapped into the unit cube, which is the
-    periodic cell (with and without background subtraction; direct_max as
-    bench.py uses for each): lists, images, and for background subtraction
-    the flags and boxes, bit-exact on sampled groups; accelerations on their
-    sinks against the oracle treecode on the same lists (FP64 and mixed);
-    for the plain periodic lists the adjoint against a directional finite
-    difference of the FP64 forward with the topology frozen."""
+    periodic cell (theta lists, theta lists with background subtraction, and
+    error-bound lists at tolerance 1e-3; direct_max as bench.py uses for
+    each): lists, images, and for background subtraction the flags and
+    boxes, for error-bound lists the orders, bit-exact on sampled groups;
+    accelerations on their sinks against the oracle treecode on the same
+    lists (FP64 and mixed); for the plain periodic lists the adjoint against
+    a directional finite difference of the FP64 forward with the topology
+    frozen."""
     t0 = time.time()
     w = W.make("zeldovich16m")
     n_leaf, n_group, dmax = BENCH["zeldovich16m"]
+    bs = mode == "bs"
     if bs:
         dmax = 0
     w.pos = np.ascontiguousarray(w.pos % 1.0)
@@ -162,17 +165,21 @@ def test_periodic_full_size(bs):
     gt = Tree(pos, n_leaf, n_group, w.box)
     if bs:
         gt.build_interaction_lists_periodic_bs(w.theta, dmax, 3)
+    elif mode == "err":
+        gt.build_interaction_lists_periodic_err(mass, 1e-3, w.p, dmax)
     else:
         gt.build_interaction_lists_periodic(w.theta, dmax)
     gt.compute_moments(pos, mass, w.p)
     g32 = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)[0].cpu().numpy()
     g64 = gt.eval_forces(pos, mass, w.eps, HOT_FP64)[0].cpu().numpy()
-    _log(f"periodic bs={bs}: gpu done {time.time() - t0:.1f}s")
+    _log(f"periodic {mode}: gpu done {time.time() - t0:.1f}s")
     ot = oracle.Tree(w.pos, n_leaf, n_group, w.box)
     G = ot.counts()["n_groups"]
     groups = W.sample_indices(G, 16, 79)
     if bs:
         ot.build_lists_periodic_bs(w.theta, dmax, width=3, groups=groups)
+    elif mode == "err":
+        ot.build_lists_periodic_err(w.mass, 1e-3, w.p, dmax, groups=groups)
     else:
         ot.build_lists_periodic(w.theta, dmax, groups=groups)
     assert_lists_equal(gt, ot, groups=groups)
@@ -183,7 +190,11 @@ def test_periodic_full_size(bs):
     if bs:
         gboff, gbox, gsg, gsub = gt.background()
         oboff, obox, osg, osub = ot.background()
+    if mode == "err":
+        gq, oq = gt.m2p_orders(), ot.m2p_orders()
     for g in groups:
+        if mode == "err":
+            assert np.array_equal(gq[gmo[g]:gmo[g + 1]], oq[omo[g]:omo[g + 1]]), g
         assert np.array_equal(gpi[gpo[g]:gpo[g + 1]], opi[opo[g]:opo[g + 1]]), g
         assert np.array_equal(gmi[gmo[g]:gmo[g + 1]], omi[omo[g]:omo[g + 1]]), g
         if bs:
@@ -196,13 +207,13 @@ def test_periodic_full_size(bs):
     sinks = np.sort(perm[np.isin(ot.group_of(), groups)])
     oa, _, _ = ot.eval(w.pos, w.mass, w.eps, sinks=sinks, with_pot=False)
     e64, e32 = rel_rms(g64[sinks], oa), rel_rms(g32[sinks], oa)
-    _log(f"periodic bs={bs}: vs oracle treecode fp64 {e64:.3e} mixed {e32:.3e} ({len(sinks)} sinks) "
+    _log(f"periodic {mode}: vs oracle treecode fp64 {e64:.3e} mixed {e32:.3e} ({len(sinks)} sinks) "
          f"{time.time() - t0:.1f}s")
     assert e64 <= 1e-10
     # without subtraction the near-uniform field's net force is a small remainder
     # of large FP32 contributions; with it the FP32 terms are perturbations
     assert e32 <= (1e-5 if bs else 1e-4)
-    if bs:
+    if mode != "theta":
         return
     abar = torch.from_numpy(W.cotangent(w.n, 406)).cuda()
     xbar, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64)
