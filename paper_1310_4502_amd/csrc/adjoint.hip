@@ -232,40 +232,50 @@ __device__ __forceinline__ uint32_t order_end(const uint64_t* __restrict__ key, 
   return lo;
 }
 
-// (ish: image bits below the order when the lists are periodic)
+// (ish: image bits below the order when the lists are periodic). Also keeps
+// the record boundaries of the cell's order runs: bnd[c][0] = first record,
+// bnd[c][q + 1] = one past its order-q records.
+constexpr int kBnd = kMaxP + 2;
 __global__ void k_cq_count(const uint64_t* __restrict__ key, const uint32_t* __restrict__ rec_off,
-                           int64_t C, int ish, uint32_t* __restrict__ nit) {
+                           int64_t C, int ish, uint32_t* __restrict__ nit,
+                           uint32_t* __restrict__ bnd) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
   const uint32_t hi = rec_off[c + 1];
   uint32_t b = rec_off[c], n = 0;
+  bnd[c * kBnd] = b;
   for (int q = 0; q <= kMaxP; ++q) {
     const uint32_t e = order_end(key, b, hi, (((uint64_t)c << 4) | (uint64_t)(q + 1)) << ish);
     n += (e - b + kCellItemGroups - 1) / kCellItemGroups;
+    bnd[c * kBnd + q + 1] = e;
     b = e;
   }
   nit[c] = n;
 }
 
-__global__ void k_cq_items(const uint64_t* __restrict__ key, const uint32_t* __restrict__ rec_off,
-                           const uint32_t* __restrict__ it_off, int64_t C, int ish,
-                           uint32_t* __restrict__ citem_rec, uint32_t* __restrict__ citem_end,
-                           int32_t* __restrict__ citem_cell, uint64_t* __restrict__ qkey,
-                           uint32_t* __restrict__ qval) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const uint32_t hi = rec_off[c + 1];
-  uint32_t b = rec_off[c], k = it_off[c];
+// one thread per item: its cell, its order run and its records
+__global__ void k_cq_items(const uint32_t* __restrict__ bnd, const uint32_t* __restrict__ it_off,
+                           int64_t C, int64_t n_items, uint32_t* __restrict__ citem_rec,
+                           uint32_t* __restrict__ citem_end, int32_t* __restrict__ citem_cell,
+                           uint64_t* __restrict__ qkey, uint32_t* __restrict__ qval) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_items) return;
+  const int64_t c = owner_of(it_off, C, (uint32_t)k);
+  const uint32_t* bc = bnd + c * kBnd;
+  uint32_t local = (uint32_t)k - it_off[c];
   for (int q = 0; q <= kMaxP; ++q) {
-    const uint32_t e = order_end(key, b, hi, (((uint64_t)c << 4) | (uint64_t)(q + 1)) << ish);
-    for (uint32_t r = b; r < e; r += kCellItemGroups, ++k) {
+    const uint32_t b = bc[q], e = bc[q + 1];
+    const uint32_t n = (e - b + kCellItemGroups - 1) / kCellItemGroups;
+    if (local < n) {
+      const uint32_t r = b + local * kCellItemGroups;
       citem_rec[k] = r;
       citem_end[k] = r + kCellItemGroups < e ? r + kCellItemGroups : e;
       citem_cell[k] = (int32_t)c;
       qkey[k] = (uint64_t)q;
-      qval[k] = k;
+      qval[k] = (uint32_t)k;
+      return;
     }
-    b = e;
+    local -= n;
   }
 }
 
@@ -402,8 +412,14 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
 
 // ------------------------------------------------- expansion terms, sink side
 // MIXQ: per-entry orders (error-bound lists); PER: per-entry images (periodic)
+// The FP32 order-8 kernel is held to three waves per SIMD (168 VGPRs): the
+// periodic variants otherwise take a few registers more and drop to two.
+template <int P, typename T>
+constexpr int sink_adj_waves_per_simd() { return (sizeof(T) == 4 && P == 8) ? 3 : 1; }
+
 template <int P, typename T, bool MIXQ, bool PER>
-__global__ __launch_bounds__(kB) void k_m2p_sink_adj(
+__global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(sink_adj_waves_per_simd<P, T>())))
+void k_m2p_sink_adj(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
     const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_q,
     const int8_t* __restrict__ m2p_img, double side,
@@ -902,13 +918,16 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, qsh + ish, C,
                                                       t->mcell_rec.as<uint32_t>());
     HOT_CHECK_LAUNCH();
-    if (qsh)
+    DBuf bnd;
+    if (qsh) {
+      bnd.alloc(ctx, (size_t)C * kBnd * sizeof(uint32_t));
       k_cq_count<<<grid_for(C, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(),
                                                  t->mcell_rec.as<uint32_t>(), C, ish,
-                                                 t->mcell_item.as<uint32_t>());
-    else
+                                                 t->mcell_item.as<uint32_t>(), bnd.as<uint32_t>());
+    } else {
       k_items_from_off<<<grid_for(C, kB), kB, 0, st>>>(t->mcell_rec.as<uint32_t>(), C,
                                                        t->mcell_item.as<uint32_t>());
+    }
     HOT_CHECK_LAUNCH();
     scan_u32(ctx, t->mcell_item.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C,
              t->mcell_item.as<uint32_t>() + C);
@@ -926,11 +945,13 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
       DBuf qkey, qoff;
       qkey.alloc(ctx, std::max<int64_t>(1, nci) * sizeof(uint64_t));
       qoff.alloc(ctx, (kMaxP + 2) * sizeof(uint32_t));
-      k_cq_items<<<grid_for(C, kB), kB, 0, st>>>(
-          t->mrec_key.as<uint64_t>(), t->mcell_rec.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C,
-          ish, t->citem_rec.as<uint32_t>(), t->citem_end.as<uint32_t>(), t->citem_cell.as<int32_t>(),
-          qkey.as<uint64_t>(), t->qitems.as<uint32_t>());
-      HOT_CHECK_LAUNCH();
+      if (nci > 0) {
+        k_cq_items<<<grid_for(nci, kB), kB, 0, st>>>(
+            bnd.as<uint32_t>(), t->mcell_item.as<uint32_t>(), C, nci, t->citem_rec.as<uint32_t>(),
+            t->citem_end.as<uint32_t>(), t->citem_cell.as<int32_t>(), qkey.as<uint64_t>(),
+            t->qitems.as<uint32_t>());
+        HOT_CHECK_LAUNCH();
+      }
       radix_sort(ctx, qkey.as<uint64_t>(), t->qitems.as<uint32_t>(), nci, 4);
       k_lower_bound<<<1, kB, 0, st>>>(qkey.as<uint64_t>(), nci, 0, kMaxP + 1, qoff.as<uint32_t>());
       HOT_CHECK_LAUNCH();
