@@ -365,12 +365,16 @@ class Tree:
 
 def forces(pos: torch.Tensor, mass: torch.Tensor, eps: float, theta: float, p: int,
            precision: str = "mixed", n_leaf: int = 16, n_group: int = 64, direct_max: int = 0,
-           box=None, with_pot: bool = False):
-    """One force evaluation: tree_build, compute_moments, build_interaction_lists,
+           box=None, with_pot: bool = False, periodic: bool = False):
+    """One force evaluation: tree_build, compute_moments, build_interaction_lists
+    (the periodic ones, with the given box as the periodic cell, if periodic),
     eval_forces. Returns (acc, pot or None, tree)."""
     t = Tree(pos, n_leaf, n_group, box)
     t.compute_moments(pos, mass, p)
-    t.build_interaction_lists(theta, direct_max)
+    if periodic:
+        t.build_interaction_lists_periodic(theta, direct_max)
+    else:
+        t.build_interaction_lists(theta, direct_max)
     prec = HOT_FP64 if precision == "fp64" else HOT_MIXED
     acc, pot, _ = t.eval_forces(pos, mass, eps, prec, with_pot)
     return acc, pot, t

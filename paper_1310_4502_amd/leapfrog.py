@@ -19,6 +19,11 @@ The paper's integrator is the symplectic comoving leapfrog (Time Integration
 section); its checkpoints keep the leapfrog offset between position and
 velocity. The kick-drift-kick states kept here are synchronous, so a restart
 from one needs no offset.
+
+With periodic=True the box (lo, L) is the periodic cell: positions are
+integrated unwrapped, and every force evaluation sees them wrapped into the
+cell (x - L floor((x - lo) / L), whose derivative is the identity almost
+everywhere), on periodic lists.
 """
 from __future__ import annotations
 
@@ -41,21 +46,39 @@ class ForceField:
     direct_max: int = 0
     precision: int = HOT_MIXED
     box: Optional[tuple] = None
+    periodic: bool = False
+
+    def _wrap(self, x: torch.Tensor) -> torch.Tensor:
+        if not self.periodic:
+            return x
+        lo = torch.tensor(self.box[:3], dtype=x.dtype, device=x.device)
+        side = float(self.box[3])
+        w = x - side * torch.floor((x - lo) / side)
+        # a coordinate rounding up to lo + L lies on the cell's far face: keep it inside
+        return torch.where(w >= lo + side, w - side, w).contiguous()
 
     def tree(self, x: torch.Tensor) -> Tree:
-        t = Tree(x, self.n_leaf, self.n_group, self.box)
-        t.build_interaction_lists(self.theta, self.direct_max)
+        if self.periodic and self.box is None:
+            raise ValueError("periodic force fields need the box (lo, L) of the periodic cell")
+        t = Tree(self._wrap(x), self.n_leaf, self.n_group, self.box)
+        if self.periodic:
+            t.build_interaction_lists_periodic(self.theta, self.direct_max)
+        else:
+            t.build_interaction_lists(self.theta, self.direct_max)
         return t
 
     def accel(self, t: Tree, x: torch.Tensor, precision: Optional[int] = None) -> torch.Tensor:
-        t.compute_moments(x, self.mass, self.p)
-        a, _, _ = t.eval_forces(x, self.mass, self.eps,
+        xw = self._wrap(x)
+        t.compute_moments(xw, self.mass, self.p)
+        a, _, _ = t.eval_forces(xw, self.mass, self.eps,
                                 self.precision if precision is None else precision)
         return a
 
     def vjp(self, t: Tree, x: torch.Tensor, abar: torch.Tensor) -> torch.Tensor:
-        t.compute_moments(x, self.mass, self.p)
-        xbar, _ = t.eval_forces_adjoint(x, self.mass, self.eps, abar.contiguous(), self.precision)
+        xw = self._wrap(x)
+        t.compute_moments(xw, self.mass, self.p)
+        xbar, _ = t.eval_forces_adjoint(xw, self.mass, self.eps, abar.contiguous(),
+                                        self.precision)
         return xbar
 
 
