@@ -300,6 +300,16 @@ def box_field(lo, hi, x):
     return out
 
 
+def box_grad(lo, hi, x):
+    """Gradient (n, 3, 3), [k, l] = d a_k / d x_l, of the unit-density box field."""
+    lo = _f64(np.asarray(lo, dtype=np.float64))
+    hi = _f64(np.asarray(hi, dtype=np.float64))
+    x = _f64(np.atleast_2d(x))
+    out = np.empty((x.shape[0], 3, 3))
+    _chk(lib().oracle_box_grad(_p(lo), _p(hi), ctypes.c_int64(x.shape[0]), _p(x), _p(out)))
+    return out
+
+
 def cube_moments(p, s):
     """Raw moments (slot order) of unit density filling a cube of side s."""
     out = np.empty((p + 1) * (p + 2) * (p + 3) // 6)

@@ -922,6 +922,55 @@ void box_field(const double lo[3], const double hi[3], const double x[3], double
       }
 }
 
+// ln(b + R) for the gradient of the box field, where its sum over the corners
+// is finite: for b < 0 written as ln(rho2) - ln(R - b), rho2 the sum of the
+// other two squares; when rho2 = 0 (the point lies on the line of a box edge)
+// ln(rho2) is dropped: it cancels between the edge's two corners whenever the
+// point lies beyond the edge, the only place the gradient is finite.
+double log_edge(double b, double rho2, double R) {
+  if (b >= 0.0) return R > 0.0 ? std::log(b + R) : 0.0;
+  return rho2 > 0.0 ? std::log(rho2 / (R - b)) : -std::log(R - b);
+}
+
+// atan(num / (c R)) for the gradient; at c = 0 its one-sided limit from
+// c > 0 (the gradient jumps across the plane of a face).
+double atan_face(double num, double c, double R) {
+  if (c != 0.0) return std::atan(num / (c * R));
+  if (num == 0.0) return 0.0;
+  return num > 0.0 ? M_PI / 2 : -M_PI / 2;
+}
+
+// Gradient of box_field, T[k][l] = d a_k / d x_l (symmetric). From
+// a_z = - sum s Phi(u, v, w) with u, v, w = corner - x and the mixed
+// derivatives of Phi: dPhi/da = ln(b + R) + (terms constant in b),
+// dPhi/dc = -atan(ab / (cR)) + (terms constant in a or in b); the constant
+// terms cancel in the corner sums, leaving
+//   T_xx = -sum s atan(v w / (u R)),  T_xy = sum s ln(w + R),
+// and the others by symmetry.
+void box_grad(const double lo[3], const double hi[3], const double x[3], double T[3][3]) {
+  const double u2[2] = {lo[0] - x[0], hi[0] - x[0]};
+  const double v2[2] = {lo[1] - x[1], hi[1] - x[1]};
+  const double w2[2] = {lo[2] - x[2], hi[2] - x[2]};
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) T[k][l] = 0.0;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k) {
+        const double u = u2[i], v = v2[j], w = w2[k];
+        const double R = std::sqrt((u * u + v * v) + w * w);
+        const double s = ((i ^ j ^ k) & 1) ? 1.0 : -1.0;
+        T[0][0] -= s * atan_face(v * w, u, R);
+        T[1][1] -= s * atan_face(u * w, v, R);
+        T[2][2] -= s * atan_face(u * v, w, R);
+        T[0][1] += s * log_edge(w, u * u + v * v, R);
+        T[0][2] += s * log_edge(v, u * u + w * w, R);
+        T[1][2] += s * log_edge(u, v * v + w * w, R);
+      }
+  T[1][0] = T[0][1];
+  T[2][0] = T[0][2];
+  T[2][1] = T[1][2];
+}
+
 // Raw moments of unit density filling a cube of side s about its centre:
 // prod_d 2 (s/2)^(alpha_d + 1) / (alpha_d + 1) for all alpha_d even, else 0.
 double cube_moment(int a, int b, int c, double s) {
@@ -1335,6 +1384,13 @@ int oracle_cube_moments(int p, double s, double* out) {
   return 0;
 }
 
+// Gradient of the field of unit density filling [lo, hi] at n points, 9 per
+// point, row k = d a_k / d x (for the pins).
+int oracle_box_grad(const double* lo, const double* hi, int64_t n, const double* x, double* T) {
+  for (int64_t i = 0; i < n; ++i) box_grad(lo, hi, &x[3 * i], (double(*)[3]) & T[9 * i]);
+  return 0;
+}
+
 // Field of unit density filling [lo, hi] at n points (for the pins).
 int oracle_box_field(const double* lo, const double* hi, int64_t n, const double* x, double* a) {
   for (int64_t i = 0; i < n; ++i) box_field(lo, hi, &x[3 * i], &a[3 * i]);
@@ -1690,7 +1746,6 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
   if (!t->list_sel.empty()) return fail("the VJP needs the lists of every group");
   if (t->p < 0) return fail("moments not computed");
   if (t->p < t->list_p) return fail("moments of lower order than the lists");
-  if (t->bg) return fail("the VJP of background-subtracted lists is not provided");
   const int64_t n = t->n;
   const int p = t->p;
   const int K = nm(p);
@@ -1698,6 +1753,11 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
   const int64_t G = (int64_t)t->groups.size();
   for (int64_t c = 0; c < C; ++c)
     if (!t->mom_valid[c]) return fail("all moments are needed for the VJP");
+  // background subtraction: the mean density and, per group, the derivative
+  // of the loss with respect to it (every mass enters through it)
+  const double L3 = t->side * t->side * t->side;
+  const double bg_rho = t->bg ? t->mom[0] / L3 : 0.0;
+  std::vector<double> drho(G, 0.0);
   std::vector<double> xb(3 * n, 0.0), mb(n, 0.0);   // indexed by sorted position
   std::vector<double> Mbar(C * K, 0.0);
   std::vector<char> used(C, 0);
@@ -1744,10 +1804,22 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
           src_m[g][off] += ra * inv3;              // d a_i / d m_j = r s^-3/2
         }
       }
+      std::vector<double> msub(t->bg ? K : 0), cube(t->bg ? K : 0);
       for (int64_t e = t->m2p_off[g]; e < t->m2p_off[g + 1]; ++e) {
         const int64_t cid = t->m2p[e];
         const Cell& c = t->cells[cid];
         const double* M = &t->mom[cid * K];
+        const bool subt = t->bg && t->m2p_sub[e];
+        if (subt) {
+          // matter minus the cell's uniform cube (see eval)
+          const double s = std::ldexp(t->side, -c.level);
+          for (int sl = 0; sl < K; ++sl) {
+            const int* al = &g_alpha[3 * sl];
+            cube[sl] = cube_moment(al[0], al[1], al[2], s);
+            msub[sl] = M[sl] - bg_rho * cube[sl];
+          }
+          M = msub.data();
+        }
         double sh[3] = {0, 0, 0};
         if (t->periodic) image_shift((int)t->m2p_img[e], t->side, sh);
         double R[3] = {xi[0] - (c.centre[0] + sh[0]), xi[1] - (c.centre[1] + sh[1]),
@@ -1767,12 +1839,41 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
             b[k] += 1;
             double d1 = dG(b[0], b[1], b[2], R, rad);
             Mb[sl] -= w * ab[k] * d1;
+            // d M_sub / d rho = -cube
+            if (subt) drho[g] += w * ab[k] * d1 * cube[sl];
             for (int l = 0; l < 3; ++l) {
               int bb[3] = {b[0], b[1], b[2]};
               bb[l] += 1;
               xb[3 * si + l] -= w * M[sl] * ab[k] * dG(bb[0], bb[1], bb[2], R, rad);
             }
           }
+        }
+      }
+      if (t->bg) {
+        // exact box fields: rho (sum of signed boxes - N(g) + near zone);
+        // the sink moves them, the mean density scales them
+        double T[3][3], f[3], Bsum[3] = {0, 0, 0}, Tsum[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        auto add = [&](const double* lo, const double* hi, double sg) {
+          box_field(lo, hi, xi, f);
+          box_grad(lo, hi, xi, T);
+          for (int k = 0; k < 3; ++k) {
+            Bsum[k] += sg * f[k];
+            for (int l = 0; l < 3; ++l) Tsum[k][l] += sg * T[k][l];
+          }
+        };
+        for (int64_t b = t->box_off[g]; b < t->box_off[g + 1]; ++b)
+          add(&t->boxes[6 * b], &t->boxes[6 * b + 3], (double)t->box_sign[b]);
+        double nlo[3], nhi[3], zlo[3], zhi[3];
+        neighbourhood(*t, gc, t->bg_width, nlo, nhi);
+        add(nlo, nhi, -1.0);
+        for (int d = 0; d < 3; ++d) {
+          zlo[d] = t->lo[d] - (double)kWs * t->side;
+          zhi[d] = t->lo[d] + (double)(kWs + 1) * t->side;
+        }
+        add(zlo, zhi, 1.0);
+        for (int k = 0; k < 3; ++k) {
+          drho[g] += ab[k] * Bsum[k];
+          for (int l = 0; l < 3; ++l) xb[3 * si + l] += bg_rho * ab[k] * Tsum[k][l];
         }
       }
     }
@@ -1873,6 +1974,12 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
       for (int q = 0; q < 3; ++q) xb[3 * j + q] += mass[cj] * gx[q];
       mb[j] += gm;
     }
+  }
+  // the mean density is the total mass over L^3: every mass gets d/d rho / L^3
+  if (t->bg) {
+    double dr = 0.0;
+    for (int64_t g = 0; g < G; ++g) dr += drho[g];
+    for (int64_t j = 0; j < n; ++j) mb[j] += dr / L3;
   }
   for (int64_t j = 0; j < n; ++j) {
     const int64_t cj = t->perm[j];

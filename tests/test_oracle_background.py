@@ -15,9 +15,11 @@ that exact field; the bookkeeping of the lists through a tiling of the near
 zone (every point of the 5L cube covered exactly once by the subtracted
 pieces and the neighbourhood) and through the identity that ties the
 subtracted result to the unsubtracted one (they differ only by the
-truncation of the subtracted cubes); and the purpose of the method: in a
+truncation of the subtracted cubes); the purpose of the method: in a
 perfect lattice, whose exact periodic force is zero, and in a perturbed one,
-the subtracted treecode is more accurate at the same order."""
+the subtracted treecode is more accurate at the same order; and the VJP
+(the box field's gradient against differences and Poisson's equation, the
+whole VJP against differences in positions and masses)."""
 import numpy as np
 import pytest
 
@@ -256,11 +258,72 @@ def test_bs_more_accurate_in_lattices(orc):
     assert res[True] <= res[False] / 1.5
 
 
+def test_box_grad_against_differences_and_poisson(orc):
+    """The gradient of the box field against central differences of the
+    field, and its trace: -4 pi inside the box, 0 outside (Poisson)."""
+    lo, hi = np.array([0.1, -0.2, 0.3]), np.array([0.6, 0.5, 0.45])
+    pts = np.array([[1.2, 0.7, -0.4], [0.35, 0.15, 0.375], [0.35, 0.15, 1.0], [0.6, 0.1, 0.2],
+                    [0.2, -0.1, 0.32]])
+    T = orc.box_grad(lo, hi, pts)
+    h = 1e-5
+    for x, Tx in zip(pts, T):
+        F = np.stack([(orc.box_field(lo, hi, x + h * e)[0] - orc.box_field(lo, hi, x - h * e)[0])
+                      / (2 * h) for e in np.eye(3)], axis=1)
+        assert np.abs(Tx - F).max() <= 1e-7 * np.abs(F).max()
+        assert np.allclose(Tx, Tx.T, rtol=0, atol=1e-14)
+        inside = np.all((x > lo) & (x < hi))
+        assert abs(np.trace(Tx) - (-4 * np.pi if inside else 0.0)) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["lattice", "clustered"])
+def test_bs_vjp_matches_fd(orc, kind):
+    """The VJP of background-subtracted lists (subtracted moments at the sink,
+    the exact box fields and their gradients, the mean density through every
+    mass) against Richardson-extrapolated central differences of the
+    evaluation on the same lists, in positions and in masses."""
+    if kind == "lattice":
+        pos, mass = _lattice(10, 0.3, 12)
+        t = orc.Tree(pos, 8, 32, BOX)
+        t.build_lists_periodic_bs(0.5, 0, width=3)
+    else:
+        pos, mass = _clustered(1200, 0.04, 13)
+        mass = mass * (0.5 + np.random.default_rng(14).random(mass.shape))
+        t = orc.Tree(pos, 8, 32, BOX)
+        t.build_lists_periodic_bs(0.6, 4, width=3)
+        assert (t.background()[2] > 0).any()
+    p, eps = 4, 1e-2
+    t.compute_moments(pos, mass, p)
+    abar = W_cot(pos.shape[0], 15)
+    xb, mb = t.vjp(pos, mass, eps, abar)
+
+    def L(x, m):
+        t.compute_moments(x, m, p)
+        a, _, _ = t.eval(x, m, eps, with_pot=False)
+        return float((a * abar).sum())
+
+    rng = np.random.default_rng(16)
+    v, dm = rng.normal(size=pos.shape), rng.normal(size=mass.shape) * mass
+    h = 1e-6
+
+    def cd(fx, hh):
+        return (fx(hh) - fx(-hh)) / (2 * hh)
+
+    fx = lambda hh: L(pos + hh * v, mass)
+    fm = lambda hh: L(pos, mass + hh * dm)
+    fd_x = (4 * cd(fx, h) - cd(fx, 2 * h)) / 3
+    fd_m = (4 * cd(fm, h) - cd(fm, 2 * h)) / 3
+    assert abs(float((xb * v).sum()) - fd_x) <= 1e-7 * abs(fd_x)
+    assert abs(float((mb * dm).sum()) - fd_m) <= 1e-7 * abs(fd_m)
+
+
+def W_cot(n, seed):
+    a = np.random.default_rng(seed).standard_normal((n, 3))
+    return a / np.linalg.norm(a)
+
+
 def test_bs_refusals(orc):
     pos, mass = _lattice(8, 0.2, 1)
     t = _bs_tree(orc, pos, mass, 0.5, 8, 32, 4)
-    with pytest.raises(RuntimeError):
-        t.vjp(pos, mass, 1e-3, np.zeros_like(pos))
     t.build_lists_periodic(0.5, 0)
     with pytest.raises(RuntimeError):
         t.background()
