@@ -95,7 +95,7 @@ def main():
                          "the periodic cell")
     ap.add_argument("--background", action="store_true",
                     help="periodic boundaries with background subtraction (implies "
-                         "--periodic; forward only: the adjoint is not provided for these lists)")
+                         "--periodic)")
     ap.add_argument("--bg-width", type=int, default=3,
                     help="background subtraction: side of each group's neighbourhood in group "
                          "sides (odd, 3 .. 9)")
@@ -182,9 +182,7 @@ def main():
         ev0.record()
         acc, _, st = t.eval_forces(pos, mass, w.eps, prec, stats=True)
         ev1.record()
-        xbar = None
-        if not args.background:
-            xbar, _ = t.eval_forces_adjoint(pos, mass, w.eps, abar, prec)
+        xbar, _ = t.eval_forces_adjoint(pos, mass, w.eps, abar, prec)
         ev2.record()
         return t, acc, xbar, st, evs
 
@@ -208,8 +206,7 @@ def main():
     ms_p2p = float(np.mean([r[0] for r in recs]))
     ms_m2p = float(np.mean([r[1] for r in recs]))
     ms_fwd_eval = float(np.mean([r[2] for r in recs]))
-    ms_adj = (None if args.background else
-              float(np.mean([r[5][1].elapsed_time(r[5][2]) for r in recs])))
+    ms_adj = float(np.mean([r[5][1].elapsed_time(r[5][2]) for r in recs]))
     step_ms = [r[5][3].elapsed_time(r[5][2]) for r in recs]
     p2p_pairs, m2p_pairs = recs[-1][3], recs[-1][4]
     inter = p2p_pairs + m2p_pairs

@@ -208,8 +208,10 @@ int build_interaction_lists_periodic_err(hot_ctx* ctx, hot_tree* tree, const dou
  * sink, rho times the exact fields of its group's boxes, minus N(g)'s, plus
  * that of the whole 5L cube of the near zone (unsoftened, FP64), so that
  * with no truncation the result equals that of the periodic lists without
- * subtraction. Potentials and the adjoint are not available with these
- * lists (HOT_E_INVALID, HOT_E_STATE). theta: (0, 1); direct_max: >= 0.
+ * subtraction. eval_forces_adjoint differentiates all of it: the
+ * subtracted moments at the sink, the box fields through the sink position,
+ * and the mean density through every mass. Potentials are not available
+ * with these lists (HOT_E_INVALID). theta: (0, 1); direct_max: >= 0.
  * Synchronises the stream.
  */
 int build_interaction_lists_periodic_bs(hot_ctx* ctx, hot_tree* tree, double theta,

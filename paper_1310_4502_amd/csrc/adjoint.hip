@@ -417,7 +417,9 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
 template <int P, typename T>
 constexpr int sink_adj_waves_per_simd() { return (sizeof(T) == 4 && P == 8) ? 3 : 1; }
 
-template <int P, typename T, bool MIXQ, bool PER>
+// BG: background subtraction; an entry flagged in m2p_sub takes its cell's
+// cube-subtracted moments (momsub) instead of momw.
+template <int P, typename T, bool MIXQ, bool PER, bool BG = false>
 __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(sink_adj_waves_per_simd<P, T>())))
 void k_m2p_sink_adj(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
@@ -427,7 +429,8 @@ void k_m2p_sink_adj(
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
     const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, const T* __restrict__ momw,
-    double inv_side, double eps, T* __restrict__ state) {
+    double inv_side, double eps, T* __restrict__ state, const int8_t* __restrict__ m2p_sub,
+    const T* __restrict__ momsub) {
   using Stage = MomentStage<P, T>;
   __shared__ T smom[Stage::kLds ? kWPB * Stage::kStride : 1];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -458,12 +461,13 @@ void k_m2p_sink_adj(
   const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
   T* slot = smom + (Stage::kLds ? w * Stage::kStride : 0);
   typename Stage::Regs pre;
-  int cn = 0, ln = 0, qn = P;
+  int cn = 0, ln = 0, qn = P, sn = 0;
   double nx = 0, ny = 0, nz = 0;
   if (e0 < e1) {
     cn = uniform_i32(m2p[e0]);
     if (MIXQ) qn = uniform_i32(m2p_q[e0]);
-    Stage::prefetch(pre, momw, cn, lane);
+    if (BG) sn = uniform_i32(m2p_sub[e0]);
+    Stage::prefetch(pre, (BG && sn) ? momsub : momw, cn, lane);
     ln = c_level[cn];
     nx = c_centre[3 * cn];
     ny = c_centre[3 * cn + 1];
@@ -483,11 +487,12 @@ void k_m2p_sink_adj(
     const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
     const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
     const T Z = (T)((cgz - nz) * inv_s) + me.z * (T)inv_s;
-    const T* M = Stage::commit(pre, momw, c, slot, lane);
+    const T* M = Stage::commit(pre, (BG && sn) ? momsub : momw, c, slot, lane);
     if (e + 1 < e1) {
       cn = uniform_i32(m2p[e + 1]);
       if (MIXQ) qn = uniform_i32(m2p_q[e + 1]);
-      Stage::prefetch(pre, momw, cn, lane);
+      if (BG) sn = uniform_i32(m2p_sub[e + 1]);
+      Stage::prefetch(pre, (BG && sn) ? momsub : momw, cn, lane);
       ln = c_level[cn];
       nx = c_centre[3 * cn];
       ny = c_centre[3 * cn + 1];
@@ -1003,7 +1008,8 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
 
 template <int P, typename T>
 void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<T>* ab,
-                          const T* momw, double eps, T* sink_state, double* mbar64,
+                          const T* momw, const T* momsub, double eps, T* sink_state,
+                          double* mbar64,
                           const double* pos, const double* abar) {
   hipStream_t st = ctx->stream;
   const double inv_side = 1.0 / t->side;
@@ -1013,10 +1019,13 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
         t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
         t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
         t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
-        t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state);
+        t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state,
+        t->m2p_sub.as<int8_t>(), momsub);
     HOT_CHECK_LAUNCH();
   };
-  if (mixq && t->periodic)
+  if (t->bg)
+    sink(k_m2p_sink_adj<P, T, false, true, true>);
+  else if (mixq && t->periodic)
     sink(k_m2p_sink_adj<P, T, true, true>);
   else if (mixq)
     sink(k_m2p_sink_adj<P, T, true, false>);
@@ -1166,6 +1175,11 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   HOT_CHECK_LAUNCH();
   // expansion terms
   const T* momw = nullptr;
+  const T* momsub = nullptr;
+  if (t->bg) {
+    weighted_sub(ctx, t, sizeof(T) == 8);
+    momsub = t->momsub.as<T>();
+  }
   if constexpr (sizeof(T) == 4) {
     momw = t->mom32.as<T>();
   } else {
@@ -1177,15 +1191,15 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   double* M = mbar64.as<double>();
   T* S = sink.as<T>();
   switch (p) {
-    case 0: launch_expansion_adj<0, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 1: launch_expansion_adj<1, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 2: launch_expansion_adj<2, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 3: launch_expansion_adj<3, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 4: launch_expansion_adj<4, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 5: launch_expansion_adj<5, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 6: launch_expansion_adj<6, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 7: launch_expansion_adj<7, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
-    case 8: launch_expansion_adj<8, T>(ctx, t, o4, a4, momw, eps, S, M, pos, abar); break;
+    case 0: launch_expansion_adj<0, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 1: launch_expansion_adj<1, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 2: launch_expansion_adj<2, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 3: launch_expansion_adj<3, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 4: launch_expansion_adj<4, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 5: launch_expansion_adj<5, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 6: launch_expansion_adj<6, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 7: launch_expansion_adj<7, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    case 8: launch_expansion_adj<8, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
     default: invalid("p out of range");
   }
   const double* sp = spos.as<double>();
@@ -1207,6 +1221,8 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   HOT_CHECK_LAUNCH();
   // far periodic replicas: their direct dependence on the sink position
   if (t->periodic) far_replicas_xbar(ctx, t, pos, abar, xbar);
+  // background subtraction: the exact box fields and the mean density
+  if (t->bg) background_adjoint(ctx, t, pos, mass, eps, sizeof(T) == 8, abar, xbar, mbar);
 }
 
 }  // namespace

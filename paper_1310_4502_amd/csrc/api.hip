@@ -328,7 +328,6 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     if (!(eps >= 0.0) || !std::isfinite(eps)) hot::invalid("eps must be finite and >= 0");
     if (precision != HOT_MIXED && precision != HOT_FP64) hot::invalid("unknown precision");
     if (!tree->has_lists) hot::state("build_interaction_lists first");
-    if (tree->bg) hot::state("the adjoint of background-subtracted lists is not provided");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
     hot::adjoint(ctx, tree, pos, mass, eps, precision, acc_bar, pos_bar, mass_bar);

@@ -214,6 +214,16 @@ void build_lists_periodic_err(hot_ctx* ctx, hot_tree* t, const double* mass, dou
 void weighted_sub(hot_ctx* ctx, hot_tree* t, bool fp64);
 // exact background fields of the listed boxes, minus N(g), plus the near zone
 void background_boxes(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
+// their adjoint and that of the mean density (through every mass)
+void background_adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
+                        double eps, bool fp64, const double* abar, double* xbar, double* mbar);
+// weighted scaled moments of every cell's uniform cube per unit density, negated
+// (C x nm_pad(p), FP32 or FP64)
+void weighted_cube(hot_ctx* ctx, hot_tree* t, bool fp64, void* out);
+// field (caller order, N x 3) of the flagged M2P entries' uniform cubes per
+// unit mean density, with the sign they enter the forces with
+void cube_field(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+                bool fp64, double* out);
 void lattice_tensor(hot_ctx* ctx, hot_tree* t);
 void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
 void far_replicas_mbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,

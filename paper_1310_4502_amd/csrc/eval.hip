@@ -412,7 +412,52 @@ void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, 
   }
 }
 
+template <typename T>
+__global__ void k_zero_t(T* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
+}
+
+// The expansion kernel on the background-subtracted lists with zero matter
+// moments and the negated unit-density cube moments: the derivative of the
+// forces with respect to the mean density through the flagged entries.
+template <typename T>
+void cube_field_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+                  double* out) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = t->n;
+  const int64_t nmom = t->n_cells * nm_pad(t->p);
+  DBuf off, state, zero, cube;
+  off.alloc(ctx, n * sizeof(V4<T>));
+  state.alloc(ctx, n * 8 * sizeof(T));
+  zero.alloc(ctx, nmom * sizeof(T));
+  cube.alloc(ctx, nmom * sizeof(T));
+  k_offsets<T><<<grid_for(n, kB), kB, 0, st>>>(pos, mass, t->perm.as<uint32_t>(),
+                                               t->group_of.as<int32_t>(), t->g_cell.as<int32_t>(),
+                                               t->c_centre.as<double>(), n, off.as<V4<T>>(),
+                                               ctx->d_flags);
+  HOT_CHECK_LAUNCH();
+  k_zero_t<T><<<grid_for(n * 8, kB), kB, 0, st>>>(state.as<T>(), n * 8);
+  HOT_CHECK_LAUNCH();
+  k_zero_t<T><<<grid_for(nmom, kB), kB, 0, st>>>(zero.as<T>(), nmom);
+  HOT_CHECK_LAUNCH();
+  weighted_cube(ctx, t, sizeof(T) == 8, cube.p);
+  launch_m2p<T, false>(ctx, t, off.as<V4<T>>(), zero.as<T>(), cube.as<T>(), eps, state.as<T>());
+  k_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(state.as<T>(), t->perm.as<uint32_t>(), n, out,
+                                                nullptr);
+  HOT_CHECK_LAUNCH();
+}
+
 }  // namespace
+
+void cube_field(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
+                bool fp64, double* out) {
+  if (!t->bg) state("cube field without background-subtracted lists");
+  if (fp64)
+    cube_field_t<double>(ctx, t, pos, mass, eps, out);
+  else
+    cube_field_t<float>(ctx, t, pos, mass, eps, out);
+}
 
 void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
             int precision, double* acc, double* pot, hot_stats* stats) {

@@ -196,7 +196,40 @@ __global__ void k_weighted_sub(const double* __restrict__ mom, int64_t C,
   out[c * stride + s] = (T)(kAlpha.w[s] * v);
 }
 
+// Weighted scaled moments of each cell's uniform cube per unit density, with
+// the minus sign they are subtracted with: -w_alpha L^3 2^(-3 level - |alpha|)
+// prod_d 1 / (alpha_d + 1) for all alpha_d even, else 0.
+template <typename T>
+__global__ void k_weighted_cube(int64_t C, const int8_t* __restrict__ c_level, double vol, int p,
+                                T* __restrict__ out) {
+  const int nmv = nm(p), stride = nm_pad(p);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = t / stride;
+  const int s = (int)(t - c * stride);
+  if (c >= C) return;
+  double v = 0.0;
+  if (s < nmv) {
+    const int a = kAlpha.a[s], b = kAlpha.b[s], cc = kAlpha.c[s];
+    if (!((a | b | cc) & 1))
+      v = -kAlpha.w[s] * ldexp(vol, -3 * (int)c_level[c] - (a + b + cc)) /
+          ((double)(a + 1) * (double)(b + 1) * (double)(cc + 1));
+  }
+  out[c * stride + s] = (T)v;
+}
+
 }  // namespace
+
+void weighted_cube(hot_ctx* ctx, hot_tree* t, bool fp64, void* out) {
+  const int64_t tot = t->n_cells * nm_pad(t->p);
+  const double vol = (t->side * t->side) * t->side;
+  if (fp64)
+    k_weighted_cube<double><<<grid_for(tot, kB), kB, 0, ctx->stream>>>(
+        t->n_cells, t->c_level.as<int8_t>(), vol, t->p, static_cast<double*>(out));
+  else
+    k_weighted_cube<float><<<grid_for(tot, kB), kB, 0, ctx->stream>>>(
+        t->n_cells, t->c_level.as<int8_t>(), vol, t->p, static_cast<float*>(out));
+  HOT_CHECK_LAUNCH();
+}
 
 void weighted_sub(hot_ctx* ctx, hot_tree* t, bool fp64) {
   const int64_t C = t->n_cells;

@@ -3,8 +3,8 @@ images, subtraction flags and boxes bit-exact; forces against the oracle
 treecode on the same lists (FP64 and mixed precision) and against the Ewald
 direct sum; the gain the method is for (more accurate than the unsubtracted
 lists at the same order in near-uniform volumes, far less FP32 rounding
-there, and so fewer interactions at equal accuracy); and the entry point's
-checks."""
+there, and so fewer interactions at equal accuracy); the adjoint against the
+oracle's VJP and finite differences; and the entry point's checks."""
 import sys
 
 import numpy as np
@@ -137,14 +137,65 @@ def test_bs_checks():
     t.compute_moments(pos, mass, 4)
     with pytest.raises(HotError):
         t.eval_forces(pos, mass, 1e-3, HOT_MIXED, with_pot=True)
-    with pytest.raises(HotError):
-        t.eval_forces_adjoint(pos, mass, 1e-3, torch.zeros_like(pos), HOT_MIXED)
     a, _, _ = t.eval_forces(pos, mass, 1e-3, HOT_MIXED)
     assert torch.isfinite(a).all()
-    # back to plain periodic lists: the adjoint is available again
-    t.build_interaction_lists_periodic(0.5, 0)
-    xb, _ = t.eval_forces_adjoint(pos, mass, 1e-3, torch.zeros_like(pos), HOT_MIXED)
-    assert torch.all(xb == 0)
+    xb, mb = t.eval_forces_adjoint(pos, mass, 1e-3, torch.zeros_like(pos), HOT_MIXED,
+                                   with_mass=True)
+    assert torch.all(xb == 0) and torch.all(mb == 0)
+
+
+@pytest.mark.parametrize("kind,size,a,p,theta,dmax,n_leaf,n_group,width", [
+    ("lattice", 12, 0.3, 6, 0.5, 0, 16, 64, 3),
+    ("clustered", 1500, 0.04, 4, 0.6, 4, 8, 32, 3),   # straddling pieces
+    ("clustered", 1200, 0.1, 4, 0.5, 0, 8, 32, 5),
+])
+def test_bs_adjoint_vs_oracle_vjp(kind, size, a, p, theta, dmax, n_leaf, n_group, width):
+    """The adjoint of background-subtracted lists (subtracted moments at the
+    sink, the box fields' gradients, the mean density through every mass)
+    against the oracle's VJP on the same lists, and a directional finite
+    difference of the FP64 forward in positions and in masses."""
+    pos_np, mass_np = _pos(kind, size, a)
+    if kind == "clustered":
+        mass_np = mass_np * (0.5 + np.random.default_rng(3).random(mass_np.shape))
+    n, eps = pos_np.shape[0], 1e-3
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    gt = Tree(pos, n_leaf, n_group, BOX)
+    ot = oracle.Tree(pos_np, n_leaf, n_group, BOX)
+    gt.build_interaction_lists_periodic_bs(theta, dmax, width)
+    ot.build_lists_periodic_bs(theta, dmax, width=width)
+    gt.compute_moments(pos, mass, p)
+    ot.compute_moments(pos_np, mass_np, p)
+    abar_np = np.random.default_rng(46).standard_normal((n, 3))
+    abar_np /= np.linalg.norm(abar_np)
+    ox, om = ot.vjp(pos_np, mass_np, eps, abar_np)
+    abar = torch.from_numpy(abar_np).cuda()
+    gx64, gm64 = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_FP64, with_mass=True)
+    gx, gm = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_MIXED, with_mass=True)
+    r = [rel_rms(gx64.cpu().numpy(), ox), rel_rms(gm64.cpu().numpy(), om),
+         rel_rms(gx.cpu().numpy(), ox), rel_rms(gm.cpu().numpy(), om)]
+    _log(kind, n, "bs adjoint vs oracle VJP: fp64", r[:2], "mixed", r[2:])
+    assert max(r[:2]) <= 1e-11 and max(r[2:]) <= 1e-5
+    rng = np.random.default_rng(47)
+    v = torch.from_numpy(rng.normal(size=pos_np.shape)).cuda()
+    dm = torch.from_numpy(rng.normal(size=mass_np.shape) * mass_np).cuda()
+
+    def L(x, m):
+        gt.compute_moments(x, m, p)
+        acc, _, _ = gt.eval_forces(x, m, eps, HOT_FP64)
+        return float((acc * abar).sum())
+
+    def cd(f, h):
+        return (f(h) - f(-h)) / (2 * h)
+
+    fx = lambda h: L(pos + h * v, mass)
+    fm = lambda h: L(pos, mass + h * dm)
+    fdx = (4 * cd(fx, 1e-6) - cd(fx, 2e-6)) / 3
+    fdm = (4 * cd(fm, 1e-6) - cd(fm, 2e-6)) / 3
+    anx, anm = float((gx64 * v).sum()), float((gm64 * dm).sum())
+    _log("directional", anx, fdx, "mass", anm, fdm)
+    assert abs(anx - fdx) <= 1e-6 * abs(fdx)
+    assert abs(anm - fdm) <= 1e-6 * abs(fdm)
 
 
 def test_bs_fewer_interactions_at_equal_accuracy():
