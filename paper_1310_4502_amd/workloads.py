@@ -122,7 +122,7 @@ def zeldovich(ngrid: int, seed: int, rms_disp_cells: float = 0.3) -> np.ndarray:
     dk[0, 0, 0] = 0.0
     disp = np.empty((g, g, g, 3))
     for d, kd in enumerate((kx, ky, kz)):
-        disp[..., d] = np.fft.irfftn(1j * kd * dk / k2, s=(g, g, g))
+        disp[..., d] = np.fft.irfftn(1j * kd * dk / k2, s=(g, g, g), axes=(0, 1, 2))
     del dk
     rms = np.sqrt(np.mean(np.sum(disp * disp, axis=-1)))
     disp *= (rms_disp_cells / g) / rms
