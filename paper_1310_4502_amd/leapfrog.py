@@ -23,7 +23,9 @@ from one needs no offset.
 With periodic=True the box (lo, L) is the periodic cell: positions are
 integrated unwrapped, and every force evaluation sees them wrapped into the
 cell (x - L floor((x - lo) / L), whose derivative is the identity almost
-everywhere), on periodic lists.
+everywhere), on periodic lists; background=True subtracts the mean density
+on them (neighbourhood of bg_width group sides). err_tol, if set, replaces
+the theta test by the error-bound test (orders up to p).
 """
 from __future__ import annotations
 
@@ -47,6 +49,9 @@ class ForceField:
     precision: int = HOT_MIXED
     box: Optional[tuple] = None
     periodic: bool = False
+    background: bool = False
+    bg_width: int = 3
+    err_tol: Optional[float] = None
 
     def _wrap(self, x: torch.Tensor) -> torch.Tensor:
         if not self.periodic:
@@ -60,9 +65,17 @@ class ForceField:
     def tree(self, x: torch.Tensor) -> Tree:
         if self.periodic and self.box is None:
             raise ValueError("periodic force fields need the box (lo, L) of the periodic cell")
+        if self.background and (not self.periodic or self.err_tol is not None):
+            raise ValueError("background subtraction needs periodic theta lists")
         t = Tree(self._wrap(x), self.n_leaf, self.n_group, self.box)
-        if self.periodic:
+        if self.background:
+            t.build_interaction_lists_periodic_bs(self.theta, self.direct_max, self.bg_width)
+        elif self.periodic and self.err_tol is not None:
+            t.build_interaction_lists_periodic_err(self.mass, self.err_tol, self.p, self.direct_max)
+        elif self.periodic:
             t.build_interaction_lists_periodic(self.theta, self.direct_max)
+        elif self.err_tol is not None:
+            t.build_interaction_lists_err(self.mass, self.err_tol, self.p, self.direct_max)
         else:
             t.build_interaction_lists(self.theta, self.direct_max)
         return t

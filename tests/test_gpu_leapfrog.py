@@ -135,18 +135,22 @@ def test_leapfrog_gradient_vs_oracle_replay():
     assert err <= 1e-4
 
 
-def test_periodic_leapfrog_gradient_vs_fd():
+@pytest.mark.parametrize("lists", ["theta", "background", "error_bound"])
+def test_periodic_leapfrog_gradient_vs_fd(lists):
     """The same gradient in the periodic unit cube: positions integrated
     unwrapped and wrapped for every force evaluation (some cross a face
-    during the run); periodic lists, their adjoint, against central
-    differences of the FP64 replay with the run's topology."""
+    during the run); periodic lists (theta, theta with background
+    subtraction, error-bound), their adjoint, against central differences of
+    the FP64 replay with the run's topology."""
     n = 4096
     rng = np.random.default_rng(600)
     x0 = torch.from_numpy(rng.random((n, 3))).cuda()
     v0 = torch.from_numpy(0.5 * rng.standard_normal((n, 3))).cuda()
     mass = torch.full((n,), 1.0 / n, dtype=torch.float64).cuda()
     dt, steps, every = 1e-3, 16, 4
-    field = LF.ForceField(mass, 1e-3, 0.5, 4, 16, 64, 0, HOT_MIXED, (0.0, 0.0, 0.0, 1.0), True)
+    field = LF.ForceField(mass, 1e-3, 0.5, 4, 16, 64, 0, HOT_MIXED, (0.0, 0.0, 0.0, 1.0), True,
+                          background=lists == "background",
+                          err_tol=1e-3 if lists == "error_bound" else None)
     xt = x0 + torch.from_numpy(0.01 * rng.standard_normal((n, 3))).cuda()
     xK, vK, ck = LF.run(field, x0, v0, dt, steps, every)
     crossed = int(((xK < 0) | (xK >= 1)).any(dim=1).sum())
@@ -176,5 +180,6 @@ def test_periodic_leapfrog_gradient_vs_fd():
         ad.append(float((gx if which == 0 else gv)[i, d]))
     fd, ad = np.array(fd), np.array(ad)
     err = np.max(np.abs(ad - fd)) / np.sqrt(np.mean(fd ** 2))
-    _log(f"periodic leapfrog: {crossed} particles crossed a face; max |g_adj - g_fd| / rms = {err:.3e}")
+    _log(f"periodic leapfrog ({lists}): {crossed} particles crossed a face; "
+         f"max |g_adj - g_fd| / rms = {err:.3e}")
     assert err <= 1e-4
