@@ -14,6 +14,12 @@
 //                  Mbar flows down the tree through the transpose of the
 //                  re-centring (M2M^T) and into the particles of each leaf
 //                  through the transpose of the moment definition (P2M^T).
+// Variants of the lists: per-entry orders (error-bound lists: the records of
+// a cell are split by order, one cell-side launch per order), images
+// (periodic lists: sources shifted by n L, the far replicas differentiated
+// through the sink positions and the root's moments), cube-subtracted
+// moments (background subtraction: the box fields and the mean density are
+// differentiated separately).
 // Every reduction is a gather in a fixed order: no floating-point atomics.
 #include "common.h"
 #include "eval_common.h"

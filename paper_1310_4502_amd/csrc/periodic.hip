@@ -9,6 +9,9 @@
 //   L_beta = sum_{|alpha| <= p} (-1)^|alpha|/alpha! M_alpha(root) T_{alpha+beta}   (|beta| <= p+1)
 //   a_k(x) += sum_{|beta| <= p} (x - c)^beta/beta! L_{beta+e_k}.
 // T is a constant of the cube side, computed once on the host in FP64.
+// Adjoint: x_bar += sum_k abar_k sum_{|beta| <= p-1} u^beta/beta! L_{beta+e_k+e_l},
+// and the root's moment cotangent w_alpha sum_gamma T_{alpha+gamma} D_gamma
+// with D_gamma = sum_i sum_k abar_ik u_i^(gamma-e_k)/(gamma-e_k)!.
 #include <cmath>
 #include <vector>
 
