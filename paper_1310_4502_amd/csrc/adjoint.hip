@@ -287,8 +287,9 @@ __global__ void k_cq_items(const uint32_t* __restrict__ bnd, const uint32_t* __r
 
 // ------------------------------------------------------------------- gathers
 template <typename T>
+// sorted cotangents, and three times them for the source-side pair kernel
 __global__ void k_abar(const double* __restrict__ abar, const uint32_t* __restrict__ perm,
-                       int64_t n, V4<T>* __restrict__ ab) {
+                       int64_t n, V4<T>* __restrict__ ab, V4<T>* __restrict__ ab3) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t j = perm[i];
@@ -298,6 +299,10 @@ __global__ void k_abar(const double* __restrict__ abar, const uint32_t* __restri
   v.z = (T)abar[3 * j + 2];
   v.w = T(0);
   ab[i] = v;
+  v.x = T(3) * v.x;
+  v.y = T(3) * v.y;
+  v.z = T(3) * v.z;
+  ab3[i] = v;
 }
 
 // Image index -> shift of the source replica (periodic lists): n L with
@@ -339,6 +344,7 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     me = off[i];
     ab = ab4[i];
   }
+  const T a3x = T(3) * ab.x, a3y = T(3) * ab.y, a3z = T(3) * ab.z;
   T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
   const int64_t e1 = p2p_off[g + 1];
   int64_t e = p2p_off[g];
@@ -384,8 +390,8 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     if (SELF && jj == i) inv = T(0);                                                 \
     const T inv2 = inv * inv;                                                        \
     const T m3 = s.w * (inv * inv2);                                                 \
-    const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));                    \
-    const T q = (T(3) * m3) * (rd * inv2);                                           \
+    const T rd3 = hot_fma(rx, a3x, hot_fma(ry, a3y, rz * a3z));                      \
+    const T q = m3 * (rd3 * inv2);                                                   \
     A += m3;                                                                         \
     Bx = hot_fma(q, rx, Bx);                                                         \
     By = hot_fma(q, ry, By);                                                         \
@@ -548,7 +554,7 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
     const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
-    const V4<T>* __restrict__ ab4, T eps2, T* __restrict__ out) {
+    const V4<T>* __restrict__ ab3, T eps2, T* __restrict__ out) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t q = (int64_t)blockIdx.x * kWPB + w;
   if (q >= n_items) return;
@@ -591,23 +597,25 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     }
     const int i0 = uniform_i32(g_first[g]);
     const int i1 = i0 + uniform_i32(g_count[g]);
+    // three times the sums: with b = 3 abar_i and d = r . b,
+    // 3 H abar = s^-3/2 (b - 3 d r s^-1) and 3 abar . r s^-3/2 = d s^-3/2
     T gx = 0, gy = 0, gz = 0, gm = 0;
 #define HOT_SRC_PAIR(SELF)                                                           \
   {                                                                                  \
     const V4<T> si = off[i];                                                         \
-    const V4<T> ab = ab4[i];                                                         \
+    const V4<T> b = ab3[i];                                                          \
     const T rx = tx - si.x, ry = ty - si.y, rz = tz - si.z;                          \
     const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
     T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
     if (SELF && i == j) inv = T(0);                                                  \
     const T inv2 = inv * inv;                                                        \
     const T inv3 = inv * inv2;                                                       \
-    const T rd = hot_fma(rx, ab.x, hot_fma(ry, ab.y, rz * ab.z));                    \
-    const T qq = (T(3) * rd) * (inv3 * inv2);                                        \
-    gx = hot_fma(ab.x, inv3, hot_fma(-qq, rx, gx));                                  \
-    gy = hot_fma(ab.y, inv3, hot_fma(-qq, ry, gy));                                  \
-    gz = hot_fma(ab.z, inv3, hot_fma(-qq, rz, gz));                                  \
-    gm = hot_fma(rd, inv3, gm);                                                      \
+    const T d = hot_fma(rx, b.x, hot_fma(ry, b.y, rz * b.z));                        \
+    const T u = (T(3) * d) * inv2;                                                   \
+    gx = hot_fma(inv3, hot_fma(-u, rx, b.x), gx);                                    \
+    gy = hot_fma(inv3, hot_fma(-u, ry, b.y), gy);                                    \
+    gz = hot_fma(inv3, hot_fma(-u, rz, b.z), gz);                                    \
+    gm = hot_fma(d, inv3, gm);                                                       \
   }
     if (g == gs && im0 == kCentreImage) {
       for (int i = i0; i < i1; ++i) HOT_SRC_PAIR(true)
@@ -617,10 +625,12 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     }
 #undef HOT_SRC_PAIR
     if (mine) {
-      kahan_add(sx, cx, me.w * gx);
-      kahan_add(sy, cy, me.w * gy);
-      kahan_add(sz, cz, me.w * gz);
-      kahan_add(sm, cm, gm);
+      const T third = T(1) / T(3);
+      const T mw = me.w * third;
+      kahan_add(sx, cx, mw * gx);
+      kahan_add(sy, cy, mw * gy);
+      kahan_add(sz, cz, mw * gz);
+      kahan_add(sm, cm, gm * third);
     }
   }
   if (active) {
@@ -1134,9 +1144,10 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   const int64_t n = t->n, C = t->n_cells;
   const int p = t->p;
   if (!t->has_transpose) build_transpose(ctx, t);
-  DBuf off, ab, sink, src, mbar64, spos, smass, xb, mb;
+  DBuf off, ab, ab3, sink, src, mbar64, spos, smass, xb, mb;
   off.alloc(ctx, n * sizeof(V4<T>));
   ab.alloc(ctx, n * sizeof(V4<T>));
+  ab3.alloc(ctx, n * sizeof(V4<T>));
   sink.alloc(ctx, n * 8 * sizeof(T));
   src.alloc(ctx, n * 8 * sizeof(T));
   mbar64.alloc(ctx, (size_t)C * nm(p) * sizeof(double));
@@ -1149,7 +1160,8 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
                                                t->c_centre.as<double>(), n, off.as<V4<T>>(),
                                                ctx->d_flags);
   HOT_CHECK_LAUNCH();
-  k_abar<T><<<grid_for(n, kB), kB, 0, st>>>(abar, t->perm.as<uint32_t>(), n, ab.as<V4<T>>());
+  k_abar<T><<<grid_for(n, kB), kB, 0, st>>>(abar, t->perm.as<uint32_t>(), n, ab.as<V4<T>>(),
+                                            ab3.as<V4<T>>());
   HOT_CHECK_LAUNCH();
   gather_sorted(ctx, t, pos, mass, spos.as<double>(), smass.as<double>(), 0);
   const T e2 = (T)(eps * eps);
@@ -1177,7 +1189,7 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
                            t->p2p_img.as<int8_t>(), t->side, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
                            t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
                            t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off.as<V4<T>>(),
-                           ab.as<V4<T>>(), e2, src.as<T>());
+                           ab3.as<V4<T>>(), e2, src.as<T>());
   HOT_CHECK_LAUNCH();
   // expansion terms
   const T* momw = nullptr;
