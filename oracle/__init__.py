@@ -330,19 +330,20 @@ def ewald_self(L, split=2.0):
     return f(ctypes.c_double(L), ctypes.c_double(split))
 
 
-def ewald_direct(pos, mass, L, eps, sinks=None):
-    """Periodic accelerations by definition (near replicas softened, far by
-    Ewald sums) for the selected sinks."""
+def ewald_direct(pos, mass, L, eps, sinks=None, with_pot=False):
+    """Periodic accelerations (and potentials) by definition (near replicas
+    softened, far by Ewald sums) for the selected sinks."""
     pos = _f64(pos)
     mass = _f64(mass)
     n = pos.shape[0]
     sel = _i64(sinks)
     ns = n if sel is None else sel.shape[0]
     acc = np.empty((ns, 3))
+    pot = np.empty(ns) if with_pot else None
     _chk(lib().oracle_ewald_direct(ctypes.c_int64(n), _p(pos), _p(mass), ctypes.c_double(L),
                                    ctypes.c_double(eps), ctypes.c_int64(0 if sel is None else ns),
-                                   _p(sel), _p(acc)))
-    return acc
+                                   _p(sel), _p(acc), _p(pot)))
+    return (acc, pot) if with_pot else acc
 
 
 def m2p(p, M, R, eps):

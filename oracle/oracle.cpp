@@ -722,6 +722,10 @@ std::vector<double> lattice_tensor(double L, int K, double split) {
           T[g] += w * sg * ipow(k[0], mi[g][0]) * ipow(k[1], mi[g][1]) * ipow(k[2], mi[g][2]);
         }
       }
+  // the neutralising background's constant of Ewald's split (the k = 0
+  // term), which makes F, and T_0, independent of the split; it enters
+  // potentials only
+  T[0] -= M_PI / (a * a * L * L * L);
   // F is even in each coordinate (the cubic lattice is symmetric under each
   // reflection x_d -> -x_d): every T_gamma with an odd component vanishes
   // exactly; the sums above leave only rounding there
@@ -798,6 +802,36 @@ void grad_far(const double r[3], double L, double split, double g[3]) {
         const double sn = std::sin((k[0] * r[0] + k[1] * r[1]) + k[2] * r[2]);
         for (int d = 0; d < 3; ++d) g[d] -= w * k[d] * sn;
       }
+}
+
+// F(r) = psi(r) - sum_near 1/|r + nL| itself (the potential of the far
+// replicas and the background per unit mass, up to the sign), by Ewald's
+// split; F(0) is finite (the n = 0 near term's singularity is removed).
+double pot_far(const double r[3], double L, double split) {
+  const double a = split / L;
+  double f = -M_PI / (a * a * L * L * L);
+  for (int nx = -4; nx <= 4; ++nx)
+    for (int ny = -4; ny <= 4; ++ny)
+      for (int nz = -4; nz <= 4; ++nz) {
+        const int m = std::max(std::abs(nx), std::max(std::abs(ny), std::abs(nz)));
+        const double p[3] = {r[0] + nx * L, r[1] + ny * L, r[2] + nz * L};
+        const double rho = std::sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+        if (m <= kWs)
+          f -= rho > 0.0 ? std::erf(a * rho) / rho : 2.0 * a / kSqrtPi;
+        else
+          f += std::erfc(a * rho) / rho;
+      }
+  const double twopi = 2.0 * M_PI / L;
+  for (int mx = -5; mx <= 5; ++mx)
+    for (int my = -5; my <= 5; ++my)
+      for (int mz = -5; mz <= 5; ++mz) {
+        if (!mx && !my && !mz) continue;
+        const double k[3] = {twopi * mx, twopi * my, twopi * mz};
+        const double k2 = (k[0] * k[0] + k[1] * k[1]) + k[2] * k[2];
+        f += 4.0 * M_PI / (L * L * L) * std::exp(-k2 / (4.0 * a * a)) / k2 *
+             std::cos((k[0] * r[0] + k[1] * r[1]) + k[2] * r[2]);
+      }
+  return f;
 }
 
 // periodic walk: the tree of image img (centres shifted), theta test as above
@@ -1418,7 +1452,7 @@ double oracle_ewald_self(double L, double split) { return ewald_self(L, split); 
 // O-D periodic: the definition above, for the selected sinks (caller
 // indices; all if null), near zone softened, far part by Ewald sums.
 int oracle_ewald_direct(int64_t n, const double* pos, const double* mass, double L, double eps,
-                        int64_t n_sinks, const int64_t* sinks, double* acc) {
+                        int64_t n_sinks, const int64_t* sinks, double* acc, double* pot) {
   if (n < 1 || !pos || !mass || !acc || !(L > 0)) return fail("bad arguments");
   std::vector<int64_t> todo;
   if (sinks) {
@@ -1431,26 +1465,30 @@ int oracle_ewald_direct(int64_t n, const double* pos, const double* mass, double
   for (int64_t k = 0; k < (int64_t)todo.size(); ++k) {
     const int64_t i = todo[k];
     const double* xi = &pos[3 * i];
-    NSum s[3];
+    NSum s[3], sp;
     for (int64_t j = 0; j < n; ++j) {
       const double* xj = &pos[3 * j];
-      double a[3] = {0, 0, 0};
+      double a[3] = {0, 0, 0}, ph = 0.0;
       for (int img = 0; img < kImages; ++img) {
         if (j == i && img == kImages / 2) continue;
         double sh[3];
         image_shift(img, L, sh);
         double r[3] = {(xj[0] + sh[0]) - xi[0], (xj[1] + sh[1]) - xi[1], (xj[2] + sh[2]) - xi[2]};
-        p2p_pair(mass[j], r, eps, a, nullptr);
+        p2p_pair(mass[j], r, eps, a, pot ? &ph : nullptr);
       }
+      const double r[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
       if (j != i) {
-        const double r[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
         double g[3];
         grad_far(r, L, kSplit, g);
         for (int d = 0; d < 3; ++d) a[d] += mass[j] * g[d];
       }
+      // the far replicas of j (of i itself too) and the background
+      if (pot) ph -= mass[j] * pot_far(r, L, kSplit);
       for (int d = 0; d < 3; ++d) s[d].add(a[d]);
+      sp.add(ph);
     }
     for (int d = 0; d < 3; ++d) acc[3 * k + d] = s[d].value();
+    if (pot) pot[k] = sp.value();
   }
   return 0;
 }
@@ -1661,6 +1699,8 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
           bk[d] += 1;
           a[d] += mono * far_L[slot_of(bk)];
         }
+        // potential: phi = -sum_beta u^beta/beta! L_beta
+        ph -= mono * far_L[slot_of(be)];
       }
     }
     for (int d = 0; d < 3; ++d) acc[3 * k + d] = a[d];

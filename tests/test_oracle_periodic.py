@@ -12,7 +12,9 @@ function against its direct gradient, and for the periodic forces: zero net
 force, invariance under a periodic translation, zero force in a perfect
 lattice, the large-box limit, and the treecode against the direct sum; with
 the error-bound test, every accepted image interaction within the tolerance
-of its exact field."""
+of its exact field; potentials: the Madelung-type value of a lone particle,
+the direct sum's potential as the one whose gradient is minus its
+acceleration, the treecode's against it."""
 import numpy as np
 import pytest
 
@@ -84,9 +86,11 @@ def test_lattice_tensor_split_independence(orc):
     mx = _order_max(A, mi)
     for k, (a, b, c) in enumerate(mi):
         n = a + b + c
-        if n == 0:
-            continue  # F(0) carries the split-dependent constant; forces never use it
         assert abs(A[k] - B[k]) <= _tol(n) * mx[n], (a, b, c, A[k], B[k])
+    # F(0) = psi_reg(0) - sum over the near images n != 0 of 1/|n L|
+    near = sum(1.0 / np.sqrt(x * x + y * y + z * z) for x in range(-2, 3) for y in range(-2, 3)
+               for z in range(-2, 3) if (x, y, z) != (0, 0, 0))
+    assert abs(A[0] - (orc.ewald_self(1.0, 2.0) - near)) <= 1e-12 * near
 
 
 def test_far_gradient_matches_its_taylor_series(orc):
@@ -272,3 +276,45 @@ def test_periodic_error_bound_lists(orc):
     fd = (4 * cd(h) - cd(2 * h)) / 3
     an = float((xb * v).sum())
     assert abs(an - fd) <= 1e-8 * abs(fd)
+
+
+def test_periodic_potentials(orc):
+    """Potentials with periodic boundaries: a lone particle sits at the
+    simple-cubic Madelung-type potential -m psi_reg(0) = +2.837297479480620 m / L
+    (eps = 0), in the Ewald direct sum and in the treecode; the direct sum's
+    potential is the one whose gradient is minus its acceleration; the
+    treecode's potentials approach the direct sum's."""
+    box = np.array([0.0, 0.0, 0.0, 1.0])
+    # at the cube centre every expansion of the treecode is exact (a lone
+    # monopole at the expansion centre); off centre the order-8 truncation shows
+    for x, tol in ((np.array([[0.5, 0.5, 0.5]]), 1e-12), (np.array([[0.13, 0.71, 0.42]]), 1e-3)):
+        a, phi = orc.ewald_direct(x, np.ones(1), 1.0, 0.0, with_pot=True)
+        assert abs(phi[0] + MADELUNG_SC) <= 1e-12
+        t = orc.Tree(x, 16, 64, box)
+        t.build_lists_periodic(0.5, 0)
+        t.compute_moments(x, np.ones(1), 8)
+        _, tp, _ = t.eval(x, np.ones(1), 0.0)
+        assert abs(tp[0] + MADELUNG_SC) <= tol
+    rng = np.random.default_rng(31)
+    n = 300
+    pos = rng.random((n, 3))
+    mass = rng.random(n) / n
+    eps = 1e-2
+    sinks = np.array([3, 77, 150])
+    acc, phi = orc.ewald_direct(pos, mass, 1.0, eps, sinks=sinks, with_pot=True)
+    h = 1e-5
+    for k, i in enumerate(sinks):
+        for d in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[i, d] += h
+            pm[i, d] -= h
+            # only sink i moves: the potential of i changes through r_ij, and
+            # its gradient is the acceleration (self-image terms are constant)
+            fp = orc.ewald_direct(pp, mass, 1.0, eps, sinks=[i], with_pot=True)[1][0]
+            fm = orc.ewald_direct(pm, mass, 1.0, eps, sinks=[i], with_pot=True)[1][0]
+            assert abs(-(fp - fm) / (2 * h) - acc[k, d]) <= 1e-6 * np.abs(acc[k]).max()
+    t = orc.Tree(pos, 8, 32, box)
+    t.build_lists_periodic(0.3, 0)
+    t.compute_moments(pos, mass, 8)
+    _, tp, _ = t.eval(pos, mass, eps, sinks=sinks)
+    assert np.abs(tp - phi).max() <= 1e-6 * np.abs(phi).max()
