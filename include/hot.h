@@ -171,8 +171,10 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
  * expansion about the cube centre built from the root's moments, derivatives
  * of the far function to order 2p + 1, applied to order p. eval_forces_adjoint
  * differentiates all of it, the far replicas included (through the sink
- * positions and the root's moments). Potentials are not available with
- * periodic lists (HOT_E_INVALID). theta: (0, 1); direct_max: >= 0.
+ * positions and the root's moments). Potentials, where asked for, are those
+ * of the same split: with the background, whose constant enters the order-0
+ * lattice sum, a lone particle at the cube centre has phi = +2.8373 m / L.
+ * theta: (0, 1); direct_max: >= 0.
  * Synchronises the stream.
  */
 int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
@@ -181,8 +183,9 @@ int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta,
  * build_interaction_lists_periodic_err -- the periodic lists above with the
  * error-bound test of build_interaction_lists_err in place of the theta test
  * (per image entry, on the shifted centre; every M2P entry carries its order,
- * tree_get_m2p_orders, and its image, tree_get_list_images). Evaluation and
- * adjoint as for periodic lists; moments of order >= p_max are needed.
+ * tree_get_m2p_orders, and its image, tree_get_list_images). Evaluation,
+ * potentials and adjoint as for periodic lists; moments of order >= p_max
+ * are needed.
  * mass: N (device; only its maximum is used). err_tol: finite, > 0.
  * p_max: 0 .. 8. direct_max: >= 0. Synchronises the stream.
  */

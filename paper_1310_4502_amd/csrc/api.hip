@@ -312,9 +312,10 @@ int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* m
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
-    if (tree->periodic && pot) hot::invalid("potentials are not available with periodic lists");
+    if (tree->bg && pot)
+      hot::invalid("potentials are not available with background-subtracted lists");
     hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats);
-    if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc);
+    if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc, pot);
     if (tree->bg) hot::background_boxes(ctx, tree, pos, acc);
   });
 }

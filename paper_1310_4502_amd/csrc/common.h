@@ -225,7 +225,7 @@ void weighted_cube(hot_ctx* ctx, hot_tree* t, bool fp64, void* out);
 void cube_field(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
                 bool fp64, double* out);
 void lattice_tensor(hot_ctx* ctx, hot_tree* t);
-void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
+void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc, double* pot);
 void far_replicas_mbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,
                        double* mbar_root);
 void far_replicas_xbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,

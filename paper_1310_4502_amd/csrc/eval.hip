@@ -320,16 +320,12 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, co
     HOT_CHECK_LAUNCH();
   };
   if (t->list_p >= 0) {
-    // potentials are refused with periodic lists: no periodic variant for them
-    if constexpr (!POT) {
-      if (t->periodic) {
-        go(k_m2p<P, T, POT, true, true, false>);
-        return;
-      }
-    }
-    go(k_m2p<P, T, POT, true, false, false>);
+    if (t->periodic)
+      go(k_m2p<P, T, POT, true, true, false>);
+    else
+      go(k_m2p<P, T, POT, true, false, false>);
   } else if (t->periodic) {
-    // potentials are refused with periodic lists: no subtracted variant for them
+    // potentials are refused with background subtraction: no variant for them
     if constexpr (!POT) {
       if (t->bg) {
         go(k_m2p<P, T, POT, false, true, true>);

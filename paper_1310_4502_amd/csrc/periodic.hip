@@ -135,6 +135,9 @@ std::vector<double> lattice_sums(double L) {
             }
         }
       }
+  // the neutralising background's constant (the k = 0 term of the split):
+  // makes T_0 independent of the split; potentials only
+  T[0] -= M_PI / (a * a * L * L * L);
   // F is even in every coordinate: entries with an odd exponent are zero
   for (int s = 0; s <= K; ++s)
     for (int t = s; t >= 0; --t)
@@ -178,12 +181,14 @@ __global__ void k_far_local(const double* __restrict__ M, int p, const double* _
 }
 
 // a_k(x_i) += sum_{|beta| <= p} u^beta / beta! L_{beta + e_k}, u = x_i - c
+// (pot, if not null: phi -= sum_{|beta| <= p} u^beta/beta! L_beta)
 __global__ void k_far_l2p(const double* __restrict__ pos, int64_t n, const double* __restrict__ c,
-                          int p, const double* __restrict__ Lc, double* __restrict__ acc) {
+                          int p, const double* __restrict__ Lc, double* __restrict__ acc,
+                          double* __restrict__ pot) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double u0 = pos[3 * i] - c[0], u1 = pos[3 * i + 1] - c[1], u2 = pos[3 * i + 2] - c[2];
-  double ax = 0.0, ay = 0.0, az = 0.0;
+  double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
   double px = 1.0;  // u0^a / a!
   for (int a = 0; a <= p; ++a) {
     double py = 1.0;
@@ -194,6 +199,7 @@ __global__ void k_far_l2p(const double* __restrict__ pos, int64_t n, const doubl
         ax += m * Lc[slot3(a + 1, b, d)];
         ay += m * Lc[slot3(a, b + 1, d)];
         az += m * Lc[slot3(a, b, d + 1)];
+        ph -= m * Lc[slot3(a, b, d)];
         pz *= u2 / (d + 1);
       }
       py *= u1 / (b + 1);
@@ -203,6 +209,7 @@ __global__ void k_far_l2p(const double* __restrict__ pos, int64_t n, const doubl
   acc[3 * i] += ax;
   acc[3 * i + 1] += ay;
   acc[3 * i + 2] += az;
+  if (pot) pot[i] += ph;
 }
 
 // Adjoint of the far replicas (u = x_i - c, b_i the acceleration cotangent):
@@ -399,7 +406,7 @@ void lattice_tensor(hot_ctx* ctx, hot_tree* t) {
   HOT_HIP(hipStreamSynchronize(ctx->stream));
 }
 
-void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc) {
+void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc, double* pot) {
   hipStream_t st = ctx->stream;
   const int p = t->p;
   DBuf Lc;
@@ -408,7 +415,7 @@ void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc) {
                                                          t->lattice.as<double>(), Lc.as<double>());
   HOT_CHECK_LAUNCH();
   k_far_l2p<<<grid_for(t->n, 256), 256, 0, st>>>(pos, t->n, t->c_centre.as<double>(), p,
-                                                 Lc.as<double>(), acc);
+                                                 Lc.as<double>(), acc, pot);
   HOT_CHECK_LAUNCH();
 }
 

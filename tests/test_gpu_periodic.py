@@ -171,8 +171,6 @@ def test_periodic_checks():
         t.list_images()
     t.build_interaction_lists_periodic(0.5, 0)
     t.compute_moments(pos, mass, 4)
-    with pytest.raises(HotError):
-        t.eval_forces(pos, mass, w.eps, HOT_MIXED, with_pot=True)
     a, _, _ = t.eval_forces(pos, mass, w.eps, HOT_MIXED)
     assert torch.isfinite(a).all()
     xb, _ = t.eval_forces_adjoint(pos, mass, w.eps, torch.zeros_like(pos), HOT_MIXED)
@@ -289,3 +287,48 @@ def test_periodic_error_bound_lists(name, n, tol, p_max, dmax, n_leaf, n_group):
     an = float((xbar * v).sum())
     _log("directional", an, fd)
     assert abs(an - fd) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("lists", ["theta", "error_bound"])
+def test_periodic_potentials(lists):
+    """Potentials with periodic lists (near images softened, the far replicas'
+    local potential with the background's constant): against the oracle
+    treecode on the same lists, and against the Ewald direct sum; a lone
+    particle at the cube centre sits at the Madelung-type value."""
+    pos_np, mass_np = _clustered(6000, 14)
+    eps, p = 1e-3, 8
+    pos = torch.from_numpy(pos_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    gt = Tree(pos, 16, 64, BOX)
+    ot = oracle.Tree(pos_np, 16, 64, BOX)
+    if lists == "theta":
+        gt.build_interaction_lists_periodic(0.4, 0)
+        ot.build_lists_periodic(0.4, 0)
+    else:
+        gt.build_interaction_lists_periodic_err(mass, 1e-4, p, 0)
+        ot.build_lists_periodic_err(mass_np, 1e-4, p, 0)
+    gt.compute_moments(pos, mass, p)
+    ot.compute_moments(pos_np, mass_np, p)
+    ts = np.sort(np.random.default_rng(5).choice(6000, 256, replace=False))
+    oa, op, _ = ot.eval(pos_np, mass_np, eps, sinks=ts)
+    g64 = gt.eval_forces(pos, mass, eps, HOT_FP64, with_pot=True)
+    g32 = gt.eval_forces(pos, mass, eps, HOT_MIXED, with_pot=True)
+    e64 = rel_rms(g64[1].cpu().numpy()[ts], op)
+    e32 = rel_rms(g32[1].cpu().numpy()[ts], op)
+    _log(lists, "potential vs oracle treecode: fp64", e64, "mixed", e32)
+    assert e64 <= 1e-11 and e32 <= 1e-5
+    # the forces are those without potentials
+    assert torch.equal(g64[0], gt.eval_forces(pos, mass, eps, HOT_FP64)[0])
+    sinks = ts[:32]
+    _, pd = oracle.ewald_direct(pos_np, mass_np, 1.0, eps, sinks=sinks, with_pot=True)
+    ed = rel_rms(g64[1].cpu().numpy()[sinks], pd)
+    _log("vs Ewald direct sum", ed)
+    assert ed <= 1e-5
+    if lists == "theta":
+        c = torch.full((1, 3), 0.5, dtype=torch.float64).cuda()
+        one = torch.ones(1, dtype=torch.float64).cuda()
+        t = Tree(c, 16, 64, BOX)
+        t.build_interaction_lists_periodic(0.5, 0)
+        t.compute_moments(c, one, p)
+        ph = t.eval_forces(c, one, 0.0, HOT_FP64, with_pot=True)[1].cpu().numpy()
+        assert abs(ph[0] - 2.837297479480620) <= 1e-12
