@@ -35,6 +35,7 @@ static __constant__ AlphaTable kAlpha = make_alpha_table();
 constexpr int kB = 256;
 constexpr int kWPB = kB / 64;
 constexpr int kCellItemGroups = 48;  // groups per work item of the cell-side kernel
+constexpr int kSrcChunk = 512;  // records per work unit of the source-side pair kernel
 
 
 int bits_for(int64_t v) {
@@ -115,6 +116,29 @@ __global__ __launch_bounds__(kB) void k_srec_fill(
       val[at + (q - q0)] = (uint32_t)e;
     }
     o += total;
+  }
+}
+
+// work units of the source-side pair kernel: each item's records cut into runs
+// of at most kSrcChunk (an item without records still gets one unit)
+__global__ void k_sunit_count(const uint32_t* __restrict__ soff, int64_t n_items,
+                              uint32_t* __restrict__ cnt) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_items) return;
+  const uint32_t n = soff[q + 1] - soff[q];
+  cnt[q] = n == 0 ? 1u : (n + kSrcChunk - 1) / kSrcChunk;
+}
+
+__global__ void k_sunit_fill(const uint32_t* __restrict__ soff, int64_t n_items,
+                             const uint32_t* __restrict__ uoff, int4* __restrict__ units) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_items) return;
+  const uint32_t b = soff[q], e = soff[q + 1];
+  const uint32_t u0 = uoff[q], nu = uoff[q + 1] - u0;
+  for (uint32_t k = 0; k < nu; ++k) {
+    const uint32_t rb = b + k * kSrcChunk;
+    const uint32_t re = rb + kSrcChunk < e ? rb + kSrcChunk : e;
+    units[u0 + k] = make_int4((int)q, (int)rb, (int)re, nu == 1 ? 1 : 0);
   }
 }
 
@@ -540,25 +564,33 @@ void k_m2p_sink_adj(
 }
 
 // ----------------------------------------------------- pair terms, source side
-// One wavefront per source item (at most 64 particles of one group); lanes are
-// source particles. The records of the item are sorted by sink group; runs of
-// one group are merged into a lane mask (the lanes whose particles lie in one
-// of that group's P2P cells), then the group's sinks are swept uniformly.
+// One wavefront per source item (at most 64 particles of one group). The
+// records of the item are sorted by sink group; runs of one group are merged
+// into a lane mask (the lanes whose particles lie in one of that group's P2P
+// cells). With more than 32 such lanes, lanes are the item's particles and the
+// group's sinks are swept uniformly. With k <= 32 of them, the k particles are
+// packed into the first W = 2^ceil(log2 k) lanes and the wavefront splits into
+// 64 / W slices that sweep interleaved subsets of the sinks, so a group that
+// pair-sums only a leaf or two of the item costs n_sinks W / 64 iterations
+// instead of n_sinks; the slices' sums are then added across lanes and handed
+// back to the particles' own lanes.
 // out per sorted particle: s_x s_y s_z s_m c_x c_y c_z c_m
 template <typename T, bool EPS0, bool PER>
 __global__ __launch_bounds__(kB) void k_p2p_src_adj(
-    const int2* __restrict__ items, int64_t n_items, const uint64_t* __restrict__ skey,
-    const uint32_t* __restrict__ sval, const uint32_t* __restrict__ soff, uint64_t gmask,
+    const int4* __restrict__ units, int64_t n_units, const int2* __restrict__ items,
+    const uint64_t* __restrict__ skey, const uint32_t* __restrict__ sval, uint64_t gmask,
     const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
     const int32_t* __restrict__ c_first,
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
     const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
-    const V4<T>* __restrict__ ab3, T eps2, T* __restrict__ out) {
+    const V4<T>* __restrict__ ab3, T eps2, T* __restrict__ out, T* __restrict__ part) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * kWPB + w;
-  if (q >= n_items) return;
-  const int2 item = items[q];
+  const int64_t wu = (int64_t)blockIdx.x * kWPB + w;
+  if (wu >= n_units) return;
+  const int4 unit = units[wu];
+  const int2 item = items[uniform_i32(unit.x)];
+  const uint32_t r0 = (uint32_t)uniform_i32(unit.y), r1 = (uint32_t)uniform_i32(unit.z);
   const int gs = uniform_i32(item.x);
   const int j = item.y + lane;
   const bool active = j < g_first[gs] + g_count[gs];
@@ -568,73 +600,153 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
   me.x = me.y = me.z = me.w = T(0);
   if (active) me = off[j];
   T sx = 0, sy = 0, sz = 0, sm = 0, cx = 0, cy = 0, cz = 0, cm = 0;
-  uint32_t r = soff[q];
-  const uint32_t rend = soff[q + 1];
-  while (r < rend) {
-    const uint64_t k0 = skey[r];
-    const int g = uniform_i32((int)(k0 & gmask));
-    // consecutive records of the same sink group (and, periodic, the same image)
-    const int im0 = PER ? uniform_i32(p2p_img[sval[r]]) : kCentreImage;
-    bool mine = false;
-    while (r < rend && skey[r] == k0 && (!PER || uniform_i32(p2p_img[sval[r]]) == im0)) {
-      const int c = p2p[sval[r]];
-      const int f = c_first[c];
-      mine |= (j >= f) && (j < f + c_count[c]);
-      ++r;
-    }
-    const int gc = uniform_i32(g_cell[g]);
-    T tx, ty, tz;  // r_ij = x_j - x_i = t - off_i
-    if (PER) {
-      double shx, shy, shz;
-      image_shift(im0, side, shx, shy, shz);
-      tx = (T)((csx + shx) - c_centre[3 * gc]) + me.x;
-      ty = (T)((csy + shy) - c_centre[3 * gc + 1]) + me.y;
-      tz = (T)((csz + shz) - c_centre[3 * gc + 2]) + me.z;
-    } else {
-      tx = (T)(csx - c_centre[3 * gc]) + me.x;
-      ty = (T)(csy - c_centre[3 * gc + 1]) + me.y;
-      tz = (T)(csz - c_centre[3 * gc + 2]) + me.z;
-    }
-    const int i0 = uniform_i32(g_first[g]);
-    const int i1 = i0 + uniform_i32(g_count[g]);
-    // three times the sums: with b = 3 abar_i and d = r . b,
-    // 3 H abar = s^-3/2 (b - 3 d r s^-1) and 3 abar . r s^-3/2 = d s^-3/2
-    T gx = 0, gy = 0, gz = 0, gm = 0;
-#define HOT_SRC_PAIR(SELF)                                                           \
+  // three times the pair sums: with b = 3 abar_i and d = r . b,
+  // 3 H abar = s^-3/2 (b - 3 d r s^-1) and 3 abar . r s^-3/2 = d s^-3/2
+#define HOT_SRC_PAIR(SI, B, TX, TY, TZ, ZERO)                                        \
   {                                                                                  \
-    const V4<T> si = off[i];                                                         \
-    const V4<T> b = ab3[i];                                                          \
-    const T rx = tx - si.x, ry = ty - si.y, rz = tz - si.z;                          \
+    const T rx = (TX) - (SI).x, ry = (TY) - (SI).y, rz = (TZ) - (SI).z;              \
     const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
     T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
-    if (SELF && i == j) inv = T(0);                                                  \
+    if (ZERO) inv = T(0);                                                            \
     const T inv2 = inv * inv;                                                        \
     const T inv3 = inv * inv2;                                                       \
-    const T d = hot_fma(rx, b.x, hot_fma(ry, b.y, rz * b.z));                        \
-    const T u = (T(3) * d) * inv2;                                                   \
-    gx = hot_fma(inv3, hot_fma(-u, rx, b.x), gx);                                    \
-    gy = hot_fma(inv3, hot_fma(-u, ry, b.y), gy);                                    \
-    gz = hot_fma(inv3, hot_fma(-u, rz, b.z), gz);                                    \
+    const T d = hot_fma(rx, (B).x, hot_fma(ry, (B).y, rz * (B).z));                  \
+    const T dd = (T(3) * d) * inv2;                                                  \
+    gx = hot_fma(inv3, hot_fma(-dd, rx, (B).x), gx);                                 \
+    gy = hot_fma(inv3, hot_fma(-dd, ry, (B).y), gy);                                 \
+    gz = hot_fma(inv3, hot_fma(-dd, rz, (B).z), gz);                                 \
     gm = hot_fma(d, inv3, gm);                                                       \
   }
-    if (g == gs && im0 == kCentreImage) {
-      for (int i = i0; i < i1; ++i) HOT_SRC_PAIR(true)
-    } else {
-#pragma unroll 4
-      for (int i = i0; i < i1; ++i) HOT_SRC_PAIR(false)
+  // Records are read in batches of 64, one per lane, so that their loads
+  // overlap; position r1 is an end marker that closes the last run. A run is
+  // the records of one sink group (and image); mine marks the lanes whose
+  // particle lies in one of the run's cells.
+  int g = -1, im0 = -1;
+  bool mine = false;
+  for (uint32_t base = r0; base <= r1; base += 64) {
+    const uint32_t rl = base + lane;
+    int lg = -1, lim = -1, lf = 0, lc = 0;
+    if (rl < r1) {
+      const uint32_t e = sval[rl];
+      const int c = p2p[e];
+      lg = (int)(skey[rl] & gmask);
+      lf = c_first[c];
+      lc = c_count[c];
+      lim = PER ? (int)p2p_img[e] : kCentreImage;
     }
-#undef HOT_SRC_PAIR
-    if (mine) {
-      const T third = T(1) / T(3);
-      const T mw = me.w * third;
-      kahan_add(sx, cx, mw * gx);
-      kahan_add(sy, cy, mw * gy);
-      kahan_add(sz, cz, mw * gz);
-      kahan_add(sm, cm, gm * third);
+    const int nb = (int)(r1 + 1 - base < 64u ? r1 + 1 - base : 64u);
+    for (int bq = 0; bq < nb; ++bq) {
+      const int gb = __builtin_amdgcn_readlane(lg, bq);
+      const int imb = __builtin_amdgcn_readlane(lim, bq);
+      if (gb != g || imb != im0) {
+        mine = mine && active;
+        const uint64_t mask = __ballot(mine);
+        const int k = __popcll(mask);
+        if (g >= 0 && k > 0) {
+          // sweep the finished run's sink group
+          const int gc = uniform_i32(g_cell[g]);
+          T dx, dy, dz;  // source group centre minus sink group centre
+          if (PER) {
+            double shx, shy, shz;
+            image_shift(im0, side, shx, shy, shz);
+            dx = (T)((csx + shx) - c_centre[3 * gc]);
+            dy = (T)((csy + shy) - c_centre[3 * gc + 1]);
+            dz = (T)((csz + shz) - c_centre[3 * gc + 2]);
+          } else {
+            dx = (T)(csx - c_centre[3 * gc]);
+            dy = (T)(csy - c_centre[3 * gc + 1]);
+            dz = (T)(csz - c_centre[3 * gc + 2]);
+          }
+          const int i0 = uniform_i32(g_first[g]);
+          const int i1 = i0 + uniform_i32(g_count[g]);
+          const bool self = g == gs && im0 == kCentreImage;
+          T gx = 0, gy = 0, gz = 0, gm = 0;
+          if (k > 32) {
+            // lanes are the item's particles, sinks wavefront-uniform:
+            // r_ij = x_j - x_i = t - off_i
+            const T tx = dx + me.x, ty = dy + me.y, tz = dz + me.z;
+            if (self) {
+              for (int i = i0; i < i1; ++i) {
+                const V4<T> si = off[i];
+                const V4<T> b = ab3[i];
+                HOT_SRC_PAIR(si, b, tx, ty, tz, i == j)
+              }
+            } else {
+#pragma unroll 4
+              for (int i = i0; i < i1; ++i) {
+                const V4<T> si = off[i];
+                const V4<T> b = ab3[i];
+                HOT_SRC_PAIR(si, b, tx, ty, tz, false)
+              }
+            }
+          } else {
+            // rank of each marked lane among the marked lanes below it; a
+            // stable partition (marked lanes first) tells packed lane p its
+            // source lane
+            const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            const int dest = mine ? below : k + (lane - below);
+            const int src_of = __builtin_amdgcn_ds_permute(dest << 2, lane);
+            const int lw = k <= 1 ? 0 : 32 - __clz(k - 1);
+            const int p = lane & ((1 << lw) - 1);
+            const int sl = lane >> lw;  // slice
+            const int S = 64 >> lw;
+            const int sp = __shfl(src_of, p);
+            const bool pact = p < k;
+            const int jp = item.y + sp;
+            const T tx = dx + __shfl(me.x, sp), ty = dy + __shfl(me.y, sp),
+                    tz = dz + __shfl(me.z, sp);
+#pragma unroll 2
+            for (int i_base = i0; i_base < i1; i_base += S) {
+              const int i = i_base + sl;
+              const bool ok = pact && i < i1;
+              const int ic = ok ? i : i0;
+              const V4<T> si = off[ic];
+              const V4<T> b = ab3[ic];
+              HOT_SRC_PAIR(si, b, tx, ty, tz, !ok || (self && i == jp))
+            }
+            // sum over the slices; packed lane 'below' of slice 0 then holds
+            // the marked lane's totals
+#pragma unroll
+            for (int m = 32; m > 0; m >>= 1) {
+              if (m < (1 << lw)) break;
+              gx += __shfl_xor(gx, m);
+              gy += __shfl_xor(gy, m);
+              gz += __shfl_xor(gz, m);
+              gm += __shfl_xor(gm, m);
+            }
+            gx = __shfl(gx, below);
+            gy = __shfl(gy, below);
+            gz = __shfl(gz, below);
+            gm = __shfl(gm, below);
+          }
+          if (mine) {
+            const T third = T(1) / T(3);
+            const T mw = me.w * third;
+            kahan_add(sx, cx, mw * gx);
+            kahan_add(sy, cy, mw * gy);
+            kahan_add(sz, cz, mw * gz);
+            kahan_add(sm, cm, gm * third);
+          }
+        }
+        g = gb;
+        im0 = imb;
+        mine = false;
+      }
+      if (gb >= 0) {
+        const int f = __builtin_amdgcn_readlane(lf, bq);
+        mine = mine || ((j >= f) && (j < f + __builtin_amdgcn_readlane(lc, bq)));
+      }
     }
   }
-  if (active) {
-    T* o = out + (int64_t)j * 8;
+#undef HOT_SRC_PAIR
+  T* o = nullptr;
+  if (unit.w) {
+    if (active) o = out + (int64_t)j * 8;  // the item's only unit
+  } else {
+    o = part + (wu * 64 + lane) * 8;  // summed over the item's units later
+  }
+  if (o) {
     o[0] = sx;
     o[1] = sy;
     o[2] = sz;
@@ -643,6 +755,36 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     o[5] = cy;
     o[6] = cz;
     o[7] = cm;
+  }
+}
+
+// Items with several units: per particle, the units' (sum, compensation) pairs
+// added in FP64 in unit order, written back as one pair.
+template <typename T>
+__global__ void k_src_unit_sum(const int2* __restrict__ items, int64_t n_items,
+                               const uint32_t* __restrict__ unit_off,
+                               const int32_t* __restrict__ g_first,
+                               const int32_t* __restrict__ g_count, const T* __restrict__ part,
+                               T* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t q = t >> 6;
+  const int l = (int)(t & 63);
+  if (q >= n_items) return;
+  const uint32_t u0 = unit_off[q], u1 = unit_off[q + 1];
+  if (u1 - u0 <= 1) return;
+  const int2 it = items[q];
+  const int j = it.y + l;
+  if (j >= g_first[it.x] + g_count[it.x]) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (uint32_t v = u0; v < u1; ++v) {
+    const T* a = part + ((int64_t)v * 64 + l) * 8;
+    for (int k = 0; k < 4; ++k) acc[k] += (double)a[k] - (double)a[4 + k];
+  }
+  T* o = out + (int64_t)j * 8;
+  for (int k = 0; k < 4; ++k) {
+    const T hi = (T)acc[k];
+    o[k] = hi;
+    o[4 + k] = (T)((double)hi - acc[k]);
   }
 }
 
@@ -741,13 +883,29 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
   }
   T* o = part + it * (int64_t)(MIXQ ? out_stride : nm_pad(P));
+  // Sum the rows over the 64 lanes as a reduce-scatter: the row vector, padded
+  // with zeros to 64 KR entries, is halved six times; at each step a lane keeps
+  // one half (selected by its lane bit), receives the partner's copy of it and
+  // adds. Lane l ends with the sums of rows KR l .. KR l + KR - 1, after
+  // 32 KR + 16 KR + ... + KR exchanges instead of 6 per row.
+  constexpr int KR = (NM + 63) / 64;
+  T v[64 * KR];
 #pragma unroll
-  for (int a = 0; a < NM; ++a) {
-    T v = row[a];
+  for (int a = 0; a < 64 * KR; ++a) v[a] = a < NM ? row[a] : T(0);
 #pragma unroll
-    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
-    if (lane == (a & 63)) o[a] = v;
+  for (int m = 32, h = 32 * KR; m > 0; m >>= 1, h >>= 1) {
+    const bool up = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const T lo = v[i], hi = v[i + h];
+      const T send = up ? lo : hi;
+      const T keep = up ? hi : lo;
+      v[i] = keep + __shfl_xor(send, m);
+    }
   }
+#pragma unroll
+  for (int i = 0; i < KR; ++i)
+    if (KR * lane + i < NM) o[KR * lane + i] = v[i];
   if (MIXQ)
     for (int a = NM + lane; a < out_nm; a += 64) o[a] = T(0);
 }
@@ -899,7 +1057,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     int64_t nrec = 0;
     HOT_HIP(hipMemcpyAsync(&nrec, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HOT_HIP(hipStreamSynchronize(st));
-    if (nrec >= (int64_t)UINT32_MAX) throw Error{HOT_E_CAPACITY, "too many P2P records"};
+    if (nrec >= (int64_t)INT32_MAX - 128) throw Error{HOT_E_CAPACITY, "too many P2P records"};
     t->n_srec = nrec;
     const int gbits = bits_for(G);
     const int qbits = bits_for(NI);
@@ -917,6 +1075,25 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
                                                        t->srec_off.as<uint32_t>());
     HOT_CHECK_LAUNCH();
     t->srec_gbits = gbits;
+    // work units of the source-side kernel
+    t->schunk_off.alloc(ctx, (NI + 1) * sizeof(uint32_t));
+    DBuf ucnt;
+    ucnt.alloc(ctx, (NI + 1) * sizeof(uint32_t));
+    k_sunit_count<<<grid_for(NI, kB), kB, 0, st>>>(t->srec_off.as<uint32_t>(), NI,
+                                                   ucnt.as<uint32_t>());
+    HOT_CHECK_LAUNCH();
+    // exclusive offsets of the NI items, the total in the last slot
+    uint32_t* uoff = t->schunk_off.as<uint32_t>();
+    scan_u32(ctx, ucnt.as<uint32_t>(), uoff, NI, uoff + NI);
+    uint32_t nu = 0;
+    HOT_HIP(hipMemcpyAsync(&nu, uoff + NI, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HOT_HIP(hipStreamSynchronize(st));
+    t->n_schunk = nu;
+    t->schunk.alloc(ctx, std::max<int64_t>(1, (int64_t)nu) * sizeof(int4));
+    k_sunit_fill<<<grid_for(NI, kB), kB, 0, st>>>(t->srec_off.as<uint32_t>(), NI,
+                                                  t->schunk_off.as<uint32_t>(),
+                                                  t->schunk.as<int4>());
+    HOT_CHECK_LAUNCH();
   }
   // ---- expansion records by source cell, split into items
   {
@@ -1183,14 +1360,23 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
                                           : k_p2p_src_adj<T, true, true>)
                            : (e2 > T(0) ? k_p2p_src_adj<T, false, false>
                                         : k_p2p_src_adj<T, true, false>);
-  src_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->srec_key.as<uint64_t>(),
-                           t->srec_val.as<uint32_t>(), t->srec_off.as<uint32_t>(),
-                           (1ull << t->srec_gbits) - 1ull, t->p2p.as<int32_t>(),
-                           t->p2p_img.as<int8_t>(), t->side, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
-                           t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
-                           t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off.as<V4<T>>(),
-                           ab3.as<V4<T>>(), e2, src.as<T>());
+  const int64_t NU = t->n_schunk;
+  DBuf upart;
+  if (NU > t->n_items) upart.alloc(ctx, (size_t)NU * 64 * 8 * sizeof(T));
+  src_k<<<grid_for(NU, kWPB), kB, 0, st>>>(
+      t->schunk.as<int4>(), NU, t->items.as<int2>(), t->srec_key.as<uint64_t>(),
+      t->srec_val.as<uint32_t>(), (1ull << t->srec_gbits) - 1ull, t->p2p.as<int32_t>(),
+      t->p2p_img.as<int8_t>(), t->side, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+      t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
+      t->c_centre.as<double>(), off.as<V4<T>>(), ab3.as<V4<T>>(), e2, src.as<T>(),
+      upart.as<T>());
   HOT_CHECK_LAUNCH();
+  if (NU > t->n_items) {
+    k_src_unit_sum<T><<<grid_for(t->n_items * 64, kB), kB, 0, st>>>(
+        t->items.as<int2>(), t->n_items, t->schunk_off.as<uint32_t>(), t->g_first.as<int32_t>(),
+        t->g_count.as<int32_t>(), upart.as<T>(), src.as<T>());
+    HOT_CHECK_LAUNCH();
+  }
   // expansion terms
   const T* momw = nullptr;
   const T* momsub = nullptr;

@@ -166,6 +166,10 @@ struct hot_tree {
   int64_t n_srec = 0;
   int srec_gbits = 1;
   hot::DBuf srec_key, srec_val, srec_off;
+  // work units of the source-side pair adjoint: (item, first record, end
+  // record, single-unit flag) and each item's first unit
+  int64_t n_schunk = 0;
+  hot::DBuf schunk, schunk_off;
   // M2P by source cell: records sorted by (cell, group), split in items of
   // at most kCellItemGroups groups; citem_rec: first record of each item
   int64_t n_mrec = 0, n_citems = 0, n_mcells = 0;
