@@ -34,11 +34,11 @@ WORKLOADS = {
     "zeldovich16m": (16, 96, 64, "2^24 particles, 256^3 grid displaced by a P(k)~k^-2 "
                                  "Gaussian field (RMS 0.3 cells), eps=2e-5, theta=0.5, p=8, "
                                  "forward + one adjoint VJP"),
-    "clustered16m": (16, 64, 32, "2^24 particles, half in 512 Plummer halos, half uniform, "
+    "clustered16m": (16, 256, 32, "2^24 particles, half in 512 Plummer halos, half uniform, "
                                  "eps=5e-5, theta=0.5, p=6"),
-    "clustered4m": (16, 64, 32, "2^22 particles, half in 512 Plummer halos, half uniform, "
+    "clustered4m": (16, 256, 32, "2^22 particles, half in 512 Plummer halos, half uniform, "
                                 "eps=5e-5, theta=0.5, p=6"),
-    "plummer1m": (16, 64, 16, "2^20 Plummer sphere a=1/16, eps=1e-4, theta=0.6, p=4"),
+    "plummer1m": (16, 256, 16, "2^20 Plummer sphere a=1/16, eps=1e-4, theta=0.6, p=4"),
     "uniform4k": (16, 64, 0, "4096 uniform, eps=1e-3, theta=0.5, p=2"),
 }
 

@@ -23,8 +23,8 @@ from gpu_util import (assert_lists_equal, assert_moments_close, assert_tree_equa
 pytestmark = pytest.mark.gpu
 
 # workload -> (n_leaf, n_group, direct_max) as timed by bench.py
-BENCH = {"plummer1m": (16, 64, 16), "clustered4m": (16, 64, 32), "zeldovich16m": (16, 96, 64),
-         "clustered16m": (16, 64, 32)}
+BENCH = {"plummer1m": (16, 256, 16), "clustered4m": (16, 256, 32), "zeldovich16m": (16, 96, 64),
+         "clustered16m": (16, 256, 32)}
 
 
 def _log(*a):
