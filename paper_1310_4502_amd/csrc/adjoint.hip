@@ -351,7 +351,9 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
     const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, T eps2,
     T* __restrict__ state) {
+  __shared__ V4<T> stage[kWPB][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  V4<T>* slot = stage[w];
   const int64_t it = (int64_t)blockIdx.x * kWPB + w;
   if (it >= n_items) return;
   const int2 item = items[it];
@@ -388,6 +390,7 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     double shx = 0.0, shy = 0.0, shz = 0.0;
     if (PER) image_shift(im0, side, shx, shy, shz);
     T A = 0, Bx = 0, By = 0, Bz = 0;  // sum m inv3 ; sum 3 m (r.ab) inv5 r
+    T A2 = 0, Bx2 = 0, By2 = 0, Bz2 = 0;  // odd sources of each batch
     int j = f;
     while (j < end) {
       const int sg = uniform_i32(group_of[j]);
@@ -405,13 +408,15 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
         ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
         tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
       }
-#define HOT_SINK_PAIR(SELF)                                                          \
+      // sources in batches of 64 staged through the wavefront's LDS slot
+      // (one coalesced load per lane, read back as broadcasts)
+#define HOT_SINK_PAIR(SELF, KK, A, Bx, By, Bz)                                       \
   {                                                                                  \
-    const V4<T> s = off[jj];                                                         \
+    const V4<T> s = slot[KK];                                                        \
     const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;                             \
     const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
     T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
-    if (SELF && jj == i) inv = T(0);                                                 \
+    if (SELF && jb + (KK) == i) inv = T(0);                                          \
     const T inv2 = inv * inv;                                                        \
     const T m3 = s.w * (inv * inv2);                                                 \
     const T rd3 = hot_fma(rx, a3x, hot_fma(ry, a3y, rz * a3z));                      \
@@ -421,15 +426,34 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     By = hot_fma(q, ry, By);                                                         \
     Bz = hot_fma(q, rz, Bz);                                                         \
   }
-      if (sg == g && im0 == kCentreImage) {
-        for (int jj = j; jj < jend; ++jj) HOT_SINK_PAIR(true)
-      } else {
+      const bool self = sg == g && im0 == kCentreImage;
+      for (int jb = j; jb < jend; jb += 64) {
+        const int nbt = jend - jb < 64 ? jend - jb : 64;
+        V4<T> v;
+        v.x = v.y = v.z = v.w = T(0);
+        if (lane < nbt) v = off[jb + lane];
+        __builtin_amdgcn_wave_barrier();
+        slot[lane] = v;
+        __builtin_amdgcn_wave_barrier();
+        if (self) {
+          for (int k = 0; k < nbt; ++k) HOT_SINK_PAIR(true, k, A, Bx, By, Bz)
+        } else {
+          int k = 0;
 #pragma unroll 4
-        for (int jj = j; jj < jend; ++jj) HOT_SINK_PAIR(false)
+          for (; k + 1 < nbt; k += 2) {
+            HOT_SINK_PAIR(false, k, A, Bx, By, Bz)
+            HOT_SINK_PAIR(false, k + 1, A2, Bx2, By2, Bz2)
+          }
+          if (k < nbt) HOT_SINK_PAIR(false, k, A, Bx, By, Bz)
+        }
       }
 #undef HOT_SINK_PAIR
       j = jend;
     }
+    A += A2;
+    Bx += Bx2;
+    By += By2;
+    Bz += Bz2;
     // xbar_i -= m_j H ab = -(sum m inv3) ab + sum 3 m rd inv5 r
     kahan_add(sx, cx, hot_fma(-A, ab.x, Bx));
     kahan_add(sy, cy, hot_fma(-A, ab.y, By));

@@ -49,7 +49,9 @@ __global__ __launch_bounds__(kB) void k_p2p(
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
     const V4<T>* __restrict__ off, T eps2, T* __restrict__ state, int64_t n) {
+  __shared__ V4<T> stage[kWavesPerBlock][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  V4<T>* slot = stage[w];
   const int64_t it = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (it >= n_items) return;
   const int2 item = items[it];
@@ -100,13 +102,16 @@ __global__ __launch_bounds__(kB) void k_p2p(
         ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
         tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
       }
-#define HOT_PAIR(SELF, JJ, AX, AY, AZ, AP)                                            \
+      // the segment's sources in batches of 64: one coalesced load per lane
+      // into the wavefront's LDS slot, then every lane reads them back as
+      // broadcasts (no scalar-cache round trip per few sources)
+#define HOT_PAIR(SELF, KK, AX, AY, AZ, AP)                                            \
   {                                                                                  \
-    const V4<T> s = off[JJ];                                                         \
+    const V4<T> s = slot[KK];                                                        \
     const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;                             \
     const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
     T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
-    if (SELF && (JJ) == i) inv = T(0);                                               \
+    if (SELF && jb + (KK) == i) inv = T(0);                                          \
     const T mi = s.w * inv;                                                          \
     const T f3 = mi * (inv * inv);                                                   \
     AX = hot_fma(f3, rx, AX);                                                        \
@@ -114,16 +119,26 @@ __global__ __launch_bounds__(kB) void k_p2p(
     AZ = hot_fma(f3, rz, AZ);                                                        \
     if (POT) AP -= mi;                                                               \
   }
-      if (sg == g && im0 == kCentreImage) {
-        for (int jj = j; jj < jend; ++jj) HOT_PAIR(true, jj, ax, ay, az, ap)
-      } else {
-        int jj = j;
-#pragma unroll 2
-        for (; jj + 1 < jend; jj += 2) {
-          HOT_PAIR(false, jj, ax, ay, az, ap)
-          HOT_PAIR(false, jj + 1, bx, by, bz, bp)
+      const bool self = sg == g && im0 == kCentreImage;
+      for (int jb = j; jb < jend; jb += 64) {
+        const int nbt = jend - jb < 64 ? jend - jb : 64;
+        V4<T> v;
+        v.x = v.y = v.z = v.w = T(0);
+        if (lane < nbt) v = off[jb + lane];
+        __builtin_amdgcn_wave_barrier();
+        slot[lane] = v;
+        __builtin_amdgcn_wave_barrier();
+        if (self) {
+          for (int k = 0; k < nbt; ++k) HOT_PAIR(true, k, ax, ay, az, ap)
+        } else {
+          int k = 0;
+#pragma unroll 4
+          for (; k + 1 < nbt; k += 2) {
+            HOT_PAIR(false, k, ax, ay, az, ap)
+            HOT_PAIR(false, k + 1, bx, by, bz, bp)
+          }
+          if (k < nbt) HOT_PAIR(false, k, ax, ay, az, ap)
         }
-        if (jj < jend) HOT_PAIR(false, jj, ax, ay, az, ap)
       }
 #undef HOT_PAIR
       j = jend;
