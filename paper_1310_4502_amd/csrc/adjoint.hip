@@ -609,7 +609,9 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
     const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
     const V4<T>* __restrict__ ab3, T eps2, T* __restrict__ out, T* __restrict__ part) {
+  __shared__ V4<T> stage[kWPB][128];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  V4<T>* slot = stage[w];
   const int64_t wu = (int64_t)blockIdx.x * kWPB + w;
   if (wu >= n_units) return;
   const int4 unit = units[wu];
@@ -687,20 +689,35 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
           T gx = 0, gy = 0, gz = 0, gm = 0;
           if (k > 32) {
             // lanes are the item's particles, sinks wavefront-uniform:
-            // r_ij = x_j - x_i = t - off_i
+            // r_ij = x_j - x_i = t - off_i; the sinks (offsets and scaled
+            // cotangents) staged through LDS in batches of 64
             const T tx = dx + me.x, ty = dy + me.y, tz = dz + me.z;
-            if (self) {
-              for (int i = i0; i < i1; ++i) {
-                const V4<T> si = off[i];
-                const V4<T> b = ab3[i];
-                HOT_SRC_PAIR(si, b, tx, ty, tz, i == j)
+            for (int ib = i0; ib < i1; ib += 64) {
+              const int nbt = i1 - ib < 64 ? i1 - ib : 64;
+              V4<T> v, bv;
+              v.x = v.y = v.z = v.w = T(0);
+              bv = v;
+              if (lane < nbt) {
+                v = off[ib + lane];
+                bv = ab3[ib + lane];
               }
-            } else {
+              __builtin_amdgcn_wave_barrier();
+              slot[lane] = v;
+              slot[64 + lane] = bv;
+              __builtin_amdgcn_wave_barrier();
+              if (self) {
+                for (int kk = 0; kk < nbt; ++kk) {
+                  const V4<T> si = slot[kk];
+                  const V4<T> b = slot[64 + kk];
+                  HOT_SRC_PAIR(si, b, tx, ty, tz, ib + kk == j)
+                }
+              } else {
 #pragma unroll 4
-              for (int i = i0; i < i1; ++i) {
-                const V4<T> si = off[i];
-                const V4<T> b = ab3[i];
-                HOT_SRC_PAIR(si, b, tx, ty, tz, false)
+                for (int kk = 0; kk < nbt; ++kk) {
+                  const V4<T> si = slot[kk];
+                  const V4<T> b = slot[64 + kk];
+                  HOT_SRC_PAIR(si, b, tx, ty, tz, false)
+                }
               }
             }
           } else {
@@ -720,14 +737,28 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
             const int jp = item.y + sp;
             const T tx = dx + __shfl(me.x, sp), ty = dy + __shfl(me.y, sp),
                     tz = dz + __shfl(me.z, sp);
+            for (int ib = i0; ib < i1; ib += 64) {
+              const int nbt = i1 - ib < 64 ? i1 - ib : 64;
+              V4<T> v, bv;
+              v.x = v.y = v.z = v.w = T(0);
+              bv = v;
+              if (lane < nbt) {
+                v = off[ib + lane];
+                bv = ab3[ib + lane];
+              }
+              __builtin_amdgcn_wave_barrier();
+              slot[lane] = v;
+              slot[64 + lane] = bv;
+              __builtin_amdgcn_wave_barrier();
 #pragma unroll 2
-            for (int i_base = i0; i_base < i1; i_base += S) {
-              const int i = i_base + sl;
-              const bool ok = pact && i < i1;
-              const int ic = ok ? i : i0;
-              const V4<T> si = off[ic];
-              const V4<T> b = ab3[ic];
-              HOT_SRC_PAIR(si, b, tx, ty, tz, !ok || (self && i == jp))
+              for (int kb = 0; kb < nbt; kb += S) {
+                const int kk = kb + sl;
+                const bool ok = pact && kk < nbt;
+                const int kc = ok ? kk : 0;
+                const V4<T> si = slot[kc];
+                const V4<T> b = slot[64 + kc];
+                HOT_SRC_PAIR(si, b, tx, ty, tz, !ok || (self && ib + kk == jp))
+              }
             }
             // sum over the slices; packed lane 'below' of slice 0 then holds
             // the marked lane's totals
