@@ -53,6 +53,61 @@ def test_adjoint_vs_oracle_vjp(name, n, p, theta, dmax, n_leaf, n_group):
     assert torch.equal(gx, gx2)
 
 
+def _source_runs(ot):
+    """Records per source item (a 64-particle chunk of a group) and, per
+    (item, sink group) run, the number of the item's particles that lie in
+    the group's P2P cells, from the oracle's lists."""
+    cells = ot.cells()
+    gcell = ot.groups()
+    po, pl, _, _ = ot.lists()
+    gf, gn = cells["first"][gcell], cells["count"][gcell]
+    n = int(gn.sum())
+    item_of = np.empty(n, np.int64)
+    first = []
+    for g in range(len(gcell)):
+        for f in range(gf[g], gf[g] + gn[g], 64):
+            item_of[f:min(f + 64, gf[g] + gn[g])] = len(first)
+            first.append(f)
+    first = np.array(first)
+    eg = np.repeat(np.arange(len(gcell)), np.diff(po))
+    cf, cc = cells["first"][pl], cells["count"][pl]
+    nrec = np.zeros(len(first), np.int64)
+    marked = {}
+    for e in range(len(pl)):
+        for q in range(item_of[cf[e]], item_of[cf[e] + cc[e] - 1] + 1):
+            nrec[q] += 1
+            lo, hi = max(cf[e], first[q]), min(cf[e] + cc[e], first[q] + 64)
+            marked[(q, eg[e])] = marked.get((q, eg[e]), 0) + hi - lo
+    return nrec, np.array(list(marked.values()))
+
+
+def test_adjoint_source_units_and_packed_runs():
+    """In a Plummer core a source item is pair-summed by thousands of sink
+    groups: its records are split into several work units whose partial sums
+    are added afterwards, and runs that touch at most 32 of its particles are
+    swept by packed lane slices. Both must reproduce the oracle VJP."""
+    w = W.make("plummer1m", n=32768)
+    w.n_leaf, w.n_group = 16, 64
+    gt, ot, pos, mass, p = build_both(w, theta=0.6, direct_max=16, p=4)
+    nrec, marked = _source_runs(ot)
+    _log("records per item: max", nrec.max(), "items with > 512:", int((nrec > 512).sum()),
+         "runs with <= 32 / > 32 particles:", int((marked <= 32).sum()), int((marked > 32).sum()))
+    assert nrec.max() > 2 * 512 and (marked <= 32).any() and (marked > 32).any()
+    ot.compute_moments(w.pos, w.mass, p)
+    abar_np = W.cotangent(w.n, 405)
+    ox, om = ot.vjp(w.pos, w.mass, w.eps, abar_np)
+    abar = torch.from_numpy(abar_np).cuda()
+    gx64, gm64 = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64, with_mass=True)
+    e64 = rel_rms(gx64.cpu().numpy(), ox)
+    m64 = rel_rms(gm64.cpu().numpy(), om)
+    gx, gm = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED, with_mass=True)
+    e32 = rel_rms(gx.cpu().numpy(), ox)
+    m32 = rel_rms(gm.cpu().numpy(), om)
+    _log("fp64 xbar", e64, "mbar", m64, "mixed xbar", e32, "mbar", m32)
+    assert e64 <= 1e-11 and m64 <= 1e-11
+    assert e32 <= 1e-5 and m32 <= 1e-5
+
+
 def test_adjoint_directional_fd():
     """x̄ . v equals the central difference of sum abar . a along v (topology
     frozen, FP64 GPU forward), Richardson-extrapolated from h = 2e-6 and 1e-6.
