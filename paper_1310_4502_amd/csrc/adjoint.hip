@@ -6,7 +6,8 @@
 //  pair terms    a_i += m_j K(x_j - x_i), K(r) = r (|r|^2+eps^2)^(-3/2),
 //                dK/dr = H(r) = s^(-3/2) I - 3 r r^T s^(-5/2):
 //                  sink   xbar_i -= m_j H(r_ij) abar_i      (group-major, like the forward)
-//                  source xbar_j += m_j H(r_ij) abar_i      (source-major over transposed lists)
+//                  source xbar_j += m_j H(r_ij) abar_i      (source-major over transposed lists,
+//                                 in work units whose sums are added in a fixed order)
 //                                 mbar_j += abar_i . r_ij s^(-3/2)
 //  expansion     a_i = -sum_alpha w_alpha M_alpha d^(alpha+e_k) G(x_i - c):
 //                  sink   xbar_i += -sum_k abar_ik sum_alpha w M d^(alpha+e_k+e_l) G
