@@ -160,6 +160,9 @@ struct hot_tree {
   // eval work items: (group, first sink) per wave
   int64_t n_items = 0;
   hot::DBuf items;
+  // items of at most 32 sinks and the others (split on first use; -1: not yet)
+  int64_t n_items_small = -1, n_items_big = 0;
+  hot::DBuf items_small, items_big;
   // adjoint caches built from the lists on first use
   bool has_transpose = false;
   // P2P by source item: records sorted by (item, group); rec_off per item

@@ -282,6 +282,159 @@ void k_m2p(
   }
 }
 
+// Expansion terms for an item of at most 32 sinks (theta lists without
+// background subtraction): the wavefront splits into S = 64 / W slices of
+// W = max(8, 2^ceil(log2 n_sinks)) lanes. In each round slice s evaluates
+// entry e0 + round S + s for the item's sinks; the round's S cells have their
+// coefficients staged together in the wavefront's LDS, so the lanes that an
+// item of few sinks leaves idle in k_m2p do useful work. The slices'
+// compensated sums are added at the end. Every cross-lane read is executed by
+// all lanes (never inside a lane-dependent branch or operand).
+template <int P, typename T, bool POT, bool PER>
+__global__ __launch_bounds__(64) void k_m2p_sl(
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
+    const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_img, double side,
+    const int8_t* __restrict__ c_level, const int32_t* __restrict__ g_first,
+    const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
+    const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
+    const T* __restrict__ momw, double inv_side, double eps, T* __restrict__ state) {
+  constexpr int kStride = nm_pad(P);
+  constexpr int kChunks = kStride * (int)sizeof(T) / 16;
+  constexpr int kMaxS = 8;
+  constexpr int kRounds = (kMaxS * kChunks + 63) / 64;
+  __shared__ uint4 smom[kMaxS * kChunks];
+  const int lane = threadIdx.x;
+  const int64_t it = blockIdx.x;
+  if (it >= n_items) return;
+  const int2 item = items[it];
+  const int g = uniform_i32(item.x);
+  const int gend = uniform_i32(g_first[g] + g_count[g]);
+  const int ns = gend - item.y < 64 ? gend - item.y : 64;  // <= 32 for these items
+  const int lw = ns <= 8 ? 3 : 32 - __clz(ns - 1);
+  const int S = 64 >> lw;
+  const int p = lane & ((1 << lw) - 1), sl = lane >> lw;
+  const int i = item.y + p;
+  const bool active = p < ns;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  V4<T> me;
+  me.x = me.y = me.z = me.w = T(0);
+  if (active) me = off[i];
+  T sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
+  if (active && sl == 0) {
+    const T* st = state + (int64_t)i * 8;
+    sx = st[0];
+    sy = st[1];
+    sz = st[2];
+    sp = st[3];
+    cx = st[4];
+    cy = st[5];
+    cz = st[6];
+    cp = st[7];
+  }
+  const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
+  for (int64_t eb = e0; eb < e1; eb += S) {
+    // the round's cells (and images), one per lane
+    int cl = -1, il = kCentreImage;
+    if (lane < S && eb + lane < e1) {
+      cl = m2p[eb + lane];
+      if (PER) il = m2p_img[eb + lane];
+    }
+    // stage their coefficients: chunk k of slice s at smom[s kChunks + k]
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int ch = lane + 64 * r;
+      const int s2 = ch / kChunks;
+      const int cs = __shfl(cl, s2 < kMaxS ? s2 : 0);
+      if (s2 < S && cs >= 0)
+        smom[ch] = reinterpret_cast<const uint4*>(momw + (int64_t)cs * kStride)[ch - s2 * kChunks];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // slices without an entry this round evaluate slice 0's and add nothing
+    const int cme = __shfl(cl, sl);
+    const int c0 = __shfl(cl, 0);  // valid in every round
+    const bool ok = cme >= 0;
+    const int sme = ok ? sl : 0;
+    const int c = ok ? cme : c0;
+    double nx = c_centre[3 * c], ny = c_centre[3 * c + 1], nz = c_centre[3 * c + 2];
+    if (PER) {
+      const int ime = __shfl(il, sl), i0m = __shfl(il, 0);
+      double shx, shy, shz;
+      image_shift(ok ? ime : i0m, side, shx, shy, shz);
+      nx += shx;
+      ny += shy;
+      nz += shz;
+    }
+    const double inv_s = ldexp(inv_side, (int)c_level[c]);
+    const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
+    const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
+    const T Z = (T)((cgz - nz) * inv_s) + me.z * (T)inv_s;
+    const T* M = reinterpret_cast<const T*>(smom) + sme * kStride;
+    const double es = eps * inv_s;
+    const T e2 = (T)(es * es);
+    T ax = 0, ay = 0, az = 0, ph = 0;
+    expansion_fwd<P, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph);
+    const T sa = ok ? (T)(-(inv_s * inv_s)) : T(0);
+    kahan_add(sx, cx, ax * sa);
+    kahan_add(sy, cy, ay * sa);
+    kahan_add(sz, cz, az * sa);
+    if (POT) kahan_add(sp, cp, ph * (ok ? (T)inv_s : T(0)));
+  }
+  // add the slices' compensated sums (true value s - c) across lanes
+  for (int m = 32; m >= (1 << lw); m >>= 1) {
+    T o = __shfl_xor(sx, m), oc = __shfl_xor(cx, m);
+    kahan_add(sx, cx, o);
+    cx += oc;
+    o = __shfl_xor(sy, m);
+    oc = __shfl_xor(cy, m);
+    kahan_add(sy, cy, o);
+    cy += oc;
+    o = __shfl_xor(sz, m);
+    oc = __shfl_xor(cz, m);
+    kahan_add(sz, cz, o);
+    cz += oc;
+    if (POT) {
+      o = __shfl_xor(sp, m);
+      oc = __shfl_xor(cp, m);
+      kahan_add(sp, cp, o);
+      cp += oc;
+    }
+  }
+  if (active && sl == 0) {
+    T* st = state + (int64_t)i * 8;
+    st[0] = sx;
+    st[1] = sy;
+    st[2] = sz;
+    st[3] = sp;
+    st[4] = cx;
+    st[5] = cy;
+    st[6] = cz;
+    st[7] = cp;
+  }
+}
+
+// split of the work items by sink count (at most 32, or more)
+__global__ void k_item_flags(const int2* __restrict__ items, int64_t n_items,
+                             const int32_t* __restrict__ g_first,
+                             const int32_t* __restrict__ g_count, uint32_t* __restrict__ small) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_items) return;
+  const int2 it = items[k];
+  small[k] = g_first[it.x] + g_count[it.x] - it.y <= 32 ? 1u : 0u;
+}
+
+__global__ void k_item_split(const int2* __restrict__ items, int64_t n_items,
+                             const uint32_t* __restrict__ small, const uint32_t* __restrict__ pos,
+                             int2* __restrict__ out_small, int2* __restrict__ out_big) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_items) return;
+  if (small[k])
+    out_small[pos[k]] = items[k];
+  else
+    out_big[k - (int64_t)pos[k]] = items[k];
+}
+
 template <typename T>
 __global__ void k_finalize(const T* __restrict__ state, const uint32_t* __restrict__ perm,
                            int64_t n, double* __restrict__ acc, double* __restrict__ pot) {
@@ -339,6 +492,28 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, co
       go(k_m2p<P, T, POT, true, true, false>);
     else
       go(k_m2p<P, T, POT, true, false, false>);
+  } else if (!t->bg && t->n_items_small * 10 >= t->n_items) {
+    // theta lists with many part-empty items: those of at most 32 sinks by
+    // slices of one wavefront, the others as usual
+    if (t->n_items_big > 0) {
+      auto kb = t->periodic ? k_m2p<P, T, POT, false, true, false>
+                            : k_m2p<P, T, POT, false, false, false>;
+      kb<<<grid_for(t->n_items_big, kWavesPerBlock), kB, 0, ctx->stream>>>(
+          t->items_big.as<int2>(), t->n_items_big, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
+          t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->m2p_sub.as<int8_t>(),
+          momsub, t->c_level.as<int8_t>(), t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+          t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, momw, 1.0 / t->side, eps, state);
+      HOT_CHECK_LAUNCH();
+    }
+    if (t->n_items_small > 0) {
+      auto ks = t->periodic ? k_m2p_sl<P, T, POT, true> : k_m2p_sl<P, T, POT, false>;
+      ks<<<(unsigned)t->n_items_small, 64, 0, ctx->stream>>>(
+          t->items_small.as<int2>(), t->n_items_small, t->m2p_off.as<int64_t>(),
+          t->m2p.as<int32_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
+          t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
+          t->c_centre.as<double>(), off, momw, 1.0 / t->side, eps, state);
+      HOT_CHECK_LAUNCH();
+    }
   } else if (t->periodic) {
     // potentials are refused with background subtraction: no variant for them
     if constexpr (!POT) {
@@ -351,6 +526,30 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, co
   } else {
     go(k_m2p<P, T, POT, false, false, false>);
   }
+}
+
+void split_items(hot_ctx* ctx, hot_tree* t) {
+  hipStream_t st = ctx->stream;
+  const int64_t NI = t->n_items;
+  DBuf flag, pos;
+  flag.alloc(ctx, std::max<int64_t>(1, NI) * sizeof(uint32_t));
+  pos.alloc(ctx, (NI + 1) * sizeof(uint32_t));
+  k_item_flags<<<grid_for(NI, kB), kB, 0, st>>>(t->items.as<int2>(), NI, t->g_first.as<int32_t>(),
+                                               t->g_count.as<int32_t>(), flag.as<uint32_t>());
+  HOT_CHECK_LAUNCH();
+  // exclusive offsets of the small items, their number in the last slot
+  uint32_t* pp = pos.as<uint32_t>();
+  scan_u32(ctx, flag.as<uint32_t>(), pp, NI, pp + NI);
+  uint32_t ns = 0;
+  HOT_HIP(hipMemcpyAsync(&ns, pp + NI, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipStreamSynchronize(st));
+  t->items_small.alloc(ctx, std::max<int64_t>(1, (int64_t)ns) * sizeof(int2));
+  t->items_big.alloc(ctx, std::max<int64_t>(1, NI - (int64_t)ns) * sizeof(int2));
+  k_item_split<<<grid_for(NI, kB), kB, 0, st>>>(t->items.as<int2>(), NI, flag.as<uint32_t>(), pp,
+                                               t->items_small.as<int2>(), t->items_big.as<int2>());
+  HOT_CHECK_LAUNCH();
+  t->n_items_small = ns;
+  t->n_items_big = NI - (int64_t)ns;
 }
 
 template <typename T, bool POT>
@@ -395,6 +594,7 @@ void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, 
     weighted_sub(ctx, t, sizeof(T) == 8);
     momsub = t->momsub.as<T>();
   }
+  if (t->n_items_small < 0) split_items(ctx, t);
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[0], st));
   if (pot)
     launch_p2p<T, true>(ctx, t, off.as<V4<T>>(), eps, state.as<T>());
