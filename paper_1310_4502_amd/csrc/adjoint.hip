@@ -588,6 +588,125 @@ void k_m2p_sink_adj(
   }
 }
 
+// Sink-side expansion terms for an item of at most 32 sinks (theta lists
+// without background subtraction), split like the forward's k_m2p_sl: slices
+// of W = max(8, 2^ceil(log2 n_sinks)) lanes take interleaved list entries, the
+// round's cells' coefficients staged together in LDS, and the slices'
+// compensated sums are added at the end. Every cross-lane read is executed by
+// all lanes.
+template <int P, typename T, bool PER>
+__global__ __launch_bounds__(64) void k_m2p_sink_adj_sl(
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
+    const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_img, double side,
+    const int8_t* __restrict__ c_level, const int32_t* __restrict__ g_first,
+    const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
+    const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
+    const V4<T>* __restrict__ ab4, const T* __restrict__ momw, double inv_side, double eps,
+    T* __restrict__ state) {
+  constexpr int kStride = nm_pad(P);
+  constexpr int kChunks = kStride * (int)sizeof(T) / 16;
+  constexpr int kMaxS = 8;
+  constexpr int kRounds = (kMaxS * kChunks + 63) / 64;
+  __shared__ uint4 smom[kMaxS * kChunks];
+  const int lane = threadIdx.x;
+  const int64_t it = blockIdx.x;
+  if (it >= n_items) return;
+  const int2 item = items[it];
+  const int g = uniform_i32(item.x);
+  const int gend = uniform_i32(g_first[g] + g_count[g]);
+  const int ns = gend - item.y < 64 ? gend - item.y : 64;  // <= 32 for these items
+  const int lw = ns <= 8 ? 3 : 32 - __clz(ns - 1);
+  const int S = 64 >> lw;
+  const int p = lane & ((1 << lw) - 1), sl = lane >> lw;
+  const int i = item.y + p;
+  const bool active = p < ns;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  V4<T> me, ab;
+  me.x = me.y = me.z = me.w = T(0);
+  ab = me;
+  if (active) {
+    me = off[i];
+    ab = ab4[i];
+  }
+  T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
+  if (active && sl == 0) {
+    const T* st = state + (int64_t)i * 8;
+    sx = st[0];
+    sy = st[1];
+    sz = st[2];
+    cx = st[4];
+    cy = st[5];
+    cz = st[6];
+  }
+  const int64_t e0 = m2p_off[g], e1 = m2p_off[g + 1];
+  for (int64_t eb = e0; eb < e1; eb += S) {
+    int cl = -1, il = kCentreImage;
+    if (lane < S && eb + lane < e1) {
+      cl = m2p[eb + lane];
+      if (PER) il = m2p_img[eb + lane];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int ch = lane + 64 * r;
+      const int s2 = ch / kChunks;
+      const int cs = __shfl(cl, s2 < kMaxS ? s2 : 0);
+      if (s2 < S && cs >= 0)
+        smom[ch] = reinterpret_cast<const uint4*>(momw + (int64_t)cs * kStride)[ch - s2 * kChunks];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int cme = __shfl(cl, sl);
+    const int c0 = __shfl(cl, 0);  // valid in every round
+    const bool ok = cme >= 0;
+    const int sme = ok ? sl : 0;
+    const int c = ok ? cme : c0;
+    double nx = c_centre[3 * c], ny = c_centre[3 * c + 1], nz = c_centre[3 * c + 2];
+    if (PER) {
+      const int ime = __shfl(il, sl), i0m = __shfl(il, 0);
+      double shx, shy, shz;
+      image_shift(ok ? ime : i0m, side, shx, shy, shz);
+      nx += shx;
+      ny += shy;
+      nz += shz;
+    }
+    const double inv_s = ldexp(inv_side, (int)c_level[c]);
+    const T X = (T)((cgx - nx) * inv_s) + me.x * (T)inv_s;
+    const T Y = (T)((cgy - ny) * inv_s) + me.y * (T)inv_s;
+    const T Z = (T)((cgz - nz) * inv_s) + me.z * (T)inv_s;
+    const T* M = reinterpret_cast<const T*>(smom) + sme * kStride;
+    const double es = eps * inv_s;
+    T gx = 0, gy = 0, gz = 0;
+    expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
+    const T sc = ok ? (T)(-(inv_s * inv_s * inv_s)) : T(0);
+    kahan_add(sx, cx, gx * sc);
+    kahan_add(sy, cy, gy * sc);
+    kahan_add(sz, cz, gz * sc);
+  }
+  for (int m = 32; m >= (1 << lw); m >>= 1) {
+    T o = __shfl_xor(sx, m), oc = __shfl_xor(cx, m);
+    kahan_add(sx, cx, o);
+    cx += oc;
+    o = __shfl_xor(sy, m);
+    oc = __shfl_xor(cy, m);
+    kahan_add(sy, cy, o);
+    cy += oc;
+    o = __shfl_xor(sz, m);
+    oc = __shfl_xor(cz, m);
+    kahan_add(sz, cz, o);
+    cz += oc;
+  }
+  if (active && sl == 0) {
+    T* st = state + (int64_t)i * 8;
+    st[0] = sx;
+    st[1] = sy;
+    st[2] = sz;
+    st[4] = cx;
+    st[5] = cy;
+    st[6] = cz;
+  }
+}
+
 // ----------------------------------------------------- pair terms, source side
 // One wavefront per source item (at most 64 particles of one group). The
 // records of the item are sorted by sink group; runs of one group are merged
@@ -1272,7 +1391,29 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
         t->m2p_sub.as<int8_t>(), momsub);
     HOT_CHECK_LAUNCH();
   };
-  if (t->bg)
+  if (!t->bg && !mixq && t->n_items_small >= 0 && t->n_items_small * 10 >= t->n_items) {
+    // many part-empty items (split by the forward evaluation): those of at
+    // most 32 sinks by slices of one wavefront, the others as usual
+    if (t->n_items_big > 0) {
+      auto kb = t->periodic ? k_m2p_sink_adj<P, T, false, true> : k_m2p_sink_adj<P, T, false, false>;
+      kb<<<grid_for(t->n_items_big, kWPB), kB, 0, st>>>(
+          t->items_big.as<int2>(), t->n_items_big, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
+          t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
+          t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
+          t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state,
+          t->m2p_sub.as<int8_t>(), momsub);
+      HOT_CHECK_LAUNCH();
+    }
+    if (t->n_items_small > 0) {
+      auto ks = t->periodic ? k_m2p_sink_adj_sl<P, T, true> : k_m2p_sink_adj_sl<P, T, false>;
+      ks<<<(unsigned)t->n_items_small, 64, 0, st>>>(
+          t->items_small.as<int2>(), t->n_items_small, t->m2p_off.as<int64_t>(),
+          t->m2p.as<int32_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
+          t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
+          t->c_centre.as<double>(), off, ab, momw, inv_side, eps, sink_state);
+      HOT_CHECK_LAUNCH();
+    }
+  } else if (t->bg)
     sink(k_m2p_sink_adj<P, T, false, true, true>);
   else if (mixq && t->periodic)
     sink(k_m2p_sink_adj<P, T, true, true>);
