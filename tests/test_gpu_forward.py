@@ -242,3 +242,40 @@ def test_allocator_failure_is_reported_and_leaves_no_tree():
     assert len(blocks) == 0  # everything the failed call allocated was freed
     L.hot_ctx_destroy(h)
     ctx.close()
+
+
+@pytest.mark.parametrize("p", [7, 8])
+def test_small_items_sliced(p):
+    """Items of at most 32 sinks go to the sliced expansion kernels (forward
+    and sink-side adjoint) when they are at least a tenth of all items. At
+    orders 7 and 8 in FP32, where an idle slice evaluating the wrong cell
+    would overflow and show as a non-finite value, forces and the adjoint
+    match the oracle."""
+    w = W.make("plummer1m", n=8000)
+    gt, ot, pos, mass, p = build_both(w, p=p)
+    cells = ot.cells()
+    gn = cells["count"][ot.groups()]
+    sizes = np.array([min(64, n - f) for n in gn for f in range(0, n, 64)])
+    frac = float(np.mean(sizes <= 32))
+    _log("items of at most 32 sinks:", frac)
+    assert frac >= 0.1
+    ot.compute_moments(w.pos, w.mass, p)
+    oa, _, _ = ot.eval(w.pos, w.mass, w.eps)
+    ga, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)
+    ga = ga.cpu().numpy()
+    assert np.isfinite(ga).all()
+    e32 = rel_rms(ga, oa)
+    ga64, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_FP64)
+    e64 = rel_rms(ga64.cpu().numpy(), oa)
+    abar_np = W.cotangent(w.n, 17)
+    ox, _ = ot.vjp(w.pos, w.mass, w.eps, abar_np)
+    abar = torch.from_numpy(abar_np).cuda()
+    gx, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED)
+    gx = gx.cpu().numpy()
+    assert np.isfinite(gx).all()
+    a32 = rel_rms(gx, ox)
+    gx64, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64)
+    a64 = rel_rms(gx64.cpu().numpy(), ox)
+    _log("forces mixed", e32, "fp64", e64, "adjoint mixed", a32, "fp64", a64)
+    assert e32 <= 1e-5 and e64 <= 1e-12
+    assert a32 <= 1e-5 and a64 <= 1e-11
