@@ -91,7 +91,10 @@ int hot_ctx_destroy(hot_ctx* ctx);
 const char* hot_last_error(hot_ctx* ctx);
 /* Wait for the stream; returns a deferred device-side error (e.g. a
  * non-finite position or mass found by an asynchronous call) as
- * HOT_E_INVALID, or a HIP error as HOT_E_DEVICE. */
+ * HOT_E_INVALID, or a HIP error as HOT_E_DEVICE. A deferred error is
+ * reported once: by hot_sync or by the next call that synchronises the stream
+ * (tree_build, the build_interaction_lists* calls), which then fails with it
+ * and does nothing else. */
 int hot_sync(hot_ctx* ctx);
 
 /*

@@ -33,33 +33,11 @@ void hot_ctx::free_dev(void* p) {
 namespace {
 
 using hot::Error;
-
-template <class F>
-int guard(hot_ctx* ctx, F&& f) {
-  if (!ctx) return HOT_E_INVALID;
-  try {
-    HOT_HIP(hipSetDevice(ctx->device));
-    f();
-    return HOT_OK;
-  } catch (const Error& e) {
-    ctx->err = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    ctx->err = "host allocation failed";
-    return HOT_E_OOM;
-  } catch (...) {
-    ctx->err = "unexpected exception";
-    return HOT_E_DEVICE;
-  }
-}
-
-void need_tree(hot_ctx* ctx, hot_tree* t) {
-  if (!t) hot::invalid("null tree");
-  if (t->ctx != ctx) hot::invalid("tree belongs to another context");
-  if (!t->valid) hot::state("tree is invalid (a previous call failed)");
-}
+using hot::guard;
+using hot::need_tree;
 
 __global__ void k_zero_flags(unsigned* f) { *f = 0u; }
+__global__ void k_zero_flag_words(unsigned* f) { f[threadIdx.x] = 0u; }
 
 bool pow2(double s) {
   if (!(s > 0) || !std::isfinite(s)) return false;
@@ -74,6 +52,27 @@ void d2h(hot_ctx* ctx, void* dst, const void* src, size_t count) {
 }
 
 }  // namespace
+
+namespace hot {
+
+void zero_flag_word(hot_ctx* ctx, int word) {
+  k_zero_flags<<<1, 1, 0, ctx->stream>>>(ctx->d_flags + word);
+  HOT_CHECK_LAUNCH();
+}
+
+void raise_deferred(hot_ctx* ctx, unsigned f) {
+  if (!f) return;
+  zero_flag_word(ctx, kFlagDeferred);
+  HOT_HIP(hipStreamSynchronize(ctx->stream));
+  if (f & FLAG_NONFINITE_POS) invalid("non-finite position (deferred from an earlier call)");
+  if (f & FLAG_BAD_MASS) invalid("non-finite or negative mass (deferred from an earlier call)");
+  if (f & FLAG_OUTSIDE_BOX) invalid("point outside the box (deferred from an earlier call)");
+  if (f & FLAG_INTERNAL)
+    throw Error{HOT_E_DEVICE, "kernel consistency check failed (deferred from an earlier call)"};
+  invalid("device error flags set (deferred from an earlier call)");
+}
+
+}  // namespace hot
 
 extern "C" {
 
@@ -101,7 +100,7 @@ int hot_ctx_create(int device, void* hip_stream, const hot_allocator* allocator,
     HOT_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) hot::invalid("no such device");
     HOT_HIP(hipMalloc(&c->d_flags, 64));
-    k_zero_flags<<<1, 1, 0, c->stream>>>(c->d_flags);
+    k_zero_flag_words<<<1, 16, 0, c->stream>>>(c->d_flags);
     HOT_CHECK_LAUNCH();
     for (auto& e : c->ev) HOT_HIP(hipEventCreate(&e));
     HOT_HIP(hipStreamSynchronize(c->stream));
@@ -137,18 +136,10 @@ const char* hot_last_error(hot_ctx* ctx) {
 int hot_sync(hot_ctx* ctx) {
   return guard(ctx, [&] {
     unsigned f = 0;
-    HOT_HIP(hipMemcpyAsync(&f, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    HOT_HIP(hipMemcpyAsync(&f, ctx->d_flags + hot::kFlagDeferred, sizeof(unsigned),
+                           hipMemcpyDeviceToHost, ctx->stream));
     HOT_HIP(hipStreamSynchronize(ctx->stream));
-    if (f) {
-      k_zero_flags<<<1, 1, 0, ctx->stream>>>(ctx->d_flags);
-      HOT_CHECK_LAUNCH();
-      HOT_HIP(hipStreamSynchronize(ctx->stream));
-      if (f & hot::FLAG_NONFINITE_POS) hot::invalid("non-finite position (deferred)");
-      if (f & hot::FLAG_BAD_MASS) hot::invalid("non-finite or negative mass (deferred)");
-      if (f & hot::FLAG_OUTSIDE_BOX) hot::invalid("point outside the box (deferred)");
-      if (f & hot::FLAG_INTERNAL) throw hot::Error{HOT_E_DEVICE, "kernel consistency check failed"};
-      hot::invalid("device error flags set (deferred)");
-    }
+    hot::raise_deferred(ctx, f);
   });
 }
 

@@ -43,9 +43,25 @@ struct Error {
 #define HOT_CHECK_LAUNCH() HOT_HIP(hipGetLastError())
 
 inline void invalid(const std::string& m) { throw Error{HOT_E_INVALID, m}; }
+// clear one flag word (stream-ordered)
+void zero_flag_word(hot_ctx* ctx, int word);
+// after a stream synchronisation: if deferred flags f were read, clear the
+// device word and fail with the check they name
+void raise_deferred(hot_ctx* ctx, unsigned f);
 inline void state(const std::string& m) { throw Error{HOT_E_STATE, m}; }
 
-// Device-side error flags (bit set by kernels, read by the host).
+// Body of a C entry point: runs f with the context's device current and turns
+// a thrown Error (or a host allocation failure) into its status code and the
+// context's message.
+template <class F>
+int guard(hot_ctx* ctx, F&& f);
+
+// Device-side error flags (bits set by kernels, read by the host). Two words:
+// kernels of asynchronous calls (moments, evaluation, adjoint, the fill pass
+// of the walk) set the deferred word, which hot_sync and the next
+// synchronising call report; synchronous calls (tree_build, the list
+// builders) clear and read their own local word.
+enum : int { kFlagDeferred = 0, kFlagLocal = 1 };
 enum : unsigned {
   FLAG_NONFINITE_POS = 1u,
   FLAG_BAD_MASS = 2u,
@@ -65,8 +81,7 @@ struct hot_ctx {
   hot_allocator alloc{};
   bool user_alloc = false;
   std::string err;
-  unsigned* d_flags = nullptr;     // device error flags
-  unsigned* h_flags = nullptr;     // pinned host mirror
+  unsigned* d_flags = nullptr;     // device error flags: [kFlagDeferred], [kFlagLocal]
   hipEvent_t ev[8]{};
   // lattice sums of the far periodic replicas (host FP64) for one cube side
   std::vector<double> lattice;
@@ -160,7 +175,7 @@ struct hot_tree {
   // eval work items: (group, first sink) per wave
   int64_t n_items = 0;
   hot::DBuf items;
-  // items of at most 32 sinks and the others (split on first use; -1: not yet)
+  // items of at most 32 sinks and the others (split at tree build; -1: not yet)
   int64_t n_items_small = -1, n_items_big = 0;
   hot::DBuf items_small, items_big;
   // adjoint caches built from the lists on first use
@@ -205,6 +220,8 @@ void scan_i64(hot_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, int64_t*
 void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits);
 
 void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box);
+// the work items split by sink count (at most 32, or more), at tree build
+void split_items(hot_ctx* ctx, hot_tree* t);
 void gather_sorted(hot_ctx* ctx, const hot_tree* t, const double* pos, const double* mass,
                    double* spos, double* smass, int check_mass);
 void build_moments(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, int p);
@@ -232,13 +249,27 @@ void weighted_cube(hot_ctx* ctx, hot_tree* t, bool fp64, void* out);
 void cube_field(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
                 bool fp64, double* out);
 void lattice_tensor(hot_ctx* ctx, hot_tree* t);
-void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc, double* pot);
+// lc_mem (nullable): room for the far replicas' local coefficients
+// (far_local_count(p) doubles); allocated by the call when null
+void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc, double* pot,
+                  double* lc_mem = nullptr);
+constexpr int far_local_count(int p) { return (p + 2) * (p + 3) * (p + 4) / 6; }
 void far_replicas_mbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,
                        double* mbar_root);
 void far_replicas_xbar(hot_ctx* ctx, hot_tree* t, const double* pos, const double* abar,
                        double* xbar);
+// Device memory of one evaluation supplied by the caller (every pointer
+// nullable: the call allocates what is null): FP32 or FP64 offsets and masses
+// (N x 4), the per-sink compensated sums (N x 8), the far replicas' local
+// coefficients (periodic lists).
+struct EvalMem {
+  void* off = nullptr;
+  void* state = nullptr;
+  double* far_local = nullptr;
+};
 void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-            int precision, double* acc, double* pot, hot_stats* stats);
+            int precision, double* acc, double* pot, hot_stats* stats,
+            const EvalMem* mem = nullptr);
 void adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
              int precision, const double* abar, double* xbar, double* mbar);
 void hash_lookup(hot_ctx* ctx, const hot_tree* t, const uint64_t* keys, int32_t* out, int64_t nq);
@@ -285,6 +316,35 @@ __device__ __forceinline__ int32_t hash_find(const uint64_t* __restrict__ hk,
     if (k == kEmptyKey) return -1;
     s = (s + 1) & mask;
   }
+}
+
+}  // namespace hot
+
+namespace hot {
+
+template <class F>
+int guard(hot_ctx* ctx, F&& f) {
+  if (!ctx) return HOT_E_INVALID;
+  try {
+    HOT_HIP(hipSetDevice(ctx->device));
+    f();
+    return HOT_OK;
+  } catch (const Error& e) {
+    ctx->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return HOT_E_OOM;
+  } catch (...) {
+    ctx->err = "unexpected exception";
+    return HOT_E_DEVICE;
+  }
+}
+
+inline void need_tree(hot_ctx* ctx, hot_tree* t) {
+  if (!t) invalid("null tree");
+  if (t->ctx != ctx) invalid("tree belongs to another context");
+  if (!t->valid) state("tree is invalid (a previous call failed)");
 }
 
 }  // namespace hot

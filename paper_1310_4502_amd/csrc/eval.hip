@@ -528,6 +528,9 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, co
   }
 }
 
+}  // namespace
+
+// Items of at most 32 sinks and the others, listed apart (built with the tree)
 void split_items(hot_ctx* ctx, hot_tree* t) {
   hipStream_t st = ctx->stream;
   const int64_t NI = t->n_items;
@@ -552,6 +555,8 @@ void split_items(hot_ctx* ctx, hot_tree* t) {
   t->n_items_big = NI - (int64_t)ns;
 }
 
+namespace {
+
 template <typename T, bool POT>
 void launch_m2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, const T* momsub,
                 double eps, T* state) {
@@ -571,16 +576,26 @@ void launch_m2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, cons
 
 template <typename T>
 void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-              double* acc, double* pot, hot_stats* stats) {
+              double* acc, double* pot, hot_stats* stats, const EvalMem* mem) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
-  DBuf off, state;
-  off.alloc(ctx, n * sizeof(V4<T>));
-  state.alloc(ctx, n * 8 * sizeof(T));
+  // caller memory where given (every element is written below before it is
+  // read: the offsets by k_offsets, the sums by the pair kernel, which
+  // covers every sink), else the context allocator
+  DBuf off_buf, state_buf;
+  V4<T>* off = mem ? static_cast<V4<T>*>(mem->off) : nullptr;
+  T* state = mem ? static_cast<T*>(mem->state) : nullptr;
+  if (!off) {
+    off_buf.alloc(ctx, n * sizeof(V4<T>));
+    off = off_buf.as<V4<T>>();
+  }
+  if (!state) {
+    state_buf.alloc(ctx, n * 8 * sizeof(T));
+    state = state_buf.as<T>();
+  }
   k_offsets<T><<<grid_for(n, kB), kB, 0, st>>>(pos, mass, t->perm.as<uint32_t>(),
                                                t->group_of.as<int32_t>(), t->g_cell.as<int32_t>(),
-                                               t->c_centre.as<double>(), n, off.as<V4<T>>(),
-                                               ctx->d_flags);
+                                               t->c_centre.as<double>(), n, off, ctx->d_flags);
   HOT_CHECK_LAUNCH();
   const T* momw = nullptr;
   if constexpr (sizeof(T) == 4) {
@@ -594,19 +609,19 @@ void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, 
     weighted_sub(ctx, t, sizeof(T) == 8);
     momsub = t->momsub.as<T>();
   }
-  if (t->n_items_small < 0) split_items(ctx, t);
+  if (t->n_items_small < 0) ::hot::state("tree without its item split");
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[0], st));
   if (pot)
-    launch_p2p<T, true>(ctx, t, off.as<V4<T>>(), eps, state.as<T>());
+    launch_p2p<T, true>(ctx, t, off, eps, state);
   else
-    launch_p2p<T, false>(ctx, t, off.as<V4<T>>(), eps, state.as<T>());
+    launch_p2p<T, false>(ctx, t, off, eps, state);
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[1], st));
   if (pot)
-    launch_m2p<T, true>(ctx, t, off.as<V4<T>>(), momw, momsub, eps, state.as<T>());
+    launch_m2p<T, true>(ctx, t, off, momw, momsub, eps, state);
   else
-    launch_m2p<T, false>(ctx, t, off.as<V4<T>>(), momw, momsub, eps, state.as<T>());
+    launch_m2p<T, false>(ctx, t, off, momw, momsub, eps, state);
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[2], st));
-  k_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(state.as<T>(), t->perm.as<uint32_t>(), n, acc, pot);
+  k_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(state, t->perm.as<uint32_t>(), n, acc, pot);
   HOT_CHECK_LAUNCH();
   if (stats) {
     HOT_HIP(hipEventRecord(ctx->ev[3], st));
@@ -671,11 +686,12 @@ void cube_field(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass
 }
 
 void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-            int precision, double* acc, double* pot, hot_stats* stats) {
+            int precision, double* acc, double* pot, hot_stats* stats, const EvalMem* mem) {
   if (precision == HOT_FP64)
-    forces_t<double>(ctx, t, pos, mass, eps, acc, pot, stats);
+    forces_t<double>(ctx, t, pos, mass, eps, acc, pot, stats, mem);
   else
-    forces_t<float>(ctx, t, pos, mass, eps, acc, pot, stats);
+    forces_t<float>(ctx, t, pos, mass, eps, acc, pot, stats, mem);
 }
+
 
 }  // namespace hot

@@ -406,16 +406,22 @@ void lattice_tensor(hot_ctx* ctx, hot_tree* t) {
   HOT_HIP(hipStreamSynchronize(ctx->stream));
 }
 
-void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc, double* pot) {
+void far_replicas(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc, double* pot,
+                  double* lc_mem) {
   hipStream_t st = ctx->stream;
   const int p = t->p;
-  DBuf Lc;
-  Lc.alloc(ctx, tri(p + 2) * sizeof(double));
+  DBuf Lbuf;
+  double* Lc = lc_mem;
+  if (!Lc) {
+    Lbuf.alloc(ctx, tri(p + 2) * sizeof(double));
+    Lc = Lbuf.as<double>();
+  }
+  // every coefficient is written before k_far_l2p reads it
   k_far_local<<<grid_for(tri(p + 2), 256), 256, 0, st>>>(t->mom64.as<double>(), p,
-                                                         t->lattice.as<double>(), Lc.as<double>());
+                                                         t->lattice.as<double>(), Lc);
   HOT_CHECK_LAUNCH();
-  k_far_l2p<<<grid_for(t->n, 256), 256, 0, st>>>(pos, t->n, t->c_centre.as<double>(), p,
-                                                 Lc.as<double>(), acc, pot);
+  k_far_l2p<<<grid_for(t->n, 256), 256, 0, st>>>(pos, t->n, t->c_centre.as<double>(), p, Lc, acc,
+                                                 pot);
   HOT_CHECK_LAUNCH();
 }
 

@@ -454,20 +454,20 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
   const unsigned gb = grid_for(n, kB);
-  k_fill<unsigned><<<1, 1, 0, st>>>(ctx->d_flags, 1, 0u);
-  HOT_CHECK_LAUNCH();
+  unsigned* lflags = ctx->d_flags + kFlagLocal;
+  zero_flag_word(ctx, kFlagLocal);
   // ---- root cube
   t->root.alloc(ctx, 8 * sizeof(double));
   if (box) {
     double r[8] = {box[0], box[1], box[2], box[3], 2097152.0 / box[3], 0, 0, 0};
     HOT_HIP(hipMemcpyAsync(t->root.p, r, sizeof(r), hipMemcpyHostToDevice, st));
-    k_box_check<<<gb, kB, 0, st>>>(pos, n, t->root.as<double>(), ctx->d_flags);
+    k_box_check<<<gb, kB, 0, st>>>(pos, n, t->root.as<double>(), lflags);
     HOT_CHECK_LAUNCH();
   } else {
     const int nparts = (int)std::min<int64_t>(1024, (n + kB - 1) / kB);
     DBuf part;
     part.alloc(ctx, (size_t)nparts * 6 * sizeof(double));
-    k_bbox_partial<<<nparts, kB, 0, st>>>(pos, n, part.as<double>(), ctx->d_flags);
+    k_bbox_partial<<<nparts, kB, 0, st>>>(pos, n, part.as<double>(), lflags);
     HOT_CHECK_LAUNCH();
     k_bbox_final<<<1, 64, 0, st>>>(part.as<double>(), nparts, t->root.as<double>());
     HOT_CHECK_LAUNCH();
@@ -503,11 +503,13 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   HOT_CHECK_LAUNCH();
   int64_t lv[kMaxLevel + 2];
   double rootv[8];
-  unsigned flags = 0;
+  unsigned fw[2] = {0u, 0u};
   HOT_HIP(hipMemcpyAsync(lv, tot.p, sizeof(lv), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipMemcpyAsync(rootv, t->root.p, sizeof(rootv), hipMemcpyDeviceToHost, st));
-  HOT_HIP(hipMemcpyAsync(&flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipMemcpyAsync(fw, ctx->d_flags, sizeof(fw), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipStreamSynchronize(st));
+  raise_deferred(ctx, fw[kFlagDeferred]);
+  unsigned flags = fw[kFlagLocal];
   if (flags & FLAG_NONFINITE_POS) invalid("non-finite position");
   if (flags & FLAG_OUTSIDE_BOX) invalid("point outside the given box");
   for (int d = 0; d < 3; ++d) t->lo[d] = rootv[d];
@@ -554,7 +556,7 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   HOT_CHECK_LAUNCH();
   k_hash_insert<<<gc, kB, 0, st>>>(t->c_key.as<uint64_t>(), C,
                                   t->h_keys.as<unsigned long long>(), t->h_vals.as<int32_t>(),
-                                  slots - 1, ctx->d_flags);
+                                  slots - 1, lflags);
   HOT_CHECK_LAUNCH();
   k_links<<<gc, kB, 0, st>>>(t->c_key.as<uint64_t>(), t->c_level.as<int8_t>(),
                             t->c_leaf.as<uint8_t>(), C, t->h_keys.as<uint64_t>(),
@@ -587,7 +589,7 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   scan_u32(ctx, gflag.as<uint32_t>(), gflag.as<uint32_t>(), n, gtot.as<uint32_t>());
   uint32_t G32 = 0;
   HOT_HIP(hipMemcpyAsync(&G32, gtot.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HOT_HIP(hipMemcpyAsync(&flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipMemcpyAsync(&flags, lflags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipStreamSynchronize(st));
   if (flags & FLAG_HASH_FULL) throw Error{HOT_E_CAPACITY, "cell hash table full"};
   const int64_t G = G32;
@@ -625,6 +627,7 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
                                             t->g_count.as<int32_t>(), t->item_of.as<int32_t>());
   HOT_CHECK_LAUNCH();
   t->c_bmax2.release();
+  split_items(ctx, t);
 }
 
 void hash_lookup(hot_ctx* ctx, const hot_tree* t, const uint64_t* keys, int32_t* out, int64_t nq) {

@@ -379,7 +379,7 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
       t->c_nchild.as<int32_t>(), theta, em, im, bg, direct_max, t->p2p_off.as<int64_t>(),
       t->m2p_off.as<int64_t>(), pairs.as<int64_t>(), nullptr, nullptr, nullptr, nullptr,
-      t->n_cells, ctx->d_flags);
+      t->n_cells, ctx->d_flags + kFlagLocal);
   HOT_CHECK_LAUNCH();
   // pair counts: P2P sources x sinks, M2P cells x sinks
   HOT_HIP(hipMemcpyAsync(mcount.p, t->m2p_off.p, G * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
@@ -395,8 +395,8 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
     scan_i64(ctx, t->box_off.as<int64_t>(), t->box_off.as<int64_t>(), G,
              t->box_off.as<int64_t>() + G);
   int64_t h[5] = {0, 0, 0, 0, 0};
-  unsigned flags = 0;
-  HOT_HIP(hipMemcpyAsync(&flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  unsigned fw[2] = {0u, 0u};
+  HOT_HIP(hipMemcpyAsync(fw, ctx->d_flags, sizeof(fw), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipMemcpyAsync(&h[0], t->p2p_off.as<int64_t>() + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipMemcpyAsync(&h[1], t->m2p_off.as<int64_t>() + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HOT_HIP(hipMemcpyAsync(&h[2], tot + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -404,6 +404,8 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
     HOT_HIP(hipMemcpyAsync(&h[4], t->box_off.as<int64_t>() + G, sizeof(int64_t),
                            hipMemcpyDeviceToHost, st));
   HOT_HIP(hipStreamSynchronize(st));
+  raise_deferred(ctx, fw[kFlagDeferred]);
+  const unsigned flags = fw[kFlagLocal];
   if (flags & FLAG_INTERNAL) throw Error{HOT_E_DEVICE, "walk consistency check failed"};
   if (ERR && (flags & FLAG_BAD_MASS)) throw Error{HOT_E_INVALID, "non-finite or negative mass"};
   t->n_p2p = h[0];
@@ -448,7 +450,7 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
       t->c_count.as<int32_t>(), t->c_leaf.as<uint8_t>(), t->c_child.as<int32_t>(),
       t->c_nchild.as<int32_t>(), theta, em, im, bg, direct_max, nullptr, nullptr, nullptr,
       t->p2p_off.as<int64_t>(), t->m2p_off.as<int64_t>(), t->p2p.as<int32_t>(),
-      t->m2p.as<int32_t>(), t->n_cells, ctx->d_flags);
+      t->m2p.as<int32_t>(), t->n_cells, ctx->d_flags + kFlagDeferred);
   HOT_CHECK_LAUNCH();
   t->theta = theta;
   t->direct_max = direct_max;
@@ -462,17 +464,20 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
 }  // namespace
 
 void build_lists(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+  zero_flag_word(ctx, kFlagLocal);
   ErrMac em{0.0, nullptr, 0, nullptr};
   walk_lists<false, false>(ctx, t, theta, em, direct_max);
 }
 
 void build_lists_periodic(hot_ctx* ctx, hot_tree* t, double theta, int direct_max) {
+  zero_flag_word(ctx, kFlagLocal);
   ErrMac em{0.0, nullptr, 0, nullptr};
   lattice_tensor(ctx, t);
   walk_lists<false, true>(ctx, t, theta, em, direct_max);
 }
 
 void build_lists_periodic_bs(hot_ctx* ctx, hot_tree* t, double theta, int direct_max, int width) {
+  zero_flag_word(ctx, kFlagLocal);
   ErrMac em{0.0, nullptr, 0, nullptr};
   lattice_tensor(ctx, t);
   walk_lists<false, true, true>(ctx, t, theta, em, direct_max, width);
@@ -485,13 +490,14 @@ void mass_max(hot_ctx* ctx, hot_tree* t, const double* mass, DBuf& mm) {
   k_zero_u64<<<1, 1, 0, ctx->stream>>>(mm.as<unsigned long long>());
   HOT_CHECK_LAUNCH();
   k_mass_max<<<grid_for(t->n, kB), kB, 0, ctx->stream>>>(mass, t->n, mm.as<unsigned long long>(),
-                                                         ctx->d_flags);
+                                                         ctx->d_flags + kFlagLocal);
   HOT_CHECK_LAUNCH();
 }
 }  // namespace
 
 void build_lists_periodic_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol,
                               int p_max, int direct_max) {
+  zero_flag_word(ctx, kFlagLocal);
   DBuf mm;
   mass_max(ctx, t, mass, mm);
   ErrMac em{tol, mm.as<double>(), p_max, nullptr};
@@ -501,12 +507,13 @@ void build_lists_periodic_err(hot_ctx* ctx, hot_tree* t, const double* mass, dou
 
 void build_lists_err(hot_ctx* ctx, hot_tree* t, const double* mass, double tol, int p_max,
                      int direct_max) {
+  zero_flag_word(ctx, kFlagLocal);
   DBuf mm;
   mm.alloc(ctx, sizeof(unsigned long long));
   k_zero_u64<<<1, 1, 0, ctx->stream>>>(mm.as<unsigned long long>());
   HOT_CHECK_LAUNCH();
   k_mass_max<<<grid_for(t->n, kB), kB, 0, ctx->stream>>>(mass, t->n, mm.as<unsigned long long>(),
-                                                         ctx->d_flags);
+                                                         ctx->d_flags + kFlagLocal);
   HOT_CHECK_LAUNCH();
   ErrMac em{tol, mm.as<double>(), p_max, nullptr};
   walk_lists<true, false>(ctx, t, 0.0, em, direct_max);

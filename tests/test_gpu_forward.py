@@ -206,6 +206,38 @@ def test_argument_and_state_errors():
     assert torch.isfinite(a).all()
 
 
+def test_deferred_flags_reported_by_next_synchronising_call():
+    """A bad mass found asynchronously (compute_moments, eval_forces) is not
+    lost when the next call is tree_build or a list build: that call fails
+    with the deferred check named, once; calls after it succeed."""
+    w = W.make("uniform4k")
+    pos, mass = to_dev(w)
+    bad = mass.clone()
+    bad[7] = float("nan")
+    t = Tree(pos, w.n_leaf, w.n_group, w.box)
+    t.build_interaction_lists(w.theta)
+    # moments with a bad mass, then a new tree: the build reports it
+    t.compute_moments(pos, bad, 2)
+    with pytest.raises(HotError) as e:
+        Tree(pos, w.n_leaf, w.n_group, w.box)
+    assert e.value.code == HOT_E_INVALID and "deferred" in str(e.value)
+    t2 = Tree(pos, w.n_leaf, w.n_group, w.box)  # reported once, then cleared
+    t.ctx.sync()
+    # an evaluation with a bad mass, then a list build on another tree
+    t.compute_moments(pos, mass, 2)
+    t.eval_forces(pos, bad, w.eps)
+    with pytest.raises(HotError) as e:
+        t2.build_interaction_lists(w.theta)
+    assert e.value.code == HOT_E_INVALID and "mass" in str(e.value)
+    t2.build_interaction_lists(w.theta)
+    # and hot_sync reports what is still pending
+    t.compute_moments(pos, bad, 2)
+    with pytest.raises(HotError) as e:
+        t.ctx.sync()
+    assert e.value.code == HOT_E_INVALID
+    t.ctx.sync()
+
+
 def test_allocator_failure_is_reported_and_leaves_no_tree():
     w = W.make("uniform4k")
     pos, mass = to_dev(w)
