@@ -63,6 +63,14 @@ def _i64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.int64)
 
 
+# softening kernels: Plummer, and Dehnen's compensating K1 with compact support
+KERNELS = {"plummer": 0, "k1": 1}
+
+
+def _kern(kernel) -> int:
+    return KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+
+
 def nm(p: int) -> int:
     return (p + 1) * (p + 2) * (p + 3) // 6
 
@@ -237,7 +245,7 @@ class Tree:
         _chk(lib().oracle_get_moments(self.h, _p(out)))
         return out
 
-    def eval(self, pos, mass, eps, sinks=None, with_pot=True):
+    def eval(self, pos, mass, eps, sinks=None, with_pot=True, kernel="plummer"):
         pos = _f64(pos)
         mass = _f64(mass)
         s = _i64(sinks)
@@ -245,23 +253,23 @@ class Tree:
         acc = np.empty((T, 3))
         pot = np.empty(T) if with_pot else None
         counts = np.zeros(2, np.int64)
-        _chk(lib().oracle_eval_tree(self.h, _p(pos), _p(mass), ctypes.c_double(eps),
+        _chk(lib().oracle_eval_tree(self.h, _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps),
                                     ctypes.c_int64(0 if s is None else T), _p(s), _p(acc),
                                     _p(pot), _p(counts)))
         return acc, pot, counts
 
-    def vjp(self, pos, mass, eps, abar):
+    def vjp(self, pos, mass, eps, abar, kernel="plummer"):
         pos = _f64(pos)
         mass = _f64(mass)
         abar = _f64(abar)
         xbar = np.empty_like(pos)
         mbar = np.empty(self.n)
-        _chk(lib().oracle_tree_vjp(self.h, _p(pos), _p(mass), ctypes.c_double(eps), _p(abar),
+        _chk(lib().oracle_tree_vjp(self.h, _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps), _p(abar),
                                    _p(xbar), _p(mbar)))
         return xbar, mbar
 
 
-def direct(pos, mass, eps, sinks=None):
+def direct(pos, mass, eps, sinks=None, kernel="plummer"):
     """O-D: exact softened direct sum (compensated), sinks = caller indices."""
     pos = _f64(pos)
     mass = _f64(mass)
@@ -270,12 +278,12 @@ def direct(pos, mass, eps, sinks=None):
     T = n if s is None else s.shape[0]
     acc = np.empty((T, 3))
     pot = np.empty(T)
-    _chk(lib().oracle_direct(ctypes.c_int64(n), _p(pos), _p(mass), ctypes.c_double(eps),
+    _chk(lib().oracle_direct(ctypes.c_int64(n), _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps),
                              ctypes.c_int64(0 if s is None else T), _p(s), _p(acc), _p(pot)))
     return acc, pot
 
 
-def direct_vjp(pos, mass, eps, abar, rows=None):
+def direct_vjp(pos, mass, eps, abar, rows=None, kernel="plummer"):
     pos = _f64(pos)
     mass = _f64(mass)
     abar = _f64(abar)
@@ -284,7 +292,7 @@ def direct_vjp(pos, mass, eps, abar, rows=None):
     T = n if r is None else r.shape[0]
     xbar = np.empty((T, 3))
     mbar = np.empty(T)
-    _chk(lib().oracle_direct_vjp(ctypes.c_int64(n), _p(pos), _p(mass), ctypes.c_double(eps),
+    _chk(lib().oracle_direct_vjp(ctypes.c_int64(n), _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps),
                                  _p(abar), ctypes.c_int64(0 if r is None else T), _p(r),
                                  _p(xbar), _p(mbar)))
     return xbar, mbar
@@ -346,11 +354,11 @@ def ewald_direct(pos, mass, L, eps, sinks=None, with_pot=False):
     return (acc, pot) if with_pot else acc
 
 
-def m2p(p, M, R, eps):
+def m2p(p, M, R, eps, kernel="plummer"):
     M = _f64(M)
     R = _f64(R)
     out = np.empty(4)
-    _chk(lib().oracle_m2p(int(p), _p(M), _p(R), ctypes.c_double(eps), _p(out)))
+    _chk(lib().oracle_m2p(int(p), _p(M), _p(R), _kern(kernel), ctypes.c_double(eps), _p(out)))
     return out[:3], out[3]
 
 
@@ -372,10 +380,10 @@ def m2m(p, M, shift):
     return out
 
 
-def derivs(order, R, eps):
+def derivs(order, R, eps, kernel="plummer"):
     R = _f64(R)
     out = np.empty(nm(order))
-    _chk(lib().oracle_derivs(int(order), _p(R), ctypes.c_double(eps), _p(out)))
+    _chk(lib().oracle_derivs(int(order), _p(R), _kern(kernel), ctypes.c_double(eps), _p(out)))
     return out
 
 

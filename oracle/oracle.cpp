@@ -504,6 +504,70 @@ void p2m_direct(const double* spos, const double* smass, const Cell& c, int p, d
 }
 
 // ---------------------------------------------------------------------------
+// Softening kernels (Force Smoothing section). Two kernels are provided:
+//   * Plummer: the potential of a unit mass is -(r^2 + eps^2)^(-1/2);
+//   * K1, Dehnen's compensating kernel with compact support (the section
+//     names it as the one used for production runs; its defining reference
+//     is not at hand, so the reading used here builds it from the properties
+//     the section and that reference state): the unit mass is spread with the
+//     density
+//       rho(r) = 1575 / (128 pi eps^3) (1 - x^2)^2 (1 - 11 x^2 / 5),  x = r / eps < 1,
+//     and nothing beyond eps. (1 - x^2)^2 makes the density vanish with its
+//     slope at the edge; the second factor is the lowest-degree one giving
+//     unit mass and a zero second moment, int r^2 rho d^3r = 0, the
+//     compensation that cancels the leading-order force bias (the density is
+//     negative for x > sqrt(5/11), and the force exceeds the Newtonian one
+//     over part of the kernel). Enclosed mass mu(x) and potential follow by
+//     integration:
+//       mu(x)  = x^3 (525 - 1323 x^2 + 1215 x^4 - 385 x^6) / 32,
+//       psi(r) = (945 - 2100 x^2 + 2646 x^4 - 1620 x^6 + 385 x^8) / (256 eps)
+//     (phi = -m psi); for r >= eps, mu = 1 and psi = 1/r exactly.
+// A pair term is written as acceleration m r K(r^2) with r = x_j - x_i and
+// Hessian d(r K)/dr = K I + B r r^T; the expansion needs f(s) with
+// G(R) = f(|R|^2 + eps^2) (Plummer) or f(|R|^2) (K1).
+// ---------------------------------------------------------------------------
+enum { kPlummer = 0, kK1 = 1 };
+
+struct Soft {
+  int kind;
+  double eps;
+};
+
+int check_soft(int kind, double eps) {
+  if (!(eps >= 0) || !std::isfinite(eps)) return fail("eps must be finite and >= 0");
+  if (kind != kPlummer && kind != kK1) return fail("unknown softening kernel");
+  return 0;
+}
+
+struct PairTerms {
+  double K;    // acceleration per unit mass and unit offset
+  double psi;  // minus the potential per unit mass
+  double B;    // coefficient of r r^T in the Hessian
+};
+
+// r2 = |r|^2. Returns false for a pair that contributes nothing (zero
+// separation with nothing to soften it).
+bool pair_terms(const Soft& sf, double r2, PairTerms* o) {
+  if (sf.kind == kK1 && r2 < sf.eps * sf.eps) {
+    const double e = sf.eps;
+    const double u = r2 / (e * e);
+    const double e3 = e * e * e;
+    o->K = (525.0 + u * (-1323.0 + u * (1215.0 - 385.0 * u))) / (32.0 * e3);
+    o->psi = (945.0 + u * (-2100.0 + u * (2646.0 + u * (-1620.0 + 385.0 * u)))) / (256.0 * e);
+    o->B = (-1323.0 + u * (2430.0 - 1155.0 * u)) / (16.0 * e3 * e * e);
+    return true;
+  }
+  const double s = sf.kind == kK1 ? r2 : r2 + sf.eps * sf.eps;
+  if (s == 0.0) return false;
+  const double inv = 1.0 / std::sqrt(s);
+  const double inv3 = inv * inv * inv;
+  o->K = inv3;
+  o->psi = inv;
+  o->B = -3.0 * inv3 * inv * inv;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Derivatives of the softened Green's function G(R) = -(|R|^2 + eps^2)^(-1/2)
 // (Force Smoothing section: Plummer smoothing; the expansion of the Multipole
 // Error Bounds section is written for an arbitrary G). For any f(s) with
@@ -526,6 +590,33 @@ Radial radial(double s, int nmax) {
     r.F[n] = sign * dfact * v;
     dfact *= (double)(2 * n + 1);
     v *= is;
+  }
+  return r;
+}
+
+// F[n] = 2^n f^(n) for the kernel: Plummer takes s = r2 + eps^2 in the form
+// above; K1 takes s = r2, the form above outside eps and inside
+// f(s) = -P(s / eps^2) / (256 eps), P(u) = 945 - 2100 u + 2646 u^2 - 1620 u^3
+// + 385 u^4, so f^(n)(s) = -P^(n)(u) / (256 eps^(2n+1)) (zero for n > 4).
+Radial radial_soft(const Soft& sf, double r2, int nmax) {
+  if (sf.kind == kPlummer) return radial(r2 + sf.eps * sf.eps, nmax);
+  if (!(r2 < sf.eps * sf.eps)) return radial(r2, nmax);
+  Radial r;
+  const double e = sf.eps;
+  const double u = r2 / (e * e);
+  // coefficients of P and of its successive derivatives, lowest power first
+  double c[5] = {945.0, -2100.0, 2646.0, -1620.0, 385.0};
+  int deg = 4;
+  double scale = -1.0 / (256.0 * e);  // 2^n / (256 eps^(2n+1)), negated
+  for (int n = 0; n <= nmax; ++n) {
+    double v = 0.0;
+    for (int k = deg; k >= 0; --k) v = v * u + c[k];
+    r.F[n] = deg >= 0 ? scale * v : 0.0;
+    // differentiate P once
+    for (int k = 0; k < deg; ++k) c[k] = c[k + 1] * (double)(k + 1);
+    if (deg >= 0) c[deg] = 0.0;
+    --deg;
+    scale *= 2.0 / (e * e);
   }
   return r;
 }
@@ -554,9 +645,10 @@ double dG(int a, int b, int c, const double R[3], const Radial& rad) {
 // Cell-body expansion (Delta = 0): the potential at R = x - centre is
 //   phi = sum_{|alpha|<=p} (-1)^|alpha| / alpha! M_alpha d^alpha G(R)
 // and the acceleration a_k = -d phi / d x_k.
-void m2p_one(const double* M, int p, const double R[3], double eps, double acc[3], double* phi) {
-  double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
-  Radial rad = radial(s, p + 1);
+void m2p_one(const double* M, int p, const double R[3], const Soft& sf, double acc[3],
+             double* phi) {
+  const double r2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
+  Radial rad = radial_soft(sf, r2, p + 1);
   double a[3] = {0, 0, 0}, ph = 0.0;
   for (int sl = 0; sl < nm(p); ++sl) {
     const int* al = &g_alpha[3 * sl];
@@ -575,13 +667,11 @@ void m2p_one(const double* M, int p, const double R[3], double eps, double acc[3
 }
 
 // Softened pair kernel: contribution of source j (mass m, offset r = x_j - x_i).
-inline void p2p_pair(double m, const double r[3], double eps, double acc[3], double* phi) {
-  double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
-  if (s == 0.0) return;
-  double inv = 1.0 / std::sqrt(s);
-  double inv3 = inv * inv * inv;
-  for (int d = 0; d < 3; ++d) acc[d] += m * r[d] * inv3;
-  if (phi) *phi -= m * inv;
+inline void p2p_pair(double m, const double r[3], const Soft& sf, double acc[3], double* phi) {
+  PairTerms pt;
+  if (!pair_terms(sf, (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2], &pt)) return;
+  for (int d = 0; d < 3; ++d) acc[d] += m * r[d] * pt.K;
+  if (phi) *phi -= m * pt.psi;
 }
 
 // Neumaier-compensated accumulator.
@@ -1474,7 +1564,7 @@ int oracle_ewald_direct(int64_t n, const double* pos, const double* mass, double
         double sh[3];
         image_shift(img, L, sh);
         double r[3] = {(xj[0] + sh[0]) - xi[0], (xj[1] + sh[1]) - xi[1], (xj[2] + sh[2]) - xi[2]};
-        p2p_pair(mass[j], r, eps, a, pot ? &ph : nullptr);
+        p2p_pair(mass[j], r, Soft{kPlummer, eps}, a, pot ? &ph : nullptr);
       }
       const double r[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
       if (j != i) {
@@ -1565,13 +1655,15 @@ int oracle_get_moments(void* h, double* out) {
 // indices; all if null), accumulated in FP64 in list order: P2P entries first,
 // then M2P entries. counts[0] = P2P pairs (including the skipped self slot),
 // counts[1] = M2P pairs, over the evaluated sinks.
-int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps, int64_t n_sinks,
-                     const int64_t* sinks, double* acc, double* pot, int64_t* counts) {
+int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel, double eps,
+                     int64_t n_sinks, const int64_t* sinks, double* acc, double* pot,
+                     int64_t* counts) {
   Tree* t = (Tree*)h;
   if (!t->has_lists) return fail("lists not built");
   if (t->p < 0) return fail("moments not computed");
   if (t->p < t->list_p) return fail("moments of lower order than the lists");
-  if (!(eps >= 0) || !std::isfinite(eps)) return fail("eps must be finite and >= 0");
+  if (check_soft(kernel, eps)) return -1;
+  const Soft sf{kernel, eps};
   const int64_t n = t->n;
   const int K = nm(t->p);
   std::vector<int64_t> inv(n);
@@ -1636,7 +1728,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
         if (j == si && img == kImages / 2) continue;
         const double* xj = &pos[3 * t->perm[j]];
         double r[3] = {(xj[0] + sh[0]) - xi[0], (xj[1] + sh[1]) - xi[1], (xj[2] + sh[2]) - xi[2]};
-        p2p_pair(mass[t->perm[j]], r, eps, a, &ph);
+        p2p_pair(mass[t->perm[j]], r, sf, a, &ph);
       }
     }
     std::vector<double> msub(t->bg ? K : 0);
@@ -1659,7 +1751,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
         }
         Mc = msub.data();
       }
-      m2p_one(Mc, q, R, eps, da, &dphi);
+      m2p_one(Mc, q, R, sf, da, &dphi);
       a[0] += da[0], a[1] += da[1], a[2] += da[2];
       ph += dphi;
       c_m2p += 1;
@@ -1715,9 +1807,11 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, double eps,
 
 // O-D: exact softened direct sum for the selected sinks (caller indices; all
 // if null) over all sources, j = i skipped, compensated sums.
-int oracle_direct(int64_t n, const double* pos, const double* mass, double eps, int64_t n_sinks,
-                  const int64_t* sinks, double* acc, double* pot) {
+int oracle_direct(int64_t n, const double* pos, const double* mass, int kernel, double eps,
+                  int64_t n_sinks, const int64_t* sinks, double* acc, double* pot) {
   if (n < 1 || !pos || !mass || !acc) return fail("bad arguments");
+  if (check_soft(kernel, eps)) return -1;
+  const Soft sf{kernel, eps};
   const int64_t T = sinks ? n_sinks : n;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < T; ++k) {
@@ -1727,12 +1821,10 @@ int oracle_direct(int64_t n, const double* pos, const double* mass, double eps, 
       if (j == i) continue;
       double r[3] = {pos[3 * j] - pos[3 * i], pos[3 * j + 1] - pos[3 * i + 1],
                      pos[3 * j + 2] - pos[3 * i + 2]};
-      double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
-      if (s == 0.0) continue;
-      double inv = 1.0 / std::sqrt(s);
-      double inv3 = inv * inv * inv;
-      for (int d = 0; d < 3; ++d) a[d].add(mass[j] * r[d] * inv3);
-      ph.add(-mass[j] * inv);
+      PairTerms pt;
+      if (!pair_terms(sf, (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2], &pt)) continue;
+      for (int d = 0; d < 3; ++d) a[d].add(mass[j] * r[d] * pt.K);
+      ph.add(-mass[j] * pt.psi);
     }
     for (int d = 0; d < 3; ++d) acc[3 * k + d] = a[d].value();
     if (pot) pot[k] = ph.value();
@@ -1741,12 +1833,15 @@ int oracle_direct(int64_t n, const double* pos, const double* mass, double eps, 
 }
 
 // VJP of O-D: xbar_k = sum_{j != k} H(r_kj) (m_k abar_j - m_j abar_k), with
-// r_kj = x_j - x_k and H(r) = s^(-3/2) I - 3 r r^T s^(-5/2), s = |r|^2 + eps^2;
-// mbar_k = sum_{i != k} abar_i . (x_k - x_i) s^(-3/2).
-int oracle_direct_vjp(int64_t n, const double* pos, const double* mass, double eps,
+// r_kj = x_j - x_k and H(r) = K I + B r r^T the pair Hessian (Plummer:
+// K = s^(-3/2), B = -3 s^(-5/2), s = |r|^2 + eps^2);
+// mbar_k = sum_{i != k} abar_i . (x_k - x_i) K.
+int oracle_direct_vjp(int64_t n, const double* pos, const double* mass, int kernel, double eps,
                       const double* abar, int64_t n_rows, const int64_t* rows, double* xbar,
                       double* mbar) {
   if (n < 1 || !pos || !mass || !abar || !xbar) return fail("bad arguments");
+  if (check_soft(kernel, eps)) return -1;
+  const Soft sf{kernel, eps};
   const int64_t T = rows ? n_rows : n;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t q = 0; q < T; ++q) {
@@ -1756,18 +1851,15 @@ int oracle_direct_vjp(int64_t n, const double* pos, const double* mass, double e
       if (j == k) continue;
       double r[3] = {pos[3 * j] - pos[3 * k], pos[3 * j + 1] - pos[3 * k + 1],
                      pos[3 * j + 2] - pos[3 * k + 2]};
-      double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
-      if (s == 0.0) continue;
-      double inv = 1.0 / std::sqrt(s);
-      double inv3 = inv * inv * inv;
-      double inv5 = inv3 * inv * inv;
+      PairTerms pt;
+      if (!pair_terms(sf, (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2], &pt)) continue;
       double v[3];
       for (int d = 0; d < 3; ++d) v[d] = mass[k] * abar[3 * j + d] - mass[j] * abar[3 * k + d];
       double rv = (r[0] * v[0] + r[1] * v[1]) + r[2] * v[2];
-      for (int d = 0; d < 3; ++d) xb[d].add(v[d] * inv3 - 3.0 * r[d] * rv * inv5);
-      // d a_j / d m_k = (x_k - x_j) s^-3/2 = -r s^-3/2
+      for (int d = 0; d < 3; ++d) xb[d].add(v[d] * pt.K + pt.B * r[d] * rv);
+      // d a_j / d m_k = (x_k - x_j) K = -r K
       double ra = (r[0] * abar[3 * j] + r[1] * abar[3 * j + 1]) + r[2] * abar[3 * j + 2];
-      mb.add(-ra * inv3);
+      mb.add(-ra * pt.K);
     }
     for (int d = 0; d < 3; ++d) xbar[3 * q + d] = xb[d].value();
     if (mbar) mbar[q] = mb.value();
@@ -1779,9 +1871,11 @@ int oracle_direct_vjp(int64_t n, const double* pos, const double* mass, double e
 // fixed: the gradient of sum_i abar_i . a_i with respect to every position
 // (and mass). Moments are functions of the positions through their
 // definition; centres do not move.
-int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
+int oracle_tree_vjp(void* h, const double* pos, const double* mass, int kernel, double eps,
                     const double* abar, double* xbar, double* mbar) {
   Tree* t = (Tree*)h;
+  if (check_soft(kernel, eps)) return -1;
+  const Soft sf{kernel, eps};
   if (!t->has_lists) return fail("lists not built");
   if (!t->list_sel.empty()) return fail("the VJP needs the lists of every group");
   if (t->p < 0) return fail("moments not computed");
@@ -1829,19 +1923,17 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
           const int64_t cj = t->perm[j];
           double r[3] = {(pos[3 * cj] + sh[0]) - xi[0], (pos[3 * cj + 1] + sh[1]) - xi[1],
                          (pos[3 * cj + 2] + sh[2]) - xi[2]};
-          double s = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] + eps * eps;
-          if (s == 0.0) continue;
-          double inv = 1.0 / std::sqrt(s);
-          double inv3 = inv * inv * inv, inv5 = inv3 * inv * inv;
+          PairTerms pt;
+          if (!pair_terms(sf, (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2], &pt)) continue;
           double ra = (r[0] * ab[0] + r[1] * ab[1]) + r[2] * ab[2];
           double mj = mass[cj];
           double Hab[3];
-          for (int d = 0; d < 3; ++d) Hab[d] = ab[d] * inv3 - 3.0 * r[d] * ra * inv5;
+          for (int d = 0; d < 3; ++d) Hab[d] = ab[d] * pt.K + pt.B * r[d] * ra;
           for (int d = 0; d < 3; ++d) {
             xb[3 * si + d] -= mj * Hab[d];         // sink moves: r = x_j - x_i
             src_x[g][3 * off + d] += mj * Hab[d];  // source moves
           }
-          src_m[g][off] += ra * inv3;              // d a_i / d m_j = r s^-3/2
+          src_m[g][off] += ra * pt.K;              // d a_i / d m_j = r K
         }
       }
       std::vector<double> msub(t->bg ? K : 0), cube(t->bg ? K : 0);
@@ -1864,9 +1956,9 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
         if (t->periodic) image_shift((int)t->m2p_img[e], t->side, sh);
         double R[3] = {xi[0] - (c.centre[0] + sh[0]), xi[1] - (c.centre[1] + sh[1]),
                        xi[2] - (c.centre[2] + sh[2])};
-        double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
+        const double r2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
         const int q = t->list_p >= 0 ? (int)t->m2p_q[e] : p;
-        Radial rad = radial(s, q + 2);
+        Radial rad = radial_soft(sf, r2, q + 2);
         double* Mb = &cellbar[g][(e - t->m2p_off[g]) * K];
         for (int sl = 0; sl < nm(q); ++sl) {
           const int* al = &g_alpha[3 * sl];
@@ -2030,10 +2122,11 @@ int oracle_tree_vjp(void* h, const double* pos, const double* mass, double eps,
 }
 
 // Single cell-body expansion (for pins): acc[0..2], acc[3] = phi.
-int oracle_m2p(int p, const double* M, const double* R, double eps, double* acc4) {
+int oracle_m2p(int p, const double* M, const double* R, int kernel, double eps, double* acc4) {
   ensure_alpha();
   if (p < 0 || p > 10) return fail("p must lie in [0, 10]");
-  m2p_one(M, p, R, eps, acc4, &acc4[3]);
+  if (check_soft(kernel, eps)) return -1;
+  m2p_one(M, p, R, Soft{kernel, eps}, acc4, &acc4[3]);
   return 0;
 }
 
@@ -2050,11 +2143,11 @@ int oracle_p2m(int p, int64_t n, const double* pos, const double* mass, const do
 }
 
 // All derivatives d^alpha G(R), |alpha| <= order, in storage order (for pins).
-int oracle_derivs(int order, const double* R, double eps, double* out) {
+int oracle_derivs(int order, const double* R, int kernel, double eps, double* out) {
   ensure_alpha();
   if (order < 0 || order > 12) return fail("order must lie in [0, 12]");
-  double s = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2] + eps * eps;
-  Radial rad = radial(s, order);
+  if (check_soft(kernel, eps)) return -1;
+  Radial rad = radial_soft(Soft{kernel, eps}, (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2], order);
   for (int sl = 0; sl < nm(order); ++sl) {
     const int* al = &g_alpha[3 * sl];
     out[sl] = dG(al[0], al[1], al[2], R, rad);
