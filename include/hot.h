@@ -254,6 +254,26 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
                         double eps, int precision, const double* acc_bar, double* pos_bar,
                         double* mass_bar);
 
+/*
+ * eval_forces_noalloc -- eval_forces for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, results and errors as eval_forces
+ * (bit-identical results: the same kernels run), and it allocates nothing:
+ * the per-particle buffers of the evaluation (FP32 offsets and masses, the
+ * compensated sums) and the far replicas' local coefficients live in one
+ * fixed device array of the library, 48 MiB + 4 KiB on every GPU it runs on,
+ * held from the library's load until the process ends. Limits: precision
+ * HOT_MIXED only (HOT_E_INVALID otherwise); at most 2^20 particles
+ * (HOT_E_CAPACITY beyond); theta, error-bound and periodic lists, not
+ * background-subtracted ones (HOT_E_INVALID). Every call on one GPU uses
+ * that GPU's array: calls that overlap on one GPU (on other streams, from
+ * other threads or contexts) race, and the caller must order them; calls on
+ * one stream are ordered by it. The array keeps the last call's contents;
+ * nothing in it needs clearing (every element is written before it is read).
+ */
+int eval_forces_noalloc(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass,
+                        double eps, int precision, double* acc, double* pot, hot_stats* stats);
+
 /* ---- host-copy getters (synchronise; for tests and diagnostics) ---------- */
 
 /* out[16]: n, n_cells, n_groups, n_leaves, max_level, n_p2p_entries,

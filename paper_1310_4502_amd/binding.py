@@ -29,7 +29,7 @@ EXPORTS = ["hot_ctx_create", "hot_ctx_destroy", "hot_last_error", "hot_sync", "t
            "tree_lookup", "build_interaction_lists_err", "tree_get_m2p_orders",
            "build_interaction_lists_periodic", "tree_get_list_images",
            "build_interaction_lists_periodic_bs", "tree_get_background",
-           "build_interaction_lists_periodic_err"]
+           "build_interaction_lists_periodic_err", "eval_forces_noalloc"]
 
 
 class HotError(RuntimeError):
@@ -88,6 +88,7 @@ def load(path: Optional[str] = None):
     L.tree_get_background.argtypes = [vp, vp, vp, vp, vp, vp]
     L.eval_forces.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     L.eval_forces_adjoint.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, vp]
+    L.eval_forces_noalloc.argtypes = [vp, vp, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     L.tree_get_counts.argtypes = [vp, vp, vp]
     L.tree_get_root.argtypes = [vp, vp, vp]
     L.tree_get_keys.argtypes = [vp, vp, vp, vp]
@@ -118,10 +119,12 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self._blocks = {}
         self._alloc = None
+        self.n_allocs = 0  # calls of the allocator callback
         if torch_alloc:
             dev = torch.device("cuda", device)
 
             def _a(user, nbytes, stream):
+                self.n_allocs += 1
                 try:
                     t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
                 except RuntimeError:
@@ -290,6 +293,24 @@ class Tree:
                                           int(precision), _dev(acc), _dev(pot),
                                           ctypes.byref(st) if st is not None else None))
         return acc, pot, st
+
+    def eval_forces_noalloc(self, pos, mass, eps, acc, pot=None, precision=HOT_MIXED,
+                            stats=False):
+        """eval_forces into caller-allocated outputs without any device
+        allocation by the library (its fixed scratch array; at most 2^20
+        particles, mixed precision, no background subtraction)."""
+        pos = _as_pos(pos)
+        mass = _as_vec(mass, self.n)
+        if acc.dtype != torch.float64 or acc.shape != (self.n, 3) or not acc.is_contiguous():
+            raise ValueError("acc must be a contiguous float64 tensor of shape [N, 3]")
+        if pot is not None and (pot.dtype != torch.float64 or pot.shape != (self.n,)):
+            raise ValueError("pot must be a float64 tensor of shape [N]")
+        st = Stats() if stats else None
+        self.ctx.check(load().eval_forces_noalloc(self.ctx.h, self.h, _dev(pos), _dev(mass),
+                                                  float(eps), int(precision), _dev(acc),
+                                                  _dev(pot),
+                                                  ctypes.byref(st) if st is not None else None))
+        return st
 
     def eval_forces_adjoint(self, pos, mass, eps, acc_bar, precision=HOT_MIXED, with_mass=False):
         pos = _as_pos(pos)

@@ -2,6 +2,7 @@
 // reporting, host-copy getters. The computation itself lives in the other
 // translation units.
 #include <cmath>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -30,6 +31,25 @@ void hot_ctx::free_dev(void* p) {
     (void)hipFreeAsync(p, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of eval_forces_noalloc, for callers that cannot allocate
+// device memory. One array per GPU, held from the library's load until the
+// process ends: the FP32 offsets and masses (16 B) and the compensated sums
+// (32 B) of at most kNoAllocMaxN particles, then the far replicas' local
+// coefficients. Host code never uses the array's name as an address: the
+// device address of each GPU's copy is looked up once per device (with that
+// device current) and kept in scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 20;
+constexpr size_t kScratchOff = 0;
+constexpr size_t kScratchState = (size_t)kNoAllocMaxN * 16;
+constexpr size_t kScratchLocal = kScratchState + (size_t)kNoAllocMaxN * 32;
+constexpr size_t kScratchBytes = kScratchLocal + 4096;
+static_assert(hot::far_local_count(hot::kMaxP) * sizeof(double) <= 4096, "local coefficients");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+
 namespace {
 
 using hot::Error;
@@ -49,6 +69,23 @@ template <typename T>
 void d2h(hot_ctx* ctx, void* dst, const void* src, size_t count) {
   if (!dst || count == 0) return;
   HOT_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the device must be current).
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) hot::invalid("device index beyond this build's table");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[device]) {
+    void* ptr = nullptr;
+    HOT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw hot::Error{HOT_E_DEVICE, "no device address for the scratch array"};
+    scratch_ptr[device] = ptr;
+  }
+  return scratch_ptr[device];
 }
 
 }  // namespace
@@ -99,6 +136,7 @@ int hot_ctx_create(int device, void* hip_stream, const hot_allocator* allocator,
     int ndev = 0;
     HOT_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) hot::invalid("no such device");
+    (void)scratch_address(device);
     HOT_HIP(hipMalloc(&c->d_flags, 64));
     k_zero_flag_words<<<1, 16, 0, c->stream>>>(c->d_flags);
     HOT_CHECK_LAUNCH();
@@ -308,6 +346,34 @@ int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* m
     hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats);
     if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc, pot);
     if (tree->bg) hot::background_boxes(ctx, tree, pos, acc);
+  });
+}
+
+int eval_forces_noalloc(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass,
+                        double eps, int precision, double* acc, double* pot, hot_stats* stats) {
+  return guard(ctx, [&] {
+    need_tree(ctx, tree);
+    if (!pos || !mass || !acc) hot::invalid("null positions, masses or output");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) hot::invalid("eps must be finite and >= 0");
+    if (precision != HOT_MIXED)
+      hot::invalid("eval_forces_noalloc computes in HOT_MIXED only (FP64 needs per-tree moments)");
+    if (!tree->has_lists) hot::state("build_interaction_lists first");
+    if (tree->p < 0) hot::state("compute_moments first");
+    if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
+    if (tree->bg)
+      hot::invalid("eval_forces_noalloc does not take background-subtracted lists "
+                   "(their subtracted moments need device memory)");
+    if (tree->n > kNoAllocMaxN)
+      throw hot::Error{HOT_E_CAPACITY, "eval_forces_noalloc takes at most " +
+                                           std::to_string(kNoAllocMaxN) + " particles, the tree has " +
+                                           std::to_string(tree->n)};
+    unsigned char* base = static_cast<unsigned char*>(scratch_address(ctx->device));
+    hot::EvalMem mem;
+    mem.off = base + kScratchOff;
+    mem.state = base + kScratchState;
+    mem.far_local = reinterpret_cast<double*>(base + kScratchLocal);
+    hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats, &mem);
+    if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc, pot, mem.far_local);
   });
 }
 
