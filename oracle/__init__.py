@@ -255,8 +255,23 @@ class Tree:
         counts = np.zeros(2, np.int64)
         _chk(lib().oracle_eval_tree(self.h, _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps),
                                     ctypes.c_int64(0 if s is None else T), _p(s), _p(acc),
-                                    _p(pot), _p(counts)))
+                                    _p(pot), _p(counts), None))
         return acc, pot, counts
+
+    def eval_abs(self, pos, mass, eps, sinks=None, kernel="plummer"):
+        """(acc, absum): accelerations as eval, and per sink the sum of the
+        magnitudes of the terms that add up to it (pairs, expansion entries,
+        background boxes, far replicas); absum / |acc| measures cancellation."""
+        pos = _f64(pos)
+        mass = _f64(mass)
+        s = _i64(sinks)
+        T = self.n if s is None else s.shape[0]
+        acc = np.empty((T, 3))
+        absum = np.empty(T)
+        _chk(lib().oracle_eval_tree(self.h, _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps),
+                                    ctypes.c_int64(0 if s is None else T), _p(s), _p(acc),
+                                    None, None, _p(absum)))
+        return acc, absum
 
     def vjp(self, pos, mass, eps, abar, kernel="plummer"):
         pos = _f64(pos)

@@ -490,17 +490,25 @@ int build_lists(Tree& t, double theta, int direct_max, const std::vector<char>& 
 // M_alpha(z) = sum_j m_j (y_j - z)^alpha, raw (not traceless) multi-index
 // moments, |alpha| <= p, about the geometric cell centre.
 // ---------------------------------------------------------------------------
+// The sum over the cell's particles is Neumaier-compensated, so that its
+// rounding does not grow with the particle count: the result is the
+// definition's value up to the rounding of the individual terms.
 void p2m_direct(const double* spos, const double* smass, const Cell& c, int p, double* out) {
   const int K = nm(p);
+  std::vector<double> comp(K, 0.0);
   for (int s = 0; s < K; ++s) out[s] = 0.0;
   for (int64_t j = c.first; j < c.first + c.count; ++j) {
     double d[3] = {spos[3 * j] - c.centre[0], spos[3 * j + 1] - c.centre[1],
                    spos[3 * j + 2] - c.centre[2]};
     for (int s = 0; s < K; ++s) {
       const int* al = &g_alpha[3 * s];
-      out[s] += smass[j] * (ipow(d[0], al[0]) * ipow(d[1], al[1]) * ipow(d[2], al[2]));
+      const double x = smass[j] * (ipow(d[0], al[0]) * ipow(d[1], al[1]) * ipow(d[2], al[2]));
+      const double t = out[s] + x;
+      comp[s] += std::fabs(out[s]) >= std::fabs(x) ? (out[s] - t) + x : (x - t) + out[s];
+      out[s] = t;
     }
   }
+  for (int s = 0; s < K; ++s) out[s] += comp[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -1654,10 +1662,14 @@ int oracle_get_moments(void* h, double* out) {
 // O-T: treecode accelerations (and potentials) for the selected sinks (caller
 // indices; all if null), accumulated in FP64 in list order: P2P entries first,
 // then M2P entries. counts[0] = P2P pairs (including the skipped self slot),
-// counts[1] = M2P pairs, over the evaluated sinks.
+// counts[1] = M2P pairs, over the evaluated sinks. absum (nullable): per sink
+// the sum of the magnitudes of the terms that make up its acceleration (every
+// pair, every expansion entry, every background box, the far replicas): the
+// scale against which the rounding of a sum of those terms is measured
+// (|a| much below it means cancellation).
 int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel, double eps,
                      int64_t n_sinks, const int64_t* sinks, double* acc, double* pot,
-                     int64_t* counts) {
+                     int64_t* counts, double* absum) {
   Tree* t = (Tree*)h;
   if (!t->has_lists) return fail("lists not built");
   if (t->p < 0) return fail("moments not computed");
@@ -1717,7 +1729,8 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
     const int64_t si = inv[ci];
     const int64_t g = t->group_of[si];
     const double* xi = &pos[3 * ci];
-    double a[3] = {0, 0, 0}, ph = 0.0;
+    double a[3] = {0, 0, 0}, ph = 0.0, ab = 0.0;
+    auto norm3 = [](const double* v) { return std::sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]); };
     for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) {
       const Cell& c = t->cells[t->p2p[e]];
       double sh[3] = {0, 0, 0};
@@ -1728,6 +1741,11 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
         if (j == si && img == kImages / 2) continue;
         const double* xj = &pos[3 * t->perm[j]];
         double r[3] = {(xj[0] + sh[0]) - xi[0], (xj[1] + sh[1]) - xi[1], (xj[2] + sh[2]) - xi[2]};
+        if (absum) {
+          double da[3] = {0, 0, 0}, dph = 0.0;
+          p2p_pair(mass[t->perm[j]], r, sf, da, &dph);
+          ab += norm3(da);
+        }
         p2p_pair(mass[t->perm[j]], r, sf, a, &ph);
       }
     }
@@ -1754,6 +1772,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
       m2p_one(Mc, q, R, sf, da, &dphi);
       a[0] += da[0], a[1] += da[1], a[2] += da[2];
       ph += dphi;
+      ab += norm3(da);
       c_m2p += 1;
     }
     if (t->bg) {
@@ -1764,11 +1783,13 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
         box_field(&t->boxes[6 * b], &t->boxes[6 * b + 3], xi, f);
         const double sg = (double)t->box_sign[b];
         for (int d = 0; d < 3; ++d) a[d] += sg * bg_rho * f[d];
+        ab += bg_rho * norm3(f);
       }
       double nlo[3], nhi[3];
       neighbourhood(*t, t->cells[t->groups[g]], t->bg_width, nlo, nhi);
       box_field(nlo, nhi, xi, f);
       for (int d = 0; d < 3; ++d) a[d] -= bg_rho * f[d];
+      ab += bg_rho * norm3(f);
       double zlo[3], zhi[3];
       for (int d = 0; d < 3; ++d) {
         zlo[d] = t->lo[d] - (double)kWs * t->side;
@@ -1776,11 +1797,13 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
       }
       box_field(zlo, zhi, xi, f);
       for (int d = 0; d < 3; ++d) a[d] += bg_rho * f[d];
+      ab += bg_rho * norm3(f);
     }
     if (t->periodic) {
       // far replicas: a_k = sum_{|beta| <= p} u^beta/beta! L_{beta+e_k}
       const double* c0 = t->cells[0].centre;
       const double u[3] = {xi[0] - c0[0], xi[1] - c0[1], xi[2] - c0[2]};
+      const double a_near[3] = {a[0], a[1], a[2]};
       for (size_t b = 0; b < far_mi.size(); ++b) {
         const auto& be = far_mi[b];
         if (be[0] + be[1] + be[2] > t->p) break;
@@ -1794,9 +1817,12 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
         // potential: phi = -sum_beta u^beta/beta! L_beta
         ph -= mono * far_L[slot_of(be)];
       }
+      const double far[3] = {a[0] - a_near[0], a[1] - a_near[1], a[2] - a_near[2]};
+      ab += norm3(far);
     }
     for (int d = 0; d < 3; ++d) acc[3 * k + d] = a[d];
     if (pot) pot[k] = ph;
+    if (absum) absum[k] = ab;
   }
   if (counts) {
     counts[0] = c_p2p;

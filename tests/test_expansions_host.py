@@ -102,7 +102,9 @@ def test_p2m_m2m_match_oracle(orc, shim, p):
             d = pts[j] - c
             shim.shim_p2m(N, d[0], d[1], d[2], m[j], P(acc))
         got[off:off + len(acc)] = acc
-    assert np.array_equal(got, ref)  # same operations in the same order
+    # the same monomials; the oracle's sum is compensated, the generated
+    # code's plain (20 terms)
+    assert np.allclose(got, ref, rtol=0, atol=1e-15 * np.abs(ref).max())
     parent = np.array([0.5, 0.5, 0.5])
     refp = orc.m2m(p, ref, c - parent)
     gotp = np.zeros(orc.nm(p))

@@ -160,6 +160,27 @@ def test_p2m_m2m_identity(orc):
     assert M[0] == 1.0
 
 
+def test_p2m_sum_does_not_grow_with_count(orc):
+    """Moments of 2^16 particles against long-double sums of the same
+    monomials: the oracle's compensated sum leaves only the rounding of the
+    terms themselves (random in sign, ~u S / sqrt(N) for S the sum of the
+    term magnitudes), where a plain running sum would drift by ~u S sqrt(N)."""
+    rng = np.random.default_rng(6)
+    n = 1 << 16
+    pts = rng.random((n, 3))
+    m = np.full(n, 1.0 / n)
+    c = np.array([0.5, 0.5, 0.5])
+    p = 4
+    M = orc.p2m(p, pts, m, c)
+    d = (pts - c).astype(np.longdouble)
+    u = np.finfo(np.float64).eps / 2
+    for s, (a, b, cc) in enumerate(orc.multi_indices(p)):
+        terms = np.longdouble(1.0 / n) * d[:, 0] ** a * d[:, 1] ** b * d[:, 2] ** cc
+        exact = terms.sum()
+        S = float(np.abs(terms).sum())
+        assert abs(float(M[s] - exact)) <= u * abs(float(exact)) + 0.05 * u * S, (a, b, cc)
+
+
 # ------------------------------------------------------- cell-body expansion
 @pytest.mark.parametrize("p", [0, 1, 2, 4, 6, 8])
 @pytest.mark.parametrize("eps", [0.0, 0.3])
@@ -277,3 +298,29 @@ def test_tree_plummer_closed_form(orc):
         sel = (r >= lo_) & (r < hi_)
         assert abs(np.mean(ar[sel]) / np.mean(-menc[sel] / r[sel] ** 2) - 1) < 0.03
         assert abs(np.mean(pot[sel]) / np.mean(phi[sel]) - 1) < 0.01
+
+
+def test_tree_absum_brute_force(orc):
+    """The per-sink sum of term magnitudes: with theta -> 0 every term is a
+    pair, so it equals sum_j m_j |r_ij| (r^2 + eps^2)^(-3/2) by brute force;
+    with expansions it is at least |a| (triangle inequality)."""
+    rng = np.random.default_rng(21)
+    n = 500
+    pos = rng.random((n, 3))
+    mass = rng.random(n) + 0.1
+    eps = 0.01
+    t = orc.Tree(pos, 8, 16)
+    t.build_lists(1e-6, 0)
+    t.compute_moments(pos, mass, 2)
+    acc, ab = t.eval_abs(pos, mass, eps)
+    for i in range(0, n, 37):
+        r = pos - pos[i]
+        d = np.sqrt(np.sum(r * r, axis=1))
+        term = mass * d * (d * d + eps * eps) ** -1.5
+        term[i] = 0.0
+        assert abs(ab[i] - term.sum()) <= 1e-13 * term.sum()
+    t.build_lists(0.6, 0)
+    acc, ab = t.eval_abs(pos, mass, eps)
+    a0, _, _ = t.eval(pos, mass, eps)
+    assert np.array_equal(acc, a0)
+    assert np.all(ab >= np.linalg.norm(acc, axis=1) * (1 - 1e-12))
