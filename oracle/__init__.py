@@ -255,23 +255,27 @@ class Tree:
         counts = np.zeros(2, np.int64)
         _chk(lib().oracle_eval_tree(self.h, _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps),
                                     ctypes.c_int64(0 if s is None else T), _p(s), _p(acc),
-                                    _p(pot), _p(counts), None))
+                                    _p(pot), _p(counts), None, None))
         return acc, pot, counts
 
-    def eval_abs(self, pos, mass, eps, sinks=None, kernel="plummer"):
-        """(acc, absum): accelerations as eval, and per sink the sum of the
-        magnitudes of the terms that add up to it (pairs, expansion entries,
-        background boxes, far replicas); absum / |acc| measures cancellation."""
+    def eval_abs(self, pos, mass, eps, sinks=None, kernel="plummer", cond=False):
+        """(acc, absum) or, with cond, (acc, absum, condsum): accelerations as
+        eval; per sink the sum of the magnitudes of the terms that add up to
+        it (pairs, expansion entries, background boxes, far replicas), so
+        absum / |acc| measures cancellation; condsum weights each term by its
+        condition with respect to rounding the relative coordinates from
+        offsets about the sinks' group centres (see oracle_eval_tree)."""
         pos = _f64(pos)
         mass = _f64(mass)
         s = _i64(sinks)
         T = self.n if s is None else s.shape[0]
         acc = np.empty((T, 3))
         absum = np.empty(T)
+        cs = np.empty(T) if cond else None
         _chk(lib().oracle_eval_tree(self.h, _p(pos), _p(mass), _kern(kernel), ctypes.c_double(eps),
                                     ctypes.c_int64(0 if s is None else T), _p(s), _p(acc),
-                                    None, None, _p(absum)))
-        return acc, absum
+                                    None, None, _p(absum), _p(cs)))
+        return (acc, absum, cs) if cond else (acc, absum)
 
     def vjp(self, pos, mass, eps, abar, kernel="plummer"):
         pos = _f64(pos)

@@ -1666,10 +1666,15 @@ int oracle_get_moments(void* h, double* out) {
 // the sum of the magnitudes of the terms that make up its acceleration (every
 // pair, every expansion entry, every background box, the far replicas): the
 // scale against which the rounding of a sum of those terms is measured
-// (|a| much below it means cancellation).
+// (|a| much below it means cancellation). condsum (nullable): the same sum
+// with each term weighted by its condition with respect to rounding its
+// relative coordinates from the offsets of the mixed-precision path, whose
+// positions are offsets from the centre of their sink group: a pair term by
+// 1 + (|x_i - c_g(i)| + |x_j - c_g(j)|) / |r|, an expansion term by
+// 1 + |x_i - c_g(i)| / |R| (the rest by 1).
 int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel, double eps,
                      int64_t n_sinks, const int64_t* sinks, double* acc, double* pot,
-                     int64_t* counts, double* absum) {
+                     int64_t* counts, double* absum, double* condsum) {
   Tree* t = (Tree*)h;
   if (!t->has_lists) return fail("lists not built");
   if (t->p < 0) return fail("moments not computed");
@@ -1729,8 +1734,15 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
     const int64_t si = inv[ci];
     const int64_t g = t->group_of[si];
     const double* xi = &pos[3 * ci];
-    double a[3] = {0, 0, 0}, ph = 0.0, ab = 0.0;
+    double a[3] = {0, 0, 0}, ph = 0.0, ab = 0.0, cs = 0.0;
     auto norm3 = [](const double* v) { return std::sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]); };
+    // distance of a particle (sorted index) from its group's centre
+    auto goff = [&](int64_t sj, const double* x) {
+      const double* c = t->cells[t->groups[t->group_of[sj]]].centre;
+      const double d[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+      return norm3(d);
+    };
+    const double oi = (absum || condsum) ? goff(si, xi) : 0.0;
     for (int64_t e = t->p2p_off[g]; e < t->p2p_off[g + 1]; ++e) {
       const Cell& c = t->cells[t->p2p[e]];
       double sh[3] = {0, 0, 0};
@@ -1741,10 +1753,12 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
         if (j == si && img == kImages / 2) continue;
         const double* xj = &pos[3 * t->perm[j]];
         double r[3] = {(xj[0] + sh[0]) - xi[0], (xj[1] + sh[1]) - xi[1], (xj[2] + sh[2]) - xi[2]};
-        if (absum) {
+        if (absum || condsum) {
           double da[3] = {0, 0, 0}, dph = 0.0;
           p2p_pair(mass[t->perm[j]], r, sf, da, &dph);
-          ab += norm3(da);
+          const double m = norm3(da), rn = norm3(r);
+          ab += m;
+          if (m > 0.0) cs += m * (1.0 + (oi + goff(j, xj)) / rn);
         }
         p2p_pair(mass[t->perm[j]], r, sf, a, &ph);
       }
@@ -1773,6 +1787,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
       a[0] += da[0], a[1] += da[1], a[2] += da[2];
       ph += dphi;
       ab += norm3(da);
+      cs += norm3(da) * (1.0 + oi / norm3(R));
       c_m2p += 1;
     }
     if (t->bg) {
@@ -1784,12 +1799,14 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
         const double sg = (double)t->box_sign[b];
         for (int d = 0; d < 3; ++d) a[d] += sg * bg_rho * f[d];
         ab += bg_rho * norm3(f);
+        cs += bg_rho * norm3(f);
       }
       double nlo[3], nhi[3];
       neighbourhood(*t, t->cells[t->groups[g]], t->bg_width, nlo, nhi);
       box_field(nlo, nhi, xi, f);
       for (int d = 0; d < 3; ++d) a[d] -= bg_rho * f[d];
       ab += bg_rho * norm3(f);
+      cs += bg_rho * norm3(f);
       double zlo[3], zhi[3];
       for (int d = 0; d < 3; ++d) {
         zlo[d] = t->lo[d] - (double)kWs * t->side;
@@ -1798,6 +1815,7 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
       box_field(zlo, zhi, xi, f);
       for (int d = 0; d < 3; ++d) a[d] += bg_rho * f[d];
       ab += bg_rho * norm3(f);
+      cs += bg_rho * norm3(f);
     }
     if (t->periodic) {
       // far replicas: a_k = sum_{|beta| <= p} u^beta/beta! L_{beta+e_k}
@@ -1819,10 +1837,12 @@ int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel,
       }
       const double far[3] = {a[0] - a_near[0], a[1] - a_near[1], a[2] - a_near[2]};
       ab += norm3(far);
+      cs += norm3(far);
     }
     for (int d = 0; d < 3; ++d) acc[3 * k + d] = a[d];
     if (pot) pot[k] = ph;
     if (absum) absum[k] = ab;
+    if (condsum) condsum[k] = cs;
   }
   if (counts) {
     counts[0] = c_p2p;

@@ -28,7 +28,7 @@ int oracle_compute_moments(void* h, const double* pos, const double* mass, int p
                            const int64_t* sel);
 int oracle_eval_tree(void* h, const double* pos, const double* mass, int kernel, double eps,
                      int64_t n_sinks, const int64_t* sinks, double* acc, double* pot,
-                     int64_t* counts, double* absum);
+                     int64_t* counts, double* absum, double* condsum);
 int oracle_tree_vjp(void* h, const double* pos, const double* mass, int kernel, double eps,
                     const double* abar, double* xbar, double* mbar);
 int oracle_direct(int64_t n, const double* pos, const double* mass, int kernel, double eps,
@@ -60,7 +60,7 @@ int main() {
   for (auto& m : mass) m = 1.0 / n;
   for (auto& a : abar) a = U(rng) - 0.5;
   const double box[4] = {0.0, 0.0, 0.0, 1.0};
-  std::vector<double> acc(3 * n), pot(n), ab(n), xbar(3 * n), mbar(n);
+  std::vector<double> acc(3 * n), pot(n), ab(n), cs(n), xbar(3 * n), mbar(n);
   int64_t counts[16];
   for (int kernel = 0; kernel < 2; ++kernel) {
     for (int mode = 0; mode < 5; ++mode) {
@@ -79,7 +79,8 @@ int main() {
       EXPECT(oracle_tree_counts(t, counts) == 0);
       const double eps = 0.01;
       EXPECT(oracle_eval_tree(t, pos.data(), mass.data(), kernel, eps, 0, nullptr, acc.data(),
-                              mode == 3 ? nullptr : pot.data(), counts, ab.data()) == 0);
+                              mode == 3 ? nullptr : pot.data(), counts, ab.data(),
+                              cs.data()) == 0);
       for (int64_t i = 0; i < 3 * n; ++i) EXPECT(std::isfinite(acc[i]));
       EXPECT(oracle_tree_vjp(t, pos.data(), mass.data(), kernel, eps, abar.data(), xbar.data(),
                              mbar.data()) == 0);
@@ -88,13 +89,13 @@ int main() {
       if (mode == 1) {
         EXPECT(oracle_compute_moments(t, pos.data(), mass.data(), 2, 0, nullptr) == 0);
         EXPECT(oracle_eval_tree(t, pos.data(), mass.data(), kernel, eps, 0, nullptr, acc.data(),
-                                nullptr, counts, nullptr) != 0);
+                                nullptr, counts, nullptr, nullptr) != 0);
       }
       // bad arguments are refused, not read out of bounds
       EXPECT(oracle_eval_tree(t, pos.data(), mass.data(), 7, eps, 0, nullptr, acc.data(), nullptr,
-                              counts, nullptr) != 0);
+                              counts, nullptr, nullptr) != 0);
       EXPECT(oracle_eval_tree(t, pos.data(), mass.data(), kernel, -1.0, 0, nullptr, acc.data(),
-                              nullptr, counts, nullptr) != 0);
+                              nullptr, counts, nullptr, nullptr) != 0);
       oracle_tree_destroy(t);
     }
     const int64_t sinks[3] = {0, 17, n - 1};
