@@ -312,13 +312,23 @@ def test_tree_absum_brute_force(orc):
     t = orc.Tree(pos, 8, 16)
     t.build_lists(1e-6, 0)
     t.compute_moments(pos, mass, 2)
-    acc, ab = t.eval_abs(pos, mass, eps)
+    acc, ab, cs = t.eval_abs(pos, mass, eps, cond=True)
+    # each particle's distance from the centre of its sink group
+    cells = t.cells()
+    _, perm = t.keys()
+    gof = t.group_of()
+    gcent = cells["centre"][t.groups()]
+    off = np.empty(n)
+    off[perm] = np.linalg.norm(pos[perm] - gcent[gof], axis=1)
     for i in range(0, n, 37):
         r = pos - pos[i]
         d = np.sqrt(np.sum(r * r, axis=1))
         term = mass * d * (d * d + eps * eps) ** -1.5
         term[i] = 0.0
         assert abs(ab[i] - term.sum()) <= 1e-13 * term.sum()
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w = np.where(term > 0, 1.0 + (off[i] + off) / d, 0.0)
+        assert abs(cs[i] - (term * w).sum()) <= 1e-13 * (term * w).sum()
     t.build_lists(0.6, 0)
     acc, ab = t.eval_abs(pos, mass, eps)
     a0, _, _ = t.eval(pos, mass, eps)
