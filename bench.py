@@ -7,10 +7,13 @@ already resident in HBM. Prints one JSON line.
 
 value = particle interactions (P2P pairs + M2P sink-cell pairs of the
 forward lists) per second of whole step time. The line also carries
-forces/s, the per-kernel split, the adjoint/forward cost ratio, the RMS
-force error against direct summation on sampled sinks, the roofline of the
-dominant kernel (timed with HIP events on the library's stream) and the
-CPU oracle's rate on a bounded sample.
+forces/s, the per-phase split (the library's phase timers: HIP events on its
+stream), the adjoint/forward cost ratio, the RMS force error against direct
+summation on sampled sinks, the roofline of each of the six interaction
+kernels (forward pair and expansion, pair sink and source adjoint, expansion
+sink and cell adjoint) at algorithmic flop counts, with the dominant one as
+"roofline", a sub-record of the clustered 2^24 workload, and the CPU
+oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -47,12 +50,71 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_flops():
-    """FP32 operations per interaction of the P2P and M2P kernels, counted
-    from the code the generator emits (FMA = 2)."""
-    sys.path.insert(0, os.path.join(ROOT, "paper_1310_4502_amd", "csrc"))
-    import gen_expansions as ge
-    return ge.flops_p2p(), {p: ge.flops_m2p(p) for p in range(9)}
+def nm(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def comb(n, k):
+    from math import comb as c
+    return c(n, k)
+
+
+# Algorithmic FP32 operations per interaction (FMA = 2, reciprocal square
+# root = 1), from the formulas each kernel evaluates, independent of how the
+# code is written:
+#  pair forward: r = x_j - x_i (3), r^2 + eps^2 (3 FMA), rsq, m s^-3/2 (3 mul),
+#    a += f r (3 FMA): the count of 20 per pair;
+#  expansion forward at order p: derivatives of G to order p + 1 by the Hermite
+#    recursion, 2 C(p+5, 4); the contraction with the moments, 3 components of
+#    n_m(p) FMAs, 6 n_m(p); powers and rsq, p + 4;
+#  pair adjoint, sink side: r, s, rsq as above (10), s^-3/2, s^-5/2, m s^-3/2
+#    (3 mul), r . abar (1 mul + 2 FMA = 5), the r r^T coefficient (2 mul), the
+#    running sums of m s^-3/2 (1) and of the r r^T term (3 FMA): 28;
+#  pair adjoint, source side: r, s, rsq (10), s^-1, s^-3/2 (2 mul), r . b (5),
+#    its coefficient (2 mul), the Hessian row (3 x 2 FMA = 12), the mass
+#    cotangent (1 FMA): 33;
+#  expansion adjoint, sink side: derivatives to order p + 2, 2 C(p+6, 4); the
+#    six Hessian entries contracted with the moments, 6 n_m(p) FMAs = 12 n_m(p);
+#    the Hessian times abar (9 mul-adds as 3 x (1 mul + 2 FMA) = 15); powers
+#    and rsq, p + 5;
+#  expansion adjoint, cell side: derivatives to order p + 1, 2 C(p+5, 4); the
+#    moment cotangent row, n_m(p) entries of 3 FMAs, 6 n_m(p); p + 4.
+FLOPS_P2P = 20
+FLOPS_P2P_SINK_ADJ = 28
+FLOPS_P2P_SRC_ADJ = 33
+
+
+def flops_m2p(p):
+    return 2 * comb(p + 5, 4) + 6 * nm(p) + (p + 4)
+
+
+def flops_m2p_sink_adj(p):
+    return 2 * comb(p + 6, 4) + 12 * nm(p) + 15 + (p + 5)
+
+
+def flops_m2p_cell_adj(p):
+    return 2 * comb(p + 5, 4) + 6 * nm(p) + (p + 4)
+
+
+def git_head():
+    """The checked-out commit, where the tree is a git checkout (else None)."""
+    import subprocess
+    try:
+        r = subprocess.run(["git", "-C", ROOT, "rev-parse", "HEAD"], capture_output=True,
+                           text=True, timeout=10)
+        return r.stdout.strip() or None if r.returncode == 0 else None
+    except Exception:
+        return None
+
+
+def tree_digest():
+    """Digest of the library sources, the binding and this script: names the
+    code a line was measured on where no git metadata travels with the tree."""
+    csrc = os.path.join("paper_1310_4502_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(os.path.join(ROOT, csrc))
+                   if f.endswith((".hip", ".h", ".py")))
+    files += ["include/hot.h", "paper_1310_4502_amd/binding.py", "bench.py"]
+    return source_digest(files)
 
 
 def source_digest(files):
@@ -107,7 +169,11 @@ def main():
                     help="skip the FP64 evaluation on the last tree (mixed/FP64 speed-up)")
     ap.add_argument("--cpu-groups", type=int, default=160,
                     help="sink groups evaluated by the CPU oracle sample")
-    ap.add_argument("--err-sinks", type=int, default=256)
+    ap.add_argument("--err-sinks", type=int, default=4096,
+                    help="sampled sinks of the direct-sum error check (a quarter of them for "
+                         "the clustered sub-record)")
+    ap.add_argument("--no-sub-clustered", dest="sub_clustered", action="store_false",
+                    help="skip the clustered 2^24 sub-record")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer once (known traffic for the HBM "
                          "byte counters) and exit")
@@ -131,12 +197,17 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1310_4502_amd import workloads as W
-    from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
+    from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    prec = HOT_FP64 if args.precision == "fp64" else HOT_MIXED
+    if args.background:
+        args.periodic = True
+    if args.periodic and args.err_tol is not None and args.background:
+        print("--background and --err-tol are exclusive", file=sys.stderr)
+        sys.exit(2)
     n_leaf, n_group, direct_max, desc = WORKLOADS[args.workload]
     n_leaf = args.n_leaf or n_leaf
     n_group = args.n_group or n_group
@@ -145,39 +216,117 @@ def main():
         # accepted cells summed pair by pair outside the neighbourhood would
         # each need an exact box field: with subtraction they stay expansions
         direct_max = 0
-    prec = HOT_FP64 if args.precision == "fp64" else HOT_MIXED
+    cfg = dict(n_leaf=n_leaf, n_group=n_group, direct_max=direct_max, periodic=args.periodic,
+               background=args.background, bg_width=args.bg_width, err_tol=args.err_tol,
+               prec=prec)
+    m = measure(args.workload, cfg, args.steps, args.warmup, not args.no_fp64)
+    w = m.pop("_w")
+    tree, acc, acc64 = m.pop("_tree"), m.pop("_acc"), m.pop("_acc64")
+    ms_step = m["ms_per_step"]
+    out = {
+        "metric": METRIC,
+        "value": m["interactions_per_step"] / (ms_step * 1e-3),
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "ms_per_step_median_min_max": m.pop("ms_per_step_median_min_max"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == HOT_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n": w.n, "p": w.p,
+                   "theta": w.theta if args.err_tol is None else None,
+                   "err_tol": args.err_tol, "eps": w.eps, "n_leaf": n_leaf,
+                   "n_group": n_group, "direct_max": direct_max, "precision": args.precision,
+                   "boundary": (f"periodic, background subtracted (neighbourhood "
+                                f"{args.bg_width} group sides)" if args.background else
+                                "periodic" if args.periodic else "open")},
+    }
+    out.update(m)
+    out["git_head"] = git_head()
+    out["source_digest"] = tree_digest()
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], errs = cpu_baseline(
+            w, {"mixed": acc, "fp64": acc64}, n_leaf, n_group, direct_max, args.cpu_groups,
+            args.err_sinks, args.err_tol, args.periodic,
+            args.bg_width if args.background else None)
+        key = "rms_err_vs_oracle_treecode" if args.periodic else "rms_err_vs_direct"
+        out[key] = errs.get("mixed" if prec == HOT_MIXED else "fp64")
+        out["err_sinks"] = errs.get("n_sinks")
+        if acc64 is not None:
+            out[key + "_fp64"] = errs["fp64"]
+        # per-particle relative errors of the evaluated precision
+        pp = errs.get("per_particle_" + ("mixed" if prec == HOT_MIXED else "fp64"))
+        if pp is not None:
+            out[key.replace("rms_", "") + "_per_particle_median_p99"] = pp
+    del tree, acc, acc64
+    if args.sub_clustered and args.workload != "clustered16m" and not args.periodic \
+            and args.err_tol is None:
+        # the clustered 2^24 set in its own configuration, same step, fewer steps
+        cl, cd, cdm, cdesc = WORKLOADS["clustered16m"]
+        ccfg = dict(n_leaf=cl, n_group=cd, direct_max=cdm, periodic=False, background=False,
+                    bg_width=3, err_tol=None, prec=prec)
+        torch.cuda.empty_cache()
+        cm = measure("clustered16m", ccfg, 5, 2, not args.no_fp64)
+        cw = cm.pop("_w")
+        cacc, cacc64 = cm.pop("_acc"), cm.pop("_acc64")
+        cm.pop("_tree")
+        cm.pop("ms_per_step_median_min_max", None)
+        cm["workload"] = f"clustered16m: {cdesc}"
+        cm["config"] = {"n": cw.n, "p": cw.p, "theta": cw.theta, "eps": cw.eps, "n_leaf": cl,
+                        "n_group": cd, "direct_max": cdm, "steps": 5, "warmup": 2}
+        cm["interactions_per_s"] = cm["interactions_per_step"] / (cm["ms_per_step"] * 1e-3)
+        if not args.no_cpu_baseline:
+            cm["rms_err_vs_direct"], cm["rms_err_vs_direct_fp64"], cm["err_sinks"], pp = \
+                direct_errors(cw, cacc, cacc64, args.err_sinks // 4)
+            cm["err_vs_direct_per_particle_median_p99"] = pp
+        out["clustered16m"] = cm
+    print(json.dumps(out), flush=True)
 
-    if args.background:
-        args.periodic = True
+
+def measure(name, cfg, steps, warmup, with_fp64):
+    """Times `steps` whole steps of workload `name` after `warmup` ones and
+    returns the figures of the line (plus the last tree and forces under
+    keys starting with _)."""
+    import numpy as np
+    import torch
+
+    from paper_1310_4502_amd import workloads as W
+    from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, Tree, context
+
+    prec = cfg["prec"]
     t0 = time.time()
-    w = W.make(args.workload)
-    log(f"workload {args.workload}: N={w.n} generated in {time.time() - t0:.1f}s")
-    if args.periodic:
-        if args.err_tol is not None and args.background:
-            print("--background and --err-tol are exclusive", file=sys.stderr)
-            sys.exit(2)
+    w = W.make(name)
+    log(f"workload {name}: N={w.n} generated in {time.time() - t0:.1f}s")
+    if cfg["periodic"]:
         w.pos = np.ascontiguousarray(w.pos % 1.0)
         w.box = (0.0, 0.0, 0.0, 1.0)
     pos = torch.from_numpy(w.pos).cuda()
     mass = torch.from_numpy(w.mass).cuda()
     abar = torch.from_numpy(W.cotangent(w.n, 404)).cuda()
     torch.cuda.synchronize()
+    ctx = context(pos.device.index or 0)
+    err_tol, dmax = cfg["err_tol"], cfg["direct_max"]
 
     def step():
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         evs[3].record()
-        t = Tree(pos, n_leaf, n_group, w.box)
+        t = Tree(pos, cfg["n_leaf"], cfg["n_group"], w.box, ctx=ctx)
         t.compute_moments(pos, mass, w.p)
-        if args.background:
-            t.build_interaction_lists_periodic_bs(w.theta, direct_max, args.bg_width)
-        elif args.periodic and args.err_tol is not None:
-            t.build_interaction_lists_periodic_err(mass, args.err_tol, w.p, direct_max)
-        elif args.periodic:
-            t.build_interaction_lists_periodic(w.theta, direct_max)
-        elif args.err_tol is None:
-            t.build_interaction_lists(w.theta, direct_max)
+        if cfg["background"]:
+            t.build_interaction_lists_periodic_bs(w.theta, dmax, cfg["bg_width"])
+        elif cfg["periodic"] and err_tol is not None:
+            t.build_interaction_lists_periodic_err(mass, err_tol, w.p, dmax)
+        elif cfg["periodic"]:
+            t.build_interaction_lists_periodic(w.theta, dmax)
+        elif err_tol is None:
+            t.build_interaction_lists(w.theta, dmax)
         else:
-            t.build_interaction_lists_err(mass, args.err_tol, w.p, direct_max)
+            t.build_interaction_lists_err(mass, err_tol, w.p, dmax)
         ev0, ev1, ev2 = evs[:3]
         ev0.record()
         acc, _, st = t.eval_forces(pos, mass, w.eps, prec, stats=True)
@@ -186,31 +335,35 @@ def main():
         ev2.record()
         return t, acc, xbar, st, evs
 
-    for k in range(args.warmup):
+    for k in range(warmup):
         t, *_ = step()
         del t
         torch.cuda.synchronize()
-        log(f"warmup step {k + 1}/{args.warmup} done")
+        log(f"{name}: warmup step {k + 1}/{warmup} done")
 
-    recs = []
+    ctx.set_timing(True)
+    recs, phases = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         t, acc, xbar, st, evs = step()
-        recs.append((st.ms_p2p, st.ms_m2p, st.ms_total, st.p2p_pairs, st.m2p_pairs, evs))
+        # the phases of this step (waits for the stream: the step is over)
+        phases.append(ctx.timings())
+        recs.append((st.ms_total, st.p2p_pairs, st.m2p_pairs, evs))
         last = (t, acc, xbar)
-        log(f"timed step {k + 1}/{args.steps} done")
+        log(f"{name}: timed step {k + 1}/{steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    ms_step = 1000.0 * elapsed / args.steps
-    ms_p2p = float(np.mean([r[0] for r in recs]))
-    ms_m2p = float(np.mean([r[1] for r in recs]))
-    ms_fwd_eval = float(np.mean([r[2] for r in recs]))
-    ms_adj = float(np.mean([r[5][1].elapsed_time(r[5][2]) for r in recs]))
-    step_ms = [r[5][3].elapsed_time(r[5][2]) for r in recs]
+    ctx.set_timing(False)
+    ms_step = 1000.0 * elapsed / steps
+    ph = {k: float(np.mean([p[k] for p in phases if k in p]))
+          for k in phases[0] if all(k in p for p in phases)}
+    ms_fwd_eval = float(np.mean([r[0] for r in recs]))
+    ms_adj = float(np.mean([r[3][1].elapsed_time(r[3][2]) for r in recs]))
+    step_ms = [r[3][3].elapsed_time(r[3][2]) for r in recs]
     # the forward path alone: tree build, moments, lists and eval_forces
-    fwd_ms = float(np.mean([r[5][3].elapsed_time(r[5][1]) for r in recs]))
-    p2p_pairs, m2p_pairs = recs[-1][3], recs[-1][4]
+    fwd_ms = float(np.mean([r[3][3].elapsed_time(r[3][1]) for r in recs]))
+    p2p_pairs, m2p_pairs = recs[-1][1], recs[-1][2]
     inter = p2p_pairs + m2p_pairs
     tree, acc, xbar = last
     counts = tree.counts()
@@ -229,66 +382,59 @@ def main():
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
         return min(ts), r
-    ms_adj_cached = None
-    if xbar is not None:
-        ms_adj_cached, _ = timed(lambda: tree.eval_forces_adjoint(pos, mass, w.eps, abar, prec))
+    ms_adj_cached, _ = timed(lambda: tree.eval_forces_adjoint(pos, mass, w.eps, abar, prec))
     acc64, ms_eval64 = None, None
-    if prec == HOT_MIXED and not args.no_fp64:
+    if prec == HOT_MIXED and with_fp64:
         ms_eval64, r64 = timed(lambda: tree.eval_forces(pos, mass, w.eps, HOT_FP64))
         acc64 = r64[0]
-        log(f"fp64 eval on the same lists: {ms_eval64:.1f} ms")
+        log(f"{name}: fp64 eval on the same lists: {ms_eval64:.1f} ms")
 
-    f_p2p, f_m2p = kernel_flops()
-    if args.err_tol is None:
-        m2p_flops = m2p_pairs * f_m2p[w.p]
+    # algorithmic flops of the expansion kernels: per entry at its order
+    # (error-bound lists) or at p, times the sinks of its group
+    if err_tol is None:
+        q_pairs = {w.p: m2p_pairs}
         orders = None
     else:
-        # per-entry orders: flops of each entry's order times its group's sinks
         _, _, mo, _ = tree.lists()
         q = tree.m2p_orders()
         gcount = tree.cells()["count"][tree.groups()].astype(np.int64)
         per_entry = np.repeat(gcount, np.diff(mo))
-        fq = np.array([f_m2p[k] for k in range(9)], dtype=np.int64)
-        m2p_flops = int((per_entry * fq[q]).sum())
+        q_pairs = {int(k): int(per_entry[q == k].sum()) for k in np.unique(q)}
         orders = np.bincount(q, minlength=w.p + 1).tolist()
-    # dominant kernel: the longer of P2P and M2P in eval_forces
-    if ms_m2p >= ms_p2p:
-        dom, dom_ms, dom_flops = f"m2p_p{w.p}", ms_m2p, m2p_flops
-    else:
-        dom, dom_ms, dom_flops = "p2p", ms_p2p, p2p_pairs * f_p2p
-    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    kern = {
+        "p2p": ("eval_p2p", p2p_pairs * FLOPS_P2P, FLOPS_P2P),
+        "m2p": ("eval_m2p", sum(n * flops_m2p(k) for k, n in q_pairs.items()), None),
+        "p2p_sink_adj": ("adj_p2p_sink", p2p_pairs * FLOPS_P2P_SINK_ADJ, FLOPS_P2P_SINK_ADJ),
+        "p2p_src_adj": ("adj_p2p_source", p2p_pairs * FLOPS_P2P_SRC_ADJ, FLOPS_P2P_SRC_ADJ),
+        "m2p_sink_adj": ("adj_m2p_sink", sum(n * flops_m2p_sink_adj(k)
+                                            for k, n in q_pairs.items()), None),
+        "m2p_cell_adj": ("adj_m2p_cell", sum(n * flops_m2p_cell_adj(k)
+                                            for k, n in q_pairs.items()), None),
+    }
+    rooflines = {}
+    for k, (phase, flops, per) in kern.items():
+        if phase not in ph or ph[phase] <= 0:
+            continue
+        n_int = p2p_pairs if k.startswith("p2p") else m2p_pairs
+        achieved = flops / (ph[phase] * 1e-3) / 1e12
+        rooflines[k] = {"bound": "alu", "achieved": round(achieved, 3),
+                        "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                        "flops_per_interaction": (per if per is not None else
+                                                  round(flops / max(n_int, 1), 1)),
+                        "interactions": int(n_int), "ms_per_launch": round(ph[phase], 3)}
+    dom = max(rooflines, key=lambda k: rooflines[k]["ms_per_launch"])
+    roofline = dict(rooflines[dom])
+    roofline["kernel"] = dom
     # the committed counter record covers the default (open, theta) lists only
-    traffic = (traffic_from_profiles(dom) if args.err_tol is None and not args.periodic
-               else None)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": traffic, "kernel": dom,
-                "flops_per_interaction": (round(m2p_flops / max(m2p_pairs, 1), 1)
-                                          if dom.startswith("m2p") else f_p2p),
-                "ms_per_launch": round(dom_ms, 3)}
-
-    out = {
-        "metric": METRIC,
-        "value": inter / (ms_step * 1e-3),
-        "unit": "interactions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    roofline["traffic"] = (traffic_from_profiles(f"{dom}_p{w.p}" if dom.startswith("m2p")
+                                                 else dom)
+                           if err_tol is None and not cfg["periodic"] else None)
+    res = {
         "ms_per_step": ms_step,
         "ms_per_step_median_min_max": [float(np.median(step_ms)), float(np.min(step_ms)),
                                        float(np.max(step_ms))],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if prec == HOT_MIXED else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "n": w.n, "p": w.p,
-                   "theta": w.theta if args.err_tol is None else None,
-                   "err_tol": args.err_tol, "eps": w.eps, "n_leaf": n_leaf,
-                   "n_group": n_group, "direct_max": direct_max, "precision": args.precision,
-                   "boundary": (f"periodic, background subtracted (neighbourhood "
-                                f"{args.bg_width} group sides)" if args.background else
-                                "periodic" if args.periodic else "open")},
+        "interactions_per_step": inter,
         "forces_per_s": w.n / (ms_step * 1e-3),
         "ms_forward_path": fwd_ms,
         "forces_per_s_forward_path": w.n / (fwd_ms * 1e-3),
@@ -296,8 +442,9 @@ def main():
         "p2p_pairs": p2p_pairs,
         "m2p_pairs": m2p_pairs,
         "ms_eval_forces": ms_fwd_eval,
-        "ms_p2p": ms_p2p,
-        "ms_m2p": ms_m2p,
+        "ms_p2p": ph.get("eval_p2p"),
+        "ms_m2p": ph.get("eval_m2p"),
+        "ms_phases": {k: round(v, 3) for k, v in ph.items()},
         "ms_adjoint": ms_adj,
         "adjoint_over_eval": ms_adj / ms_fwd_eval if ms_adj and ms_fwd_eval > 0 else None,
         "ms_adjoint_lists_cached": ms_adj_cached,
@@ -306,28 +453,37 @@ def main():
         "ms_eval_forces_fp64": ms_eval64,
         "fp64_over_mixed_eval": ms_eval64 / ms_fwd_eval if ms_eval64 else None,
         "interactions_per_s_eval": inter / (ms_fwd_eval * 1e-3),
-        "p2p_gflops_28flop_convention": p2p_pairs * 28 / (ms_p2p * 1e-3) / 1e9,
+        "p2p_gflops_28flop_convention": (p2p_pairs * 28 / (ph["eval_p2p"] * 1e-3) / 1e9
+                                         if ph.get("eval_p2p") else None),
         "tree": {k: counts[k] for k in ("n_cells", "n_groups", "n_leaves", "max_level",
                                         "n_p2p", "n_m2p", "n_items", "n_boxes")},
         "roofline": roofline,
+        "rooflines": rooflines,
         "m2p_orders": orders,
-        "cpu_baseline": None,
+        "_w": w, "_tree": tree, "_acc": acc, "_acc64": acc64,
     }
+    return res
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"], errs = cpu_baseline(
-            w, {"mixed": acc, "fp64": acc64}, n_leaf, n_group, direct_max, args.cpu_groups,
-            args.err_sinks, args.err_tol, args.periodic,
-            args.bg_width if args.background else None)
-        key = "rms_err_vs_oracle_treecode" if args.periodic else "rms_err_vs_direct"
-        out[key] = errs.get("mixed" if prec == HOT_MIXED else "fp64")
-        if acc64 is not None:
-            out[key + "_fp64"] = errs["fp64"]
-        # per-particle relative errors of the evaluated precision
-        pp = errs.get("per_particle_" + ("mixed" if prec == HOT_MIXED else "fp64"))
-        if pp is not None:
-            out[key.replace("rms_", "") + "_per_particle_median_p99"] = pp
-    print(json.dumps(out), flush=True)
+
+def direct_errors(w, acc, acc64, n_err):
+    """Relative RMS errors of the mixed and FP64 forces against the oracle's
+    direct sum on n_err sampled sinks, and the mixed per-particle median and
+    99th percentile."""
+    import numpy as np
+
+    import oracle
+    from paper_1310_4502_amd import workloads as W
+    es = W.sample_indices(w.n, n_err, 102)
+    t2 = time.time()
+    ad, _ = oracle.direct(w.pos, w.mass, w.eps, sinks=es)
+    a = acc.cpu().numpy()[es]
+    e = float(np.linalg.norm(a - ad) / np.linalg.norm(ad))
+    rel = np.linalg.norm(a - ad, axis=1) / np.linalg.norm(ad, axis=1)
+    e64 = None
+    if acc64 is not None:
+        e64 = float(np.linalg.norm(acc64.cpu().numpy()[es] - ad) / np.linalg.norm(ad))
+    log(f"{w.name}: direct-sum check on {n_err} sinks in {time.time() - t2:.1f}s: {e}, fp64 {e64}")
+    return e, e64, int(n_err), [float(np.median(rel)), float(np.percentile(rel, 99))]
 
 
 def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err, err_tol=None,
@@ -404,8 +560,9 @@ def cpu_baseline(w, accs, n_leaf, n_group, direct_max, n_groups_sample, n_err, e
         errs[k] = float(np.linalg.norm(a - ad) / np.linalg.norm(ad))
         rel = np.linalg.norm(a - ad, axis=1) / np.linalg.norm(ad, axis=1)
         errs["per_particle_" + k] = [float(np.median(rel)), float(np.percentile(rel, 99))]
+    errs["n_sinks"] = int(n_err)
     log(f"direct-sum check on {n_err} sinks in {time.time() - t2:.1f}s: rel RMS "
-        f"{ {k: v for k, v in errs.items() if not k.startswith('per_particle')} }")
+        f"{ {k: v for k, v in errs.items() if k in ('mixed', 'fp64')} }")
     return base, errs
 
 

@@ -48,6 +48,20 @@ enum {
 
 enum { HOT_MIXED = 0, HOT_FP64 = 1 };
 
+/* Softening kernel (Force Smoothing section), ORed into the precision
+ * argument of eval_forces, eval_forces_noalloc and eval_forces_adjoint:
+ * without it the Plummer kernel, phi = -m (r^2 + eps^2)^(-1/2); with HOT_K1
+ * Dehnen's compensating kernel K1 with compact support of radius eps, the
+ * one the section names for production runs. Its density, in x = r / eps < 1,
+ *   rho(r) = 1575 / (128 pi eps^3) (1 - x^2)^2 (1 - 11 x^2 / 5)
+ * (zero beyond eps), is the lowest-degree even polynomial that vanishes with
+ * its slope at eps and has unit mass and a zero second moment (the
+ * compensation that cancels the leading force bias); its potential per unit
+ * mass is -(945 - 2100 x^2 + 2646 x^4 - 1620 x^6 + 385 x^8) / (256 eps)
+ * inside and exactly -1/r outside, so the force is Newtonian beyond eps.
+ * eps = 0 gives the Newtonian kernel with either choice. */
+enum { HOT_K1 = 16 };
+
 typedef struct hot_ctx hot_ctx;
 typedef struct hot_tree hot_tree;
 
@@ -83,6 +97,29 @@ typedef struct hot_stats {
   double ms_total;
 } hot_stats;
 
+/* Phases timed by the context when timing is on (hot_set_timing): each
+ * entry point and, inside the evaluation and the adjoint, each interaction
+ * kernel. The adjoint's transpose phase is the first call's construction of
+ * the transposed lists; its downward phase is the moment cotangents' pass
+ * down the tree (M2M transposed), the moment-to-particle transpose, the far
+ * replicas and background terms, and the final write-back. */
+enum {
+  HOT_T_TREE_BUILD = 0,
+  HOT_T_MOMENTS,
+  HOT_T_LISTS,
+  HOT_T_EVAL,
+  HOT_T_EVAL_P2P,
+  HOT_T_EVAL_M2P,
+  HOT_T_ADJOINT,
+  HOT_T_ADJ_TRANSPOSE,
+  HOT_T_ADJ_P2P_SINK,
+  HOT_T_ADJ_P2P_SOURCE,
+  HOT_T_ADJ_M2P_SINK,
+  HOT_T_ADJ_M2P_CELL,
+  HOT_T_ADJ_DOWNWARD,
+  HOT_T_COUNT
+};
+
 /* Context on one device. hip_stream (hipStream_t) may be NULL for the null
  * stream. allocator may be NULL (see hot_allocator). */
 int hot_ctx_create(int device, void* hip_stream, const hot_allocator* allocator, hot_ctx** out);
@@ -96,6 +133,15 @@ const char* hot_last_error(hot_ctx* ctx);
  * (tree_build, the build_interaction_lists* calls), which then fails with it
  * and does nothing else. */
 int hot_sync(hot_ctx* ctx);
+
+/* Phase timers. hot_set_timing(ctx, 1) makes every later call record HIP
+ * events on the context stream at the start and end of its phases (the
+ * HOT_T_* list above; recording adds no synchronisation), and forgets earlier
+ * records; 0 stops recording. hot_get_timings waits for the stream and writes
+ * ms[HOT_T_COUNT] (HOST): the duration of each phase in its most recent
+ * recorded run, -1 for phases not run since timing was switched on. */
+int hot_set_timing(hot_ctx* ctx, int on);
+int hot_get_timings(hot_ctx* ctx, double* ms);
 
 /*
  * tree_build -- keys, sort, cells, hash table, sink groups and b_max.

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libhot.so")
 
 HOT_OK, HOT_E_INVALID, HOT_E_STATE, HOT_E_OOM, HOT_E_DEVICE, HOT_E_CAPACITY = 0, -1, -2, -3, -4, -5
 HOT_MIXED, HOT_FP64 = 0, 1
+HOT_K1 = 16  # ORed into the precision argument: Dehnen's K1 softening
+KERNELS = {"plummer": 0, "k1": HOT_K1}
 _CODES = {-1: "HOT_E_INVALID", -2: "HOT_E_STATE", -3: "HOT_E_OOM", -4: "HOT_E_DEVICE",
           -5: "HOT_E_CAPACITY"}
 
@@ -29,7 +31,13 @@ EXPORTS = ["hot_ctx_create", "hot_ctx_destroy", "hot_last_error", "hot_sync", "t
            "tree_lookup", "build_interaction_lists_err", "tree_get_m2p_orders",
            "build_interaction_lists_periodic", "tree_get_list_images",
            "build_interaction_lists_periodic_bs", "tree_get_background",
-           "build_interaction_lists_periodic_err", "eval_forces_noalloc"]
+           "build_interaction_lists_periodic_err", "eval_forces_noalloc", "hot_set_timing",
+           "hot_get_timings"]
+
+# phases of hot_get_timings, in the order of the HOT_T_* constants
+PHASES = ["tree_build", "compute_moments", "build_interaction_lists", "eval_forces", "eval_p2p",
+          "eval_m2p", "eval_forces_adjoint", "adj_transpose", "adj_p2p_sink", "adj_p2p_source",
+          "adj_m2p_sink", "adj_m2p_cell", "adj_downward"]
 
 
 class HotError(RuntimeError):
@@ -75,6 +83,8 @@ def load(path: Optional[str] = None):
     L.hot_last_error.argtypes = [vp]
     L.hot_last_error.restype = ctypes.c_char_p
     L.hot_sync.argtypes = [vp]
+    L.hot_set_timing.argtypes = [vp, i32]
+    L.hot_get_timings.argtypes = [vp, vp]
     L.tree_build.argtypes = [vp, i64, vp, ctypes.POINTER(_BuildOpts), ctypes.POINTER(vp)]
     L.tree_destroy.argtypes = [vp, vp]
     L.compute_moments.argtypes = [vp, vp, vp, vp, i32]
@@ -151,6 +161,18 @@ class Context:
 
     def sync(self):
         self.check(load().hot_sync(self.h))
+
+    def set_timing(self, on: bool = True):
+        """Record HIP events around every phase of later calls (and forget
+        earlier records)."""
+        self.check(load().hot_set_timing(self.h, int(bool(on))))
+
+    def timings(self):
+        """{phase: ms of its most recent recorded run} (waits for the stream);
+        phases not run since timing was switched on are left out."""
+        out = np.empty(len(PHASES))
+        self.check(load().hot_get_timings(self.h, _np(out)))
+        return {k: float(v) for k, v in zip(PHASES, out) if v >= 0}
 
     def close(self):
         if getattr(self, "h", None):
@@ -283,7 +305,9 @@ class Tree:
         return out
 
     def eval_forces(self, pos, mass, eps, precision=HOT_MIXED, with_pot=False, stats=False,
-                    out=None):
+                    out=None, kernel="plummer"):
+        """kernel: "plummer" or "k1" (Dehnen's K1 with compact support eps)."""
+        precision = int(precision) | KERNELS[kernel]
         pos = _as_pos(pos)
         mass = _as_vec(mass, self.n)
         acc = out if out is not None else torch.empty_like(pos)
@@ -295,10 +319,11 @@ class Tree:
         return acc, pot, st
 
     def eval_forces_noalloc(self, pos, mass, eps, acc, pot=None, precision=HOT_MIXED,
-                            stats=False):
+                            stats=False, kernel="plummer"):
         """eval_forces into caller-allocated outputs without any device
         allocation by the library (its fixed scratch array; at most 2^20
         particles, mixed precision, no background subtraction)."""
+        precision = int(precision) | KERNELS[kernel]
         pos = _as_pos(pos)
         mass = _as_vec(mass, self.n)
         if acc.dtype != torch.float64 or acc.shape != (self.n, 3) or not acc.is_contiguous():
@@ -312,7 +337,9 @@ class Tree:
                                                   ctypes.byref(st) if st is not None else None))
         return st
 
-    def eval_forces_adjoint(self, pos, mass, eps, acc_bar, precision=HOT_MIXED, with_mass=False):
+    def eval_forces_adjoint(self, pos, mass, eps, acc_bar, precision=HOT_MIXED, with_mass=False,
+                            kernel="plummer"):
+        precision = int(precision) | KERNELS[kernel]
         pos = _as_pos(pos)
         mass = _as_vec(mass, self.n)
         acc_bar = _as_pos(acc_bar)

@@ -342,7 +342,7 @@ constexpr int kCentreImage = 62;  // n = (0, 0, 0)
 
 // ------------------------------------------------------- pair terms, sink side
 // state per sorted particle: s_x s_y s_z - c_x c_y c_z -
-template <typename T, bool EPS0, bool PER>
+template <typename T, bool EPS0, bool PER, bool K1>
 __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
     const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
@@ -350,9 +350,14 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
-    const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, T eps2,
-    T* __restrict__ state) {
+    const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, T eps2, T ie,
+    const unsigned* __restrict__ mdiff, T* __restrict__ state) {
   __shared__ V4<T> stage[kWPB][64];
+  // K1: eps2 is the squared kernel radius, ie its inverse radius
+  const T ie2 = ie * ie, ie3 = ie * ie2, ie5t = (ie3 * ie2) * (T(1) / T(3));
+  // every particle of the same mass: the pair loop leaves the mass out and
+  // the segment's sums are scaled once
+  const bool uni = *mdiff == 0u;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   V4<T>* slot = stage[w];
   const int64_t it = (int64_t)blockIdx.x * kWPB + w;
@@ -360,18 +365,29 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
   const int2 item = items[it];
   const int g = uniform_i32(item.x);
   const int gend = g_first[g] + g_count[g];
+  // m x n blocking with n = 2 as in the forward pair kernel: lane l holds
+  // sinks item.y + (l & 31) (A) and item.y + 32 + (l & 31) (B), half h = l / 32
+  // takes the sources of index parity h; lane l keeps the compensated sums
+  // of sink item.y + l
+  const int h = lane >> 5, sub = lane & 31;
+  const int iA = item.y + sub, iB = iA + 32;
   const int i = item.y + lane;
   const bool active = i < gend;
   const int gc = g_cell[g];
   const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
-  V4<T> me, ab;
-  me.x = me.y = me.z = me.w = T(0);
-  ab = me;
-  if (active) {
-    me = off[i];
-    ab = ab4[i];
+  V4<T> mA, mB, bA, bB;
+  mA.x = mA.y = mA.z = mA.w = T(0);
+  mB = bA = bB = mA;
+  if (iA < gend) {
+    mA = off[iA];
+    bA = ab4[iA];
   }
-  const T a3x = T(3) * ab.x, a3y = T(3) * ab.y, a3z = T(3) * ab.z;
+  if (iB < gend) {
+    mB = off[iB];
+    bB = ab4[iB];
+  }
+  const T a3Ax = T(3) * bA.x, a3Ay = T(3) * bA.y, a3Az = T(3) * bA.z;
+  const T a3Bx = T(3) * bB.x, a3By = T(3) * bB.y, a3Bz = T(3) * bB.z;
   T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
   const int64_t e1 = p2p_off[g + 1];
   int64_t e = p2p_off[g];
@@ -390,44 +406,92 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     }
     double shx = 0.0, shy = 0.0, shz = 0.0;
     if (PER) image_shift(im0, side, shx, shy, shz);
-    T A = 0, Bx = 0, By = 0, Bz = 0;  // sum m inv3 ; sum 3 m (r.ab) inv5 r
-    T A2 = 0, Bx2 = 0, By2 = 0, Bz2 = 0;  // odd sources of each batch
     int j = f;
     while (j < end) {
+      // a segment: the part of the run inside one source group
       const int sg = uniform_i32(group_of[j]);
       const int sgend = uniform_i32(g_first[sg] + g_count[sg]);
       const int jend = end < sgend ? end : sgend;
       if (jend <= j) break;
       const int sc = g_cell[sg];
-      T tx, ty, tz;
+      T dx, dy, dz;
       if (PER) {
-        tx = (T)((c_centre[3 * sc] + shx) - cgx) - me.x;
-        ty = (T)((c_centre[3 * sc + 1] + shy) - cgy) - me.y;
-        tz = (T)((c_centre[3 * sc + 2] + shz) - cgz) - me.z;
+        dx = (T)((c_centre[3 * sc] + shx) - cgx);
+        dy = (T)((c_centre[3 * sc + 1] + shy) - cgy);
+        dz = (T)((c_centre[3 * sc + 2] + shz) - cgz);
       } else {
-        tx = (T)(c_centre[3 * sc] - cgx) - me.x;
-        ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
-        tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+        dx = (T)(c_centre[3 * sc] - cgx);
+        dy = (T)(c_centre[3 * sc + 1] - cgy);
+        dz = (T)(c_centre[3 * sc + 2] - cgz);
       }
+      const T tAx = dx - mA.x, tAy = dy - mA.y, tAz = dz - mA.z;
+      const T tBx = dx - mB.x, tBy = dy - mB.y, tBz = dz - mB.z;
       // sources in batches of 64 staged through the wavefront's LDS slot
-      // (one coalesced load per lane, read back as broadcasts)
-#define HOT_SINK_PAIR(SELF, KK, A, Bx, By, Bz)                                       \
+      // (one coalesced load per lane, read back two sources a read)
+#define HOT_SINK_PAIR(SELF, UM, VALID, SINK_I, TX, TY, TZ, A3X, A3Y, A3Z, A, Bx, By, Bz) \
   {                                                                                  \
-    const V4<T> s = slot[KK];                                                        \
-    const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;                             \
-    const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
-    T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
-    if (SELF && jb + (KK) == i) inv = T(0);                                          \
-    const T inv2 = inv * inv;                                                        \
-    const T m3 = s.w * (inv * inv2);                                                 \
-    const T rd3 = hot_fma(rx, a3x, hot_fma(ry, a3y, rz * a3z));                      \
-    const T q = m3 * (rd3 * inv2);                                                   \
-    A += m3;                                                                         \
-    Bx = hot_fma(q, rx, Bx);                                                         \
-    By = hot_fma(q, ry, By);                                                         \
-    Bz = hot_fma(q, rz, Bz);                                                         \
+    const T rx = s.x + TX, ry = s.y + TY, rz = s.z + TZ;                             \
+    if constexpr (!K1) {                                                             \
+      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));          \
+      T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                           \
+      if (!(VALID) || (SELF && jb + k == (SINK_I))) inv = T(0);                      \
+      const T inv2 = inv * inv;                                                      \
+      const T m3 = UM ? inv * inv2 : s.w * (inv * inv2);                             \
+      const T rd3 = hot_fma(rx, A3X, hot_fma(ry, A3Y, rz * A3Z));                    \
+      const T q = m3 * (rd3 * inv2);                                                 \
+      A += m3;                                                                       \
+      Bx = hot_fma(q, rx, Bx);                                                       \
+      By = hot_fma(q, ry, By);                                                       \
+      Bz = hot_fma(q, rz, Bz);                                                       \
+    } else {                                                                         \
+      /* K I + B r r^T with kq = K and bb = -B / 3 */                                \
+      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, rz * rz));                        \
+      const T inv = hot_rsq(r2);                                                     \
+      const T inv2 = inv * inv;                                                      \
+      T kq = inv * inv2;                                                             \
+      T bb = kq * inv2;                                                              \
+      if (r2 < eps2) {                                                               \
+        const T v = (eps2 - r2) * ie2;                                               \
+        kq = ie3 * k1_force(v);                                                      \
+        bb = ie5t * k1_hess(v);                                                      \
+      }                                                                              \
+      if (!UM) {                                                                     \
+        kq *= s.w;                                                                   \
+        bb *= s.w;                                                                   \
+      }                                                                              \
+      if (!(VALID) || (SELF && jb + k == (SINK_I))) {                                \
+        kq = T(0);                                                                   \
+        bb = T(0);                                                                   \
+      }                                                                              \
+      const T rd3 = hot_fma(rx, A3X, hot_fma(ry, A3Y, rz * A3Z));                    \
+      const T q = bb * rd3;                                                          \
+      A += kq;                                                                       \
+      Bx = hot_fma(q, rx, Bx);                                                       \
+      By = hot_fma(q, ry, By);                                                       \
+      Bz = hot_fma(q, rz, Bz);                                                       \
+    }                                                                                \
+  }
+#define HOT_SINK_BATCH(UM, SELF)                                                     \
+  {                                                                                  \
+    int k2 = 0;                                                                      \
+    _Pragma("unroll 4") for (; k2 + 1 < nbt; k2 += 2) {                              \
+      const int k = k2 + h;                                                          \
+      const V4<T> s = slot[k];                                                       \
+      HOT_SINK_PAIR(SELF, UM, true, iA, tAx, tAy, tAz, a3Ax, a3Ay, a3Az, pA, qAx, qAy, qAz) \
+      HOT_SINK_PAIR(SELF, UM, true, iB, tBx, tBy, tBz, a3Bx, a3By, a3Bz, pB, qBx, qBy, qBz) \
+    }                                                                                \
+    if (k2 < nbt) {                                                                  \
+      const int k = k2 + h;                                                          \
+      const V4<T> s = slot[k2];                                                      \
+      HOT_SINK_PAIR(SELF, UM, h == 0, iA, tAx, tAy, tAz, a3Ax, a3Ay, a3Az, pA, qAx, qAy, qAz) \
+      HOT_SINK_PAIR(SELF, UM, h == 0, iB, tBx, tBy, tBz, a3Bx, a3By, a3Bz, pB, qBx, qBy, qBz) \
+    }                                                                                \
   }
       const bool self = sg == g && im0 == kCentreImage;
+      // per sink: sum m inv3 ; sum 3 m (r.ab) inv5 r
+      T pA = 0, qAx = 0, qAy = 0, qAz = 0;
+      T pB = 0, qBx = 0, qBy = 0, qBz = 0;
+      T mseg = T(1);
       for (int jb = j; jb < jend; jb += 64) {
         const int nbt = jend - jb < 64 ? jend - jb : 64;
         V4<T> v;
@@ -436,29 +500,34 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
         __builtin_amdgcn_wave_barrier();
         slot[lane] = v;
         __builtin_amdgcn_wave_barrier();
-        if (self) {
-          for (int k = 0; k < nbt; ++k) HOT_SINK_PAIR(true, k, A, Bx, By, Bz)
+        if (uni) {
+          if (self)
+            HOT_SINK_BATCH(true, true)
+          else
+            HOT_SINK_BATCH(true, false)
+          mseg = slot[0].w;
         } else {
-          int k = 0;
-#pragma unroll 4
-          for (; k + 1 < nbt; k += 2) {
-            HOT_SINK_PAIR(false, k, A, Bx, By, Bz)
-            HOT_SINK_PAIR(false, k + 1, A2, Bx2, By2, Bz2)
-          }
-          if (k < nbt) HOT_SINK_PAIR(false, k, A, Bx, By, Bz)
+          if (self)
+            HOT_SINK_BATCH(false, true)
+          else
+            HOT_SINK_BATCH(false, false)
         }
       }
+#undef HOT_SINK_BATCH
 #undef HOT_SINK_PAIR
+      // the halves' sums: lane l < 32 completes sink A, lane l >= 32 sink B
+      const T kp = (h ? pB : pA) + __shfl_xor(h ? pA : pB, 32);
+      const T kx = (h ? qBx : qAx) + __shfl_xor(h ? qAx : qBx, 32);
+      const T ky = (h ? qBy : qAy) + __shfl_xor(h ? qAy : qBy, 32);
+      const T kz = (h ? qBz : qAz) + __shfl_xor(h ? qAz : qBz, 32);
+      const V4<T> ab = h ? bB : bA;
+      // xbar_i -= m_j H ab = -(sum m inv3) ab + sum 3 m rd inv5 r, one
+      // compensated add per segment (at most n_group sources)
+      kahan_add(sx, cx, hot_fma(-kp, ab.x, kx) * mseg);
+      kahan_add(sy, cy, hot_fma(-kp, ab.y, ky) * mseg);
+      kahan_add(sz, cz, hot_fma(-kp, ab.z, kz) * mseg);
       j = jend;
     }
-    A += A2;
-    Bx += Bx2;
-    By += By2;
-    Bz += Bz2;
-    // xbar_i -= m_j H ab = -(sum m inv3) ab + sum 3 m rd inv5 r
-    kahan_add(sx, cx, hot_fma(-A, ab.x, Bx));
-    kahan_add(sy, cy, hot_fma(-A, ab.y, By));
-    kahan_add(sz, cz, hot_fma(-A, ab.z, Bz));
   }
   if (active) {
     T* st = state + (int64_t)i * 8;
@@ -480,7 +549,7 @@ constexpr int sink_adj_waves_per_simd() { return (sizeof(T) == 4 && P == 8) ? 3 
 
 // BG: background subtraction; an entry flagged in m2p_sub takes its cell's
 // cube-subtracted moments (momsub) instead of momw.
-template <int P, typename T, bool MIXQ, bool PER, bool BG = false>
+template <int P, typename T, bool MIXQ, bool PER, bool BG, bool K1>
 __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(sink_adj_waves_per_simd<P, T>())))
 void k_m2p_sink_adj(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
@@ -569,9 +638,9 @@ void k_m2p_sink_adj(
     const double es = eps * inv_s;
     T gx = 0, gy = 0, gz = 0;
     if (MIXQ)
-      expansion_sink_adj_q<P, T>(q, X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
+      expansion_sink_adj_q<P, T, K1>(q, X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
     else
-      expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
+      expansion_sink_adj<P, T, K1>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
     const T sc = (T)(-(inv_s * inv_s * inv_s));
     kahan_add(sx, cx, gx * sc);
     kahan_add(sy, cy, gy * sc);
@@ -594,7 +663,7 @@ void k_m2p_sink_adj(
 // round's cells' coefficients staged together in LDS, and the slices'
 // compensated sums are added at the end. Every cross-lane read is executed by
 // all lanes.
-template <int P, typename T, bool PER>
+template <int P, typename T, bool PER, bool K1>
 __global__ __launch_bounds__(64) void k_m2p_sink_adj_sl(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
     const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_img, double side,
@@ -677,7 +746,7 @@ __global__ __launch_bounds__(64) void k_m2p_sink_adj_sl(
     const T* M = reinterpret_cast<const T*>(smom) + sme * kStride;
     const double es = eps * inv_s;
     T gx = 0, gy = 0, gz = 0;
-    expansion_sink_adj<P, T>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
+    expansion_sink_adj<P, T, K1>(X, Y, Z, (T)(es * es), M, ab.x, ab.y, ab.z, gx, gy, gz);
     const T sc = ok ? (T)(-(inv_s * inv_s * inv_s)) : T(0);
     kahan_add(sx, cx, gx * sc);
     kahan_add(sy, cy, gy * sc);
@@ -719,7 +788,7 @@ __global__ __launch_bounds__(64) void k_m2p_sink_adj_sl(
 // instead of n_sinks; the slices' sums are then added across lanes and handed
 // back to the particles' own lanes.
 // out per sorted particle: s_x s_y s_z s_m c_x c_y c_z c_m
-template <typename T, bool EPS0, bool PER>
+template <typename T, bool EPS0, bool PER, bool K1>
 __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     const int4* __restrict__ units, int64_t n_units, const int2* __restrict__ items,
     const uint64_t* __restrict__ skey, const uint32_t* __restrict__ sval, uint64_t gmask,
@@ -728,8 +797,10 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
     const double* __restrict__ c_centre, const V4<T>* __restrict__ off,
-    const V4<T>* __restrict__ ab3, T eps2, T* __restrict__ out, T* __restrict__ part) {
+    const V4<T>* __restrict__ ab3, T eps2, T ie, T* __restrict__ out, T* __restrict__ part) {
   __shared__ V4<T> stage[kWPB][128];
+  // K1: eps2 is the squared kernel radius, ie its inverse radius
+  const T ie2 = ie * ie, ie3 = ie * ie2, ie5 = ie3 * ie2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   V4<T>* slot = stage[w];
   const int64_t wu = (int64_t)blockIdx.x * kWPB + w;
@@ -751,17 +822,41 @@ __global__ __launch_bounds__(kB) void k_p2p_src_adj(
 #define HOT_SRC_PAIR(SI, B, TX, TY, TZ, ZERO)                                        \
   {                                                                                  \
     const T rx = (TX) - (SI).x, ry = (TY) - (SI).y, rz = (TZ) - (SI).z;              \
-    const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
-    T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
-    if (ZERO) inv = T(0);                                                            \
-    const T inv2 = inv * inv;                                                        \
-    const T inv3 = inv * inv2;                                                       \
-    const T d = hot_fma(rx, (B).x, hot_fma(ry, (B).y, rz * (B).z));                  \
-    const T dd = (T(3) * d) * inv2;                                                  \
-    gx = hot_fma(inv3, hot_fma(-dd, rx, (B).x), gx);                                 \
-    gy = hot_fma(inv3, hot_fma(-dd, ry, (B).y), gy);                                 \
-    gz = hot_fma(inv3, hot_fma(-dd, rz, (B).z), gz);                                 \
-    gm = hot_fma(d, inv3, gm);                                                       \
+    if constexpr (!K1) {                                                             \
+      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));          \
+      T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                           \
+      if (ZERO) inv = T(0);                                                          \
+      const T inv2 = inv * inv;                                                      \
+      const T inv3 = inv * inv2;                                                     \
+      const T d = hot_fma(rx, (B).x, hot_fma(ry, (B).y, rz * (B).z));                \
+      const T dd = (T(3) * d) * inv2;                                                \
+      gx = hot_fma(inv3, hot_fma(-dd, rx, (B).x), gx);                               \
+      gy = hot_fma(inv3, hot_fma(-dd, ry, (B).y), gy);                               \
+      gz = hot_fma(inv3, hot_fma(-dd, rz, (B).z), gz);                               \
+      gm = hot_fma(d, inv3, gm);                                                     \
+    } else {                                                                         \
+      /* 3 H abar = K b + B d r with kq = K, bn = -B */                              \
+      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, rz * rz));                        \
+      const T inv = hot_rsq(r2);                                                     \
+      const T inv2 = inv * inv;                                                      \
+      T kq = inv * inv2;                                                             \
+      T bn = T(3) * (kq * inv2);                                                     \
+      if (r2 < eps2) {                                                               \
+        const T v = (eps2 - r2) * ie2;                                               \
+        kq = ie3 * k1_force(v);                                                      \
+        bn = ie5 * k1_hess(v);                                                       \
+      }                                                                              \
+      if (ZERO) {                                                                    \
+        kq = T(0);                                                                   \
+        bn = T(0);                                                                   \
+      }                                                                              \
+      const T d = hot_fma(rx, (B).x, hot_fma(ry, (B).y, rz * (B).z));                \
+      const T bd = bn * d;                                                           \
+      gx = hot_fma(kq, (B).x, hot_fma(-bd, rx, gx));                                 \
+      gy = hot_fma(kq, (B).y, hot_fma(-bd, ry, gy));                                 \
+      gz = hot_fma(kq, (B).z, hot_fma(-bd, rz, gz));                                 \
+      gm = hot_fma(d, kq, gm);                                                       \
+    }                                                                                \
   }
   // Records are read in batches of 64, one per lane, so that their loads
   // overlap; position r1 is an end marker that closes the last run. A run is
@@ -965,14 +1060,15 @@ __global__ void k_src_unit_sum(const int2* __restrict__ items, int64_t n_items,
 
 // ---------------------------------------- expansion terms, moment cotangents
 // One wavefront per cell item (a run of at most kCellItemGroups groups whose
-// M2P lists hold the cell); lanes are the sinks of each group in turn. Each
+// M2P lists hold the cell); lanes are the item's sinks, its groups
+// concatenated, 64 at a time. Each
 // lane accumulates sum_k abar_k d^(alpha+e_k) G for all alpha in registers; the
 // item's partial sums are reduced across lanes with a fixed butterfly.
 // P: the expansion order of the item's records. MIXQ (lists with per-entry
 // orders): the block's item is qitems[qbase + block], its records end at
 // citem_end, and the row is written with stride out_stride, zero-filled from
 // nm(P) up to out_nm (the cell's full moment count).
-template <int P, typename T, bool MIXQ, bool PER>
+template <int P, typename T, bool MIXQ, bool PER, bool K1>
 __global__ __launch_bounds__(64) void k_m2p_cell_adj(
     int64_t n_citems, const uint32_t* __restrict__ citem_rec, const int32_t* __restrict__ citem_cell,
     const uint32_t* __restrict__ crec_off, const uint32_t* __restrict__ qitems, int64_t qbase,
@@ -1002,60 +1098,72 @@ __global__ __launch_bounds__(64) void k_m2p_cell_adj(
   T row[NM];
 #pragma unroll
   for (int a = 0; a < NM; ++a) row[a] = T(0);
-  // one loop over the (group, chunk of 64 sinks) pairs of the item, with the
-  // next pair's data prefetched; a single back edge keeps the row registers in
-  // place across iterations
-  auto group_centre = [&](uint32_t r, int& gf, int& ge, T& dx, T& dy, T& dz) {
-    const int g = uniform_i32((int)mval[r]);
-    const int gc = uniform_i32(g_cell[g]);
-    if (PER) {
-      // the record's image of the cell sits at its centre + n L
-      double shx, shy, shz;
-      image_shift(uniform_i32((int)(mkey[r] & 127u)), side, shx, shy, shz);
-      dx = (T)((c_centre[3 * gc] - (ccx + shx)) * inv_s);
-      dy = (T)((c_centre[3 * gc + 1] - (ccy + shy)) * inv_s);
-      dz = (T)((c_centre[3 * gc + 2] - (ccz + shz)) * inv_s);
-    } else {
-      dx = (T)((c_centre[3 * gc] - ccx) * inv_s);
-      dy = (T)((c_centre[3 * gc + 1] - ccy) * inv_s);
-      dz = (T)((c_centre[3 * gc + 2] - ccz) * inv_s);
-    }
-    gf = uniform_i32(g_first[g]);
-    ge = gf + uniform_i32(g_count[g]);
-  };
-  uint32_t r = r0;
-  int s0 = 0, ge = 0;
-  T Dx = T(0), Dy = T(0), Dz = T(0);
-  V4<T> pme, pab;
-  pme.x = pme.y = pme.z = pme.w = T(0);
-  pab = pme;
-  if (r < r1) {
-    group_centre(r, s0, ge, Dx, Dy, Dz);
-    if (s0 + lane < ge) {
-      pme = off[s0 + lane];
-      pab = ab4[s0 + lane];
-    }
+  // The item's sinks, all its records' groups concatenated, in chunks of 64
+  // lanes (groups of few sinks then fill the wavefront together: every sink
+  // sees the same cell). Per record, staged in LDS by one lane each: the
+  // running sink count, the group's first sink and the scaled difference of
+  // the group centre from the (image of the) cell centre.
+  __shared__ int s_cum[kCellItemGroups + 1];
+  __shared__ int s_first[kCellItemGroups];
+  __shared__ T s_d[3][kCellItemGroups];
+  const int nr = (int)(r1 - r0);  // at most kCellItemGroups < 64
+  int cnt = 0;
+  if (lane < nr) {
+    const uint32_t r = r0 + (uint32_t)lane;
+    const int g = (int)mval[r];
+    const int gc = g_cell[g];
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    // the record's image of the cell sits at its centre + n L
+    if (PER) image_shift((int)(mkey[r] & 127u), side, shx, shy, shz);
+    s_d[0][lane] = (T)((c_centre[3 * gc] - (ccx + shx)) * inv_s);
+    s_d[1][lane] = (T)((c_centre[3 * gc + 1] - (ccy + shy)) * inv_s);
+    s_d[2][lane] = (T)((c_centre[3 * gc + 2] - (ccz + shz)) * inv_s);
+    s_first[lane] = g_first[g];
+    cnt = g_count[g];
   }
-  while (r < r1) {
-    T X = T(1), Y = T(0), Z = T(0), bx = T(0), by = T(0), bz = T(0);
-    if (s0 + lane < ge) {
-      X = Dx + pme.x * (T)inv_s;
-      Y = Dy + pme.y * (T)inv_s;
-      Z = Dz + pme.z * (T)inv_s;
-      bx = pab.x;
-      by = pab.y;
-      bz = pab.z;
+  int inc = cnt;  // inclusive running count over the lanes
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane < nr) s_cum[lane + 1] = inc;
+  if (lane == 0) s_cum[0] = 0;
+  const int total = nr > 0 ? __shfl(inc, nr - 1) : 0;
+  __syncthreads();
+  // sink t of the concatenation: record k with s_cum[k] <= t < s_cum[k + 1]
+  // (the same number of halvings on every lane), its offset and cotangent
+  auto fetch = [&](int t, T& X, T& Y, T& Z, T& bx, T& by, T& bz) {
+    X = T(1);
+    Y = Z = bx = by = bz = T(0);
+    if (t < total) {
+      int lo = 0, hi = nr;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_cum[mid] <= t)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const int si = s_first[lo] + (t - s_cum[lo]);
+      const V4<T> me = off[si];
+      const V4<T> ab = ab4[si];
+      X = s_d[0][lo] + me.x * (T)inv_s;
+      Y = s_d[1][lo] + me.y * (T)inv_s;
+      Z = s_d[2][lo] + me.z * (T)inv_s;
+      bx = ab.x;
+      by = ab.y;
+      bz = ab.z;
     }
-    s0 += 64;
-    if (s0 >= ge) {
-      ++r;
-      if (r < r1) group_centre(r, s0, ge, Dx, Dy, Dz);
-    }
-    if (r < r1 && s0 + lane < ge) {
-      pme = off[s0 + lane];
-      pab = ab4[s0 + lane];
-    }
-    expansion_cell_adj<P, T>(X, Y, Z, e2, bx, by, bz, row);
+  };
+  // one loop over the chunks with the next chunk's data fetched ahead; a
+  // single back edge keeps the row registers in place across iterations
+  T X, Y, Z, bx, by, bz;
+  fetch(lane, X, Y, Z, bx, by, bz);
+  for (int t0 = 0; t0 < total; t0 += 64) {
+    const T cX = X, cY = Y, cZ = Z, cbx = bx, cby = by, cbz = bz;
+    if (t0 + 64 < total) fetch(t0 + 64 + lane, X, Y, Z, bx, by, bz);
+    expansion_cell_adj<P, T, K1>(cX, cY, cZ, e2, cbx, cby, cbz, row);
   }
   T* o = part + it * (int64_t)(MIXQ ? out_stride : nm_pad(P));
   // Sum the rows over the 64 lanes as a reduce-scatter: the row vector, padded
@@ -1374,7 +1482,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
   t->has_transpose = true;
 }
 
-template <int P, typename T>
+template <int P, typename T, bool K1>
 void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<T>* ab,
                           const T* momw, const T* momsub, double eps, T* sink_state,
                           double* mbar64,
@@ -1382,6 +1490,7 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
   hipStream_t st = ctx->stream;
   const double inv_side = 1.0 / t->side;
   const bool mixq = t->list_p >= 0;
+  tmark(ctx, HOT_T_ADJ_M2P_SINK, false);
   auto sink = [&](auto kern) {
     kern<<<grid_for(t->n_items, kWPB), kB, 0, st>>>(
         t->items.as<int2>(), t->n_items, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
@@ -1395,7 +1504,7 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
     // many part-empty items (split by the forward evaluation): those of at
     // most 32 sinks by slices of one wavefront, the others as usual
     if (t->n_items_big > 0) {
-      auto kb = t->periodic ? k_m2p_sink_adj<P, T, false, true> : k_m2p_sink_adj<P, T, false, false>;
+      auto kb = t->periodic ? k_m2p_sink_adj<P, T, false, true, false, K1> : k_m2p_sink_adj<P, T, false, false, false, K1>;
       kb<<<grid_for(t->n_items_big, kWPB), kB, 0, st>>>(
           t->items_big.as<int2>(), t->n_items_big, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
           t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
@@ -1405,7 +1514,7 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
       HOT_CHECK_LAUNCH();
     }
     if (t->n_items_small > 0) {
-      auto ks = t->periodic ? k_m2p_sink_adj_sl<P, T, true> : k_m2p_sink_adj_sl<P, T, false>;
+      auto ks = t->periodic ? k_m2p_sink_adj_sl<P, T, true, K1> : k_m2p_sink_adj_sl<P, T, false, K1>;
       ks<<<(unsigned)t->n_items_small, 64, 0, st>>>(
           t->items_small.as<int2>(), t->n_items_small, t->m2p_off.as<int64_t>(),
           t->m2p.as<int32_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
@@ -1414,18 +1523,20 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
       HOT_CHECK_LAUNCH();
     }
   } else if (t->bg)
-    sink(k_m2p_sink_adj<P, T, false, true, true>);
+    sink(k_m2p_sink_adj<P, T, false, true, true, K1>);
   else if (mixq && t->periodic)
-    sink(k_m2p_sink_adj<P, T, true, true>);
+    sink(k_m2p_sink_adj<P, T, true, true, false, K1>);
   else if (mixq)
-    sink(k_m2p_sink_adj<P, T, true, false>);
+    sink(k_m2p_sink_adj<P, T, true, false, false, K1>);
   else if (t->periodic)
-    sink(k_m2p_sink_adj<P, T, false, true>);
+    sink(k_m2p_sink_adj<P, T, false, true, false, K1>);
   else
-    sink(k_m2p_sink_adj<P, T, false, false>);
+    sink(k_m2p_sink_adj<P, T, false, false, false, K1>);
+  tmark(ctx, HOT_T_ADJ_M2P_SINK, true);
   const int64_t C = t->n_cells;
   DBuf part;
   part.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_citems) * nm_pad(P) * sizeof(T));
+  tmark(ctx, HOT_T_ADJ_M2P_CELL, false);
   if (t->n_citems > 0) {
     auto cell = [&](auto kern, int64_t n, int64_t base) {
       if (n <= 0) return;
@@ -1443,18 +1554,18 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
 #define HOT_CELL_Q(Q) \
   if constexpr (Q <= P) {                                                       \
     if (t->periodic)                                                            \
-      cell(k_m2p_cell_adj<Q, T, true, true>, qo[Q + 1] - qo[Q], qo[Q]);         \
+      cell(k_m2p_cell_adj<Q, T, true, true, K1>, qo[Q + 1] - qo[Q], qo[Q]);         \
     else                                                                        \
-      cell(k_m2p_cell_adj<Q, T, true, false>, qo[Q + 1] - qo[Q], qo[Q]);        \
+      cell(k_m2p_cell_adj<Q, T, true, false, K1>, qo[Q + 1] - qo[Q], qo[Q]);        \
   }
       HOT_CELL_Q(0) HOT_CELL_Q(1) HOT_CELL_Q(2) HOT_CELL_Q(3) HOT_CELL_Q(4) HOT_CELL_Q(5)
       HOT_CELL_Q(6) HOT_CELL_Q(7) HOT_CELL_Q(8)
 #undef HOT_CELL_Q
     } else {
       if (t->periodic)
-        cell(k_m2p_cell_adj<P, T, false, true>, t->n_citems, 0);
+        cell(k_m2p_cell_adj<P, T, false, true, K1>, t->n_citems, 0);
       else
-        cell(k_m2p_cell_adj<P, T, false, false>, t->n_citems, 0);
+        cell(k_m2p_cell_adj<P, T, false, false, K1>, t->n_citems, 0);
     }
   }
   const int64_t tot = C * nm(P);
@@ -1490,6 +1601,8 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
                                                            mbar64);
     HOT_CHECK_LAUNCH();
   }
+  tmark(ctx, HOT_T_ADJ_M2P_CELL, true);
+  tmark(ctx, HOT_T_ADJ_DOWNWARD, false);
   // far periodic replicas: their cotangent of the root's moments (cell 0)
   if (t->periodic) far_replicas_mbar(ctx, t, pos, abar, mbar64);
   // down the tree: level L+1 cells take their parents' cotangents
@@ -1511,13 +1624,31 @@ void launch_p2mT(hot_ctx* ctx, hot_tree* t, const double* spos, const double* sm
   HOT_CHECK_LAUNCH();
 }
 
+template <typename T, bool K1>
+void launch_expansion_adj_k(hot_ctx* ctx, hot_tree* t, const V4<T>* o4, const V4<T>* a4,
+                            const T* momw, const T* momsub, double eps, T* S, double* M,
+                            const double* pos, const double* abar) {
+  switch (t->p) {
+#define HOT_EXP_ADJ(Q) \
+  case Q: launch_expansion_adj<Q, T, K1>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+    HOT_EXP_ADJ(0) HOT_EXP_ADJ(1) HOT_EXP_ADJ(2) HOT_EXP_ADJ(3) HOT_EXP_ADJ(4) HOT_EXP_ADJ(5)
+    HOT_EXP_ADJ(6) HOT_EXP_ADJ(7) HOT_EXP_ADJ(8)
+#undef HOT_EXP_ADJ
+    default: invalid("p out of range");
+  }
+}
+
 template <typename T>
 void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-               const double* abar, double* xbar, double* mbar) {
+               int precision, const double* abar, double* xbar, double* mbar) {
+  const bool k1 = use_k1(precision, eps);
   hipStream_t st = ctx->stream;
   const int64_t n = t->n, C = t->n_cells;
   const int p = t->p;
-  if (!t->has_transpose) build_transpose(ctx, t);
+  if (!t->has_transpose) {
+    Phase ph(ctx, HOT_T_ADJ_TRANSPOSE);
+    build_transpose(ctx, t);
+  }
   DBuf off, ab, ab3, sink, src, mbar64, spos, smass, xb, mb;
   off.alloc(ctx, n * sizeof(V4<T>));
   ab.alloc(ctx, n * sizeof(V4<T>));
@@ -1529,43 +1660,52 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   smass.alloc(ctx, n * sizeof(double));
   xb.alloc(ctx, 3 * n * sizeof(double));
   mb.alloc(ctx, n * sizeof(double));
+  zero_flag_word(ctx, kFlagMass);
   k_offsets<T><<<grid_for(n, kB), kB, 0, st>>>(pos, mass, t->perm.as<uint32_t>(),
                                                t->group_of.as<int32_t>(), t->g_cell.as<int32_t>(),
                                                t->c_centre.as<double>(), n, off.as<V4<T>>(),
-                                               ctx->d_flags);
+                                               ctx->d_flags, ctx->d_flags + kFlagMass);
   HOT_CHECK_LAUNCH();
   k_abar<T><<<grid_for(n, kB), kB, 0, st>>>(abar, t->perm.as<uint32_t>(), n, ab.as<V4<T>>(),
                                             ab3.as<V4<T>>());
   HOT_CHECK_LAUNCH();
   gather_sorted(ctx, t, pos, mass, spos.as<double>(), smass.as<double>(), 0);
   const T e2 = (T)(eps * eps);
+  const T ie = k1 ? (T)(1.0 / eps) : T(0);
   const unsigned gi = grid_for(t->n_items, kWPB);
   // pair terms
-  auto sink_k = t->periodic ? (e2 > T(0) ? k_p2p_sink_adj<T, false, true>
-                                           : k_p2p_sink_adj<T, true, true>)
-                            : (e2 > T(0) ? k_p2p_sink_adj<T, false, false>
-                                         : k_p2p_sink_adj<T, true, false>);
+  auto sink_k = k1 ? (t->periodic ? k_p2p_sink_adj<T, false, true, true>
+                                  : k_p2p_sink_adj<T, false, false, true>)
+              : t->periodic ? (e2 > T(0) ? k_p2p_sink_adj<T, false, true, false>
+                                         : k_p2p_sink_adj<T, true, true, false>)
+                            : (e2 > T(0) ? k_p2p_sink_adj<T, false, false, false>
+                                         : k_p2p_sink_adj<T, true, false, false>);
+  tmark(ctx, HOT_T_ADJ_P2P_SINK, false);
   sink_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
                             t->p2p.as<int32_t>(), t->p2p_img.as<int8_t>(), t->side,
                             t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
                             t->group_of.as<int32_t>(), t->g_first.as<int32_t>(),
                             t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
-                            t->c_centre.as<double>(), off.as<V4<T>>(), ab.as<V4<T>>(), e2,
-                            sink.as<T>());
+                            t->c_centre.as<double>(), off.as<V4<T>>(), ab.as<V4<T>>(), e2, ie,
+                            ctx->d_flags + kFlagMass, sink.as<T>());
   HOT_CHECK_LAUNCH();
-  auto src_k = t->periodic ? (e2 > T(0) ? k_p2p_src_adj<T, false, true>
-                                          : k_p2p_src_adj<T, true, true>)
-                           : (e2 > T(0) ? k_p2p_src_adj<T, false, false>
-                                        : k_p2p_src_adj<T, true, false>);
+  auto src_k = k1 ? (t->periodic ? k_p2p_src_adj<T, false, true, true>
+                                 : k_p2p_src_adj<T, false, false, true>)
+             : t->periodic ? (e2 > T(0) ? k_p2p_src_adj<T, false, true, false>
+                                        : k_p2p_src_adj<T, true, true, false>)
+                           : (e2 > T(0) ? k_p2p_src_adj<T, false, false, false>
+                                        : k_p2p_src_adj<T, true, false, false>);
+  tmark(ctx, HOT_T_ADJ_P2P_SINK, true);
   const int64_t NU = t->n_schunk;
   DBuf upart;
   if (NU > t->n_items) upart.alloc(ctx, (size_t)NU * 64 * 8 * sizeof(T));
+  tmark(ctx, HOT_T_ADJ_P2P_SOURCE, false);
   src_k<<<grid_for(NU, kWPB), kB, 0, st>>>(
       t->schunk.as<int4>(), NU, t->items.as<int2>(), t->srec_key.as<uint64_t>(),
       t->srec_val.as<uint32_t>(), (1ull << t->srec_gbits) - 1ull, t->p2p.as<int32_t>(),
       t->p2p_img.as<int8_t>(), t->side, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
       t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
-      t->c_centre.as<double>(), off.as<V4<T>>(), ab3.as<V4<T>>(), e2, src.as<T>(),
+      t->c_centre.as<double>(), off.as<V4<T>>(), ab3.as<V4<T>>(), e2, ie, src.as<T>(),
       upart.as<T>());
   HOT_CHECK_LAUNCH();
   if (NU > t->n_items) {
@@ -1574,6 +1714,7 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
         t->g_count.as<int32_t>(), upart.as<T>(), src.as<T>());
     HOT_CHECK_LAUNCH();
   }
+  tmark(ctx, HOT_T_ADJ_P2P_SOURCE, true);
   // expansion terms
   const T* momw = nullptr;
   const T* momsub = nullptr;
@@ -1591,18 +1732,10 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   V4<T>* a4 = ab.as<V4<T>>();
   double* M = mbar64.as<double>();
   T* S = sink.as<T>();
-  switch (p) {
-    case 0: launch_expansion_adj<0, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 1: launch_expansion_adj<1, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 2: launch_expansion_adj<2, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 3: launch_expansion_adj<3, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 4: launch_expansion_adj<4, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 5: launch_expansion_adj<5, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 6: launch_expansion_adj<6, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 7: launch_expansion_adj<7, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    case 8: launch_expansion_adj<8, T>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
-    default: invalid("p out of range");
-  }
+  if (k1)
+    launch_expansion_adj_k<T, true>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar);
+  else
+    launch_expansion_adj_k<T, false>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar);
   const double* sp = spos.as<double>();
   const double* sm = smass.as<double>();
   switch (p) {
@@ -1623,17 +1756,18 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   // far periodic replicas: their direct dependence on the sink position
   if (t->periodic) far_replicas_xbar(ctx, t, pos, abar, xbar);
   // background subtraction: the exact box fields and the mean density
-  if (t->bg) background_adjoint(ctx, t, pos, mass, eps, sizeof(T) == 8, abar, xbar, mbar);
+  if (t->bg) background_adjoint(ctx, t, pos, mass, eps, precision, abar, xbar, mbar);
+  tmark(ctx, HOT_T_ADJ_DOWNWARD, true);
 }
 
 }  // namespace
 
 void adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
              int precision, const double* abar, double* xbar, double* mbar) {
-  if (precision == HOT_FP64)
-    adjoint_t<double>(ctx, t, pos, mass, eps, abar, xbar, mbar);
+  if (fp64_mode(precision))
+    adjoint_t<double>(ctx, t, pos, mass, eps, precision, abar, xbar, mbar);
   else
-    adjoint_t<float>(ctx, t, pos, mass, eps, abar, xbar, mbar);
+    adjoint_t<float>(ctx, t, pos, mass, eps, precision, abar, xbar, mbar);
 }
 
 }  // namespace hot

@@ -161,9 +161,34 @@ int hot_ctx_destroy(hot_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->tev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   delete ctx;
   return HOT_OK;
+}
+
+int hot_set_timing(hot_ctx* ctx, int on) {
+  return guard(ctx, [&] {
+    if (on && !ctx->tev[0])
+      for (auto& e : ctx->tev) HOT_HIP(hipEventCreate(&e));
+    for (auto& r : ctx->trec) r = false;
+    ctx->timing = on != 0;
+  });
+}
+
+int hot_get_timings(hot_ctx* ctx, double* ms) {
+  return guard(ctx, [&] {
+    if (!ms) hot::invalid("null output");
+    HOT_HIP(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < HOT_T_COUNT; ++k) {
+      ms[k] = -1.0;
+      if (!ctx->trec[k]) continue;
+      float t = 0.f;
+      HOT_HIP(hipEventElapsedTime(&t, ctx->tev[2 * k], ctx->tev[2 * k + 1]));
+      ms[k] = t;
+    }
+  });
 }
 
 const char* hot_last_error(hot_ctx* ctx) {
@@ -210,6 +235,7 @@ int tree_build(hot_ctx* ctx, int64_t n, const double* pos, const hot_build_opts*
     t->n_leaf = n_leaf;
     t->n_group = n_group;
     t->box_given = box != nullptr;
+    hot::Phase ph(ctx, HOT_T_TREE_BUILD);
     hot::build_tree(ctx, t, pos, box);
     t->valid = true;
     *out = t;
@@ -237,6 +263,7 @@ int compute_moments(hot_ctx* ctx, hot_tree* tree, const double* pos, const doubl
     need_tree(ctx, tree);
     if (!pos || !mass) hot::invalid("null positions or masses");
     if (p < 0 || p > hot::kMaxP) hot::invalid("p must lie in [0, 8]");
+    hot::Phase ph(ctx, HOT_T_MOMENTS);
     try {
       hot::build_moments(ctx, tree, pos, mass, p);
     } catch (...) {
@@ -251,6 +278,7 @@ int build_interaction_lists(hot_ctx* ctx, hot_tree* tree, double theta, int dire
     need_tree(ctx, tree);
     if (!(theta > 0.0 && theta < 1.0)) hot::invalid("theta must lie in (0, 1)");
     if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    hot::Phase ph(ctx, HOT_T_LISTS);
     try {
       hot::build_lists(ctx, tree, theta, direct_max);
     } catch (...) {
@@ -268,6 +296,7 @@ int build_interaction_lists_err(hot_ctx* ctx, hot_tree* tree, const double* mass
     if (!(err_tol > 0.0) || !std::isfinite(err_tol)) hot::invalid("err_tol must be finite and > 0");
     if (p_max < 0 || p_max > 8) hot::invalid("p_max must lie in [0, 8]");
     if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    hot::Phase ph(ctx, HOT_T_LISTS);
     try {
       hot::build_lists_err(ctx, tree, mass, err_tol, p_max, direct_max);
     } catch (...) {
@@ -286,6 +315,7 @@ int build_interaction_lists_periodic_err(hot_ctx* ctx, hot_tree* tree, const dou
     if (!(err_tol > 0.0) || !std::isfinite(err_tol)) hot::invalid("err_tol must be finite and > 0");
     if (p_max < 0 || p_max > 8) hot::invalid("p_max must lie in [0, 8]");
     if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    hot::Phase ph(ctx, HOT_T_LISTS);
     try {
       hot::build_lists_periodic_err(ctx, tree, mass, err_tol, p_max, direct_max);
     } catch (...) {
@@ -302,6 +332,7 @@ int build_interaction_lists_periodic(hot_ctx* ctx, hot_tree* tree, double theta,
     if (!tree->box_given) hot::state("periodic lists need a tree built with a given box");
     if (!(theta > 0.0 && theta < 1.0)) hot::invalid("theta must lie in (0, 1)");
     if (direct_max < 0) hot::invalid("direct_max must be >= 0");
+    hot::Phase ph(ctx, HOT_T_LISTS);
     try {
       hot::build_lists_periodic(ctx, tree, theta, direct_max);
     } catch (...) {
@@ -320,6 +351,7 @@ int build_interaction_lists_periodic_bs(hot_ctx* ctx, hot_tree* tree, double the
     if (!(theta > 0.0 && theta < 1.0)) hot::invalid("theta must lie in (0, 1)");
     if (direct_max < 0) hot::invalid("direct_max must be >= 0");
     if (width < 3 || width > 9 || !(width & 1)) hot::invalid("width must be odd, in [3, 9]");
+    hot::Phase ph(ctx, HOT_T_LISTS);
     try {
       hot::build_lists_periodic_bs(ctx, tree, theta, direct_max, width);
     } catch (...) {
@@ -337,12 +369,13 @@ int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* m
     need_tree(ctx, tree);
     if (!pos || !mass || !acc) hot::invalid("null positions, masses or output");
     if (!(eps >= 0.0) || !std::isfinite(eps)) hot::invalid("eps must be finite and >= 0");
-    if (precision != HOT_MIXED && precision != HOT_FP64) hot::invalid("unknown precision");
+    if (!hot::valid_precision(precision)) hot::invalid("unknown precision or kernel flag");
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
     if (tree->bg && pot)
       hot::invalid("potentials are not available with background-subtracted lists");
+    hot::Phase ph(ctx, HOT_T_EVAL);
     hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats);
     if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc, pot);
     if (tree->bg) hot::background_boxes(ctx, tree, pos, acc);
@@ -355,7 +388,8 @@ int eval_forces_noalloc(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     need_tree(ctx, tree);
     if (!pos || !mass || !acc) hot::invalid("null positions, masses or output");
     if (!(eps >= 0.0) || !std::isfinite(eps)) hot::invalid("eps must be finite and >= 0");
-    if (precision != HOT_MIXED)
+    if (!hot::valid_precision(precision)) hot::invalid("unknown precision or kernel flag");
+    if (hot::fp64_mode(precision))
       hot::invalid("eval_forces_noalloc computes in HOT_MIXED only (FP64 needs per-tree moments)");
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
@@ -372,6 +406,7 @@ int eval_forces_noalloc(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     mem.off = base + kScratchOff;
     mem.state = base + kScratchState;
     mem.far_local = reinterpret_cast<double*>(base + kScratchLocal);
+    hot::Phase ph(ctx, HOT_T_EVAL);
     hot::forces(ctx, tree, pos, mass, eps, precision, acc, pot, stats, &mem);
     if (tree->periodic) hot::far_replicas(ctx, tree, pos, acc, pot, mem.far_local);
   });
@@ -384,10 +419,11 @@ int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
     need_tree(ctx, tree);
     if (!pos || !mass || !acc_bar || !pos_bar) hot::invalid("null argument");
     if (!(eps >= 0.0) || !std::isfinite(eps)) hot::invalid("eps must be finite and >= 0");
-    if (precision != HOT_MIXED && precision != HOT_FP64) hot::invalid("unknown precision");
+    if (!hot::valid_precision(precision)) hot::invalid("unknown precision or kernel flag");
     if (!tree->has_lists) hot::state("build_interaction_lists first");
     if (tree->p < 0) hot::state("compute_moments first");
     if (tree->p < tree->list_p) hot::state("moments of lower order than the lists");
+    hot::Phase ph(ctx, HOT_T_ADJOINT);
     hot::adjoint(ctx, tree, pos, mass, eps, precision, acc_bar, pos_bar, mass_bar);
   });
 }

@@ -259,14 +259,15 @@ __global__ __launch_bounds__(256) void k_add_drho(const double* __restrict__ par
 }  // namespace
 
 void background_adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
-                        double eps, bool fp64, const double* abar, double* xbar, double* mbar) {
+                        double eps, int precision, const double* abar, double* xbar,
+                        double* mbar) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
   DBuf cf, dpsi;
   cf.alloc(ctx, n * 3 * sizeof(double));
   dpsi.alloc(ctx, n * sizeof(double));
   // the expansions' cubes scale with the mean density too
-  cube_field(ctx, t, pos, mass, eps, fp64, cf.as<double>());
+  cube_field(ctx, t, pos, mass, eps, precision, cf.as<double>());
   k_bg_boxes_adj<<<grid_for(t->n_items, kWavesPerBlock), kB, 0, st>>>(
       t->items.as<int2>(), t->n_items, t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
       t->g_cell.as<int32_t>(), t->c_centre.as<double>(), t->c_level.as<int8_t>(),

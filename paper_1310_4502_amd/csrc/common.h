@@ -62,6 +62,10 @@ int guard(hot_ctx* ctx, F&& f);
 // synchronising call report; synchronous calls (tree_build, the list
 // builders) clear and read their own local word.
 enum : int { kFlagDeferred = 0, kFlagLocal = 1 };
+// a third word, set by the evaluation's offset pass when some particle's mass
+// differs from the first one's (not an error: it selects the pair kernels'
+// general-mass loop)
+enum : int { kFlagMass = 2 };
 enum : unsigned {
   FLAG_NONFINITE_POS = 1u,
   FLAG_BAD_MASS = 2u,
@@ -69,6 +73,16 @@ enum : unsigned {
   FLAG_HASH_FULL = 8u,
   FLAG_INTERNAL = 16u,  // a kernel's own consistency check failed
 };
+
+// The precision argument of the evaluation calls: HOT_MIXED or HOT_FP64,
+// optionally ORed with HOT_K1 (the softening kernel).
+inline bool valid_precision(int precision) {
+  const int base = precision & ~HOT_K1;
+  return base == HOT_MIXED || base == HOT_FP64;
+}
+inline bool fp64_mode(int precision) { return (precision & ~HOT_K1) == HOT_FP64; }
+// K1 with eps = 0 is the Newtonian kernel, which the Plummer kernels give.
+inline bool use_k1(int precision, double eps) { return (precision & HOT_K1) && eps > 0.0; }
 
 }  // namespace hot
 
@@ -83,6 +97,11 @@ struct hot_ctx {
   std::string err;
   unsigned* d_flags = nullptr;     // device error flags: [kFlagDeferred], [kFlagLocal]
   hipEvent_t ev[8]{};
+  // phase timers (hot_set_timing): start and end event of every phase, and
+  // whether the phase has been recorded since timing was switched on
+  bool timing = false;
+  hipEvent_t tev[2 * HOT_T_COUNT]{};
+  bool trec[HOT_T_COUNT]{};
   // lattice sums of the far periodic replicas (host FP64) for one cube side
   std::vector<double> lattice;
   double lattice_side = 0.0;
@@ -91,6 +110,28 @@ struct hot_ctx {
 };
 
 namespace hot {
+
+// Phase markers: record the start or end event of a phase on the context
+// stream when timing is on.
+inline void tmark(hot_ctx* ctx, int phase, bool end) {
+  if (!ctx->timing) return;
+  HOT_HIP(hipEventRecord(ctx->tev[2 * phase + (end ? 1 : 0)], ctx->stream));
+  if (end) ctx->trec[phase] = true;
+}
+// Scope of one phase: start marker now, end marker at scope exit (also when
+// the phase throws, so that hot_get_timings never waits on an event that was
+// not recorded).
+struct Phase {
+  hot_ctx* ctx;
+  int phase;
+  Phase(hot_ctx* c, int p) : ctx(c), phase(p) { tmark(ctx, phase, false); }
+  ~Phase() {
+    if (ctx->timing && hipEventRecord(ctx->tev[2 * phase + 1], ctx->stream) == hipSuccess)
+      ctx->trec[phase] = true;
+  }
+  Phase(const Phase&) = delete;
+  Phase& operator=(const Phase&) = delete;
+};
 
 // A device allocation owned by a tree or by a call.
 struct DBuf {
@@ -240,14 +281,14 @@ void weighted_sub(hot_ctx* ctx, hot_tree* t, bool fp64);
 void background_boxes(hot_ctx* ctx, hot_tree* t, const double* pos, double* acc);
 // their adjoint and that of the mean density (through every mass)
 void background_adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
-                        double eps, bool fp64, const double* abar, double* xbar, double* mbar);
+                        double eps, int precision, const double* abar, double* xbar, double* mbar);
 // weighted scaled moments of every cell's uniform cube per unit density, negated
 // (C x nm_pad(p), FP32 or FP64)
 void weighted_cube(hot_ctx* ctx, hot_tree* t, bool fp64, void* out);
 // field (caller order, N x 3) of the flagged M2P entries' uniform cubes per
 // unit mean density, with the sign they enter the forces with
 void cube_field(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-                bool fp64, double* out);
+                int precision, double* out);
 void lattice_tensor(hot_ctx* ctx, hot_tree* t);
 // lc_mem (nullable): room for the far replicas' local coefficients
 // (far_local_count(p) doubles); allocated by the call when null

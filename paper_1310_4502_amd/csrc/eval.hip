@@ -40,7 +40,7 @@ __device__ __forceinline__ void image_shift(int img, double side, double& sx, do
 }
 constexpr int kCentreImage = 62;  // n = (0, 0, 0)
 
-template <typename T, bool POT, bool EPS0, bool PER>
+template <typename T, bool POT, bool EPS0, bool PER, bool K1>
 __global__ __launch_bounds__(kB) void k_p2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
     const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
@@ -48,8 +48,14 @@ __global__ __launch_bounds__(kB) void k_p2p(
     const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
     const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
     const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
-    const V4<T>* __restrict__ off, T eps2, T* __restrict__ state, int64_t n) {
+    const V4<T>* __restrict__ off, T eps2, T ie, const unsigned* __restrict__ mdiff,
+    T* __restrict__ state, int64_t n) {
   __shared__ V4<T> stage[kWavesPerBlock][64];
+  // K1: eps2 is the squared kernel radius, ie its inverse radius
+  const T ie2 = ie * ie, ie3 = ie * ie2;
+  // every particle of the same mass (k_offsets found none that differs): the
+  // pair loop leaves the mass out and the segment's sums are scaled once
+  const bool uni = *mdiff == 0u;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   V4<T>* slot = stage[w];
   const int64_t it = (int64_t)blockIdx.x * kWavesPerBlock + w;
@@ -57,13 +63,24 @@ __global__ __launch_bounds__(kB) void k_p2p(
   const int2 item = items[it];
   const int g = uniform_i32(item.x);
   const int gend = g_first[g] + g_count[g];
+  // m x n blocking with n = 2: lane l holds the two sinks item.y + (l & 31)
+  // (A) and item.y + 32 + (l & 31) (B); the half h = l / 32 of the wavefront
+  // takes the sources of odd (h = 1) or even (h = 0) index, so every source
+  // read from LDS serves two pairs (the LDS return path, 16 B per lane and
+  // read, would otherwise bound the kernel). The halves' sums are added at
+  // the end of each segment; lane l keeps the compensated sums of sink
+  // item.y + l.
+  const int h = lane >> 5, sub = lane & 31;
+  const int iA = item.y + sub, iB = iA + 32;
   const int i = item.y + lane;
   const bool active = i < gend;
   const int gc = g_cell[g];
   const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
-  V4<T> me;
-  me.x = me.y = me.z = me.w = T(0);
-  if (active) me = off[i];
+  V4<T> mA, mB;
+  mA.x = mA.y = mA.z = mA.w = T(0);
+  mB = mA;
+  if (iA < gend) mA = off[iA];
+  if (iB < gend) mB = off[iB];
   T sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
   const int64_t e1 = p2p_off[g + 1];
   int64_t e = p2p_off[g];
@@ -83,43 +100,86 @@ __global__ __launch_bounds__(kB) void k_p2p(
     }
     double shx = 0.0, shy = 0.0, shz = 0.0;
     if (PER) image_shift(im0, side, shx, shy, shz);
-    T ax = 0, ay = 0, az = 0, ap = 0;
-    T bx = 0, by = 0, bz = 0, bp = 0;
     int j = f;
     while (j < end) {
+      // a segment: the part of the run inside one source group
       const int sg = uniform_i32(group_of[j]);
       const int sgend = uniform_i32(g_first[sg] + g_count[sg]);
       const int jend = end < sgend ? end : sgend;
       if (jend <= j) break;  // never true for a valid tree
       const int sc = uniform_i32(g_cell[sg]);
-      T tx, ty, tz;
+      T dx, dy, dz;
       if (PER) {
-        tx = (T)((c_centre[3 * sc] + shx) - cgx) - me.x;
-        ty = (T)((c_centre[3 * sc + 1] + shy) - cgy) - me.y;
-        tz = (T)((c_centre[3 * sc + 2] + shz) - cgz) - me.z;
+        dx = (T)((c_centre[3 * sc] + shx) - cgx);
+        dy = (T)((c_centre[3 * sc + 1] + shy) - cgy);
+        dz = (T)((c_centre[3 * sc + 2] + shz) - cgz);
       } else {
-        tx = (T)(c_centre[3 * sc] - cgx) - me.x;
-        ty = (T)(c_centre[3 * sc + 1] - cgy) - me.y;
-        tz = (T)(c_centre[3 * sc + 2] - cgz) - me.z;
+        dx = (T)(c_centre[3 * sc] - cgx);
+        dy = (T)(c_centre[3 * sc + 1] - cgy);
+        dz = (T)(c_centre[3 * sc + 2] - cgz);
       }
-      // the segment's sources in batches of 64: one coalesced load per lane
-      // into the wavefront's LDS slot, then every lane reads them back as
-      // broadcasts (no scalar-cache round trip per few sources)
-#define HOT_PAIR(SELF, KK, AX, AY, AZ, AP)                                            \
+      const T tAx = dx - mA.x, tAy = dy - mA.y, tAz = dz - mA.z;
+      const T tBx = dx - mB.x, tBy = dy - mB.y, tBz = dz - mB.z;
+      // one pair of a sink (T*) with source s, into accumulators A*
+#define HOT_PAIR1(SELF, UM, VALID, SINK_I, TX, TY, TZ, AX, AY, AZ, AP)               \
   {                                                                                  \
-    const V4<T> s = slot[KK];                                                        \
-    const T rx = s.x + tx, ry = s.y + ty, rz = s.z + tz;                             \
-    const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));            \
-    T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                             \
-    if (SELF && jb + (KK) == i) inv = T(0);                                          \
-    const T mi = s.w * inv;                                                          \
-    const T f3 = mi * (inv * inv);                                                   \
-    AX = hot_fma(f3, rx, AX);                                                        \
-    AY = hot_fma(f3, ry, AY);                                                        \
-    AZ = hot_fma(f3, rz, AZ);                                                        \
-    if (POT) AP -= mi;                                                               \
+    const T rx = s.x + TX, ry = s.y + TY, rz = s.z + TZ;                             \
+    if constexpr (!K1) {                                                             \
+      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, hot_fma(rz, rz, eps2)));          \
+      T inv = (EPS0 && !(r2 > T(0))) ? T(0) : hot_rsq(r2);                           \
+      if (!(VALID) || (SELF && jb + k == (SINK_I))) inv = T(0);                      \
+      const T mi = UM ? inv : s.w * inv;                                             \
+      const T f3 = mi * (inv * inv);                                                 \
+      AX = hot_fma(f3, rx, AX);                                                      \
+      AY = hot_fma(f3, ry, AY);                                                      \
+      AZ = hot_fma(f3, rz, AZ);                                                      \
+      if (POT) AP -= mi;                                                             \
+    } else {                                                                         \
+      const T r2 = hot_fma(rx, rx, hot_fma(ry, ry, rz * rz));                        \
+      const T inv = hot_rsq(r2);                                                     \
+      T f3 = inv * (inv * inv);                                                      \
+      T mi = inv;                                                                    \
+      if (r2 < eps2) {                                                               \
+        const T v = (eps2 - r2) * ie2;                                               \
+        f3 = ie3 * k1_force(v);                                                      \
+        if (POT) mi = ie * k1_pot(v);                                                \
+      }                                                                              \
+      if (!UM) {                                                                     \
+        f3 *= s.w;                                                                   \
+        mi *= s.w;                                                                   \
+      }                                                                              \
+      if (!(VALID) || (SELF && jb + k == (SINK_I))) {                                \
+        f3 = T(0);                                                                   \
+        mi = T(0);                                                                   \
+      }                                                                              \
+      AX = hot_fma(f3, rx, AX);                                                      \
+      AY = hot_fma(f3, ry, AY);                                                      \
+      AZ = hot_fma(f3, rz, AZ);                                                      \
+      if (POT) AP -= mi;                                                             \
+    }                                                                                \
+  }
+      // sources k2 + h for k2 = 0, 2, 4, ...: full pairs of sources first, then
+      // the odd last one (half 0 only)
+#define HOT_BATCH(UM, SELF)                                                          \
+  {                                                                                  \
+    int k2 = 0;                                                                      \
+    _Pragma("unroll 4") for (; k2 + 1 < nbt; k2 += 2) {                              \
+      const int k = k2 + h;                                                          \
+      const V4<T> s = slot[k];                                                       \
+      HOT_PAIR1(SELF, UM, true, iA, tAx, tAy, tAz, aAx, aAy, aAz, aAp)               \
+      HOT_PAIR1(SELF, UM, true, iB, tBx, tBy, tBz, aBx, aBy, aBz, aBp)               \
+    }                                                                                \
+    if (k2 < nbt) {                                                                  \
+      const int k = k2 + h;                                                          \
+      const V4<T> s = slot[k2];                                                      \
+      HOT_PAIR1(SELF, UM, h == 0, iA, tAx, tAy, tAz, aAx, aAy, aAz, aAp)             \
+      HOT_PAIR1(SELF, UM, h == 0, iB, tBx, tBy, tBz, aBx, aBy, aBz, aBp)             \
+    }                                                                                \
   }
       const bool self = sg == g && im0 == kCentreImage;
+      T aAx = 0, aAy = 0, aAz = 0, aAp = 0;
+      T aBx = 0, aBy = 0, aBz = 0, aBp = 0;
+      T mseg = T(1);
       for (int jb = j; jb < jend; jb += 64) {
         const int nbt = jend - jb < 64 ? jend - jb : 64;
         V4<T> v;
@@ -128,25 +188,37 @@ __global__ __launch_bounds__(kB) void k_p2p(
         __builtin_amdgcn_wave_barrier();
         slot[lane] = v;
         __builtin_amdgcn_wave_barrier();
-        if (self) {
-          for (int k = 0; k < nbt; ++k) HOT_PAIR(true, k, ax, ay, az, ap)
+        if (uni) {
+          if (self)
+            HOT_BATCH(true, true)
+          else
+            HOT_BATCH(true, false)
+          mseg = slot[0].w;
         } else {
-          int k = 0;
-#pragma unroll 4
-          for (; k + 1 < nbt; k += 2) {
-            HOT_PAIR(false, k, ax, ay, az, ap)
-            HOT_PAIR(false, k + 1, bx, by, bz, bp)
-          }
-          if (k < nbt) HOT_PAIR(false, k, ax, ay, az, ap)
+          if (self)
+            HOT_BATCH(false, true)
+          else
+            HOT_BATCH(false, false)
         }
       }
-#undef HOT_PAIR
+#undef HOT_BATCH
+#undef HOT_PAIR1
+      // the halves' sums: lane l < 32 completes sink A = item.y + l, lane
+      // l >= 32 sink B = item.y + l; one compensated add per segment (at most
+      // n_group sources)
+      const T kx = h ? aBx : aAx, ky = h ? aBy : aAy, kz = h ? aBz : aAz;
+      const T ox = __shfl_xor(h ? aAx : aBx, 32), oy = __shfl_xor(h ? aAy : aBy, 32),
+              oz = __shfl_xor(h ? aAz : aBz, 32);
+      kahan_add(sx, cx, (kx + ox) * mseg);
+      kahan_add(sy, cy, (ky + oy) * mseg);
+      kahan_add(sz, cz, (kz + oz) * mseg);
+      if (POT) {
+        const T kp = h ? aBp : aAp;
+        const T op = __shfl_xor(h ? aAp : aBp, 32);
+        kahan_add(sp, cp, (kp + op) * mseg);
+      }
       j = jend;
     }
-    kahan_add(sx, cx, ax + bx);
-    kahan_add(sy, cy, ay + by);
-    kahan_add(sz, cz, az + bz);
-    if (POT) kahan_add(sp, cp, ap + bp);
   }
   if (active) {
     T* st = state + (int64_t)i * 8;
@@ -170,7 +242,7 @@ constexpr int m2p_waves_per_simd() { return (sizeof(T) == 4 && P >= 7) ? 4 : 1; 
 // PER: every entry carries the image of its cell (periodic lists).
 // BG: background subtraction; an entry flagged in m2p_sub takes its cell's
 // moments minus those of its uniform cube (momsub) instead of momw.
-template <int P, typename T, bool POT, bool MIXQ, bool PER, bool BG>
+template <int P, typename T, bool POT, bool MIXQ, bool PER, bool BG, bool K1>
 __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(m2p_waves_per_simd<P, T>())))
 void k_m2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
@@ -260,9 +332,9 @@ void k_m2p(
     const T e2 = (T)(es * es);
     T ax = 0, ay = 0, az = 0, ph = 0;
     if (MIXQ)
-      expansion_fwd_q<P, T, POT>(q, X, Y, Z, e2, M, ax, ay, az, ph);
+      expansion_fwd_q<P, T, POT, K1>(q, X, Y, Z, e2, M, ax, ay, az, ph);
     else
-      expansion_fwd<P, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph);
+      expansion_fwd<P, T, POT, K1>(X, Y, Z, e2, M, ax, ay, az, ph);
     const T sa = (T)(-(inv_s * inv_s));
     kahan_add(sx, cx, ax * sa);
     kahan_add(sy, cy, ay * sa);
@@ -290,7 +362,7 @@ void k_m2p(
 // item of few sinks leaves idle in k_m2p do useful work. The slices'
 // compensated sums are added at the end. Every cross-lane read is executed by
 // all lanes (never inside a lane-dependent branch or operand).
-template <int P, typename T, bool POT, bool PER>
+template <int P, typename T, bool POT, bool PER, bool K1>
 __global__ __launch_bounds__(64) void k_m2p_sl(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ m2p_off,
     const int32_t* __restrict__ m2p, const int8_t* __restrict__ m2p_img, double side,
@@ -374,7 +446,7 @@ __global__ __launch_bounds__(64) void k_m2p_sl(
     const double es = eps * inv_s;
     const T e2 = (T)(es * es);
     T ax = 0, ay = 0, az = 0, ph = 0;
-    expansion_fwd<P, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph);
+    expansion_fwd<P, T, POT, K1>(X, Y, Z, e2, M, ax, ay, az, ph);
     const T sa = ok ? (T)(-(inv_s * inv_s)) : T(0);
     kahan_add(sx, cx, ax * sa);
     kahan_add(sy, cy, ay * sa);
@@ -449,9 +521,11 @@ __global__ void k_finalize(const T* __restrict__ state, const uint32_t* __restri
 }
 
 template <typename T, bool POT>
-void launch_p2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, double eps, T* state) {
+void launch_p2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, double eps, bool k1, T* state) {
+  const unsigned* mdiff = ctx->d_flags + kFlagMass;
   const unsigned grid = grid_for(t->n_items, kWavesPerBlock);
   const T e2 = (T)(eps * eps);
+  const T ie = k1 ? (T)(1.0 / eps) : T(0);
   auto go = [&](auto kern) {
     kern<<<grid, kB, 0, ctx->stream>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
                                        t->p2p.as<int32_t>(), t->p2p_img.as<int8_t>(), t->side,
@@ -459,23 +533,27 @@ void launch_p2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, double eps, T* stat
                                        t->c_count.as<int32_t>(), t->group_of.as<int32_t>(),
                                        t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
                                        t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, e2,
-                                       state, t->n);
+                                       ie, mdiff, state, t->n);
     HOT_CHECK_LAUNCH();
   };
   if (t->periodic) {
-    if (e2 > T(0))
-      go(k_p2p<T, POT, false, true>);
+    if (k1)
+      go(k_p2p<T, POT, false, true, true>);
+    else if (e2 > T(0))
+      go(k_p2p<T, POT, false, true, false>);
     else
-      go(k_p2p<T, POT, true, true>);
+      go(k_p2p<T, POT, true, true, false>);
   } else {
-    if (e2 > T(0))
-      go(k_p2p<T, POT, false, false>);
+    if (k1)
+      go(k_p2p<T, POT, false, false, true>);
+    else if (e2 > T(0))
+      go(k_p2p<T, POT, false, false, false>);
     else
-      go(k_p2p<T, POT, true, false>);
+      go(k_p2p<T, POT, true, false, false>);
   }
 }
 
-template <int P, typename T, bool POT>
+template <int P, typename T, bool POT, bool K1>
 void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, const T* momsub,
                   double eps, T* state) {
   const unsigned grid = grid_for(t->n_items, kWavesPerBlock);
@@ -489,15 +567,15 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, co
   };
   if (t->list_p >= 0) {
     if (t->periodic)
-      go(k_m2p<P, T, POT, true, true, false>);
+      go(k_m2p<P, T, POT, true, true, false, K1>);
     else
-      go(k_m2p<P, T, POT, true, false, false>);
+      go(k_m2p<P, T, POT, true, false, false, K1>);
   } else if (!t->bg && t->n_items_small * 10 >= t->n_items) {
     // theta lists with many part-empty items: those of at most 32 sinks by
     // slices of one wavefront, the others as usual
     if (t->n_items_big > 0) {
-      auto kb = t->periodic ? k_m2p<P, T, POT, false, true, false>
-                            : k_m2p<P, T, POT, false, false, false>;
+      auto kb = t->periodic ? k_m2p<P, T, POT, false, true, false, K1>
+                            : k_m2p<P, T, POT, false, false, false, K1>;
       kb<<<grid_for(t->n_items_big, kWavesPerBlock), kB, 0, ctx->stream>>>(
           t->items_big.as<int2>(), t->n_items_big, t->m2p_off.as<int64_t>(), t->m2p.as<int32_t>(),
           t->m2p_q.as<int8_t>(), t->m2p_img.as<int8_t>(), t->side, t->m2p_sub.as<int8_t>(),
@@ -506,7 +584,7 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, co
       HOT_CHECK_LAUNCH();
     }
     if (t->n_items_small > 0) {
-      auto ks = t->periodic ? k_m2p_sl<P, T, POT, true> : k_m2p_sl<P, T, POT, false>;
+      auto ks = t->periodic ? k_m2p_sl<P, T, POT, true, K1> : k_m2p_sl<P, T, POT, false, K1>;
       ks<<<(unsigned)t->n_items_small, 64, 0, ctx->stream>>>(
           t->items_small.as<int2>(), t->n_items_small, t->m2p_off.as<int64_t>(),
           t->m2p.as<int32_t>(), t->m2p_img.as<int8_t>(), t->side, t->c_level.as<int8_t>(),
@@ -518,13 +596,13 @@ void launch_m2p_p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, co
     // potentials are refused with background subtraction: no variant for them
     if constexpr (!POT) {
       if (t->bg) {
-        go(k_m2p<P, T, POT, false, true, true>);
+        go(k_m2p<P, T, POT, false, true, true, K1>);
         return;
       }
     }
-    go(k_m2p<P, T, POT, false, true, false>);
+    go(k_m2p<P, T, POT, false, true, false, K1>);
   } else {
-    go(k_m2p<P, T, POT, false, false, false>);
+    go(k_m2p<P, T, POT, false, false, false, K1>);
   }
 }
 
@@ -557,26 +635,35 @@ void split_items(hot_ctx* ctx, hot_tree* t) {
 
 namespace {
 
-template <typename T, bool POT>
-void launch_m2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, const T* momsub,
-                double eps, T* state) {
+template <typename T, bool POT, bool K1>
+void launch_m2p_k(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, const T* momsub,
+                  double eps, T* state) {
   switch (t->p) {
-    case 0: launch_m2p_p<0, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 1: launch_m2p_p<1, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 2: launch_m2p_p<2, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 3: launch_m2p_p<3, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 4: launch_m2p_p<4, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 5: launch_m2p_p<5, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 6: launch_m2p_p<6, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 7: launch_m2p_p<7, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
-    case 8: launch_m2p_p<8, T, POT>(ctx, t, off, momw, momsub, eps, state); break;
+    case 0: launch_m2p_p<0, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 1: launch_m2p_p<1, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 2: launch_m2p_p<2, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 3: launch_m2p_p<3, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 4: launch_m2p_p<4, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 5: launch_m2p_p<5, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 6: launch_m2p_p<6, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 7: launch_m2p_p<7, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
+    case 8: launch_m2p_p<8, T, POT, K1>(ctx, t, off, momw, momsub, eps, state); break;
     default: invalid("p out of range");
   }
 }
 
+template <typename T, bool POT>
+void launch_m2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const T* momw, const T* momsub,
+                double eps, bool k1, T* state) {
+  if (k1)
+    launch_m2p_k<T, POT, true>(ctx, t, off, momw, momsub, eps, state);
+  else
+    launch_m2p_k<T, POT, false>(ctx, t, off, momw, momsub, eps, state);
+}
+
 template <typename T>
 void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-              double* acc, double* pot, hot_stats* stats, const EvalMem* mem) {
+              bool k1, double* acc, double* pot, hot_stats* stats, const EvalMem* mem) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
   // caller memory where given (every element is written below before it is
@@ -593,9 +680,11 @@ void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, 
     state_buf.alloc(ctx, n * 8 * sizeof(T));
     state = state_buf.as<T>();
   }
+  zero_flag_word(ctx, kFlagMass);
   k_offsets<T><<<grid_for(n, kB), kB, 0, st>>>(pos, mass, t->perm.as<uint32_t>(),
                                                t->group_of.as<int32_t>(), t->g_cell.as<int32_t>(),
-                                               t->c_centre.as<double>(), n, off, ctx->d_flags);
+                                               t->c_centre.as<double>(), n, off, ctx->d_flags,
+                                               ctx->d_flags + kFlagMass);
   HOT_CHECK_LAUNCH();
   const T* momw = nullptr;
   if constexpr (sizeof(T) == 4) {
@@ -611,15 +700,21 @@ void forces_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, 
   }
   if (t->n_items_small < 0) ::hot::state("tree without its item split");
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[0], st));
-  if (pot)
-    launch_p2p<T, true>(ctx, t, off, eps, state);
-  else
-    launch_p2p<T, false>(ctx, t, off, eps, state);
+  {
+    Phase ph(ctx, HOT_T_EVAL_P2P);
+    if (pot)
+      launch_p2p<T, true>(ctx, t, off, eps, k1, state);
+    else
+      launch_p2p<T, false>(ctx, t, off, eps, k1, state);
+  }
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[1], st));
-  if (pot)
-    launch_m2p<T, true>(ctx, t, off, momw, momsub, eps, state);
-  else
-    launch_m2p<T, false>(ctx, t, off, momw, momsub, eps, state);
+  {
+    Phase ph(ctx, HOT_T_EVAL_M2P);
+    if (pot)
+      launch_m2p<T, true>(ctx, t, off, momw, momsub, eps, k1, state);
+    else
+      launch_m2p<T, false>(ctx, t, off, momw, momsub, eps, k1, state);
+  }
   if (stats) HOT_HIP(hipEventRecord(ctx->ev[2], st));
   k_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(state, t->perm.as<uint32_t>(), n, acc, pot);
   HOT_CHECK_LAUNCH();
@@ -649,7 +744,7 @@ __global__ void k_zero_t(T* __restrict__ p, int64_t n) {
 // forces with respect to the mean density through the flagged entries.
 template <typename T>
 void cube_field_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-                  double* out) {
+                  bool k1, double* out) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
   const int64_t nmom = t->n_cells * nm_pad(t->p);
@@ -668,7 +763,8 @@ void cube_field_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* ma
   k_zero_t<T><<<grid_for(nmom, kB), kB, 0, st>>>(zero.as<T>(), nmom);
   HOT_CHECK_LAUNCH();
   weighted_cube(ctx, t, sizeof(T) == 8, cube.p);
-  launch_m2p<T, false>(ctx, t, off.as<V4<T>>(), zero.as<T>(), cube.as<T>(), eps, state.as<T>());
+  launch_m2p<T, false>(ctx, t, off.as<V4<T>>(), zero.as<T>(), cube.as<T>(), eps, k1,
+                       state.as<T>());
   k_finalize<T><<<grid_for(n, kB), kB, 0, st>>>(state.as<T>(), t->perm.as<uint32_t>(), n, out,
                                                 nullptr);
   HOT_CHECK_LAUNCH();
@@ -677,20 +773,22 @@ void cube_field_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* ma
 }  // namespace
 
 void cube_field(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
-                bool fp64, double* out) {
+                int precision, double* out) {
   if (!t->bg) state("cube field without background-subtracted lists");
-  if (fp64)
-    cube_field_t<double>(ctx, t, pos, mass, eps, out);
+  const bool k1 = use_k1(precision, eps);
+  if (fp64_mode(precision))
+    cube_field_t<double>(ctx, t, pos, mass, eps, k1, out);
   else
-    cube_field_t<float>(ctx, t, pos, mass, eps, out);
+    cube_field_t<float>(ctx, t, pos, mass, eps, k1, out);
 }
 
 void forces(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
             int precision, double* acc, double* pot, hot_stats* stats, const EvalMem* mem) {
-  if (precision == HOT_FP64)
-    forces_t<double>(ctx, t, pos, mass, eps, acc, pot, stats, mem);
+  const bool k1 = use_k1(precision, eps);
+  if (fp64_mode(precision))
+    forces_t<double>(ctx, t, pos, mass, eps, k1, acc, pot, stats, mem);
   else
-    forces_t<float>(ctx, t, pos, mass, eps, acc, pot, stats, mem);
+    forces_t<float>(ctx, t, pos, mass, eps, k1, acc, pot, stats, mem);
 }
 
 

@@ -44,6 +44,26 @@ struct Vec4<double> {
 template <typename T>
 using V4 = typename Vec4<T>::type;
 
+// Dehnen's K1 kernel inside its radius eps (Force Smoothing section), as
+// polynomials in v = 1 - r^2 / eps^2 with positive coefficients (no
+// cancellation near the edge, v -> 0, where they meet the Newtonian values):
+// the pair force is m r eps^-3 k1_force(v), the potential -m eps^-1 k1_pot(v),
+// and the Hessian's r r^T coefficient -eps^-5 k1_hess(v).
+template <typename T>
+__device__ __forceinline__ T k1_force(T v) {
+  return hot_fma(v, hot_fma(v, hot_fma(v, T(12.03125), T(1.875)), T(1.5)), T(1));
+}
+template <typename T>
+__device__ __forceinline__ T k1_pot(T v) {
+  return hot_fma(v, hot_fma(v, hot_fma(v, hot_fma(v, T(1.50390625), T(0.3125)), T(0.375)),
+                            T(0.5)),
+                 T(1));
+}
+template <typename T>
+__device__ __forceinline__ T k1_hess(T v) {
+  return hot_fma(v, hot_fma(v, T(72.1875), T(7.5)), T(3));
+}
+
 template <typename T>
 __device__ __forceinline__ void kahan_add(T& s, T& c, T x) {
   const T y = x - c;
@@ -53,11 +73,14 @@ __device__ __forceinline__ void kahan_add(T& s, T& c, T x) {
 }
 
 // Offsets of every particle (sorted order) from its group's centre, and mass.
+// mdiff (nullable, cleared before the launch): set when a mass differs from
+// that of the first particle in sorted order.
 template <typename T>
 __global__ void k_offsets(const double* __restrict__ pos, const double* __restrict__ mass,
                           const uint32_t* __restrict__ perm, const int32_t* __restrict__ group_of,
                           const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
-                          int64_t n, V4<T>* __restrict__ off, unsigned* __restrict__ flags) {
+                          int64_t n, V4<T>* __restrict__ off, unsigned* __restrict__ flags,
+                          unsigned* __restrict__ mdiff = nullptr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t j = perm[i];
@@ -65,6 +88,7 @@ __global__ void k_offsets(const double* __restrict__ pos, const double* __restri
   const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2], m = mass[j];
   if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(flags, FLAG_NONFINITE_POS);
   if (!(isfinite(m) && m >= 0.0)) atomicOr(flags, FLAG_BAD_MASS);
+  if (mdiff && m != mass[perm[0]]) atomicOr(mdiff, 1u);
   V4<T> o;
   o.x = (T)(x - c_centre[3 * gc]);
   o.y = (T)(y - c_centre[3 * gc + 1]);

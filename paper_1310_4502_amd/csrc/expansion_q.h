@@ -11,14 +11,14 @@ namespace hot {
 #define HOT_Q_CASES(CALL) \
   CALL(0) CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(6) CALL(7) CALL(8)
 
-template <int P, typename T, bool POT>
+template <int P, typename T, bool POT, bool K1 = false>
 __device__ __forceinline__ void expansion_fwd_q(int q, T X, T Y, T Z, T e2,
                                                 const T* __restrict__ M, T& ax, T& ay, T& az,
                                                 T& ph) {
   switch (q) {
 #define HOT_CASE(Q)                                                     \
   case Q:                                                               \
-    if constexpr (Q <= P) expansion_fwd<Q, T, POT>(X, Y, Z, e2, M, ax, ay, az, ph); \
+    if constexpr (Q <= P) expansion_fwd<Q, T, POT, K1>(X, Y, Z, e2, M, ax, ay, az, ph); \
     break;
     HOT_Q_CASES(HOT_CASE)
 #undef HOT_CASE
@@ -27,14 +27,14 @@ __device__ __forceinline__ void expansion_fwd_q(int q, T X, T Y, T Z, T e2,
   }
 }
 
-template <int P, typename T>
+template <int P, typename T, bool K1 = false>
 __device__ __forceinline__ void expansion_sink_adj_q(int q, T X, T Y, T Z, T e2,
                                                      const T* __restrict__ M, T bx, T by, T bz,
                                                      T& gx, T& gy, T& gz) {
   switch (q) {
 #define HOT_CASE(Q)                                                                   \
   case Q:                                                                             \
-    if constexpr (Q <= P) expansion_sink_adj<Q, T>(X, Y, Z, e2, M, bx, by, bz, gx, gy, gz); \
+    if constexpr (Q <= P) expansion_sink_adj<Q, T, K1>(X, Y, Z, e2, M, bx, by, bz, gx, gy, gz); \
     break;
     HOT_Q_CASES(HOT_CASE)
 #undef HOT_CASE

@@ -56,16 +56,59 @@ class Emitter:
         self.lines.append("  " + s)
 
     def radial(self):
+        """F_n = 2^n f^(n)(s), n <= K, for both softening kernels. Plummer:
+        s = |R|^2 + e2, f = -s^(-1/2). K1 (e2 the squared kernel radius):
+        outside (s = |R|^2 >= e2) the Newtonian f = -s^(-1/2); inside f is the
+        quartic -Q(v) / (256 eps) in v = 1 - s / e2, so F_n = -(-2)^n Q^(n)(v) /
+        (256 eps^(2n+1)): Q(v) = 256 + 128 v + 96 v^2 + 80 v^3 + 385 v^4 (the
+        positive-coefficient form of the kernel's potential about its edge), zero
+        beyond n = 4. The Newtonian values are computed first and replaced lane
+        by lane (a select, so the infinities at s = 0 never enter a product)."""
         K = self.K
         e = self.e
+        e("T " + ", ".join(f"F{n}" for n in range(K + 1)) + ";")
+        e("if constexpr (!K1) {")
         e("const T s_ = hot_fma(X, X, hot_fma(Y, Y, hot_fma(Z, Z, e2)));")
         e("const T u_ = hot_rsq(s_);")
         e("const T is_ = u_ * u_;")
-        e("const T F0 = -u_;")
+        e("F0 = -u_;")
         if K >= 1:
-            e("const T F1 = u_ * is_;")
+            e("F1 = u_ * is_;")
         for n in range(1, K):
-            e(f"const T F{n + 1} = (F{n} * is_) * {lit(-(2 * n + 1))};")
+            e(f"F{n + 1} = (F{n} * is_) * {lit(-(2 * n + 1))};")
+        e("} else {")
+        e("const T s_ = hot_fma(X, X, hot_fma(Y, Y, Z * Z));")
+        e("const T u_ = hot_rsq(s_);")
+        e("const T is_ = u_ * u_;")
+        e("F0 = -u_;")
+        if K >= 1:
+            e("F1 = u_ * is_;")
+        for n in range(1, K):
+            e(f"F{n + 1} = (F{n} * is_) * {lit(-(2 * n + 1))};")
+        e("if (s_ < e2) {")
+        e("const T ie_ = hot_rsq(e2);")
+        e("const T ie2_ = ie_ * ie_;")
+        e("const T v_ = (e2 - s_) * ie2_;")
+        # Q^(n)(v) * 2^n / 256 with the sign of F_n, highest power first
+        polys = [(-1, [1.0, 0.5, 0.375, 0.3125, 1.50390625]),
+                 (1, [1.0, 1.5, 1.875, 12.03125]),
+                 (-1, [3.0, 7.5, 72.1875]),
+                 (1, [15.0, 288.75]),
+                 (-1, [577.5])]
+        e("T iep_ = ie_;")
+        for n in range(0, K + 1):
+            if n < len(polys):
+                sg, c = polys[n]
+                h = lit(c[-1])
+                for co in reversed(c[:-1]):
+                    h = f"hot_fma(v_, {h}, {lit(co)})"
+                e(f"F{n} = {'-' if sg < 0 else ''}(iep_ * {h});")
+                if n + 1 <= K and n + 1 < len(polys):
+                    e("iep_ = iep_ * ie2_;")
+            else:
+                e(f"F{n} = T(0);")
+        e("}")
+        e("}")
         # powers of X
         if K >= 2:
             e("const T X2 = X * X;")
@@ -309,12 +352,30 @@ def _count_ops(lines):
 
 
 
+def _plummer_only(lines):
+    """The emitted lines without the K1 branch of the radial functions."""
+    out, skip, depth = [], False, 0
+    for l in lines:
+        t = l.strip()
+        if not skip and t == "} else {":
+            skip, depth = True, 1
+            continue
+        if skip:
+            depth += t.count("{") - t.count("}")
+            if depth <= 0:
+                skip = False
+            continue
+        out.append(l)
+    return out
+
+
 def flops_m2p(P):
     """FP32 operations per (sink, cell) of the forward expansion kernel without
-    the potential: the generated expansion plus the per-interaction setup of the
-    kernel (scaled R: 3 multiplies and 3 adds; result scaling: 3 multiplies;
-    compensated accumulation: 4 adds for each of 3 components)."""
-    body = [l for l in gen_fwd(P) if "if constexpr (POT)" not in l]
+    the potential, Plummer softening: the generated expansion plus the
+    per-interaction setup of the kernel (scaled R: 3 multiplies and 3 adds;
+    result scaling: 3 multiplies; compensated accumulation: 4 adds for each of
+    3 components)."""
+    body = [l for l in _plummer_only(gen_fwd(P)) if "if constexpr (POT)" not in l]
     return _count_ops(body) + 6 + 3 + 12
 
 
@@ -333,7 +394,7 @@ def main(out_path):
              "#endif",
              "namespace hot {",
              ""]
-    parts.append("template <int P, typename T, bool POT>")
+    parts.append("template <int P, typename T, bool POT, bool K1 = false>")
     parts.append("__device__ __forceinline__ void expansion_fwd(T X, T Y, T Z, T e2, "
                  "const T* __restrict__ M, T& ax, T& ay, T& az, T& ph) {")
     for P in range(PMAX + 1):
@@ -343,7 +404,7 @@ def main(out_path):
     parts.append("  }")
     parts.append("}")
     parts.append("")
-    parts.append("template <int P, typename T>")
+    parts.append("template <int P, typename T, bool K1 = false>")
     parts.append("__device__ __forceinline__ void expansion_sink_adj(T X, T Y, T Z, T e2, "
                  "const T* __restrict__ M, T bx, T by, T bz, T& gx, T& gy, T& gz) {")
     for P in range(PMAX + 1):
@@ -353,7 +414,7 @@ def main(out_path):
     parts.append("  }")
     parts.append("}")
     parts.append("")
-    parts.append("template <int P, typename T>")
+    parts.append("template <int P, typename T, bool K1 = false>")
     parts.append("__device__ __forceinline__ void expansion_cell_adj(T X, T Y, T Z, T e2, "
                  "T bx, T by, T bz, T* row) {")
     for P in range(PMAX + 1):

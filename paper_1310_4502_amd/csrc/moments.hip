@@ -91,7 +91,25 @@ __device__ __forceinline__ void m2m_order(const double* __restrict__ mom, int nm
   for (int k = 0; k < K; ++k) out[off + k] = acc[k];
 }
 
-// grid.y = order; leaves only (P2M)
+// Blocks of the P2M and M2M kernels: one order of one run of kB cells each.
+// The orders of a run are consecutive blocks that land on one XCD (blocks are
+// dealt round-robin to the 8 XCDs, each with its own L2), so the run's
+// particles or children are fetched from HBM once and re-read from that L2
+// for the other orders: block b = 8 (p + 1) q + 8 o + x serves order o of
+// cell run 8 q + x.
+constexpr int kXcds = 8;
+__host__ __device__ inline unsigned order_grid(int64_t runs, int p) {
+  return (unsigned)(((runs + kXcds - 1) / kXcds) * kXcds * (p + 1));
+}
+__device__ inline void order_block(int p, int64_t& run, int& ord) {
+  const int64_t b = blockIdx.x;
+  const int64_t grp = kXcds * (p + 1);
+  const int64_t rem = b % grp;
+  ord = (int)(rem / kXcds);
+  run = (b / grp) * kXcds + rem % kXcds;
+}
+
+// leaves only (P2M)
 __global__ __launch_bounds__(kB) void k_p2m(int64_t C, const int32_t* __restrict__ c_first,
                                             const int32_t* __restrict__ c_count,
                                             const uint8_t* __restrict__ c_leaf,
@@ -99,13 +117,16 @@ __global__ __launch_bounds__(kB) void k_p2m(int64_t C, const int32_t* __restrict
                                             const double* __restrict__ spos,
                                             const double* __restrict__ smass, int64_t n, int p,
                                             double* __restrict__ mom) {
-  const int64_t c = (int64_t)blockIdx.x * kB + threadIdx.x;
+  int64_t run;
+  int ord;
+  order_block(p, run, ord);
+  const int64_t c = run * kB + threadIdx.x;
   if (c >= C || !c_leaf[c]) return;
   const int nmv = nm(p);
   double* out = mom + c * nmv;
   const double cc[3] = {c_centre[3 * c], c_centre[3 * c + 1], c_centre[3 * c + 2]};
   const int f = c_first[c], cnt = c_count[c];
-  switch (blockIdx.y) {
+  switch (ord) {
     case 0: p2m_order<0>(spos, smass, n, f, cnt, cc, out); break;
     case 1: p2m_order<1>(spos, smass, n, f, cnt, cc, out); break;
     case 2: p2m_order<2>(spos, smass, n, f, cnt, cc, out); break;
@@ -118,19 +139,22 @@ __global__ __launch_bounds__(kB) void k_p2m(int64_t C, const int32_t* __restrict
   }
 }
 
-// one level of internal cells [c0, c1); grid.y = order
+// one level of internal cells [c0, c1)
 __global__ __launch_bounds__(kB) void k_m2m(int64_t c0, int64_t c1, const int32_t* __restrict__ c_child,
                                             const int32_t* __restrict__ c_nchild,
                                             const uint8_t* __restrict__ c_leaf,
                                             const double* __restrict__ c_centre, int p,
                                             double* __restrict__ mom) {
-  const int64_t c = c0 + (int64_t)blockIdx.x * kB + threadIdx.x;
+  int64_t run;
+  int ord;
+  order_block(p, run, ord);
+  const int64_t c = c0 + run * kB + threadIdx.x;
   if (c >= c1 || c_leaf[c]) return;
   const int nmv = nm(p);
   double* out = mom + c * nmv;
   const double cp[3] = {c_centre[3 * c], c_centre[3 * c + 1], c_centre[3 * c + 2]};
   const int cf = c_child[c], nc = c_nchild[c];
-  switch (blockIdx.y) {
+  switch (ord) {
     case 0: m2m_order<0>(mom, nmv, cf, nc, c_centre, cp, out); break;
     case 1: m2m_order<1>(mom, nmv, cf, nc, c_centre, cp, out); break;
     case 2: m2m_order<2>(mom, nmv, cf, nc, c_centre, cp, out); break;
@@ -265,8 +289,7 @@ void build_moments(hot_ctx* ctx, hot_tree* t, const double* pos, const double* m
   t->mom64.alloc(ctx, (size_t)C * nm(p) * sizeof(double));
   t->p = -1;
   {
-    dim3 grid(grid_for(C, kB), p + 1);
-    k_p2m<<<grid, kB, 0, st>>>(C, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+    k_p2m<<<order_grid(grid_for(C, kB), p), kB, 0, st>>>(C, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
                                t->c_leaf.as<uint8_t>(), t->c_centre.as<double>(),
                                spos.as<double>(), smass.as<double>(), n, p,
                                t->mom64.as<double>());
@@ -275,8 +298,7 @@ void build_moments(hot_ctx* ctx, hot_tree* t, const double* pos, const double* m
   for (int L = t->max_level - 1; L >= 0; --L) {
     const int64_t c0 = t->level_off[L], c1 = t->level_off[L + 1];
     if (c1 <= c0) continue;
-    dim3 grid(grid_for(c1 - c0, kB), p + 1);
-    k_m2m<<<grid, kB, 0, st>>>(c0, c1, t->c_child.as<int32_t>(), t->c_nchild.as<int32_t>(),
+    k_m2m<<<order_grid(grid_for(c1 - c0, kB), p), kB, 0, st>>>(c0, c1, t->c_child.as<int32_t>(), t->c_nchild.as<int32_t>(),
                                t->c_leaf.as<uint8_t>(), t->c_centre.as<double>(), p,
                                t->mom64.as<double>());
     HOT_CHECK_LAUNCH();

@@ -11,20 +11,30 @@ inline double hot_rsq(double x) { return 1.0 / std::sqrt(x); }
 #include "expansions.h"
 
 template <int P>
-static void fwd(const double* M, const double* R, double e2, double* out) {
+static void fwd(int k1, const double* M, const double* R, double e2, double* out) {
   double ax = 0, ay = 0, az = 0, ph = 0;
-  hot::expansion_fwd<P, double, true>(R[0], R[1], R[2], e2, M, ax, ay, az, ph);
+  if (k1)
+    hot::expansion_fwd<P, double, true, true>(R[0], R[1], R[2], e2, M, ax, ay, az, ph);
+  else
+    hot::expansion_fwd<P, double, true>(R[0], R[1], R[2], e2, M, ax, ay, az, ph);
   out[0] = ax, out[1] = ay, out[2] = az, out[3] = ph;
 }
 template <int P>
-static void sink(const double* M, const double* R, double e2, const double* b, double* g) {
+static void sink(int k1, const double* M, const double* R, double e2, const double* b, double* g) {
   double gx = 0, gy = 0, gz = 0;
-  hot::expansion_sink_adj<P, double>(R[0], R[1], R[2], e2, M, b[0], b[1], b[2], gx, gy, gz);
+  if (k1)
+    hot::expansion_sink_adj<P, double, true>(R[0], R[1], R[2], e2, M, b[0], b[1], b[2], gx, gy,
+                                             gz);
+  else
+    hot::expansion_sink_adj<P, double>(R[0], R[1], R[2], e2, M, b[0], b[1], b[2], gx, gy, gz);
   g[0] = gx, g[1] = gy, g[2] = gz;
 }
 template <int P>
-static void cell(const double* R, double e2, const double* b, double* row) {
-  hot::expansion_cell_adj<P, double>(R[0], R[1], R[2], e2, b[0], b[1], b[2], row);
+static void cell(int k1, const double* R, double e2, const double* b, double* row) {
+  if (k1)
+    hot::expansion_cell_adj<P, double, true>(R[0], R[1], R[2], e2, b[0], b[1], b[2], row);
+  else
+    hot::expansion_cell_adj<P, double>(R[0], R[1], R[2], e2, b[0], b[1], b[2], row);
 }
 
 #define DISPATCH(F, ...)                 \
@@ -41,14 +51,16 @@ static void cell(const double* R, double e2, const double* b, double* row) {
   }
 
 extern "C" {
-void shim_fwd(int p, const double* M, const double* R, double e2, double* out) {
-  DISPATCH(fwd, M, R, e2, out);
+// k1: Dehnen's K1 softening with kernel radius sqrt(e2); else Plummer
+void shim_fwd(int p, int k1, const double* M, const double* R, double e2, double* out) {
+  DISPATCH(fwd, k1, M, R, e2, out);
 }
-void shim_sink(int p, const double* M, const double* R, double e2, const double* b, double* g) {
-  DISPATCH(sink, M, R, e2, b, g);
+void shim_sink(int p, int k1, const double* M, const double* R, double e2, const double* b,
+               double* g) {
+  DISPATCH(sink, k1, M, R, e2, b, g);
 }
-void shim_cell(int p, const double* R, double e2, const double* b, double* row) {
-  DISPATCH(cell, R, e2, b, row);
+void shim_cell(int p, int k1, const double* R, double e2, const double* b, double* row) {
+  DISPATCH(cell, k1, R, e2, b, row);
 }
 void shim_p2m(int N, double dx, double dy, double dz, double m, double* acc) {
   switch (N) {

@@ -24,9 +24,10 @@ def shim(tmp_path_factory):
     L = ctypes.CDLL(out)
     for f in ("shim_fwd", "shim_sink", "shim_cell", "shim_p2m", "shim_m2m"):
         getattr(L, f).restype = None
-    L.shim_fwd.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
-    L.shim_sink.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
-    L.shim_cell.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    i32 = ctypes.c_int
+    L.shim_fwd.argtypes = [i32, i32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
+    L.shim_sink.argtypes = [i32, i32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    L.shim_cell.argtypes = [i32, i32, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
     L.shim_p2m.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [ctypes.c_void_p]
     L.shim_m2m.argtypes = [ctypes.c_int, ctypes.c_void_p] + [ctypes.c_double] * 3 + [ctypes.c_void_p]
     return L
@@ -42,20 +43,27 @@ def weights(orc, p):
 
 
 @pytest.mark.parametrize("p", range(9))
-@pytest.mark.parametrize("eps", [0.0, 0.4])
-def test_forward_matches_oracle(orc, shim, p, eps):
+@pytest.mark.parametrize("kernel,eps", [("plummer", 0.0), ("plummer", 0.4), ("k1", 2.5)])
+def test_forward_matches_oracle(orc, shim, p, kernel, eps):
+    """Plummer, and K1 with a kernel radius that half of the evaluation points
+    fall inside (the quartic radial functions) and half outside (Newtonian)."""
     rng = np.random.default_rng(p)
     pts = rng.random((30, 3)) - 0.5
     m = rng.random(30)
     M = orc.p2m(p, pts, m, np.zeros(3))
     Mw = M * weights(orc, p)
-    for _ in range(5):
-        R = rng.normal(size=3) * 3
+    k1 = int(kernel == "k1")
+    inside = 0
+    for k in range(8):
+        R = rng.normal(size=3) * (3 if k % 2 == 0 else 0.8)
+        inside += int(np.dot(R, R) < eps * eps) if k1 else 0
         out = np.zeros(4)
-        shim.shim_fwd(p, P(Mw), P(R), eps * eps, P(out))
-        a, phi = orc.m2p(p, M, R, eps)
+        shim.shim_fwd(p, k1, P(Mw), P(R), eps * eps, P(out))
+        a, phi = orc.m2p(p, M, R, eps, kernel=kernel)
         assert np.allclose(-out[:3], a, rtol=1e-12, atol=1e-14 * np.abs(a).max())
         assert abs(out[3] - phi) <= 1e-12 * abs(phi)
+    if k1:
+        assert 0 < inside < 8, inside
 
 
 @pytest.mark.parametrize("p", range(9))
@@ -65,10 +73,13 @@ def test_adjoint_parts_match_oracle_derivatives(orc, shim, p):
     al = orc.multi_indices(p)
     Mw = rng.normal(size=len(al))
     E = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
-    for eps in (0.0, 0.3):
-        R = rng.normal(size=3) * 2.5
+    for kernel, eps, scale in (("plummer", 0.0, 2.5), ("plummer", 0.3, 2.5), ("k1", 1.5, 0.5),
+                               ("k1", 0.6, 2.5)):
+        # K1 at 0.5 x N(0,1) inside a radius of 1.5, at 2.5 x N(0,1) mostly outside 0.6
+        k1 = int(kernel == "k1")
+        R = rng.normal(size=3) * scale
         b = rng.normal(size=3)
-        D = orc.derivs(p + 2, R, eps)
+        D = orc.derivs(p + 2, R, eps, kernel=kernel)
         # sink part: g_l = sum_k b_k sum_alpha Mw[alpha] d^(alpha+e_k+e_l) G
         ref = np.zeros(3)
         for l in range(3):
@@ -77,13 +88,13 @@ def test_adjoint_parts_match_oracle_derivatives(orc, shim, p):
                     t = tuple(a[q] + E[k][q] + E[l][q] for q in range(3))
                     ref[l] += b[k] * Mw[s] * D[idx[t]]
         g = np.zeros(3)
-        shim.shim_sink(p, P(Mw), P(R), eps * eps, P(b), P(g))
+        shim.shim_sink(p, k1, P(Mw), P(R), eps * eps, P(b), P(g))
         assert np.allclose(g, ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
         # cell part: row[alpha] += sum_k b_k d^(alpha+e_k) G
         refc = np.array([sum(b[k] * D[idx[tuple(a[q] + E[k][q] for q in range(3))]] for k in range(3))
                          for a in al])
         row = np.full(len(al), 0.25)
-        shim.shim_cell(p, P(R), eps * eps, P(b), P(row))
+        shim.shim_cell(p, k1, P(R), eps * eps, P(b), P(row))
         assert np.allclose(row - 0.25, refc, rtol=1e-11, atol=1e-13 * np.abs(refc).max())
 
 
