@@ -10,7 +10,7 @@ import torch
 import oracle
 from paper_1310_4502_amd import workloads as W
 from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, Tree
-from gpu_util import build_both, rel_rms, to_dev
+from gpu_util import SINK_TOL_FP64, SINK_TOL_MIXED, assert_sinks, build_both, rel_rms, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -43,11 +43,15 @@ def test_adjoint_vs_oracle_vjp(name, n, p, theta, dmax, n_leaf, n_group):
     m64 = rel_rms(gm64.cpu().numpy(), om)
     _log("fp64 xbar", e64, "mbar", m64)
     assert e64 <= 1e-11 and m64 <= 1e-11
+    assert_sinks(gx64.cpu().numpy(), ox, SINK_TOL_FP64, "xbar fp64")
+    assert_sinks(gm64.cpu().numpy(), om, SINK_TOL_FP64, "mbar fp64")
     gx, gm = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED, with_mass=True)
     e32 = rel_rms(gx.cpu().numpy(), ox)
     m32 = rel_rms(gm.cpu().numpy(), om)
     _log("mixed xbar", e32, "mbar", m32)
     assert e32 <= 1e-5 and m32 <= 1e-5
+    _log("per-sink max xbar", assert_sinks(gx.cpu().numpy(), ox, SINK_TOL_MIXED, "xbar mixed"),
+         "mbar", assert_sinks(gm.cpu().numpy(), om, SINK_TOL_MIXED, "mbar mixed"))
     # deterministic
     gx2, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED)
     assert torch.equal(gx, gx2)
@@ -106,6 +110,9 @@ def test_adjoint_source_units_and_packed_runs():
     _log("fp64 xbar", e64, "mbar", m64, "mixed xbar", e32, "mbar", m32)
     assert e64 <= 1e-11 and m64 <= 1e-11
     assert e32 <= 1e-5 and m32 <= 1e-5
+    assert_sinks(gx64.cpu().numpy(), ox, SINK_TOL_FP64, "xbar fp64")
+    assert_sinks(gx.cpu().numpy(), ox, SINK_TOL_MIXED, "xbar mixed")
+    assert_sinks(gm.cpu().numpy(), om, SINK_TOL_MIXED, "mbar mixed")
 
 
 def test_adjoint_directional_fd():

@@ -13,7 +13,8 @@ import torch
 
 import oracle
 from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
-from gpu_util import assert_lists_equal, rel_rms
+from gpu_util import (SINK_TOL_FP64, SINK_TOL_MIXED, KAPPA_C_FP64, KAPPA_C_MIXED, assert_sinks,
+                      assert_sinks_kappa, assert_lists_equal, rel_rms)
 
 pytestmark = pytest.mark.gpu
 
@@ -78,13 +79,15 @@ def test_bs_lists_boxes_and_forces(kind, size, a, p, theta, dmax, n_leaf, n_grou
     gt.compute_moments(pos, mass, p)
     ot.compute_moments(pos_np, mass_np, p)
     ts = np.sort(np.random.default_rng(2).choice(n, 512, replace=False))
-    oa, _, _ = ot.eval(pos_np, mass_np, eps, sinks=ts, with_pot=False)
+    oa, ab, cs = ot.eval_abs(pos_np, mass_np, eps, sinks=ts, cond=True)
     g64, _, _ = gt.eval_forces(pos, mass, eps, HOT_FP64)
     g32, _, _ = gt.eval_forces(pos, mass, eps, HOT_MIXED)
     e64 = rel_rms(g64.cpu().numpy()[ts], oa)
     e32 = rel_rms(g32.cpu().numpy()[ts], oa)
     _log("vs oracle treecode: fp64", e64, "mixed", e32)
     assert e64 <= 1e-11 and e32 <= 1e-5
+    assert_sinks_kappa(g64.cpu().numpy()[ts], oa, cs, KAPPA_C_FP64, "fp64")
+    assert_sinks_kappa(g32.cpu().numpy()[ts], oa, cs, KAPPA_C_MIXED, "mixed")
 
 
 def test_bs_gain_in_near_uniform_volume():
@@ -176,6 +179,8 @@ def test_bs_adjoint_vs_oracle_vjp(kind, size, a, p, theta, dmax, n_leaf, n_group
          rel_rms(gx.cpu().numpy(), ox), rel_rms(gm.cpu().numpy(), om)]
     _log(kind, n, "bs adjoint vs oracle VJP: fp64", r[:2], "mixed", r[2:])
     assert max(r[:2]) <= 1e-11 and max(r[2:]) <= 1e-5
+    assert_sinks(gx64.cpu().numpy(), ox, SINK_TOL_FP64, "xbar fp64")
+    assert_sinks(gx.cpu().numpy(), ox, SINK_TOL_MIXED, "xbar mixed")
     rng = np.random.default_rng(47)
     v = torch.from_numpy(rng.normal(size=pos_np.shape)).cuda()
     dm = torch.from_numpy(rng.normal(size=mass_np.shape) * mass_np).cuda()

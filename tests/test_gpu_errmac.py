@@ -11,7 +11,8 @@ import torch
 import oracle
 from paper_1310_4502_amd import workloads as W
 from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
-from gpu_util import assert_lists_equal, rel_rms, to_dev
+from gpu_util import (SINK_TOL_FP64, SINK_TOL_MIXED, KAPPA_C_FP64, KAPPA_C_MIXED, assert_sinks,
+                      assert_sinks_kappa, assert_lists_equal, rel_rms, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -49,13 +50,16 @@ def test_lists_orders_forces_bit_exact_and_close(name, n, tol, p_max, dmax, n_le
     assert np.unique(gq).size >= 2
     gt.compute_moments(pos, mass, p_max)
     ot.compute_moments(w.pos, w.mass, p_max)
-    oa, _, _ = ot.eval(w.pos, w.mass, w.eps, with_pot=False)
+    oa, ab, cs = ot.eval_abs(w.pos, w.mass, w.eps, cond=True)
     g64, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_FP64)
     g32, _, _ = gt.eval_forces(pos, mass, w.eps, HOT_MIXED)
     e64 = rel_rms(g64.cpu().numpy(), oa)
     e32 = rel_rms(g32.cpu().numpy(), oa)
     _log("fp64", e64, "mixed", e32)
     assert e64 <= 1e-12 and e32 <= 1e-5
+    _log("per-sink error / term scale: fp64",
+         assert_sinks_kappa(g64.cpu().numpy(), oa, cs, KAPPA_C_FP64, "fp64"),
+         "mixed", assert_sinks_kappa(g32.cpu().numpy(), oa, cs, KAPPA_C_MIXED, "mixed"))
     # the accuracy the bound promises: against direct summation on sampled
     # sinks, no sink is off by more than tol times its number of M2P entries
     # plus the pair kernel's rounding (softened fields: the unsoftened bound
@@ -83,6 +87,8 @@ def test_adjoint_vs_oracle_vjp(name, n, tol, p_max, dmax, n_leaf, n_group):
     _log("adjoint fp64", e64, m64, "mixed", e32, m32)
     assert e64 <= 1e-11 and m64 <= 1e-11
     assert e32 <= 1e-5 and m32 <= 1e-5
+    assert_sinks(gx64.cpu().numpy(), ox, SINK_TOL_FP64, "xbar fp64")
+    assert_sinks(gx.cpu().numpy(), ox, SINK_TOL_MIXED, "xbar mixed")
     gx2, _ = gt.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED)
     assert torch.equal(gx, gx2)
 
@@ -134,6 +140,6 @@ def test_state_and_argument_errors():
     bad[5] = -1.0
     with pytest.raises(HotError):
         t.build_interaction_lists_err(bad, 1e-3, 4, 0)
-    with pytest.raises(HotError):
-        t.ctx.sync()  # the flag is also reported by the next synchronising call
-    t.ctx.sync()  # flags cleared
+    # a synchronous call reports what it found itself, once: nothing is left
+    # deferred for the next synchronising call
+    t.ctx.sync()

@@ -18,8 +18,9 @@ import oracle
 from paper_1310_4502_amd import workloads as W
 from paper_1310_4502_amd.binding import (HOT_FP64, HOT_MIXED, HotError, Tree, Context,
                                          HOT_E_INVALID, HOT_E_STATE, HOT_E_OOM)
-from gpu_util import (assert_lists_equal, assert_moments_close, assert_tree_equal, build_both,
-                      rel_rms, to_dev)
+from gpu_util import (KAPPA_C_FP64, KAPPA_C_MIXED, SINK_TOL_FP64, SINK_TOL_MIXED,
+                      assert_lists_equal, assert_moments_close, assert_sinks, assert_sinks_kappa,
+                      assert_tree_equal, build_both, rel_rms, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +72,7 @@ def test_tree_lists_moments_bitexact(name, n):
     assert_lists_equal(gt, ot)
     ot.compute_moments(w.pos, w.mass, p)
     gm, om = gt.moments(), ot.moments()
-    assert_moments_close(gm, om, gt.cells()["count"])
+    assert_moments_close(gm, om, gt.cells()["count"], log=_log)
     # hash table: every cell key finds its cell; absent keys find nothing
     c = gt.cells()
     assert np.array_equal(gt.lookup(c["key"]), np.arange(len(c["key"]), dtype=np.int32))
@@ -101,20 +102,26 @@ def test_forces_vs_oracle_tree(name, n, p, with_pot):
     gt, ot, pos, mass, p = build_both(w, p=p)
     ot.compute_moments(w.pos, w.mass, p)
     oa, op, ocnt = ot.eval(w.pos, w.mass, w.eps)
+    _, ab, cs = ot.eval_abs(w.pos, w.mass, w.eps, cond=True)
     ga, gp, st = gt.eval_forces(pos, mass, w.eps, HOT_MIXED, with_pot=with_pot, stats=True)
     ga = ga.cpu().numpy()
     err = rel_rms(ga, oa)
     _log(name, w.n, "p", p, "mixed rel rms vs oracle tree", err)
     assert err <= 1e-5
+    _log(name, "mixed per-sink error / term scale",
+         assert_sinks_kappa(ga, oa, cs, KAPPA_C_MIXED, "mixed"))
     assert st.p2p_pairs == ocnt[0] and st.m2p_pairs == ocnt[1]
     if with_pot:
         assert rel_rms(gp.cpu().numpy(), op) <= 1e-5
+        assert_sinks(gp.cpu().numpy(), op, SINK_TOL_MIXED, "mixed potential")
     ga64, gp64, _ = gt.eval_forces(pos, mass, w.eps, HOT_FP64, with_pot=with_pot)
     err64 = rel_rms(ga64.cpu().numpy(), oa)
     _log(name, "fp64 rel rms vs oracle tree", err64)
     assert err64 <= 1e-12
+    assert_sinks_kappa(ga64.cpu().numpy(), oa, cs, KAPPA_C_FP64, "fp64")
     if with_pot:
         assert rel_rms(gp64.cpu().numpy(), op) <= 1e-12
+        assert_sinks(gp64.cpu().numpy(), op, SINK_TOL_FP64, "fp64 potential")
 
 
 def test_forces_vs_direct_paper_level():
@@ -142,8 +149,9 @@ def test_deterministic_and_replay():
     gt.compute_moments(p2, mass, p)
     ga, _, _ = gt.eval_forces(p2, mass, w.eps, HOT_FP64)
     ot.compute_moments(pos2, w.mass, p)
-    oa, _, _ = ot.eval(pos2, w.mass, w.eps)
+    oa, ab, cs = ot.eval_abs(pos2, w.mass, w.eps, cond=True)
     assert rel_rms(ga.cpu().numpy(), oa) <= 1e-12
+    assert_sinks_kappa(ga.cpu().numpy(), oa, cs, KAPPA_C_FP64, "replay fp64")
     # rebuilding gives the identical tree and result
     gt2 = Tree(pos, w.n_leaf, w.n_group, w.box)
     gt2.build_interaction_lists(w.theta, 0)
@@ -157,11 +165,12 @@ def test_eps_zero_and_coincident():
     w.eps = 0.0
     gt, ot, pos, mass, p = build_both(w, p=3)
     ot.compute_moments(w.pos, w.mass, p)
-    oa, _, _ = ot.eval(w.pos, w.mass, 0.0)
+    oa, ab, cs = ot.eval_abs(w.pos, w.mass, 0.0, cond=True)
     ga, _, _ = gt.eval_forces(pos, mass, 0.0, HOT_FP64)
     ga = ga.cpu().numpy()
     assert np.all(np.isfinite(ga))
     assert rel_rms(ga, oa) <= 1e-12
+    assert_sinks_kappa(ga, oa, cs, KAPPA_C_FP64, "eps 0 fp64")
 
 
 def test_argument_and_state_errors():
@@ -311,3 +320,8 @@ def test_small_items_sliced(p):
     _log("forces mixed", e32, "fp64", e64, "adjoint mixed", a32, "fp64", a64)
     assert e32 <= 1e-5 and e64 <= 1e-12
     assert a32 <= 1e-5 and a64 <= 1e-11
+    _, ab, cs = ot.eval_abs(w.pos, w.mass, w.eps, cond=True)
+    assert_sinks_kappa(ga, oa, cs, KAPPA_C_MIXED, "forces mixed")
+    assert_sinks_kappa(ga64.cpu().numpy(), oa, cs, KAPPA_C_FP64, "forces fp64")
+    assert_sinks(gx, ox, SINK_TOL_MIXED, "adjoint mixed")
+    assert_sinks(gx64.cpu().numpy(), ox, SINK_TOL_FP64, "adjoint fp64")

@@ -13,7 +13,8 @@ import torch
 import oracle
 from paper_1310_4502_amd import workloads as W
 from paper_1310_4502_amd.binding import HOT_FP64, HOT_MIXED, HotError, Tree
-from gpu_util import assert_lists_equal, rel_rms
+from gpu_util import (SINK_TOL_FP64, SINK_TOL_MIXED, KAPPA_C_FP64, KAPPA_C_MIXED, assert_sinks,
+                      assert_sinks_kappa, assert_lists_equal, rel_rms)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,13 +66,18 @@ def test_periodic_lists_and_forces(name, n, p, theta, dmax, n_leaf, n_group):
     gt.compute_moments(pos, mass, p)
     ot.compute_moments(pos_np, mass_np, p)
     ts = np.sort(np.random.default_rng(2).choice(n, 768, replace=False))
-    oa, _, _ = ot.eval(pos_np, mass_np, eps, sinks=ts, with_pot=False)
+    oa, ab, cs = ot.eval_abs(pos_np, mass_np, eps, sinks=ts, cond=True)
     g64, _, _ = gt.eval_forces(pos, mass, eps, HOT_FP64)
     g32, _, _ = gt.eval_forces(pos, mass, eps, HOT_MIXED)
     e64 = rel_rms(g64.cpu().numpy()[ts], oa)
     e32 = rel_rms(g32.cpu().numpy()[ts], oa)
-    _log("vs oracle treecode: fp64", e64, "mixed", e32)
+    kap = ab / np.linalg.norm(oa, axis=1)
+    _log("vs oracle treecode: fp64", e64, "mixed", e32, "cancellation median / max",
+         float(np.median(kap)), float(kap.max()))
     assert e64 <= 1e-11 and e32 <= 1e-5
+    _log("per-sink error / term scale: fp64",
+         assert_sinks_kappa(g64.cpu().numpy()[ts], oa, cs, KAPPA_C_FP64, "fp64"),
+         "mixed", assert_sinks_kappa(g32.cpu().numpy()[ts], oa, cs, KAPPA_C_MIXED, "mixed"))
     sinks = np.sort(np.random.default_rng(3).choice(n, 48, replace=False))
     ad = oracle.ewald_direct(pos_np, mass_np, 1.0, eps, sinks=sinks)
     ed = rel_rms(g64.cpu().numpy()[sinks], ad)
@@ -127,6 +133,8 @@ def test_periodic_adjoint_vs_oracle_vjp(name, n, p, theta, dmax, n_leaf, n_group
     _log(name, n, "periodic adjoint fp64", e64, m64, "mixed", e32, m32)
     assert e64 <= 1e-11 and m64 <= 1e-11
     assert e32 <= 1e-5 and m32 <= 1e-5
+    assert_sinks(gx64.cpu().numpy(), ox, SINK_TOL_FP64, "xbar fp64")
+    assert_sinks(gx.cpu().numpy(), ox, SINK_TOL_MIXED, "xbar mixed")
     gx2, _ = gt.eval_forces_adjoint(pos, mass, eps, abar, HOT_MIXED)
     assert torch.equal(gx, gx2)
 
