@@ -177,8 +177,9 @@ __device__ __forceinline__ void box_field_grad(const double* __restrict__ lo,
   T[5] += sg * tyz;
 }
 
-// per sink: xbar += rho T^T abar (caller order), dpsi[i] = abar . (B + cf)
-// with B the unit-density box fields and cf the cube field of the expansions
+// per sink: xbar += rho T^T abar (caller order) and, where the mass cotangent
+// is wanted (dpsi non-null), dpsi[i] = abar . (B + cf) with B the unit-density
+// box fields and cf the cube field of the expansions
 __global__ __launch_bounds__(kB) void k_bg_boxes_adj(
     const int2* __restrict__ items, int64_t n_items, const int32_t* __restrict__ g_first,
     const int32_t* __restrict__ g_count, const int32_t* __restrict__ g_cell,
@@ -219,8 +220,9 @@ __global__ __launch_bounds__(kB) void k_bg_boxes_adj(
   xbar[3 * ci] += rho * ((T[0] * ax + T[3] * ay) + T[4] * az);
   xbar[3 * ci + 1] += rho * ((T[3] * ax + T[1] * ay) + T[5] * az);
   xbar[3 * ci + 2] += rho * ((T[4] * ax + T[5] * ay) + T[2] * az);
-  dpsi[ci] = ((ax * (f[0] + cf[3 * ci]) + ay * (f[1] + cf[3 * ci + 1])) +
-              az * (f[2] + cf[3 * ci + 2]));
+  if (dpsi)
+    dpsi[ci] = ((ax * (f[0] + cf[3 * ci]) + ay * (f[1] + cf[3 * ci + 1])) +
+                az * (f[2] + cf[3 * ci + 2]));
 }
 
 // deterministic sum: per block a fixed tree over a fixed grid-stride, then
@@ -264,10 +266,14 @@ void background_adjoint(hot_ctx* ctx, hot_tree* t, const double* pos, const doub
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
   DBuf cf, dpsi;
-  cf.alloc(ctx, n * 3 * sizeof(double));
-  dpsi.alloc(ctx, n * sizeof(double));
-  // the expansions' cubes scale with the mean density too
-  cube_field(ctx, t, pos, mass, eps, precision, cf.as<double>());
+  if (mbar) {
+    // the mean density's cotangent: the expansions' cubes scale with it too,
+    // so their field (an expansion pass over the flagged entries) is needed
+    // only when the mass cotangent is asked for
+    cf.alloc(ctx, n * 3 * sizeof(double));
+    dpsi.alloc(ctx, n * sizeof(double));
+    cube_field(ctx, t, pos, mass, eps, precision, cf.as<double>());
+  }
   k_bg_boxes_adj<<<grid_for(t->n_items, kWavesPerBlock), kB, 0, st>>>(
       t->items.as<int2>(), t->n_items, t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
       t->g_cell.as<int32_t>(), t->c_centre.as<double>(), t->c_level.as<int8_t>(),

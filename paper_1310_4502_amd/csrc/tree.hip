@@ -318,50 +318,81 @@ __global__ void k_links(const uint64_t* __restrict__ c_key, const int8_t* __rest
 
 // Squared b_max of every cell: for each level, the particles of a wave that
 // share a level-L cell reduce their squared distance to its centre with a
-// segmented max, and the last lane of each run does one atomic max (on the
-// bits of a non-negative double, which order like unsigned integers).
+// segmented max, and the last lane of each run does one max (on the bits of a
+// non-negative double, which order like unsigned integers). Each block takes
+// a contiguous chunk of particles; the cells of the top kBmaxTop levels (at
+// most 585, where every wave of the chunk would hit the same few addresses)
+// are reduced in LDS slots indexed by their key bits and written with one
+// global atomic per block and cell; deeper cells take a global atomic per run.
+constexpr int kBmaxTop = 4;
+constexpr int kBmaxSlots = (1 + 8 + 64 + 512);
+__device__ __forceinline__ int bmax_slot(uint64_t P, int L) {
+  // (8^L - 1) / 7 slots for the levels above, then the L x 3 key bits
+  return (int)(((1u << (3 * L)) - 1u) / 7u) + (int)(P & ((1ull << (3 * L)) - 1ull));
+}
 __global__ __launch_bounds__(kB) void k_bmax(const uint64_t* __restrict__ key,
                                              const uint8_t* __restrict__ lam,
                                              const double* __restrict__ spos, int64_t n,
-                                             const double* __restrict__ root,
+                                             int64_t chunk, const double* __restrict__ root,
                                              const uint64_t* __restrict__ hk,
                                              const int32_t* __restrict__ hv, uint64_t mask,
                                              unsigned long long* __restrict__ bmax2) {
-  const int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
+  __shared__ unsigned long long top[kBmaxSlots];
+  for (int q = threadIdx.x; q < kBmaxSlots; q += kB) top[q] = 0ull;
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const bool valid = j < n;
-  const uint64_t k = valid ? key[j] : 0ull;
-  const int lmb = valid ? (int)lam[j] : -1;
-  double x = 0, y = 0, z = 0;
-  if (valid) {
-    x = spos[j];
-    y = spos[n + j];
-    z = spos[2 * n + j];
-  }
-  for (int L = 0; L <= kMaxLevel; ++L) {
-    const bool has = L <= lmb;
-    if (!__any(has)) break;
-    const unsigned long long P = has ? (k >> (3 * (kMaxLevel - L))) : 0ull;
-    unsigned long long v = 0;
-    if (has) {
-      double c[3];
-      cell_centre(P, L, root, c);
-      const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
-      const double d2 = (dx * dx + dy * dy) + dz * dz;
-      v = (unsigned long long)__double_as_longlong(d2);
+  const int64_t j0 = (int64_t)blockIdx.x * chunk;
+  const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+  for (int64_t jb = j0; jb < j1; jb += kB) {
+    const int64_t j = jb + threadIdx.x;
+    const bool valid = j < j1;
+    const uint64_t k = valid ? key[j] : 0ull;
+    const int lmb = valid ? (int)lam[j] : -1;
+    double x = 0, y = 0, z = 0;
+    if (valid) {
+      x = spos[j];
+      y = spos[n + j];
+      z = spos[2 * n + j];
     }
+    for (int L = 0; L <= kMaxLevel; ++L) {
+      const bool has = L <= lmb;
+      if (!__any(has)) break;
+      const unsigned long long P = has ? (k >> (3 * (kMaxLevel - L))) : 0ull;
+      unsigned long long v = 0;
+      if (has) {
+        double c[3];
+        cell_centre(P, L, root, c);
+        const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        v = (unsigned long long)__double_as_longlong(d2);
+      }
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const unsigned long long Pn = __shfl_up(P, off);
-      const unsigned long long vn = __shfl_up(v, off);
-      if (lane >= off && Pn == P && vn > v) v = vn;
+      for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long Pn = __shfl_up(P, off);
+        const unsigned long long vn = __shfl_up(v, off);
+        if (lane >= off && Pn == P && vn > v) v = vn;
+      }
+      const unsigned long long Pnext = __shfl_down(P, 1);
+      const bool last = (lane == 63) || (Pnext != P) || (j + 1 >= j1);
+      if (has && last) {
+        if (L < kBmaxTop) {
+          atomicMax(&top[bmax_slot(P, L)], v);
+        } else {
+          const int32_t c = hash_find(hk, hv, mask, P);
+          if (c >= 0) atomicMax(&bmax2[c], v);
+        }
+      }
     }
-    const unsigned long long Pnext = __shfl_down(P, 1);
-    const bool last = (lane == 63) || (Pnext != P) || (j + 1 >= n);
-    if (has && last) {
-      const int32_t c = hash_find(hk, hv, mask, P);
-      if (c >= 0) atomicMax(&bmax2[c], v);
-    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kBmaxSlots; q += kB) {
+    const unsigned long long v = top[q];
+    if (v == 0ull) continue;
+    int L = 0;
+    while (L + 1 < kBmaxTop && q >= (int)(((1u << (3 * (L + 1))) - 1u) / 7u)) ++L;
+    const uint64_t P = (1ull << (3 * L)) | (uint64_t)(q - (int)(((1u << (3 * L)) - 1u) / 7u));
+    const int32_t c = hash_find(hk, hv, mask, P);
+    if (c >= 0) atomicMax(&bmax2[c], v);
   }
 }
 
@@ -566,10 +597,15 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   // ---- b_max
   k_fill<uint64_t><<<gc, kB, 0, st>>>(t->c_bmax2.as<uint64_t>(), C, 0ull);
   HOT_CHECK_LAUNCH();
-  k_bmax<<<gb, kB, 0, st>>>(t->key.as<uint64_t>(), t->lambda.as<uint8_t>(), t->spos.as<double>(),
-                           n, t->root.as<double>(), t->h_keys.as<uint64_t>(),
-                           t->h_vals.as<int32_t>(), slots - 1,
-                           t->c_bmax2.as<unsigned long long>());
+  {
+    // chunks of at least 4096 particles, at most 2048 blocks
+    const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(2048, (n + 4095) / 4096));
+    const int64_t chunk = ((n + nblk - 1) / nblk + kB - 1) / kB * kB;
+    k_bmax<<<(unsigned)nblk, kB, 0, st>>>(t->key.as<uint64_t>(), t->lambda.as<uint8_t>(),
+                                          t->spos.as<double>(), n, chunk, t->root.as<double>(),
+                                          t->h_keys.as<uint64_t>(), t->h_vals.as<int32_t>(),
+                                          slots - 1, t->c_bmax2.as<unsigned long long>());
+  }
   HOT_CHECK_LAUNCH();
   k_bmax_final<<<gc, kB, 0, st>>>(t->c_bmax2.as<unsigned long long>(), C, t->c_bmax.as<double>());
   HOT_CHECK_LAUNCH();
