@@ -339,6 +339,8 @@ __device__ __forceinline__ void image_shift(int img, double side, double& sx, do
   sz = (double)(img % 5 - 2) * side;
 }
 constexpr int kCentreImage = 62;  // n = (0, 0, 0)
+// sources summed in plain FP32 between two compensated adds of a pair kernel
+constexpr int kSumRun = 256;
 
 // ------------------------------------------------------- pair terms, sink side
 // state per sorted particle: s_x s_y s_z - c_x c_y c_z -
@@ -389,6 +391,29 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
   const T a3Ax = T(3) * bA.x, a3Ay = T(3) * bA.y, a3Az = T(3) * bA.z;
   const T a3Bx = T(3) * bB.x, a3By = T(3) * bB.y, a3Bz = T(3) * bB.z;
   T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
+  // per sink: sum m inv3 ; sum 3 m (r.ab) inv5 r, in plain FP32 over
+  // consecutive segments until at least kSumRun sources are summed, then the
+  // halves are added (lane l < 32 completes sink A, lane l >= 32 sink B) and
+  // xbar_i -= m_j H ab = -(sum m inv3) ab + sum 3 m rd inv5 r goes into the
+  // compensated sums with one compensated add
+  T pA = 0, qAx = 0, qAy = 0, qAz = 0;
+  T pB = 0, qBx = 0, qBy = 0, qBz = 0;
+  T mseg = T(1);
+  int n_acc = 0;
+#define HOT_SINK_FLUSH                                                               \
+  {                                                                                  \
+    const T kp = (h ? pB : pA) + __shfl_xor(h ? pA : pB, 32);                        \
+    const T kx = (h ? qBx : qAx) + __shfl_xor(h ? qAx : qBx, 32);                    \
+    const T ky = (h ? qBy : qAy) + __shfl_xor(h ? qAy : qBy, 32);                    \
+    const T kz = (h ? qBz : qAz) + __shfl_xor(h ? qAz : qBz, 32);                    \
+    const V4<T> ab = h ? bB : bA;                                                    \
+    kahan_add(sx, cx, hot_fma(-kp, ab.x, kx) * mseg);                                \
+    kahan_add(sy, cy, hot_fma(-kp, ab.y, ky) * mseg);                                \
+    kahan_add(sz, cz, hot_fma(-kp, ab.z, kz) * mseg);                                \
+    pA = qAx = qAy = qAz = T(0);                                                     \
+    pB = qBx = qBy = qBz = T(0);                                                     \
+    n_acc = 0;                                                                       \
+  }
   const int64_t e1 = p2p_off[g + 1];
   int64_t e = p2p_off[g];
   while (e < e1) {
@@ -488,10 +513,6 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     }                                                                                \
   }
       const bool self = sg == g && im0 == kCentreImage;
-      // per sink: sum m inv3 ; sum 3 m (r.ab) inv5 r
-      T pA = 0, qAx = 0, qAy = 0, qAz = 0;
-      T pB = 0, qBx = 0, qBy = 0, qBz = 0;
-      T mseg = T(1);
       for (int jb = j; jb < jend; jb += 64) {
         const int nbt = jend - jb < 64 ? jend - jb : 64;
         V4<T> v;
@@ -515,20 +536,13 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
       }
 #undef HOT_SINK_BATCH
 #undef HOT_SINK_PAIR
-      // the halves' sums: lane l < 32 completes sink A, lane l >= 32 sink B
-      const T kp = (h ? pB : pA) + __shfl_xor(h ? pA : pB, 32);
-      const T kx = (h ? qBx : qAx) + __shfl_xor(h ? qAx : qBx, 32);
-      const T ky = (h ? qBy : qAy) + __shfl_xor(h ? qAy : qBy, 32);
-      const T kz = (h ? qBz : qAz) + __shfl_xor(h ? qAz : qBz, 32);
-      const V4<T> ab = h ? bB : bA;
-      // xbar_i -= m_j H ab = -(sum m inv3) ab + sum 3 m rd inv5 r, one
-      // compensated add per segment (at most n_group sources)
-      kahan_add(sx, cx, hot_fma(-kp, ab.x, kx) * mseg);
-      kahan_add(sy, cy, hot_fma(-kp, ab.y, ky) * mseg);
-      kahan_add(sz, cz, hot_fma(-kp, ab.z, kz) * mseg);
+      n_acc += jend - j;
+      if (n_acc >= kSumRun) HOT_SINK_FLUSH
       j = jend;
     }
   }
+  if (n_acc > 0) HOT_SINK_FLUSH
+#undef HOT_SINK_FLUSH
   if (active) {
     T* st = state + (int64_t)i * 8;
     st[0] = sx;
@@ -1229,10 +1243,12 @@ __global__ __launch_bounds__(kB) void k_m2mT(int64_t c0, int64_t c1,
                                              const double* __restrict__ c_centre,
                                              double* __restrict__ mbar) {
   constexpr int NMV = nm(P);
-  const int64_t c = c0 + (int64_t)blockIdx.x * kB + threadIdx.x;
+  int64_t run;
+  int N;
+  order_block(P, run, N);
+  const int64_t c = c0 + run * kB + threadIdx.x;
   if (c >= c1) return;
   const int pa = parent[c];
-  const int N = blockIdx.y;
   const double dx = c_centre[3 * c] - c_centre[3 * pa];
   const double dy = c_centre[3 * c + 1] - c_centre[3 * pa + 1];
   const double dz = c_centre[3 * c + 2] - c_centre[3 * pa + 2];
@@ -1609,8 +1625,7 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
   for (int L = 1; L <= t->max_level; ++L) {
     const int64_t c0 = t->level_off[L], c1 = t->level_off[L + 1];
     if (c1 <= c0) continue;
-    dim3 grid(grid_for(c1 - c0, kB), P + 1);
-    k_m2mT<P><<<grid, kB, 0, st>>>(c0, c1, t->c_parent.as<int32_t>(), t->c_centre.as<double>(),
+    k_m2mT<P><<<order_grid(grid_for(c1 - c0, kB), P), kB, 0, st>>>(c0, c1, t->c_parent.as<int32_t>(), t->c_centre.as<double>(),
                                    mbar64);
     HOT_CHECK_LAUNCH();
   }

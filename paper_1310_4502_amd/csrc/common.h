@@ -319,6 +319,25 @@ inline unsigned grid_for(int64_t n, int block) {
   return (unsigned)((n + block - 1) / block);
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+constexpr int kXcdCount = 8;
+
+// Blocks of the kernels with one block per expansion order and run of 256
+// cells (P2M, M2M and its transpose): the orders of a run are consecutive
+// blocks on one XCD, so the run's particles, children or parents are fetched
+// from HBM once and re-read from that XCD's L2 for the other orders: block
+// b = 8 (p + 1) q + 8 o + x serves order o of cell run 8 q + x.
+inline unsigned order_grid(int64_t runs, int p) {
+  return (unsigned)(((runs + kXcdCount - 1) / kXcdCount) * kXcdCount * (p + 1));
+}
+__device__ __forceinline__ void order_block(int p, int64_t& run, int& ord) {
+  const int64_t b = blockIdx.x;
+  const int64_t grp = kXcdCount * (p + 1);
+  const int64_t rem = b % grp;
+  ord = (int)(rem / kXcdCount);
+  run = (b / grp) * kXcdCount + rem % kXcdCount;
+}
+
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------

@@ -11,7 +11,8 @@
 // wavefront-uniform, so its data arrives through scalar loads shared by all
 // 64 sinks. The interaction vector of a sink is written back once per
 // kernel (the paper's multi-stage write-back), with compensated (Kahan)
-// accumulation per list entry in mixed precision.
+// accumulation in mixed precision: one compensated add per expansion entry
+// and per block of at least kSumRun pair-summed sources.
 //
 // Mixed precision: every position enters as an FP32 offset from its own
 // group's FP64 centre; the FP64 difference of two centres is formed once per
@@ -39,9 +40,19 @@ __device__ __forceinline__ void image_shift(int img, double side, double& sx, do
   sz = (double)(img % 5 - 2) * side;
 }
 constexpr int kCentreImage = 62;  // n = (0, 0, 0)
+// sources summed in plain FP32 between two compensated adds of a pair kernel
+constexpr int kSumRun = 256;
+
+// The plain FP32 pair kernel fits 64 VGPRs without spilling and runs eight
+// waves per SIMD (its rsq latency then hides behind more waves: 4 % faster
+// than at five); the FP64, periodic and K1 forms need more registers and keep
+// the default.
+template <typename T, bool PER, bool K1>
+constexpr int p2p_waves_per_simd() { return (sizeof(T) == 4 && !PER && !K1) ? 8 : 1; }
 
 template <typename T, bool POT, bool EPS0, bool PER, bool K1>
-__global__ __launch_bounds__(kB) void k_p2p(
+__global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(p2p_waves_per_simd<T, PER, K1>())))
+void k_p2p(
     const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
     const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
     const int32_t* __restrict__ c_first,
@@ -82,6 +93,33 @@ __global__ __launch_bounds__(kB) void k_p2p(
   if (iA < gend) mA = off[iA];
   if (iB < gend) mB = off[iB];
   T sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
+  // Plain FP32 sums in two alternating accumulators per sink (the halves'
+  // sources) over consecutive segments, each segment's sources taken relative
+  // to the sink group's centre, until at least kSumRun sources are summed; then
+  // the halves are added (lane l < 32 completes sink A = item.y + l, lane
+  // l >= 32 sink B = item.y + l) and go into the compensated sums with one
+  // compensated add (fewer than kSumRun + n_group terms per plain sum).
+  T aAx = 0, aAy = 0, aAz = 0, aAp = 0;
+  T aBx = 0, aBy = 0, aBz = 0, aBp = 0;
+  T mseg = T(1);
+  int n_acc = 0;
+#define HOT_FLUSH                                                                    \
+  {                                                                                  \
+    const T kx = h ? aBx : aAx, ky = h ? aBy : aAy, kz = h ? aBz : aAz;              \
+    const T ox = __shfl_xor(h ? aAx : aBx, 32), oy = __shfl_xor(h ? aAy : aBy, 32),  \
+            oz = __shfl_xor(h ? aAz : aBz, 32);                                      \
+    kahan_add(sx, cx, (kx + ox) * mseg);                                             \
+    kahan_add(sy, cy, (ky + oy) * mseg);                                             \
+    kahan_add(sz, cz, (kz + oz) * mseg);                                             \
+    if (POT) {                                                                       \
+      const T kp = h ? aBp : aAp;                                                    \
+      const T op = __shfl_xor(h ? aAp : aBp, 32);                                    \
+      kahan_add(sp, cp, (kp + op) * mseg);                                           \
+    }                                                                                \
+    aAx = aAy = aAz = aAp = T(0);                                                    \
+    aBx = aBy = aBz = aBp = T(0);                                                    \
+    n_acc = 0;                                                                       \
+  }
   const int64_t e1 = p2p_off[g + 1];
   int64_t e = p2p_off[g];
   while (e < e1) {
@@ -177,9 +215,6 @@ __global__ __launch_bounds__(kB) void k_p2p(
     }                                                                                \
   }
       const bool self = sg == g && im0 == kCentreImage;
-      T aAx = 0, aAy = 0, aAz = 0, aAp = 0;
-      T aBx = 0, aBy = 0, aBz = 0, aBp = 0;
-      T mseg = T(1);
       for (int jb = j; jb < jend; jb += 64) {
         const int nbt = jend - jb < 64 ? jend - jb : 64;
         V4<T> v;
@@ -203,23 +238,13 @@ __global__ __launch_bounds__(kB) void k_p2p(
       }
 #undef HOT_BATCH
 #undef HOT_PAIR1
-      // the halves' sums: lane l < 32 completes sink A = item.y + l, lane
-      // l >= 32 sink B = item.y + l; one compensated add per segment (at most
-      // n_group sources)
-      const T kx = h ? aBx : aAx, ky = h ? aBy : aAy, kz = h ? aBz : aAz;
-      const T ox = __shfl_xor(h ? aAx : aBx, 32), oy = __shfl_xor(h ? aAy : aBy, 32),
-              oz = __shfl_xor(h ? aAz : aBz, 32);
-      kahan_add(sx, cx, (kx + ox) * mseg);
-      kahan_add(sy, cy, (ky + oy) * mseg);
-      kahan_add(sz, cz, (kz + oz) * mseg);
-      if (POT) {
-        const T kp = h ? aBp : aAp;
-        const T op = __shfl_xor(h ? aAp : aBp, 32);
-        kahan_add(sp, cp, (kp + op) * mseg);
-      }
+      n_acc += jend - j;
+      if (n_acc >= kSumRun) HOT_FLUSH
       j = jend;
     }
   }
+  if (n_acc > 0) HOT_FLUSH
+#undef HOT_FLUSH
   if (active) {
     T* st = state + (int64_t)i * 8;
     st[0] = sx;

@@ -91,24 +91,6 @@ __device__ __forceinline__ void m2m_order(const double* __restrict__ mom, int nm
   for (int k = 0; k < K; ++k) out[off + k] = acc[k];
 }
 
-// Blocks of the P2M and M2M kernels: one order of one run of kB cells each.
-// The orders of a run are consecutive blocks that land on one XCD (blocks are
-// dealt round-robin to the 8 XCDs, each with its own L2), so the run's
-// particles or children are fetched from HBM once and re-read from that L2
-// for the other orders: block b = 8 (p + 1) q + 8 o + x serves order o of
-// cell run 8 q + x.
-constexpr int kXcds = 8;
-__host__ __device__ inline unsigned order_grid(int64_t runs, int p) {
-  return (unsigned)(((runs + kXcds - 1) / kXcds) * kXcds * (p + 1));
-}
-__device__ inline void order_block(int p, int64_t& run, int& ord) {
-  const int64_t b = blockIdx.x;
-  const int64_t grp = kXcds * (p + 1);
-  const int64_t rem = b % grp;
-  ord = (int)(rem / kXcds);
-  run = (b / grp) * kXcds + rem % kXcds;
-}
-
 // leaves only (P2M)
 __global__ __launch_bounds__(kB) void k_p2m(int64_t C, const int32_t* __restrict__ c_first,
                                             const int32_t* __restrict__ c_count,
