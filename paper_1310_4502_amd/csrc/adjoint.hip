@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
 #define HOT_SINK_BATCH(UM, SELF)                                                     \
   {                                                                                  \
     int k2 = 0;                                                                      \
-    _Pragma("unroll 4") for (; k2 + 1 < nbt; k2 += 2) {                              \
+    _Pragma("unroll 2") for (; k2 + 1 < nbt; k2 += 2) {                              \
       const int k = k2 + h;                                                          \
       const V4<T> s = slot[k];                                                       \
       HOT_SINK_PAIR(SELF, UM, true, iA, tAx, tAy, tAz, a3Ax, a3Ay, a3Az, pA, qAx, qAy, qAz) \
@@ -1369,7 +1369,10 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
         t->c_count.as<int32_t>(), t->item_of.as<int32_t>(), cnt.as<int64_t>(), gbits,
         t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>());
     HOT_CHECK_LAUNCH();
-    radix_sort(ctx, t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>(), nrec, gbits + qbits);
+    // the records are written group by group in increasing group order, so a
+    // stable sort on the item bits alone orders them by (item, group)
+    radix_sort(ctx, t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>(), nrec, gbits + qbits,
+               gbits);
     k_lower_bound<<<grid_for(NI + 1, kB), kB, 0, st>>>(t->srec_key.as<uint64_t>(), nrec, gbits, NI,
                                                        t->srec_off.as<uint32_t>());
     HOT_CHECK_LAUNCH();

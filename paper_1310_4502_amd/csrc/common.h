@@ -256,9 +256,11 @@ namespace hot {
 void scan_u32(hot_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
 void scan_i64(hot_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, int64_t* total);
 
-// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
-// Buffers are swapped internally; the result ends in keys/vals.
-void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits);
+// Stable LSD radix sort of (key, value) pairs on key bits [lo, bits): a caller
+// whose pairs are already ordered by the bits below lo passes lo > 0 and gets
+// the order of a sort on all `bits` bits with fewer passes. Buffers are
+// swapped internally; the result ends in keys/vals.
+void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, int lo = 0);
 
 void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box);
 // the work items split by sink count (at most 32, or more), at tree build

@@ -227,9 +227,9 @@ void scan_i64(hot_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, int64_t*
   scan_impl<int64_t>(ctx, in, out, n, total);
 }
 
-void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits) {
-  if (n <= 1 || bits <= 0) return;
-  const int passes = (bits + kRBits - 1) / kRBits;
+void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, int lo) {
+  if (n <= 1 || bits <= lo) return;
+  const int passes = (bits - lo + kRBits - 1) / kRBits;
   const int64_t ntiles = (n + kRTile - 1) / kRTile;
   if ((int64_t)kRBins * ntiles >= (int64_t)UINT32_MAX) throw Error{HOT_E_CAPACITY, "sort too large"};
   if (n >= (int64_t)UINT32_MAX) throw Error{HOT_E_CAPACITY, "sort too large"};
@@ -242,7 +242,7 @@ void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bit
   uint64_t* kd = k2.as<uint64_t>();
   uint32_t* vd = v2.as<uint32_t>();
   for (int pass = 0; pass < passes; ++pass) {
-    const int shift = pass * kRBits;
+    const int shift = lo + pass * kRBits;
     k_radix_hist<<<(unsigned)ntiles, kRThreads, 0, ctx->stream>>>(ks, n, shift,
                                                                     hist.as<uint32_t>(), ntiles);
     HOT_CHECK_LAUNCH();
