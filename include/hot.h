@@ -182,8 +182,12 @@ int compute_moments(hot_ctx* ctx, hot_tree* tree, const double* pos, const doubl
  * other cell is opened. Acceptance: with d the distance between the group and
  * cell centres, d^2 > (b_c / theta + b_g)^2 (FP64, no fused multiply-add);
  * the group form of the b_max criterion in the source/sink geometry of the
- * Multipole Error Bounds section. Lists are in depth-first preorder.
- * theta: (0, 1). direct_max: >= 0. Synchronises the stream once.
+ * Multipole Error Bounds section. Lists are in depth-first preorder. Every
+ * list builder also tabulates each group's P2P list as pair segments
+ * (consecutive entries with contiguous particle ranges, cut at source-group
+ * boundaries, with their FP64 centre offsets), which the pair kernels read.
+ * theta: (0, 1). direct_max: >= 0. Synchronises the stream twice (list
+ * sizes, then the segment count).
  */
 int build_interaction_lists(hot_ctx* ctx, hot_tree* tree, double theta, int direct_max);
 

@@ -236,8 +236,9 @@ __global__ void k_seg_chunk_sum(const Tin* __restrict__ in, int in_stride,
                                 const uint32_t* __restrict__ off_out, int64_t C, int64_t n_out,
                                 int nmv, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t j = t / nmv;
-  const int a = (int)(t - j * nmv);
+  int64_t j;
+  int a;
+  row_col(t, nmv, j, a);
   if (j >= n_out) return;
   const int64_t c = owner_of(off_out, C, (uint32_t)j);
   const uint32_t k0 = off_in[c] + ((uint32_t)j - off_out[c]) * kSegChunk;
@@ -330,30 +331,16 @@ __global__ void k_abar(const double* __restrict__ abar, const uint32_t* __restri
   ab3[i] = v;
 }
 
-// Image index -> shift of the source replica (periodic lists): n L with
-// n_d = digit - 2 of the index in base 5 (x most significant).
-__device__ __forceinline__ void image_shift(int img, double side, double& sx, double& sy,
-                                           double& sz) {
-  sx = (double)(img / 25 - 2) * side;
-  sy = (double)((img / 5) % 5 - 2) * side;
-  sz = (double)(img % 5 - 2) * side;
-}
-constexpr int kCentreImage = 62;  // n = (0, 0, 0)
-// sources summed in plain FP32 between two compensated adds of a pair kernel
-constexpr int kSumRun = 256;
-
 // ------------------------------------------------------- pair terms, sink side
 // state per sorted particle: s_x s_y s_z - c_x c_y c_z -
-template <typename T, bool EPS0, bool PER, bool K1>
+// The group's list comes as its pair segments, as in the forward pair kernel.
+template <typename T, bool EPS0, bool K1>
 __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
-    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
-    const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
-    const int32_t* __restrict__ c_first,
-    const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
-    const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
-    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
-    const V4<T>* __restrict__ off, const V4<T>* __restrict__ ab4, T eps2, T ie,
-    const unsigned* __restrict__ mdiff, T* __restrict__ state) {
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ pseg_off,
+    const PairSeg* __restrict__ pseg, const int32_t* __restrict__ g_first,
+    const int32_t* __restrict__ g_count, const V4<T>* __restrict__ off,
+    const V4<T>* __restrict__ ab4, T eps2, T ie, const unsigned* __restrict__ mdiff,
+    T* __restrict__ state) {
   __shared__ V4<T> stage[kWPB][64];
   // K1: eps2 is the squared kernel radius, ie its inverse radius
   const T ie2 = ie * ie, ie3 = ie * ie2, ie5t = (ie3 * ie2) * (T(1) / T(3));
@@ -375,8 +362,6 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
   const int iA = item.y + sub, iB = iA + 32;
   const int i = item.y + lane;
   const bool active = i < gend;
-  const int gc = g_cell[g];
-  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
   V4<T> mA, mB, bA, bB;
   mA.x = mA.y = mA.z = mA.w = T(0);
   mB = bA = bB = mA;
@@ -414,41 +399,15 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
     pB = qBx = qBy = qBz = T(0);                                                     \
     n_acc = 0;                                                                       \
   }
-  const int64_t e1 = p2p_off[g + 1];
-  int64_t e = p2p_off[g];
-  while (e < e1) {
-    // a run of consecutive entries with contiguous particle ranges
-    int c = uniform_i32(p2p[e]);
-    const int im0 = PER ? uniform_i32(p2p_img[e]) : kCentreImage;
-    const int f = uniform_i32(c_first[c]);
-    int end = f + uniform_i32(c_count[c]);
-    for (++e; e < e1; ++e) {
-      c = uniform_i32(p2p[e]);
-      const int f2 = uniform_i32(c_first[c]);
-      if (f2 != end) break;
-      if (PER && uniform_i32(p2p_img[e]) != im0) break;
-      end = f2 + uniform_i32(c_count[c]);
-    }
-    double shx = 0.0, shy = 0.0, shz = 0.0;
-    if (PER) image_shift(im0, side, shx, shy, shz);
-    int j = f;
-    while (j < end) {
-      // a segment: the part of the run inside one source group
-      const int sg = uniform_i32(group_of[j]);
-      const int sgend = uniform_i32(g_first[sg] + g_count[sg]);
-      const int jend = end < sgend ? end : sgend;
-      if (jend <= j) break;
-      const int sc = g_cell[sg];
-      T dx, dy, dz;
-      if (PER) {
-        dx = (T)((c_centre[3 * sc] + shx) - cgx);
-        dy = (T)((c_centre[3 * sc + 1] + shy) - cgy);
-        dz = (T)((c_centre[3 * sc + 2] + shz) - cgz);
-      } else {
-        dx = (T)(c_centre[3 * sc] - cgx);
-        dy = (T)(c_centre[3 * sc + 1] - cgy);
-        dz = (T)(c_centre[3 * sc + 2] - cgz);
-      }
+  const int64_t q1 = pseg_off[g + 1];
+  for (int64_t q = pseg_off[g]; q < q1; ++q) {
+    {
+      // a segment: the sources [j, jend) of one source group
+      const PairSeg sgm = pseg[q];
+      const int j = uniform_i32(sgm.first);
+      const int jend = uniform_i32(sgm.end);
+      const bool self = uniform_i32(sgm.self) != 0;
+      const T dx = (T)sgm.dx, dy = (T)sgm.dy, dz = (T)sgm.dz;
       const T tAx = dx - mA.x, tAy = dy - mA.y, tAz = dz - mA.z;
       const T tBx = dx - mB.x, tBy = dy - mB.y, tBz = dz - mB.z;
       // sources in batches of 64 staged through the wavefront's LDS slot
@@ -512,7 +471,6 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
       HOT_SINK_PAIR(SELF, UM, h == 0, iB, tBx, tBy, tBz, a3Bx, a3By, a3Bz, pB, qBx, qBy, qBz) \
     }                                                                                \
   }
-      const bool self = sg == g && im0 == kCentreImage;
       for (int jb = j; jb < jend; jb += 64) {
         const int nbt = jend - jb < 64 ? jend - jb : 64;
         V4<T> v;
@@ -538,7 +496,6 @@ __global__ __launch_bounds__(kB) void k_p2p_sink_adj(
 #undef HOT_SINK_PAIR
       n_acc += jend - j;
       if (n_acc >= kSumRun) HOT_SINK_FLUSH
-      j = jend;
     }
   }
   if (n_acc > 0) HOT_SINK_FLUSH
@@ -1215,15 +1172,14 @@ __global__ void k_mbar_final(const T* __restrict__ part, int stride,
                              double* __restrict__ mbar) {
   const int nmv = nm(p);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = t / nmv;
-  const int a = (int)(t - c * nmv);
+  int64_t c;
+  int a;
+  row_col(t, nmv, c, a);
   if (c >= C) return;
   double s = 0.0;
   for (uint32_t k = it_off[c]; k < it_off[c + 1]; ++k) s += (double)part[(int64_t)k * stride + a];
   const int order = kAlpha.a[a] + kAlpha.b[a] + kAlpha.c[a];
-  const double inv_s = ldexp(inv_side, (int)c_level[c]);
-  double sc = inv_s * inv_s;
-  for (int k = 0; k < order; ++k) sc *= inv_s;
+  const double sc = pow2_pow(ldexp(inv_side, (int)c_level[c]), order + 2);
   mbar[c * nmv + a] = -kAlpha.w[a] * sc * s;
 }
 
@@ -1371,8 +1327,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
     HOT_CHECK_LAUNCH();
     // the records are written group by group in increasing group order, so a
     // stable sort on the item bits alone orders them by (item, group)
-    radix_sort(ctx, t->srec_key.as<uint64_t>(), t->srec_val.as<uint32_t>(), nrec, gbits + qbits,
-               gbits);
+    radix_sort(ctx, t->srec_key, t->srec_val, nrec, gbits + qbits, gbits);
     k_lower_bound<<<grid_for(NI + 1, kB), kB, 0, st>>>(t->srec_key.as<uint64_t>(), nrec, gbits, NI,
                                                        t->srec_off.as<uint32_t>());
     HOT_CHECK_LAUNCH();
@@ -1413,7 +1368,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
         t->periodic ? t->m2p_img.as<int8_t>() : nullptr, G, t->mrec_key.as<uint64_t>(),
         t->mrec_val.as<uint32_t>());
     HOT_CHECK_LAUNCH();
-    radix_sort(ctx, t->mrec_key.as<uint64_t>(), t->mrec_val.as<uint32_t>(), E,
+    radix_sort(ctx, t->mrec_key, t->mrec_val, E,
                bits_for(C) + qsh + ish);
     k_lower_bound<<<grid_for(C + 1, kB), kB, 0, st>>>(t->mrec_key.as<uint64_t>(), E, qsh + ish, C,
                                                       t->mcell_rec.as<uint32_t>());
@@ -1452,7 +1407,7 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
             t->qitems.as<uint32_t>());
         HOT_CHECK_LAUNCH();
       }
-      radix_sort(ctx, qkey.as<uint64_t>(), t->qitems.as<uint32_t>(), nci, 4);
+      radix_sort(ctx, qkey, t->qitems, nci, 4);
       k_lower_bound<<<1, kB, 0, st>>>(qkey.as<uint64_t>(), nci, 0, kMaxP + 1, qoff.as<uint32_t>());
       HOT_CHECK_LAUNCH();
       uint32_t h[kMaxP + 2];
@@ -1692,19 +1647,12 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   const T ie = k1 ? (T)(1.0 / eps) : T(0);
   const unsigned gi = grid_for(t->n_items, kWPB);
   // pair terms
-  auto sink_k = k1 ? (t->periodic ? k_p2p_sink_adj<T, false, true, true>
-                                  : k_p2p_sink_adj<T, false, false, true>)
-              : t->periodic ? (e2 > T(0) ? k_p2p_sink_adj<T, false, true, false>
-                                         : k_p2p_sink_adj<T, true, true, false>)
-                            : (e2 > T(0) ? k_p2p_sink_adj<T, false, false, false>
-                                         : k_p2p_sink_adj<T, true, false, false>);
+  auto sink_k = k1 ? k_p2p_sink_adj<T, false, true>
+                    : (e2 > T(0) ? k_p2p_sink_adj<T, false, false> : k_p2p_sink_adj<T, true, false>);
   tmark(ctx, HOT_T_ADJ_P2P_SINK, false);
-  sink_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
-                            t->p2p.as<int32_t>(), t->p2p_img.as<int8_t>(), t->side,
-                            t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
-                            t->group_of.as<int32_t>(), t->g_first.as<int32_t>(),
-                            t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(),
-                            t->c_centre.as<double>(), off.as<V4<T>>(), ab.as<V4<T>>(), e2, ie,
+  sink_k<<<gi, kB, 0, st>>>(t->items.as<int2>(), t->n_items, t->pseg_off.as<int64_t>(),
+                            t->pseg.as<PairSeg>(), t->g_first.as<int32_t>(),
+                            t->g_count.as<int32_t>(), off.as<V4<T>>(), ab.as<V4<T>>(), e2, ie,
                             ctx->d_flags + kFlagMass, sink.as<T>());
   HOT_CHECK_LAUNCH();
   auto src_k = k1 ? (t->periodic ? k_p2p_src_adj<T, false, true, true>

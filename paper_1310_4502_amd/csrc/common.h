@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hot.h"
@@ -156,6 +157,11 @@ struct DBuf {
   }
   template <class T>
   T* as() const { return static_cast<T*>(p); }
+  void swap(DBuf& o) {
+    std::swap(ctx, o.ctx);
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
 };
 
 }  // namespace hot
@@ -213,6 +219,11 @@ struct hot_tree {
   int bg_width = 3;  // side of N(g) in group sides
   int64_t n_boxes = 0;
   hot::DBuf m2p_sub, box_off, boxes, box_sign, momsub;
+  // pair segments of the P2P lists (CSR per group, built with the lists):
+  // consecutive entries with contiguous particle ranges (and one image) form
+  // a run, cut at source-group boundaries into segments
+  int64_t n_psegs = 0;
+  hot::DBuf pseg_off, pseg;
   // eval work items: (group, first sink) per wave
   int64_t n_items = 0;
   hot::DBuf items;
@@ -256,11 +267,13 @@ namespace hot {
 void scan_u32(hot_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
 void scan_i64(hot_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, int64_t* total);
 
-// Stable LSD radix sort of (key, value) pairs on key bits [lo, bits): a caller
-// whose pairs are already ordered by the bits below lo passes lo > 0 and gets
-// the order of a sort on all `bits` bits with fewer passes. Buffers are
-// swapped internally; the result ends in keys/vals.
-void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, int lo = 0);
+// Stable LSD radix sort of the first n (key, value) pairs on key bits
+// [lo, bits): a caller whose pairs are already ordered by the bits below lo
+// passes lo > 0 and gets the order of a sort on all `bits` bits with fewer
+// passes. The passes alternate between the caller's buffers and scratch; after
+// an odd number of passes the buffers are exchanged (keys and vals then own
+// the former scratch) rather than copied back.
+void radix_sort(hot_ctx* ctx, DBuf& keys, DBuf& vals, int64_t n, int bits, int lo = 0);
 
 void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box);
 // the work items split by sink count (at most 32, or more), at tree build
@@ -321,6 +334,25 @@ inline unsigned grid_for(int64_t n, int block) {
   return (unsigned)((n + block - 1) / block);
 }
 
+// Row and column of entry t of a row-major array with w columns: 32-bit
+// division below 2^32 entries (a few instructions), 64-bit above.
+__device__ __forceinline__ void row_col(int64_t t, int w, int64_t& r, int& col) {
+  if (t < (int64_t)0xffffffffll) {
+    const uint32_t q = (uint32_t)t / (uint32_t)w;
+    r = (int64_t)q;
+    col = (int)((uint32_t)t - q * (uint32_t)w);
+  } else {
+    r = t / w;
+    col = (int)(t - r * w);
+  }
+}
+
+// base^k for base an exact power of two (cell sides and their inverses): the
+// exponent scaled, the same value as k repeated multiplications
+__device__ __forceinline__ double pow2_pow(double base, int k) {
+  return ldexp(1.0, ilogb(base) * k);
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
 constexpr int kXcdCount = 8;
 
@@ -349,6 +381,27 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l ? (~0ull >> (64 - l)) : 0ull;
 }
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Image index of a periodic list entry -> shift of the source replica, n L
+// with n_d = digit - 2 of the index in base 5 (x most significant).
+__device__ __forceinline__ void image_shift(int img, double side, double& sx, double& sy,
+                                           double& sz) {
+  sx = (double)(img / 25 - 2) * side;
+  sy = (double)((img / 5) % 5 - 2) * side;
+  sz = (double)(img % 5 - 2) * side;
+}
+constexpr int kCentreImage = 62;  // n = (0, 0, 0)
+
+// One pair segment: sources [first, end) of one source group, all in one
+// image, for the sinks of one group; d = (source group centre + image shift)
+// - sink group centre in FP64 (rounded to the kernel's type where used);
+// self = 1 when the sources are the sink group itself in the central image.
+struct PairSeg {
+  int32_t first, end, self, pad;
+  double dx, dy, dz;
+};
+// sources summed in plain FP32 between two compensated adds of a pair kernel
+constexpr int kSumRun = 256;
 
 __device__ __forceinline__ float hot_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double hot_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }

@@ -31,41 +31,29 @@ constexpr int kB = 256;
 constexpr int kWavesPerBlock = kB / 64;
 
 // State per sorted particle: s_x s_y s_z s_phi c_x c_y c_z c_phi.
-// Image index -> shift of the source replica (periodic lists): n L with
-// n_d = digit - 2 of the index in base 5 (x most significant).
-__device__ __forceinline__ void image_shift(int img, double side, double& sx, double& sy,
-                                           double& sz) {
-  sx = (double)(img / 25 - 2) * side;
-  sy = (double)((img / 5) % 5 - 2) * side;
-  sz = (double)(img % 5 - 2) * side;
-}
-constexpr int kCentreImage = 62;  // n = (0, 0, 0)
-// sources summed in plain FP32 between two compensated adds of a pair kernel
-constexpr int kSumRun = 256;
 
 // The plain FP32 pair kernel fits 64 VGPRs without spilling and runs eight
-// waves per SIMD (its rsq latency then hides behind more waves: 4 % faster
-// than at five); the FP64, periodic and K1 forms need more registers and keep
-// the default.
-template <typename T, bool PER, bool K1>
-constexpr int p2p_waves_per_simd() { return (sizeof(T) == 4 && !PER && !K1) ? 8 : 1; }
+// waves per SIMD (4 % faster than at five); the FP64 and K1 forms need more
+// registers and keep the default.
+template <typename T, bool K1>
+constexpr int p2p_waves_per_simd() { return (sizeof(T) == 4 && !K1) ? 8 : 1; }
 
-template <typename T, bool POT, bool EPS0, bool PER, bool K1>
-__global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(p2p_waves_per_simd<T, PER, K1>())))
+// The group's list comes as its pair segments (sources [first, end) of one
+// source group in one image, the centre difference precomputed in FP64 when
+// the lists were built), so the kernel follows no list entry, cell or group
+// record of its own.
+template <typename T, bool POT, bool EPS0, bool K1>
+__global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(p2p_waves_per_simd<T, K1>())))
 void k_p2p(
-    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ p2p_off,
-    const int32_t* __restrict__ p2p, const int8_t* __restrict__ p2p_img, double side,
-    const int32_t* __restrict__ c_first,
-    const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
-    const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
-    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
-    const V4<T>* __restrict__ off, T eps2, T ie, const unsigned* __restrict__ mdiff,
-    T* __restrict__ state, int64_t n) {
+    const int2* __restrict__ items, int64_t n_items, const int64_t* __restrict__ pseg_off,
+    const PairSeg* __restrict__ pseg, const int32_t* __restrict__ g_first,
+    const int32_t* __restrict__ g_count, const V4<T>* __restrict__ off, T eps2, T ie,
+    const unsigned* __restrict__ mdiff, T* __restrict__ state, int64_t n) {
   __shared__ V4<T> stage[kWavesPerBlock][64];
   // K1: eps2 is the squared kernel radius, ie its inverse radius
   const T ie2 = ie * ie, ie3 = ie * ie2;
   // every particle of the same mass (k_offsets found none that differs): the
-  // pair loop leaves the mass out and the segment's sums are scaled once
+  // pair loop leaves the mass out and the summed blocks are scaled once
   const bool uni = *mdiff == 0u;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   V4<T>* slot = stage[w];
@@ -77,16 +65,12 @@ void k_p2p(
   // m x n blocking with n = 2: lane l holds the two sinks item.y + (l & 31)
   // (A) and item.y + 32 + (l & 31) (B); the half h = l / 32 of the wavefront
   // takes the sources of odd (h = 1) or even (h = 0) index, so every source
-  // read from LDS serves two pairs (the LDS return path, 16 B per lane and
-  // read, would otherwise bound the kernel). The halves' sums are added at
-  // the end of each segment; lane l keeps the compensated sums of sink
-  // item.y + l.
+  // read from LDS serves two pairs. The halves' sums are added at each
+  // compensated add; lane l keeps the compensated sums of sink item.y + l.
   const int h = lane >> 5, sub = lane & 31;
   const int iA = item.y + sub, iB = iA + 32;
   const int i = item.y + lane;
   const bool active = i < gend;
-  const int gc = g_cell[g];
-  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
   V4<T> mA, mB;
   mA.x = mA.y = mA.z = mA.w = T(0);
   mB = mA;
@@ -120,42 +104,15 @@ void k_p2p(
     aBx = aBy = aBz = aBp = T(0);                                                    \
     n_acc = 0;                                                                       \
   }
-  const int64_t e1 = p2p_off[g + 1];
-  int64_t e = p2p_off[g];
-  while (e < e1) {
-    // a run of consecutive entries whose particle ranges are contiguous
-    // (typically the sibling leaves of one opened cell)
-    int c = uniform_i32(p2p[e]);
-    const int im0 = PER ? uniform_i32(p2p_img[e]) : kCentreImage;
-    const int f = uniform_i32(c_first[c]);
-    int end = f + uniform_i32(c_count[c]);
-    for (++e; e < e1; ++e) {
-      c = uniform_i32(p2p[e]);
-      const int f2 = uniform_i32(c_first[c]);
-      if (f2 != end) break;
-      if (PER && uniform_i32(p2p_img[e]) != im0) break;
-      end = f2 + uniform_i32(c_count[c]);
-    }
-    double shx = 0.0, shy = 0.0, shz = 0.0;
-    if (PER) image_shift(im0, side, shx, shy, shz);
-    int j = f;
-    while (j < end) {
-      // a segment: the part of the run inside one source group
-      const int sg = uniform_i32(group_of[j]);
-      const int sgend = uniform_i32(g_first[sg] + g_count[sg]);
-      const int jend = end < sgend ? end : sgend;
-      if (jend <= j) break;  // never true for a valid tree
-      const int sc = uniform_i32(g_cell[sg]);
-      T dx, dy, dz;
-      if (PER) {
-        dx = (T)((c_centre[3 * sc] + shx) - cgx);
-        dy = (T)((c_centre[3 * sc + 1] + shy) - cgy);
-        dz = (T)((c_centre[3 * sc + 2] + shz) - cgz);
-      } else {
-        dx = (T)(c_centre[3 * sc] - cgx);
-        dy = (T)(c_centre[3 * sc + 1] - cgy);
-        dz = (T)(c_centre[3 * sc + 2] - cgz);
-      }
+  const int64_t q1 = pseg_off[g + 1];
+  for (int64_t q = pseg_off[g]; q < q1; ++q) {
+    {
+      // a segment: the sources [j, jend) of one source group
+      const PairSeg sgm = pseg[q];
+      const int j = uniform_i32(sgm.first);
+      const int jend = uniform_i32(sgm.end);
+      const bool self = uniform_i32(sgm.self) != 0;
+      const T dx = (T)sgm.dx, dy = (T)sgm.dy, dz = (T)sgm.dz;
       const T tAx = dx - mA.x, tAy = dy - mA.y, tAz = dz - mA.z;
       const T tBx = dx - mB.x, tBy = dy - mB.y, tBz = dz - mB.z;
       // one pair of a sink (T*) with source s, into accumulators A*
@@ -214,7 +171,6 @@ void k_p2p(
       HOT_PAIR1(SELF, UM, h == 0, iB, tBx, tBy, tBz, aBx, aBy, aBz, aBp)             \
     }                                                                                \
   }
-      const bool self = sg == g && im0 == kCentreImage;
       for (int jb = j; jb < jend; jb += 64) {
         const int nbt = jend - jb < 64 ? jend - jb : 64;
         V4<T> v;
@@ -240,7 +196,6 @@ void k_p2p(
 #undef HOT_PAIR1
       n_acc += jend - j;
       if (n_acc >= kSumRun) HOT_FLUSH
-      j = jend;
     }
   }
   if (n_acc > 0) HOT_FLUSH
@@ -552,30 +507,18 @@ void launch_p2p(hot_ctx* ctx, hot_tree* t, const V4<T>* off, double eps, bool k1
   const T e2 = (T)(eps * eps);
   const T ie = k1 ? (T)(1.0 / eps) : T(0);
   auto go = [&](auto kern) {
-    kern<<<grid, kB, 0, ctx->stream>>>(t->items.as<int2>(), t->n_items, t->p2p_off.as<int64_t>(),
-                                       t->p2p.as<int32_t>(), t->p2p_img.as<int8_t>(), t->side,
-                                       t->c_first.as<int32_t>(),
-                                       t->c_count.as<int32_t>(), t->group_of.as<int32_t>(),
-                                       t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
-                                       t->g_cell.as<int32_t>(), t->c_centre.as<double>(), off, e2,
-                                       ie, mdiff, state, t->n);
+    kern<<<grid, kB, 0, ctx->stream>>>(t->items.as<int2>(), t->n_items,
+                                       t->pseg_off.as<int64_t>(), t->pseg.as<PairSeg>(),
+                                       t->g_first.as<int32_t>(), t->g_count.as<int32_t>(), off,
+                                       e2, ie, mdiff, state, t->n);
     HOT_CHECK_LAUNCH();
   };
-  if (t->periodic) {
-    if (k1)
-      go(k_p2p<T, POT, false, true, true>);
-    else if (e2 > T(0))
-      go(k_p2p<T, POT, false, true, false>);
-    else
-      go(k_p2p<T, POT, true, true, false>);
-  } else {
-    if (k1)
-      go(k_p2p<T, POT, false, false, true>);
-    else if (e2 > T(0))
-      go(k_p2p<T, POT, false, false, false>);
-    else
-      go(k_p2p<T, POT, true, false, false>);
-  }
+  if (k1)
+    go(k_p2p<T, POT, false, true>);
+  else if (e2 > T(0))
+    go(k_p2p<T, POT, false, false>);
+  else
+    go(k_p2p<T, POT, true, false>);
 }
 
 template <int P, typename T, bool POT, bool K1>

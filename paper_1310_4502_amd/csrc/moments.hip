@@ -155,17 +155,16 @@ __global__ void k_weighted(const double* __restrict__ mom, int64_t C,
                            T* __restrict__ out) {
   const int nmv = nm(p), stride = nm_pad(p);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = t / stride;
-  const int s = (int)(t - c * stride);
+  int64_t c;
+  int s;
+  row_col(t, stride, c, s);
   if (c >= C) return;
   if (s >= nmv) {
     out[c * stride + s] = T(0);
     return;
   }
   const int order = kAlpha.a[s] + kAlpha.b[s] + kAlpha.c[s];
-  const double inv_s = ldexp(inv_side, (int)c_level[c]);
-  double sc = 1.0;
-  for (int k = 0; k < order; ++k) sc *= inv_s;
+  const double sc = pow2_pow(ldexp(inv_side, (int)c_level[c]), order);
   out[c * stride + s] = (T)(kAlpha.w[s] * (mom[c * nmv + s] * sc));
 }
 
@@ -180,8 +179,9 @@ __global__ void k_weighted_sub(const double* __restrict__ mom, int64_t C,
                                T* __restrict__ out) {
   const int nmv = nm(p), stride = nm_pad(p);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = t / stride;
-  const int s = (int)(t - c * stride);
+  int64_t c;
+  int s;
+  row_col(t, stride, c, s);
   if (c >= C) return;
   if (s >= nmv) {
     out[c * stride + s] = T(0);
@@ -190,9 +190,7 @@ __global__ void k_weighted_sub(const double* __restrict__ mom, int64_t C,
   const int a = kAlpha.a[s], b = kAlpha.b[s], cc = kAlpha.c[s];
   const int order = a + b + cc;
   const int lev = (int)c_level[c];
-  const double inv_s = ldexp(inv_side, lev);
-  double sc = 1.0;
-  for (int k = 0; k < order; ++k) sc *= inv_s;
+  const double sc = pow2_pow(ldexp(inv_side, lev), order);
   double v = mom[c * nmv + s] * sc;
   if (!((a | b | cc) & 1)) {
     const double cube = ldexp(mom[0], -3 * lev - order) /
@@ -210,8 +208,9 @@ __global__ void k_weighted_cube(int64_t C, const int8_t* __restrict__ c_level, d
                                 T* __restrict__ out) {
   const int nmv = nm(p), stride = nm_pad(p);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = t / stride;
-  const int s = (int)(t - c * stride);
+  int64_t c;
+  int s;
+  row_col(t, stride, c, s);
   if (c >= C) return;
   double v = 0.0;
   if (s < nmv) {

@@ -227,7 +227,7 @@ void scan_i64(hot_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, int64_t*
   scan_impl<int64_t>(ctx, in, out, n, total);
 }
 
-void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, int lo) {
+void radix_sort(hot_ctx* ctx, DBuf& keys, DBuf& vals, int64_t n, int bits, int lo) {
   if (n <= 1 || bits <= lo) return;
   const int passes = (bits - lo + kRBits - 1) / kRBits;
   const int64_t ntiles = (n + kRTile - 1) / kRTile;
@@ -237,8 +237,8 @@ void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bit
   k2.alloc(ctx, n * sizeof(uint64_t));
   v2.alloc(ctx, n * sizeof(uint32_t));
   hist.alloc(ctx, (size_t)kRBins * ntiles * sizeof(uint32_t));
-  uint64_t* ks = keys;
-  uint32_t* vs = vals;
+  uint64_t* ks = keys.as<uint64_t>();
+  uint32_t* vs = vals.as<uint32_t>();
   uint64_t* kd = k2.as<uint64_t>();
   uint32_t* vd = v2.as<uint32_t>();
   for (int pass = 0; pass < passes; ++pass) {
@@ -253,9 +253,11 @@ void radix_sort(hot_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bit
     std::swap(ks, kd);
     std::swap(vs, vd);
   }
-  if (ks != keys) {
-    HOT_HIP(hipMemcpyAsync(keys, ks, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream));
-    HOT_HIP(hipMemcpyAsync(vals, vs, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
+  if (passes & 1) {
+    // the sorted pairs are in the scratch buffers: hand them to the caller
+    // (the caller's old buffers are released, stream-ordered, with k2 / v2)
+    keys.swap(k2);
+    vals.swap(v2);
   }
 }
 

@@ -509,7 +509,7 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   k_keys<<<gb, kB, 0, st>>>(pos, n, t->root.as<double>(), t->key.as<uint64_t>(),
                            t->perm.as<uint32_t>());
   HOT_CHECK_LAUNCH();
-  radix_sort(ctx, t->key.as<uint64_t>(), t->perm.as<uint32_t>(), n, 63);
+  radix_sort(ctx, t->key, t->perm, n, 63);
   t->spos.alloc(ctx, 3 * n * sizeof(double));
   k_gather_pos<<<gb, kB, 0, st>>>(pos, t->perm.as<uint32_t>(), n, t->spos.as<double>());
   HOT_CHECK_LAUNCH();

@@ -350,6 +350,256 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
 namespace {
 
+// exclusive prefix sum over the lanes of a wavefront; *total gets the sum
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total) {
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  *total = __shfl(x, 63);
+  return x - v;
+}
+
+// Pair segments of every group's P2P list, one wavefront per group over its
+// entries 64 at a time (the pair kernels then read one record per segment
+// instead of following list entry -> cell -> particle range -> source group
+// -> centre for every entry): consecutive entries whose particle ranges are
+// contiguous (and, periodic, in one image) form a run, and a run is cut where
+// a source group ends. The lane holding the last entry of a run walks the
+// run's segments (a run still open at the end of a batch is closed by lane 0
+// of the next); an exclusive scan over the lanes places them in list order.
+// COUNT: per-group segment counts into cnt; else the records at off[g].
+template <bool COUNT>
+__global__ __launch_bounds__(kB) void k_pair_segs(
+    int64_t G, const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p,
+    const int8_t* __restrict__ p2p_img, double side, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
+    const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
+    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+    int64_t* __restrict__ cnt, const int64_t* __restrict__ off, PairSeg* __restrict__ seg,
+    unsigned* __restrict__ flags) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (g >= G) return;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  // segments of the run [a0, a1) in image im, counted, and written from o on
+  // when emit (never in the counting pass)
+  auto walk = [&](int a0, int a1, int im, int64_t o, bool emit) -> int {
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    if (p2p_img) image_shift(im, side, shx, shy, shz);
+    int m = 0;
+    for (int j = a0; j < a1;) {
+      const int sg = group_of[j];
+      const int sgend = g_first[sg] + g_count[sg];
+      const int jend = a1 < sgend ? a1 : sgend;
+      if (jend <= j) {
+        atomicOr(flags, FLAG_INTERNAL);
+        break;
+      }
+      if (!COUNT && emit) {
+        const int sc = g_cell[sg];
+        PairSeg r;
+        r.first = j;
+        r.end = jend;
+        r.self = (sg == g && im == kCentreImage) ? 1 : 0;
+        r.pad = 0;
+        if (p2p_img) {
+          r.dx = (c_centre[3 * sc] + shx) - cgx;
+          r.dy = (c_centre[3 * sc + 1] + shy) - cgy;
+          r.dz = (c_centre[3 * sc + 2] + shz) - cgz;
+        } else {
+          r.dx = c_centre[3 * sc] - cgx;
+          r.dy = c_centre[3 * sc + 1] - cgy;
+          r.dz = c_centre[3 * sc + 2] - cgz;
+        }
+        seg[o + m] = r;
+      }
+      ++m;
+      j = jend;
+    }
+    return m;
+  };
+  int64_t k = COUNT ? 0 : off[g];
+  const int64_t e0 = p2p_off[g], e1 = p2p_off[g + 1];
+  // carried between batches: the previous entry's end and image, and the
+  // first particle of the run still open (c_end < 0 before the first entry)
+  int c_end = -1, c_img = kCentreImage, c_rf = 0;
+  for (int64_t b = e0; b < e1; b += 64) {
+    const int64_t e = b + lane;
+    const bool valid = e < e1;
+    int f = 0, en = 0, im = kCentreImage;
+    if (valid) {
+      const int c = p2p[e];
+      f = c_first[c];
+      en = f + c_count[c];
+      if (p2p_img) im = (int)p2p_img[e];
+    }
+    int pe = __shfl_up(en, 1), pim = __shfl_up(im, 1);
+    if (lane == 0) {
+      pe = c_end;
+      pim = c_img;
+    }
+    const bool start = valid && (f != pe || im != pim);
+    const uint64_t smask = __ballot(start);
+    const uint64_t vmask = __ballot(valid);
+    const bool next_start = lane < 63 && ((smask >> (lane + 1)) & 1ull);
+    const bool close = valid && (next_start || e + 1 == e1);
+    // the lane's run starts at the highest start lane <= lane, or was carried
+    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t below = smask & le;
+    const int sl = below ? 63 - __clzll(below) : 0;
+    const int rf_l = __shfl(f, sl), rim_l = __shfl(im, sl);
+    const int rf = below ? rf_l : c_rf;
+    const int rim = below ? rim_l : c_img;
+    // lane 0 closes the carried run first when its own entry starts a new one
+    const bool carried = lane == 0 && start && c_end >= 0;
+    int nseg = 0;
+    if (carried) nseg += walk(c_rf, c_end, c_img, 0, false);
+    if (close) nseg += walk(rf, en, rim, 0, false);
+    int total;
+    const int64_t at = k + wave_excl_scan(nseg, lane, &total);
+    if (!COUNT && nseg > 0) {
+      int64_t o = at;
+      if (carried) o += walk(c_rf, c_end, c_img, o, true);
+      if (close) walk(rf, en, rim, o, true);
+    }
+    k += total;
+    // carry: the last valid entry's end and image, and its run's start
+    const int lv = 63 - __clzll(vmask);
+    c_end = __shfl(en, lv);
+    c_img = __shfl(im, lv);
+    c_rf = __shfl(rf, lv);
+  }
+  if (COUNT && lane == 0) cnt[g] = k;
+}
+
+// The same table when no listed cell spans two source groups (every listed
+// cell then holds at most n_group particles: direct_max <= n_group), entry by
+// entry in parallel: a segment starts at an entry that starts a run or, inside
+// a run, changes the source group; the lane of its first entry writes the
+// record and the lane of its last entry (or lane 0 of the next batch, for a
+// segment still open at the end of one) writes its end.
+template <bool COUNT>
+__global__ __launch_bounds__(kB) void k_pair_segs_flat(
+    int64_t G, const int64_t* __restrict__ p2p_off, const int32_t* __restrict__ p2p,
+    const int8_t* __restrict__ p2p_img, double side, const int32_t* __restrict__ c_first,
+    const int32_t* __restrict__ c_count, const int32_t* __restrict__ group_of,
+    const int32_t* __restrict__ g_cell, const double* __restrict__ c_centre,
+    int64_t* __restrict__ cnt, const int64_t* __restrict__ off, PairSeg* __restrict__ seg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (g >= G) return;
+  const int gc = g_cell[g];
+  const double cgx = c_centre[3 * gc], cgy = c_centre[3 * gc + 1], cgz = c_centre[3 * gc + 2];
+  int64_t k = COUNT ? 0 : off[g];
+  const int64_t e0 = p2p_off[g], e1 = p2p_off[g + 1];
+  // the previous entry's end, image and source group (c_end < 0 before the first)
+  int c_end = -1, c_img = kCentreImage, c_sg = -1;
+  for (int64_t b = e0; b < e1; b += 64) {
+    const int64_t e = b + lane;
+    const bool valid = e < e1;
+    int f = 0, en = 0, im = kCentreImage, sg = -1;
+    if (valid) {
+      const int c = p2p[e];
+      f = c_first[c];
+      en = f + c_count[c];
+      if (p2p_img) im = (int)p2p_img[e];
+      sg = group_of[f];
+    }
+    int pe = __shfl_up(en, 1), pim = __shfl_up(im, 1), psg = __shfl_up(sg, 1);
+    if (lane == 0) {
+      pe = c_end;
+      pim = c_img;
+      psg = c_sg;
+    }
+    const bool sstart = valid && (f != pe || im != pim || sg != psg);
+    const uint64_t smask = __ballot(sstart);
+    const uint64_t vmask = __ballot(valid);
+    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    // this entry's segment (k - 1 for one carried over from the last batch)
+    const int64_t idx = k + (int64_t)__popcll(smask & le) - 1;
+    const bool last = valid && ((lane < 63 && ((smask >> (lane + 1)) & 1ull)) || e + 1 == e1);
+    if (!COUNT) {
+      if (sstart) {
+        double shx = 0.0, shy = 0.0, shz = 0.0;
+        if (p2p_img) image_shift(im, side, shx, shy, shz);
+        const int sc = g_cell[sg];
+        PairSeg* r = seg + idx;
+        r->first = f;
+        r->self = (sg == g && im == kCentreImage) ? 1 : 0;
+        r->pad = 0;
+        if (p2p_img) {
+          r->dx = (c_centre[3 * sc] + shx) - cgx;
+          r->dy = (c_centre[3 * sc + 1] + shy) - cgy;
+          r->dz = (c_centre[3 * sc + 2] + shz) - cgz;
+        } else {
+          r->dx = c_centre[3 * sc] - cgx;
+          r->dy = c_centre[3 * sc + 1] - cgy;
+          r->dz = c_centre[3 * sc + 2] - cgz;
+        }
+      }
+      if (last) seg[idx].end = en;
+      if (lane == 0 && sstart && c_end >= 0) seg[k - 1].end = c_end;
+    }
+    k += (int64_t)__popcll(smask);
+    const int lv = 63 - __clzll(vmask);
+    c_end = __shfl(en, lv);
+    c_img = __shfl(im, lv);
+    c_sg = __shfl(sg, lv);
+  }
+  if (COUNT && lane == 0) cnt[g] = k;
+}
+
+// The pair-segment table of the current P2P lists (count, scan, one host
+// sync for the total, fill).
+void build_pair_segs(hot_ctx* ctx, hot_tree* t) {
+  hipStream_t st = ctx->stream;
+  const int64_t G = t->n_groups;
+  const int8_t* img = t->periodic ? t->p2p_img.as<int8_t>() : nullptr;
+  t->pseg_off.alloc(ctx, (G + 1) * sizeof(int64_t));
+  // listed cells lie inside one source group when they hold at most n_group
+  // particles (leaves hold at most n_leaf <= n_group)
+  const bool flat = t->direct_max <= t->n_group;
+  if (flat)
+    k_pair_segs_flat<true><<<grid_for(G, kWavesPerBlock), kB, 0, st>>>(
+        G, t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), img, t->side,
+        t->c_first.as<int32_t>(), t->c_count.as<int32_t>(), t->group_of.as<int32_t>(),
+        t->g_cell.as<int32_t>(), t->c_centre.as<double>(), t->pseg_off.as<int64_t>(), nullptr,
+        nullptr);
+  else
+    k_pair_segs<true><<<grid_for(G, kWavesPerBlock), kB, 0, st>>>(
+        G, t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), img, t->side, t->c_first.as<int32_t>(),
+        t->c_count.as<int32_t>(), t->group_of.as<int32_t>(), t->g_first.as<int32_t>(),
+        t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(),
+        t->pseg_off.as<int64_t>(), nullptr, nullptr, ctx->d_flags + kFlagLocal);
+  HOT_CHECK_LAUNCH();
+  int64_t* so = t->pseg_off.as<int64_t>();
+  scan_i64(ctx, so, so, G, so + G);
+  int64_t ns = 0;
+  unsigned fl = 0;
+  HOT_HIP(hipMemcpyAsync(&ns, so + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipMemcpyAsync(&fl, ctx->d_flags + kFlagLocal, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipStreamSynchronize(st));
+  if (fl & FLAG_INTERNAL) throw Error{HOT_E_DEVICE, "pair segment consistency check failed"};
+  t->n_psegs = ns;
+  t->pseg.alloc(ctx, (size_t)std::max<int64_t>(1, ns) * sizeof(PairSeg));
+  if (flat)
+    k_pair_segs_flat<false><<<grid_for(G, kWavesPerBlock), kB, 0, st>>>(
+        G, t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), img, t->side,
+        t->c_first.as<int32_t>(), t->c_count.as<int32_t>(), t->group_of.as<int32_t>(),
+        t->g_cell.as<int32_t>(), t->c_centre.as<double>(), nullptr, so, t->pseg.as<PairSeg>());
+  else
+    k_pair_segs<false><<<grid_for(G, kWavesPerBlock), kB, 0, st>>>(
+        G, t->p2p_off.as<int64_t>(), t->p2p.as<int32_t>(), img, t->side, t->c_first.as<int32_t>(),
+        t->c_count.as<int32_t>(), t->group_of.as<int32_t>(), t->g_first.as<int32_t>(),
+        t->g_count.as<int32_t>(), t->g_cell.as<int32_t>(), t->c_centre.as<double>(), nullptr, so,
+        t->pseg.as<PairSeg>(), ctx->d_flags + kFlagLocal);
+  HOT_CHECK_LAUNCH();
+}
+
 template <bool ERR, bool PER, bool BG = false>
 void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_max,
                 int width = 3) {
@@ -458,6 +708,7 @@ void walk_lists(hot_ctx* ctx, hot_tree* t, double theta, ErrMac em, int direct_m
   t->periodic = PER;
   t->bg = BG;
   t->bg_width = width;
+  build_pair_segs(ctx, t);
   t->has_lists = true;
 }
 

@@ -325,3 +325,43 @@ def test_small_items_sliced(p):
     assert_sinks_kappa(ga64.cpu().numpy(), oa, cs, KAPPA_C_FP64, "forces fp64")
     assert_sinks(gx, ox, SINK_TOL_MIXED, "adjoint mixed")
     assert_sinks(gx64.cpu().numpy(), ox, SINK_TOL_FP64, "adjoint fp64")
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_pair_segments_cells_larger_than_groups(periodic):
+    """direct_max above n_group: a pair-summed cell can hold several source
+    groups, so the pair-segment table cuts inside list entries (the run walk
+    of the list builder, not its entry-parallel form). Forces and the
+    adjoint against the oracle on the same lists."""
+    w = W.make("clustered4m", n=12000)
+    w.n_leaf, w.n_group = 8, 24
+    dmax = 200
+    pos, mass = to_dev(w)
+    box = (0.0, 0.0, 0.0, 1.0) if periodic else w.box
+    wpos = np.mod(w.pos, 1.0) if periodic else w.pos
+    if periodic:
+        pos = torch.from_numpy(wpos).cuda()
+    gt = Tree(pos, w.n_leaf, w.n_group, box)
+    ot = oracle.Tree(wpos, w.n_leaf, w.n_group, box)
+    if periodic:
+        gt.build_interaction_lists_periodic(0.5, dmax)
+        ot.build_lists_periodic(0.5, dmax)
+    else:
+        gt.build_interaction_lists(0.5, dmax)
+        ot.build_lists(0.5, dmax)
+    assert_lists_equal(gt, ot)
+    cells = ot.cells()
+    po, pl, _, _ = ot.lists()
+    assert (cells["count"][pl] > w.n_group).any(), "no listed cell spans groups"
+    gt.compute_moments(pos, mass, 4)
+    ot.compute_moments(wpos, w.mass, 4)
+    oa, _, _ = ot.eval(wpos, w.mass, w.eps, with_pot=False)
+    for prec, tol in ((HOT_FP64, 1e-12), (HOT_MIXED, 1e-5)):
+        ga, _, _ = gt.eval_forces(pos, mass, w.eps, prec)
+        e = rel_rms(ga.cpu().numpy(), oa)
+        _log("segments inside entries", "periodic" if periodic else "open", prec, e)
+        assert e <= tol
+    abar_np = W.cotangent(w.n, 404)
+    ox, _ = ot.vjp(wpos, w.mass, w.eps, abar_np)
+    gx, _ = gt.eval_forces_adjoint(pos, mass, w.eps, torch.from_numpy(abar_np).cuda(), HOT_FP64)
+    assert rel_rms(gx.cpu().numpy(), ox) <= 1e-11
