@@ -66,8 +66,14 @@ typedef struct hot_ctx hot_ctx;
 typedef struct hot_tree hot_tree;
 
 /* Optional device allocator. alloc returns NULL on failure; both run on the
- * caller's thread and receive the context stream. NULL selects
- * hipMallocAsync / hipFreeAsync on the context stream. */
+ * caller's thread and receive the stream that first uses the block: the
+ * context stream, except for the adjoint's transposed lists, which the
+ * library builds on a second stream of its own (it starts after all work
+ * queued on the context stream before the call, and the context stream waits
+ * for it before reading them). The allocator must order reuse by that
+ * stream: a block freed on one stream may go to another only once the work
+ * queued before the free has finished. NULL selects hipMallocAsync /
+ * hipFreeAsync on the given stream, which does so. */
 typedef struct hot_allocator {
   void* (*alloc)(void* user, size_t bytes, void* stream);
   void (*free)(void* user, void* ptr, void* stream);
@@ -298,7 +304,11 @@ int eval_forces(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* m
  * (second derivatives of the expansion) and the source particles through the
  * moments (centres fixed). acc_bar: N x 3 (device). pos_bar: N x 3 out.
  * mass_bar: N out or NULL. Same precision modes as eval_forces. The first call
- * on a tree builds and caches transposed lists.
+ * on a tree builds and caches transposed lists, on a second stream of the
+ * context (created on first use) while the sink-side terms run on the
+ * context stream; it waits for them on the host twice (list counts) and the
+ * context stream waits for them before the source-side terms. Later calls
+ * use only the context stream.
  */
 int eval_forces_adjoint(hot_ctx* ctx, hot_tree* tree, const double* pos, const double* mass,
                         double eps, int precision, const double* acc_bar, double* pos_bar,

@@ -133,10 +133,23 @@ class Context:
         if torch_alloc:
             dev = torch.device("cuda", device)
 
+            main = self.stream.cuda_stream
+            side = {}
+
             def _a(user, nbytes, stream):
+                # the block belongs to the stream that first uses it (the
+                # library's second stream for the adjoint's transposed
+                # lists), so that the caching allocator never hands it to
+                # another stream while work queued there may still use it
                 self.n_allocs += 1
                 try:
-                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+                    if not stream or stream == main:
+                        t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+                    else:
+                        if stream not in side:
+                            side[stream] = torch.cuda.ExternalStream(stream, device=dev)
+                        with torch.cuda.stream(side[stream]):
+                            t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
                 except RuntimeError:
                     return None
                 self._blocks[t.data_ptr()] = t

@@ -1456,11 +1456,10 @@ void build_transpose(hot_ctx* ctx, hot_tree* t) {
   t->has_transpose = true;
 }
 
+// expansion terms, sink side (needs no transposed lists)
 template <int P, typename T, bool K1>
-void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<T>* ab,
-                          const T* momw, const T* momsub, double eps, T* sink_state,
-                          double* mbar64,
-                          const double* pos, const double* abar) {
+void launch_expansion_sink_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<T>* ab,
+                               const T* momw, const T* momsub, double eps, T* sink_state) {
   hipStream_t st = ctx->stream;
   const double inv_side = 1.0 / t->side;
   const bool mixq = t->list_p >= 0;
@@ -1507,6 +1506,17 @@ void launch_expansion_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<
   else
     sink(k_m2p_sink_adj<P, T, false, false, false, K1>);
   tmark(ctx, HOT_T_ADJ_M2P_SINK, true);
+}
+
+// expansion terms, the moment cotangents (cell side, on the transposed
+// lists), then down the tree
+template <int P, typename T, bool K1>
+void launch_expansion_cell_adj(hot_ctx* ctx, hot_tree* t, const V4<T>* off, const V4<T>* ab,
+                               double eps, double* mbar64, const double* pos,
+                               const double* abar) {
+  hipStream_t st = ctx->stream;
+  const double inv_side = 1.0 / t->side;
+  const bool mixq = t->list_p >= 0;
   const int64_t C = t->n_cells;
   DBuf part;
   part.alloc(ctx, (size_t)std::max<int64_t>(1, t->n_citems) * nm_pad(P) * sizeof(T));
@@ -1598,18 +1608,82 @@ void launch_p2mT(hot_ctx* ctx, hot_tree* t, const double* spos, const double* sm
 }
 
 template <typename T, bool K1>
-void launch_expansion_adj_k(hot_ctx* ctx, hot_tree* t, const V4<T>* o4, const V4<T>* a4,
-                            const T* momw, const T* momsub, double eps, T* S, double* M,
-                            const double* pos, const double* abar) {
+void launch_expansion_sink_adj_k(hot_ctx* ctx, hot_tree* t, const V4<T>* o4, const V4<T>* a4,
+                                 const T* momw, const T* momsub, double eps, T* S) {
   switch (t->p) {
 #define HOT_EXP_ADJ(Q) \
-  case Q: launch_expansion_adj<Q, T, K1>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar); break;
+  case Q: launch_expansion_sink_adj<Q, T, K1>(ctx, t, o4, a4, momw, momsub, eps, S); break;
     HOT_EXP_ADJ(0) HOT_EXP_ADJ(1) HOT_EXP_ADJ(2) HOT_EXP_ADJ(3) HOT_EXP_ADJ(4) HOT_EXP_ADJ(5)
     HOT_EXP_ADJ(6) HOT_EXP_ADJ(7) HOT_EXP_ADJ(8)
 #undef HOT_EXP_ADJ
     default: invalid("p out of range");
   }
 }
+
+template <typename T, bool K1>
+void launch_expansion_cell_adj_k(hot_ctx* ctx, hot_tree* t, const V4<T>* o4, const V4<T>* a4,
+                                 double eps, double* M, const double* pos, const double* abar) {
+  switch (t->p) {
+#define HOT_EXP_ADJ(Q) \
+  case Q: launch_expansion_cell_adj<Q, T, K1>(ctx, t, o4, a4, eps, M, pos, abar); break;
+    HOT_EXP_ADJ(0) HOT_EXP_ADJ(1) HOT_EXP_ADJ(2) HOT_EXP_ADJ(3) HOT_EXP_ADJ(4) HOT_EXP_ADJ(5)
+    HOT_EXP_ADJ(6) HOT_EXP_ADJ(7) HOT_EXP_ADJ(8)
+#undef HOT_EXP_ADJ
+    default: invalid("p out of range");
+  }
+}
+
+// The transposed lists on the context's second stream: it starts after all
+// work queued on the main stream so far (the lists), the sink-side kernels
+// queued on the main stream next run meanwhile, and join() makes the main
+// stream wait for it before anything that reads the transposed lists. The
+// transposes allocate, run and free on the second stream (the context's
+// stream is switched for the duration); on an error the second stream is
+// drained before the error propagates.
+struct TransposeAside {
+  hot_ctx* ctx;
+  hipStream_t main;
+  bool active = false;
+  TransposeAside(hot_ctx* c, bool need) : ctx(c), main(c->stream) {
+    if (!need) return;
+    if (!ctx->aux) {
+      HOT_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+      for (auto& e : ctx->xev) HOT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    HOT_HIP(hipEventRecord(ctx->xev[0], main));
+    HOT_HIP(hipStreamWaitEvent(ctx->aux, ctx->xev[0], 0));
+    active = true;
+  }
+  // build the transposed lists on the second stream (the main stream keeps
+  // running what was queued on it)
+  void build(hot_tree* t) {
+    if (!active) return;
+    ctx->stream = ctx->aux;
+    try {
+      Phase ph(ctx, HOT_T_ADJ_TRANSPOSE);
+      build_transpose(ctx, t);
+    } catch (...) {
+      ctx->stream = main;
+      (void)hipStreamSynchronize(ctx->aux);
+      active = false;
+      throw;
+    }
+    ctx->stream = main;
+  }
+  void join() {
+    if (!active) return;
+    HOT_HIP(hipEventRecord(ctx->xev[1], ctx->aux));
+    HOT_HIP(hipStreamWaitEvent(main, ctx->xev[1], 0));
+    active = false;
+  }
+  ~TransposeAside() {
+    if (active) {
+      // an error between build and join: nothing may outlive the call
+      ctx->stream = main;
+      (void)hipStreamSynchronize(ctx->aux);
+    }
+  }
+};
 
 template <typename T>
 void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass, double eps,
@@ -1618,10 +1692,8 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
   hipStream_t st = ctx->stream;
   const int64_t n = t->n, C = t->n_cells;
   const int p = t->p;
-  if (!t->has_transpose) {
-    Phase ph(ctx, HOT_T_ADJ_TRANSPOSE);
-    build_transpose(ctx, t);
-  }
+  // the transposed lists (source side) are built beside the sink-side work
+  TransposeAside aside(ctx, !t->has_transpose);
   DBuf off, ab, ab3, sink, src, mbar64, spos, smass, xb, mb;
   off.alloc(ctx, n * sizeof(V4<T>));
   ab.alloc(ctx, n * sizeof(V4<T>));
@@ -1655,13 +1727,37 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
                             t->g_count.as<int32_t>(), off.as<V4<T>>(), ab.as<V4<T>>(), e2, ie,
                             ctx->d_flags + kFlagMass, sink.as<T>());
   HOT_CHECK_LAUNCH();
+  tmark(ctx, HOT_T_ADJ_P2P_SINK, true);
+  // expansion terms
+  const T* momw = nullptr;
+  const T* momsub = nullptr;
+  if (t->bg) {
+    weighted_sub(ctx, t, sizeof(T) == 8);
+    momsub = t->momsub.as<T>();
+  }
+  if constexpr (sizeof(T) == 4) {
+    momw = t->mom32.as<T>();
+  } else {
+    weighted_fp64(ctx, t);
+    momw = t->momw64.as<T>();
+  }
+  V4<T>* o4 = off.as<V4<T>>();
+  V4<T>* a4 = ab.as<V4<T>>();
+  double* M = mbar64.as<double>();
+  T* S = sink.as<T>();
+  if (k1)
+    launch_expansion_sink_adj_k<T, true>(ctx, t, o4, a4, momw, momsub, eps, S);
+  else
+    launch_expansion_sink_adj_k<T, false>(ctx, t, o4, a4, momw, momsub, eps, S);
+  // the source side reads the transposed lists
+  aside.build(t);
+  aside.join();
   auto src_k = k1 ? (t->periodic ? k_p2p_src_adj<T, false, true, true>
                                  : k_p2p_src_adj<T, false, false, true>)
              : t->periodic ? (e2 > T(0) ? k_p2p_src_adj<T, false, true, false>
                                         : k_p2p_src_adj<T, true, true, false>)
                            : (e2 > T(0) ? k_p2p_src_adj<T, false, false, false>
                                         : k_p2p_src_adj<T, true, false, false>);
-  tmark(ctx, HOT_T_ADJ_P2P_SINK, true);
   const int64_t NU = t->n_schunk;
   DBuf upart;
   if (NU > t->n_items) upart.alloc(ctx, (size_t)NU * 64 * 8 * sizeof(T));
@@ -1681,27 +1777,10 @@ void adjoint_t(hot_ctx* ctx, hot_tree* t, const double* pos, const double* mass,
     HOT_CHECK_LAUNCH();
   }
   tmark(ctx, HOT_T_ADJ_P2P_SOURCE, true);
-  // expansion terms
-  const T* momw = nullptr;
-  const T* momsub = nullptr;
-  if (t->bg) {
-    weighted_sub(ctx, t, sizeof(T) == 8);
-    momsub = t->momsub.as<T>();
-  }
-  if constexpr (sizeof(T) == 4) {
-    momw = t->mom32.as<T>();
-  } else {
-    weighted_fp64(ctx, t);
-    momw = t->momw64.as<T>();
-  }
-  V4<T>* o4 = off.as<V4<T>>();
-  V4<T>* a4 = ab.as<V4<T>>();
-  double* M = mbar64.as<double>();
-  T* S = sink.as<T>();
   if (k1)
-    launch_expansion_adj_k<T, true>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar);
+    launch_expansion_cell_adj_k<T, true>(ctx, t, o4, a4, eps, M, pos, abar);
   else
-    launch_expansion_adj_k<T, false>(ctx, t, o4, a4, momw, momsub, eps, S, M, pos, abar);
+    launch_expansion_cell_adj_k<T, false>(ctx, t, o4, a4, eps, M, pos, abar);
   const double* sp = spos.as<double>();
   const double* sm = smass.as<double>();
   switch (p) {

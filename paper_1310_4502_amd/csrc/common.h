@@ -98,6 +98,12 @@ struct hot_ctx {
   std::string err;
   unsigned* d_flags = nullptr;     // device error flags: [kFlagDeferred], [kFlagLocal]
   hipEvent_t ev[8]{};
+  // a second stream of the library's own (default priority) on which the
+  // adjoint builds its transposed lists while the sink-side kernels run on
+  // `stream`, and the two events that order it against `stream`; created on
+  // first use
+  hipStream_t aux = nullptr;
+  hipEvent_t xev[2]{};
   // phase timers (hot_set_timing): start and end event of every phase, and
   // whether the phase has been recorded since timing was switched on
   bool timing = false;
