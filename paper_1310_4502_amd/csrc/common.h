@@ -181,6 +181,7 @@ struct hot_tree {
   double side = 1.0;
   // particles (sorted order)
   hot::DBuf key, perm, spos, lambda, group_of, leaf_of, item_of;
+  hot::DBuf leaf_list;  // leaf cells in particle order (n_leaves of them)
   // root cube on device: lo[3], side, scale = 2^21 / side
   hot::DBuf root;
   // cells

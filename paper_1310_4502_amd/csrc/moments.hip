@@ -39,32 +39,6 @@ __global__ void k_gather_pm(const double* __restrict__ pos, const double* __rest
 }
 
 template <int N>
-__device__ __forceinline__ void p2m_order(const double* __restrict__ spos,
-                                          const double* __restrict__ smass, int64_t n, int first,
-                                          int count, const double* c, double* __restrict__ out) {
-  constexpr int K = (N + 1) * (N + 2) / 2;
-  double acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int j = first; j < first + count; ++j) {
-    const double dx = spos[j] - c[0], dy = spos[n + j] - c[1], dz = spos[2 * n + j] - c[2];
-    const double m = smass[j];
-    if constexpr (N == 0) p2m_order0(dx, dy, dz, m, acc);
-    if constexpr (N == 1) p2m_order1(dx, dy, dz, m, acc);
-    if constexpr (N == 2) p2m_order2(dx, dy, dz, m, acc);
-    if constexpr (N == 3) p2m_order3(dx, dy, dz, m, acc);
-    if constexpr (N == 4) p2m_order4(dx, dy, dz, m, acc);
-    if constexpr (N == 5) p2m_order5(dx, dy, dz, m, acc);
-    if constexpr (N == 6) p2m_order6(dx, dy, dz, m, acc);
-    if constexpr (N == 7) p2m_order7(dx, dy, dz, m, acc);
-    if constexpr (N == 8) p2m_order8(dx, dy, dz, m, acc);
-  }
-  const int off = N * (N + 1) * (N + 2) / 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) out[off + k] = acc[k];
-}
-
-template <int N>
 __device__ __forceinline__ void m2m_order(const double* __restrict__ mom, int nmv, int cf, int nc,
                                           const double* __restrict__ centre, const double* cp,
                                           double* __restrict__ out) {
@@ -91,34 +65,113 @@ __device__ __forceinline__ void m2m_order(const double* __restrict__ mom, int nm
   for (int k = 0; k < K; ++k) out[off + k] = acc[k];
 }
 
-// leaves only (P2M)
-__global__ __launch_bounds__(kB) void k_p2m(int64_t C, const int32_t* __restrict__ c_first,
+// Leaves only (P2M). One wavefront per 64 consecutive entries of the leaf list
+// (leaves in particle order) and one order, the block's: the 64 leaves'
+// particles form one contiguous range, staged through LDS in chunks by
+// coalesced loads, and lane l sums its own leaf's particles in order. The
+// moments leave through LDS in slices of kP2mSlice values per leaf, so that
+// neighbouring lanes store neighbouring addresses of a leaf's row.
+constexpr int kP2mChunk = 256;
+constexpr int kP2mSlice = 16;
+
+template <int N>
+__device__ __forceinline__ void p2m_run(int64_t run, const int32_t* __restrict__ leaf_list,
+                                        int64_t n_leaves, const int32_t* __restrict__ c_first,
+                                        const int32_t* __restrict__ c_count,
+                                        const double* __restrict__ c_centre,
+                                        const double* __restrict__ spos,
+                                        const double* __restrict__ smass, int64_t n, int nmv,
+                                        double* __restrict__ mom, double* lds, int* s_cell) {
+  constexpr int K = (N + 1) * (N + 2) / 2;
+  constexpr int OFF = N * (N + 1) * (N + 2) / 6;
+  constexpr int NS = (K + kP2mSlice - 1) / kP2mSlice;
+  constexpr int TS = kP2mSlice + 1;  // tile row stride (odd: spreads the banks)
+  const int lane = threadIdx.x;
+  const int nv = (int)(n_leaves - run * 64 < 64 ? n_leaves - run * 64 : 64);
+  int c = 0, f = 0, e = 0;
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+  if (lane < nv) {
+    c = leaf_list[run * 64 + lane];
+    f = c_first[c];
+    e = f + c_count[c];
+    cx = c_centre[3 * c];
+    cy = c_centre[3 * c + 1];
+    cz = c_centre[3 * c + 2];
+  }
+  s_cell[lane] = c;  // read after the barriers below
+  const int start = __shfl(f, 0), end = __shfl(e, nv - 1);
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  double* X = lds;
+  double* Y = lds + kP2mChunk;
+  double* Z = lds + 2 * kP2mChunk;
+  double* M = lds + 3 * kP2mChunk;
+  for (int s = start; s < end; s += kP2mChunk) {
+    const int w = end - s < kP2mChunk ? end - s : kP2mChunk;
+    __syncthreads();  // the previous chunk has been read
+    for (int i = lane; i < w; i += 64) {
+      X[i] = spos[s + i];
+      Y[i] = spos[n + s + i];
+      Z[i] = spos[2 * n + s + i];
+      M[i] = smass[s + i];
+    }
+    __syncthreads();
+    const int j0 = f > s ? f : s, j1 = e < s + w ? e : s + w;
+    for (int j = j0; j < j1; ++j) {
+      const int q = j - s;
+      const double dx = X[q] - cx, dy = Y[q] - cy, dz = Z[q] - cz;
+      if constexpr (N == 0) p2m_order0(dx, dy, dz, M[q], acc);
+      if constexpr (N == 1) p2m_order1(dx, dy, dz, M[q], acc);
+      if constexpr (N == 2) p2m_order2(dx, dy, dz, M[q], acc);
+      if constexpr (N == 3) p2m_order3(dx, dy, dz, M[q], acc);
+      if constexpr (N == 4) p2m_order4(dx, dy, dz, M[q], acc);
+      if constexpr (N == 5) p2m_order5(dx, dy, dz, M[q], acc);
+      if constexpr (N == 6) p2m_order6(dx, dy, dz, M[q], acc);
+      if constexpr (N == 7) p2m_order7(dx, dy, dz, M[q], acc);
+      if constexpr (N == 8) p2m_order8(dx, dy, dz, M[q], acc);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    __syncthreads();  // the staging area (or the previous slice) is free
+#pragma unroll
+    for (int k = 0; k < kP2mSlice; ++k)
+      if (r * kP2mSlice + k < K) lds[lane * TS + k] = acc[r * kP2mSlice + k < K ? r * kP2mSlice + k : 0];
+    __syncthreads();
+    const int W = K - r * kP2mSlice < kP2mSlice ? K - r * kP2mSlice : kP2mSlice;
+    for (int i = lane; i < nv * W; i += 64) {
+      const int l = i / W, k = i - l * W;
+      mom[(int64_t)s_cell[l] * nmv + OFF + r * kP2mSlice + k] = lds[l * TS + k];
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_p2m(int64_t n_leaves, const int32_t* __restrict__ leaf_list,
+                                            const int32_t* __restrict__ c_first,
                                             const int32_t* __restrict__ c_count,
-                                            const uint8_t* __restrict__ c_leaf,
                                             const double* __restrict__ c_centre,
                                             const double* __restrict__ spos,
                                             const double* __restrict__ smass, int64_t n, int p,
                                             double* __restrict__ mom) {
+  __shared__ double lds[64 * (kP2mSlice + 1)];
+  __shared__ int s_cell[64];
+  static_assert(64 * (kP2mSlice + 1) >= 4 * kP2mChunk, "staging area");
   int64_t run;
   int ord;
   order_block(p, run, ord);
-  const int64_t c = run * kB + threadIdx.x;
-  if (c >= C || !c_leaf[c]) return;
+  if (run * 64 >= n_leaves) return;
   const int nmv = nm(p);
-  double* out = mom + c * nmv;
-  const double cc[3] = {c_centre[3 * c], c_centre[3 * c + 1], c_centre[3 * c + 2]};
-  const int f = c_first[c], cnt = c_count[c];
+#define HOT_P2M_RUN(Q)                                                                         \
+  case Q:                                                                                      \
+    p2m_run<Q>(run, leaf_list, n_leaves, c_first, c_count, c_centre, spos, smass, n, nmv, mom, \
+               lds, s_cell);                                                                           \
+    break;
   switch (ord) {
-    case 0: p2m_order<0>(spos, smass, n, f, cnt, cc, out); break;
-    case 1: p2m_order<1>(spos, smass, n, f, cnt, cc, out); break;
-    case 2: p2m_order<2>(spos, smass, n, f, cnt, cc, out); break;
-    case 3: p2m_order<3>(spos, smass, n, f, cnt, cc, out); break;
-    case 4: p2m_order<4>(spos, smass, n, f, cnt, cc, out); break;
-    case 5: p2m_order<5>(spos, smass, n, f, cnt, cc, out); break;
-    case 6: p2m_order<6>(spos, smass, n, f, cnt, cc, out); break;
-    case 7: p2m_order<7>(spos, smass, n, f, cnt, cc, out); break;
-    case 8: p2m_order<8>(spos, smass, n, f, cnt, cc, out); break;
+    HOT_P2M_RUN(0) HOT_P2M_RUN(1) HOT_P2M_RUN(2) HOT_P2M_RUN(3) HOT_P2M_RUN(4)
+    HOT_P2M_RUN(5) HOT_P2M_RUN(6) HOT_P2M_RUN(7) HOT_P2M_RUN(8)
   }
+#undef HOT_P2M_RUN
 }
 
 // one level of internal cells [c0, c1)
@@ -270,10 +323,11 @@ void build_moments(hot_ctx* ctx, hot_tree* t, const double* pos, const double* m
   t->mom64.alloc(ctx, (size_t)C * nm(p) * sizeof(double));
   t->p = -1;
   {
-    k_p2m<<<order_grid(grid_for(C, kB), p), kB, 0, st>>>(C, t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
-                               t->c_leaf.as<uint8_t>(), t->c_centre.as<double>(),
-                               spos.as<double>(), smass.as<double>(), n, p,
-                               t->mom64.as<double>());
+    const int64_t NL = t->n_leaves;
+    k_p2m<<<order_grid((NL + 63) / 64, p), 64, 0, st>>>(
+        NL, t->leaf_list.as<int32_t>(), t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
+        t->c_centre.as<double>(), spos.as<double>(), smass.as<double>(), n, p,
+        t->mom64.as<double>());
     HOT_CHECK_LAUNCH();
   }
   for (int L = t->max_level - 1; L >= 0; --L) {

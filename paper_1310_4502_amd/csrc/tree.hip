@@ -460,6 +460,25 @@ __global__ void k_leaf_fill(const int32_t* __restrict__ c_first, const int32_t* 
   for (int j = f; j < e; ++j) leaf_of[j] = (int32_t)c;
 }
 
+// Leaves in particle (Morton) order: leaf_of changes value exactly where a
+// leaf starts, so the leaves' ranks are an exclusive scan of those starts;
+// consecutive entries of the list hold consecutive particle ranges.
+__device__ __forceinline__ bool leaf_starts(const int32_t* __restrict__ leaf_of, int64_t j) {
+  return j == 0 || leaf_of[j] != leaf_of[j - 1];
+}
+
+__global__ void k_leaf_flags(const int32_t* __restrict__ leaf_of, int64_t n,
+                             uint32_t* __restrict__ f) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) f[j] = leaf_starts(leaf_of, j) ? 1u : 0u;
+}
+
+__global__ void k_leaf_compact(const int32_t* __restrict__ leaf_of, const uint32_t* __restrict__ rank,
+                               int64_t n, int32_t* __restrict__ leaf_list) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n && leaf_starts(leaf_of, j)) leaf_list[rank[j]] = leaf_of[j];
+}
+
 // item_of[j]: the eval work item (group chunk of at most 64 particles) of j.
 __global__ void k_item_of(const int2* __restrict__ items, int64_t n_items,
                           const int32_t* __restrict__ g_first, const int32_t* __restrict__ g_count,
@@ -646,17 +665,27 @@ void build_tree(hot_ctx* ctx, hot_tree* t, const double* pos, const double* box)
   k_chunks<<<grid_for(G, kB), kB, 0, st>>>(t->g_count.as<int32_t>(), G, nch.as<uint32_t>());
   HOT_CHECK_LAUNCH();
   scan_u32(ctx, nch.as<uint32_t>(), nch.as<uint32_t>(), G, ntot.as<uint32_t>());
-  uint32_t NI = 0;
-  HOT_HIP(hipMemcpyAsync(&NI, ntot.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HOT_HIP(hipStreamSynchronize(st));
-  t->n_items = NI;
-  t->items.alloc(ctx, (size_t)NI * sizeof(int2));
-  k_items<<<grid_for(G, kB), kB, 0, st>>>(t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
-                                         nch.as<uint32_t>(), G, t->items.as<int2>());
-  HOT_CHECK_LAUNCH();
+  // ---- leaves: owner of every particle, and the list in particle order
   t->leaf_of.alloc(ctx, n * sizeof(int32_t));
   k_leaf_fill<<<gc, kB, 0, st>>>(t->c_first.as<int32_t>(), t->c_count.as<int32_t>(),
                                 t->c_leaf.as<uint8_t>(), C, t->leaf_of.as<int32_t>());
+  HOT_CHECK_LAUNCH();
+  k_leaf_flags<<<gb, kB, 0, st>>>(t->leaf_of.as<int32_t>(), n, gflag.as<uint32_t>());
+  HOT_CHECK_LAUNCH();
+  scan_u32(ctx, gflag.as<uint32_t>(), gflag.as<uint32_t>(), n, gtot.as<uint32_t>() + 1);
+  t->leaf_list.alloc(ctx, C * sizeof(int32_t));
+  k_leaf_compact<<<gb, kB, 0, st>>>(t->leaf_of.as<int32_t>(), gflag.as<uint32_t>(), n,
+                                    t->leaf_list.as<int32_t>());
+  HOT_CHECK_LAUNCH();
+  uint32_t NI = 0, NL = 0;
+  HOT_HIP(hipMemcpyAsync(&NI, ntot.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipMemcpyAsync(&NL, gtot.as<uint32_t>() + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HOT_HIP(hipStreamSynchronize(st));
+  t->n_items = NI;
+  t->n_leaves = NL;
+  t->items.alloc(ctx, (size_t)NI * sizeof(int2));
+  k_items<<<grid_for(G, kB), kB, 0, st>>>(t->g_first.as<int32_t>(), t->g_count.as<int32_t>(),
+                                         nch.as<uint32_t>(), G, t->items.as<int2>());
   HOT_CHECK_LAUNCH();
   t->item_of.alloc(ctx, n * sizeof(int32_t));
   k_item_of<<<grid_for(NI, kB), kB, 0, st>>>(t->items.as<int2>(), NI, t->g_first.as<int32_t>(),
