@@ -106,7 +106,9 @@ typedef struct hot_stats {
 /* Phases timed by the context when timing is on (hot_set_timing): each
  * entry point and, inside the evaluation and the adjoint, each interaction
  * kernel. The adjoint's transpose phase is the first call's construction of
- * the transposed lists; its downward phase is the moment cotangents' pass
+ * the transposed lists, recorded on the context's second stream: it runs
+ * beside the sink-side kernels, so its duration is the wall time it spans
+ * while sharing the GPU with them, not its cost alone; its downward phase is the moment cotangents' pass
  * down the tree (M2M transposed), the moment-to-particle transpose, the far
  * replicas and background terms, and the final write-back. */
 enum {
