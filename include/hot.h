@@ -340,7 +340,8 @@ int eval_forces_noalloc(hot_ctx* ctx, hot_tree* tree, const double* pos, const d
 
 /* out[16]: n, n_cells, n_groups, n_leaves, max_level, n_p2p_entries,
  * n_m2p_entries, p (or -1), n_work_items, hash_slots, p2p_pairs, m2p_pairs,
- * n_background_boxes, 0... (-1 where not yet built or not applicable). */
+ * n_background_boxes, entries of the particle-ordered leaf list (equal to
+ * n_leaves), 0... (-1 where not yet built or not applicable). */
 int tree_get_counts(hot_ctx* ctx, hot_tree* tree, int64_t* out);
 /* HOST: lo_side[4] = root cube lo[3], side. */
 int tree_get_root(hot_ctx* ctx, hot_tree* tree, double* lo_side);

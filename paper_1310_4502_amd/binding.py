@@ -130,6 +130,7 @@ class Context:
         self._blocks = {}
         self._alloc = None
         self.n_allocs = 0  # calls of the allocator callback
+        self.n_side_allocs = 0  # of them, blocks first used on the library's second stream
         if torch_alloc:
             dev = torch.device("cuda", device)
 
@@ -146,6 +147,7 @@ class Context:
                     if not stream or stream == main:
                         t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
                     else:
+                        self.n_side_allocs += 1
                         if stream not in side:
                             side[stream] = torch.cuda.ExternalStream(stream, device=dev)
                         with torch.cuda.stream(side[stream]):
@@ -368,7 +370,7 @@ class Tree:
         out = np.zeros(16, np.int64)
         self.ctx.check(load().tree_get_counts(self.ctx.h, self.h, _np(out)))
         keys = ["n", "n_cells", "n_groups", "n_leaves", "max_level", "n_p2p", "n_m2p", "p",
-                "n_items", "hash_slots", "p2p_pairs", "m2p_pairs", "n_boxes"]
+                "n_items", "hash_slots", "p2p_pairs", "m2p_pairs", "n_boxes", "n_leaf_list"]
         return {k: int(out[i]) for i, k in enumerate(keys)}
 
     def root(self):

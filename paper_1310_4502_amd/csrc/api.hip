@@ -457,6 +457,7 @@ int tree_get_counts(hot_ctx* ctx, hot_tree* t, int64_t* out) {
     out[10] = t->has_lists ? t->p2p_pairs : -1;
     out[11] = t->has_lists ? t->m2p_pairs : -1;
     out[12] = t->has_lists && t->bg ? t->n_boxes : -1;
+    out[13] = t->n_leaves;
   });
 }
 

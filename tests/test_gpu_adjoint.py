@@ -192,3 +192,39 @@ def test_torch_autograd_function():
     (acc * abar).sum().backward()
     ref, _ = t.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_FP64)
     assert torch.allclose(x.grad, ref, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("torch_alloc", [True, False])
+def test_adjoint_transposes_on_second_stream(torch_alloc):
+    """The first adjoint on a tree builds the transposed lists on the
+    context's second stream while the sink-side terms run on the context
+    stream. With either allocator (the torch caching allocator told the
+    stream, or hipMallocAsync) the first call, the call on cached lists and
+    the first call after the lists are rebuilt give bit-identical results,
+    in both precisions."""
+    from paper_1310_4502_amd.binding import Context
+    w = W.make("clustered4m", n=30000)
+    w.n_leaf, w.n_group = 8, 64
+    ctx = Context(0, torch.cuda.current_stream(), torch_alloc=torch_alloc)
+    pos = torch.from_numpy(w.pos).cuda()
+    mass = torch.from_numpy(w.mass).cuda()
+    abar = torch.from_numpy(W.cotangent(w.n, 405)).cuda()
+    t = Tree(pos, n_leaf=w.n_leaf, n_group=w.n_group, ctx=ctx)
+    t.compute_moments(pos, mass, 4)
+    for prec in (HOT_MIXED, HOT_FP64):
+        t.build_interaction_lists(0.5, direct_max=24)
+        side0 = ctx.n_side_allocs
+        x1, m1 = t.eval_forces_adjoint(pos, mass, w.eps, abar, prec, with_mass=True)
+        if torch_alloc:
+            assert ctx.n_side_allocs > side0  # the transposed lists came from the second stream
+        side1 = ctx.n_side_allocs
+        x2, m2 = t.eval_forces_adjoint(pos, mass, w.eps, abar, prec, with_mass=True)
+        assert ctx.n_side_allocs == side1  # cached: nothing on the second stream
+        t.build_interaction_lists(0.5, direct_max=24)
+        x3, m3 = t.eval_forces_adjoint(pos, mass, w.eps, abar, prec, with_mass=True)
+        _log("prec", prec, "allocs", ctx.n_allocs, "side", ctx.n_side_allocs)
+        assert torch.equal(x1, x2) and torch.equal(m1, m2)
+        assert torch.equal(x1, x3) and torch.equal(m1, m3)
+        assert bool(torch.isfinite(x1).all())
+    t.close()
+    ctx.close()

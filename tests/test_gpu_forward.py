@@ -46,6 +46,12 @@ def _special(name):
         pos = rng.random((10, 3))
     elif name == "bigleaf":
         pos = np.concatenate([rng.random((3000, 3)), np.full((200, 3), 0.371)])
+    elif name == "hugeleaf":
+        # leaves of 700 and 300 coincident points: one P2M run spans several
+        # staging chunks, and a single leaf more than one
+        pos = np.concatenate([rng.random((3000, 3)), np.full((700, 3), 0.613),
+                              np.full((300, 3), 0.2)])
+        rng.shuffle(pos)
     else:
         raise KeyError(name)
     n = pos.shape[0]
@@ -54,11 +60,11 @@ def _special(name):
 
 
 CASES = [("uniform4k", None), ("plummer1m", 20000), ("clustered4m", 30000), ("ties", None),
-         ("faces", None), ("one", None), ("few", None), ("bigleaf", None)]
+         ("faces", None), ("one", None), ("few", None), ("bigleaf", None), ("hugeleaf", None)]
 
 
 def _make(name, n):
-    if name in ("ties", "faces", "one", "few", "bigleaf"):
+    if name in ("ties", "faces", "one", "few", "bigleaf", "hugeleaf"):
         return _special(name)
     return W.make(name, n=n)
 
@@ -70,6 +76,8 @@ def test_tree_lists_moments_bitexact(name, n):
     gt, ot, pos, mass, p = build_both(w)
     assert_tree_equal(gt, ot)
     assert_lists_equal(gt, ot)
+    cnt = gt.counts()
+    assert cnt["n_leaf_list"] == cnt["n_leaves"]  # the particle-ordered leaf list P2M runs over
     ot.compute_moments(w.pos, w.mass, p)
     gm, om = gt.moments(), ot.moments()
     assert_moments_close(gm, om, gt.cells()["count"], log=_log)
