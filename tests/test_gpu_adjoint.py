@@ -228,3 +228,68 @@ def test_adjoint_transposes_on_second_stream(torch_alloc):
         assert bool(torch.isfinite(x1).all())
     t.close()
     ctx.close()
+
+
+def test_adjoint_allocation_failure_on_second_stream():
+    """An allocation refused while the transposed lists are being built on
+    the context's second stream fails the call with HOT_E_OOM after the
+    second stream has drained; everything the call allocated is freed, the
+    tree stays usable, and the next adjoint equals an undisturbed context's."""
+    import ctypes
+    from paper_1310_4502_amd import binding
+    from paper_1310_4502_amd.binding import HOT_E_OOM, HotError
+    w = W.make("clustered4m", n=20000)
+    pos = torch.from_numpy(w.pos).cuda()
+    mass = torch.from_numpy(w.mass).cuda()
+    abar = torch.from_numpy(W.cotangent(w.n, 406)).cuda()
+    ref = Tree(pos, n_leaf=8, n_group=64)
+    ref.compute_moments(pos, mass, 4)
+    ref.build_interaction_lists(0.5, direct_max=24)
+    xr, mr = ref.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED, with_mass=True)
+
+    main = torch.cuda.current_stream().cuda_stream
+    state = {"fail": False, "refused": 0}
+    blocks, side = {}, {}
+
+    def _a(user, nbytes, stream):
+        if stream and stream != main:
+            if state["fail"]:
+                state["refused"] += 1
+                return None
+            if stream not in side:
+                side[stream] = torch.cuda.ExternalStream(stream)
+            with torch.cuda.stream(side[stream]):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        else:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        blocks[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _f(user, ptr, stream):
+        blocks.pop(ptr, None)
+
+    afn, ffn = binding.ALLOC_FN(_a), binding.FREE_FN(_f)
+    alloc = binding._Allocator(afn, ffn, None)
+    L = binding.load()
+    ctx = binding.Context(0, torch.cuda.current_stream(), torch_alloc=False)
+    L.hot_ctx_destroy(ctx.h)
+    h = ctypes.c_void_p()
+    assert L.hot_ctx_create(0, ctypes.c_void_p(main), ctypes.byref(alloc), ctypes.byref(h)) == 0
+    ctx.h = h
+    t = Tree(pos, n_leaf=8, n_group=64, ctx=ctx)
+    t.compute_moments(pos, mass, 4)
+    t.build_interaction_lists(0.5, direct_max=24)
+    held = len(blocks)
+    state["fail"] = True
+    with pytest.raises(HotError) as e:
+        t.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED, with_mass=True)
+    assert e.value.code == HOT_E_OOM and state["refused"] == 1
+    ctx.sync()
+    assert len(blocks) == held  # the failed call freed what it allocated
+    state["fail"] = False
+    x, m = t.eval_forces_adjoint(pos, mass, w.eps, abar, HOT_MIXED, with_mass=True)
+    _log("blocks", held, len(blocks), "side streams", len(side))
+    assert torch.equal(x, xr) and torch.equal(m, mr)
+    t.close()
+    ctx.close()
+    ref.close()
