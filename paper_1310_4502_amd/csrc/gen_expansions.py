@@ -249,10 +249,14 @@ def gen_cell_adj(P):
 
 
 def gen_p2m_order(N):
-    """acc[k] += m * (dx^a dy^b dz^c) for the order-N slots, a descending,
-    then b descending (the product associates as (x-part * y-part) * z-part)."""
-    L = []
-    for name, var in (("px", "dx"), ("py", "dy"), ("pz", "dz")):
+    """acc[k] += m dx^a dy^b dz^c for the order-N slots, a descending, then b
+    descending: the mass rides on the x powers (mx_a = m dx^a), and each slot
+    takes one product with the y power and one fused multiply-add with the z
+    power (two FP64 operations per slot)."""
+    L = ["  const double mx0 = m;"]
+    for k in range(1, N + 1):
+        L.append(f"  const double mx{k} = mx{k - 1} * dx;")
+    for name, var in (("py", "dy"), ("pz", "dz")):
         L.append(f"  const double {name}0 = 1.0;")
         for k in range(1, N + 1):
             L.append(f"  const double {name}{k} = {name}{k - 1} * {var};")
@@ -260,7 +264,11 @@ def gen_p2m_order(N):
     for a in range(N, -1, -1):
         for b in range(N - a, -1, -1):
             c = N - a - b
-            L.append(f"  acc[{k}] += m * ((px{a} * py{b}) * pz{c});")
+            xy = f"mx{a}" if b == 0 else f"(mx{a} * py{b})"
+            if c == 0:
+                L.append(f"  acc[{k}] += {xy};")
+            else:
+                L.append(f"  acc[{k}] = fma({xy}, pz{c}, acc[{k}]);")
             k += 1
     return L
 
@@ -268,51 +276,64 @@ def gen_p2m_order(N):
 def gen_m2m_order(N):
     """Re-centre a child's moments (shift = child centre - parent centre) into
     the order-N slots: acc[alpha] += sum_{beta <= alpha} C(alpha,beta)
-    shift^(alpha-beta) M[beta]."""
+    shift^(alpha-beta) M[beta]. Source-major: each child moment M[beta] is
+    read once and scattered into the slots alpha >= beta with one fused
+    multiply-add each (the binomial weight folded into the shift monomial),
+    which keeps few child moments live at a time."""
     L = []
     for name, var in (("px", "dx"), ("py", "dy"), ("pz", "dz")):
         L.append(f"  const double {name}0 = 1.0;")
         for k in range(1, N + 1):
             L.append(f"  const double {name}{k} = {name}{k - 1} * {var};")
-    k = 0
+    slots = []
     for a in range(N, -1, -1):
         for b in range(N - a, -1, -1):
-            c = N - a - b
-            terms = []
-            for a2 in range(a + 1):
-                for b2 in range(b + 1):
-                    for c2 in range(c + 1):
-                        co = math.comb(a, a2) * math.comb(b, b2) * math.comb(c, c2)
-                        terms.append(f"({float(co)!r} * ((px{a - a2} * py{b - b2}) * pz{c - c2})) * M[{slot(a2, b2, c2)}]")
-            L.append(f"  acc[{k}] += " + " + ".join(terms) + ";")
-            k += 1
+            slots.append((a, b, N - a - b))
+    for n2 in range(N + 1):
+        for a2 in range(n2, -1, -1):
+            for b2 in range(n2 - a2, -1, -1):
+                c2 = n2 - a2 - b2
+                L.append(f"  {{ const double m = M[{slot(a2, b2, c2)}];")
+                for k, (a, b, c) in enumerate(slots):
+                    if a < a2 or b < b2 or c < c2:
+                        continue
+                    co = math.comb(a, a2) * math.comb(b, b2) * math.comb(c, c2)
+                    mono = f"((px{a - a2} * py{b - b2}) * pz{c - c2})"
+                    w = mono if co == 1 else f"({float(co)!r} * {mono})"
+                    L.append(f"    acc[{k}] = fma({w}, m, acc[{k}]);")
+                L.append("  }")
     return L
 
 
 def gen_m2mT_order(P, N):
     """Transpose of the re-centring for the order-N output slots beta:
     acc[beta] += sum_{alpha >= beta, |alpha| <= P} C(alpha,beta)
-    shift^(alpha-beta) Mbar[alpha]  (shift = child centre - parent centre)."""
+    shift^(alpha-beta) Mbar[alpha]  (shift = child centre - parent centre).
+    Source-major like the re-centring itself: each parent cotangent
+    Mbar[alpha] is read once and scattered into the slots beta <= alpha with
+    one fused multiply-add each."""
     L = []
     for name, var in (("px", "dx"), ("py", "dy"), ("pz", "dz")):
         L.append(f"  const double {name}0 = 1.0;")
         for k in range(1, P - N + 1):
             L.append(f"  const double {name}{k} = {name}{k - 1} * {var};")
-    k = 0
+    outs = []
     for b0 in range(N, -1, -1):
         for b1 in range(N - b0, -1, -1):
-            b2 = N - b0 - b1
-            terms = []
-            for n in range(N, P + 1):
-                for a0 in range(n, -1, -1):
-                    for a1 in range(n - a0, -1, -1):
-                        a2 = n - a0 - a1
-                        if a0 < b0 or a1 < b1 or a2 < b2:
-                            continue
-                        co = math.comb(a0, b0) * math.comb(a1, b1) * math.comb(a2, b2)
-                        terms.append(f"({float(co)!r} * ((px{a0 - b0} * py{a1 - b1}) * pz{a2 - b2})) * Mb[{slot(a0, a1, a2)}]")
-            L.append(f"  acc[{k}] += " + " + ".join(terms) + ";")
-            k += 1
+            outs.append((b0, b1, N - b0 - b1))
+    for n in range(N, P + 1):
+        for a0 in range(n, -1, -1):
+            for a1 in range(n - a0, -1, -1):
+                a2 = n - a0 - a1
+                L.append(f"  {{ const double mb = Mb[{slot(a0, a1, a2)}];")
+                for k, (b0, b1, b2) in enumerate(outs):
+                    if a0 < b0 or a1 < b1 or a2 < b2:
+                        continue
+                    co = math.comb(a0, b0) * math.comb(a1, b1) * math.comb(a2, b2)
+                    mono = f"((px{a0 - b0} * py{a1 - b1}) * pz{a2 - b2})"
+                    w = mono if co == 1 else f"({float(co)!r} * {mono})"
+                    L.append(f"    acc[{k}] = fma({w}, mb, acc[{k}]);")
+                L.append("  }")
     return L
 
 

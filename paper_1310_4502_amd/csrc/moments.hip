@@ -154,9 +154,10 @@ __global__ __launch_bounds__(64) void k_p2m(int64_t n_leaves, const int32_t* __r
                                             const double* __restrict__ spos,
                                             const double* __restrict__ smass, int64_t n, int p,
                                             double* __restrict__ mom) {
-  __shared__ double lds[64 * (kP2mSlice + 1)];
+  // the staging chunk (four arrays) and, after it, the output slices
+  constexpr int kLds = 4 * kP2mChunk > 64 * (kP2mSlice + 1) ? 4 * kP2mChunk : 64 * (kP2mSlice + 1);
+  __shared__ double lds[kLds];
   __shared__ int s_cell[64];
-  static_assert(64 * (kP2mSlice + 1) >= 4 * kP2mChunk, "staging area");
   int64_t run;
   int ord;
   order_block(p, run, ord);
