@@ -354,14 +354,22 @@ __global__ __launch_bounds__(kB) void k_bmax(const uint64_t* __restrict__ key,
       y = spos[n + j];
       z = spos[2 * n + j];
     }
+    // the particle's integer coordinates at the deepest level, decoded once:
+    // its level-L cell has the top L bits of each (the digits cell_centre
+    // takes from the key prefix), so the centres below are the same numbers
+    const uint64_t dig = k & ((1ull << (3 * kMaxLevel)) - 1ull);
+    const uint32_t IX = compact3(dig >> 2), IY = compact3(dig >> 1), IZ = compact3(dig);
     for (int L = 0; L <= kMaxLevel; ++L) {
       const bool has = L <= lmb;
       if (!__any(has)) break;
       const unsigned long long P = has ? (k >> (3 * (kMaxLevel - L))) : 0ull;
       unsigned long long v = 0;
       if (has) {
-        double c[3];
-        cell_centre(P, L, root, c);
+        const int sh = kMaxLevel - L;
+        const double h = ldexp(root[3], -(L + 1));
+        const double c[3] = {root[0] + (double)(2u * (IX >> sh) + 1u) * h,
+                             root[1] + (double)(2u * (IY >> sh) + 1u) * h,
+                             root[2] + (double)(2u * (IZ >> sh) + 1u) * h};
         const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         v = (unsigned long long)__double_as_longlong(d2);
