@@ -43,7 +43,7 @@ enum {
   HOT_E_STATE = -2,    /* call out of order (e.g. eval before moments) */
   HOT_E_OOM = -3,      /* device allocation failed */
   HOT_E_DEVICE = -4,   /* a HIP runtime error */
-  HOT_E_CAPACITY = -5  /* a size limit of this build was exceeded */
+  HOT_E_CAPACITY = -5  /* a size limit of the library was exceeded */
 };
 
 enum { HOT_MIXED = 0, HOT_FP64 = 1 };

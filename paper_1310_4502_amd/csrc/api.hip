@@ -77,7 +77,7 @@ void* scratch_ptr[kMaxDevices] = {};
 
 // Device address of this device's scratch array (the device must be current).
 void* scratch_address(int device) {
-  if (device < 0 || device >= kMaxDevices) hot::invalid("device index beyond this build's table");
+  if (device < 0 || device >= kMaxDevices) hot::invalid("device index beyond the library's device table");
   std::lock_guard<std::mutex> lock(scratch_mu);
   if (!scratch_ptr[device]) {
     void* ptr = nullptr;
