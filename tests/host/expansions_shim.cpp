@@ -88,4 +88,52 @@ void shim_m2m(int N, const double* M, double dx, double dy, double dz, double* a
     case 8: hot::m2m_order8(M, dx, dy, dz, acc); break;
   }
 }
+// transpose of the re-centring for a parent of order p, output order N
+void shim_m2mT(int p, int N, const double* Mb, double dx, double dy, double dz, double* acc) {
+  if (p == 0 && N == 0) hot::m2mT_p0_order0(Mb, dx, dy, dz, acc);
+  if (p == 1 && N == 0) hot::m2mT_p1_order0(Mb, dx, dy, dz, acc);
+  if (p == 1 && N == 1) hot::m2mT_p1_order1(Mb, dx, dy, dz, acc);
+  if (p == 2 && N == 0) hot::m2mT_p2_order0(Mb, dx, dy, dz, acc);
+  if (p == 2 && N == 1) hot::m2mT_p2_order1(Mb, dx, dy, dz, acc);
+  if (p == 2 && N == 2) hot::m2mT_p2_order2(Mb, dx, dy, dz, acc);
+  if (p == 3 && N == 0) hot::m2mT_p3_order0(Mb, dx, dy, dz, acc);
+  if (p == 3 && N == 1) hot::m2mT_p3_order1(Mb, dx, dy, dz, acc);
+  if (p == 3 && N == 2) hot::m2mT_p3_order2(Mb, dx, dy, dz, acc);
+  if (p == 3 && N == 3) hot::m2mT_p3_order3(Mb, dx, dy, dz, acc);
+  if (p == 4 && N == 0) hot::m2mT_p4_order0(Mb, dx, dy, dz, acc);
+  if (p == 4 && N == 1) hot::m2mT_p4_order1(Mb, dx, dy, dz, acc);
+  if (p == 4 && N == 2) hot::m2mT_p4_order2(Mb, dx, dy, dz, acc);
+  if (p == 4 && N == 3) hot::m2mT_p4_order3(Mb, dx, dy, dz, acc);
+  if (p == 4 && N == 4) hot::m2mT_p4_order4(Mb, dx, dy, dz, acc);
+  if (p == 5 && N == 0) hot::m2mT_p5_order0(Mb, dx, dy, dz, acc);
+  if (p == 5 && N == 1) hot::m2mT_p5_order1(Mb, dx, dy, dz, acc);
+  if (p == 5 && N == 2) hot::m2mT_p5_order2(Mb, dx, dy, dz, acc);
+  if (p == 5 && N == 3) hot::m2mT_p5_order3(Mb, dx, dy, dz, acc);
+  if (p == 5 && N == 4) hot::m2mT_p5_order4(Mb, dx, dy, dz, acc);
+  if (p == 5 && N == 5) hot::m2mT_p5_order5(Mb, dx, dy, dz, acc);
+  if (p == 6 && N == 0) hot::m2mT_p6_order0(Mb, dx, dy, dz, acc);
+  if (p == 6 && N == 1) hot::m2mT_p6_order1(Mb, dx, dy, dz, acc);
+  if (p == 6 && N == 2) hot::m2mT_p6_order2(Mb, dx, dy, dz, acc);
+  if (p == 6 && N == 3) hot::m2mT_p6_order3(Mb, dx, dy, dz, acc);
+  if (p == 6 && N == 4) hot::m2mT_p6_order4(Mb, dx, dy, dz, acc);
+  if (p == 6 && N == 5) hot::m2mT_p6_order5(Mb, dx, dy, dz, acc);
+  if (p == 6 && N == 6) hot::m2mT_p6_order6(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 0) hot::m2mT_p7_order0(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 1) hot::m2mT_p7_order1(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 2) hot::m2mT_p7_order2(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 3) hot::m2mT_p7_order3(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 4) hot::m2mT_p7_order4(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 5) hot::m2mT_p7_order5(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 6) hot::m2mT_p7_order6(Mb, dx, dy, dz, acc);
+  if (p == 7 && N == 7) hot::m2mT_p7_order7(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 0) hot::m2mT_p8_order0(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 1) hot::m2mT_p8_order1(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 2) hot::m2mT_p8_order2(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 3) hot::m2mT_p8_order3(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 4) hot::m2mT_p8_order4(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 5) hot::m2mT_p8_order5(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 6) hot::m2mT_p8_order6(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 7) hot::m2mT_p8_order7(Mb, dx, dy, dz, acc);
+  if (p == 8 && N == 8) hot::m2mT_p8_order8(Mb, dx, dy, dz, acc);
+}
 }

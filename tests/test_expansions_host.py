@@ -22,7 +22,7 @@ def shim(tmp_path_factory):
                     "-I", os.path.dirname(gen), os.path.join(ROOT, "tests", "host", "expansions_shim.cpp"),
                     "-o", out], check=True)
     L = ctypes.CDLL(out)
-    for f in ("shim_fwd", "shim_sink", "shim_cell", "shim_p2m", "shim_m2m"):
+    for f in ("shim_fwd", "shim_sink", "shim_cell", "shim_p2m", "shim_m2m", "shim_m2mT"):
         getattr(L, f).restype = None
     i32 = ctypes.c_int
     L.shim_fwd.argtypes = [i32, i32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
@@ -30,6 +30,8 @@ def shim(tmp_path_factory):
     L.shim_cell.argtypes = [i32, i32, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
     L.shim_p2m.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [ctypes.c_void_p]
     L.shim_m2m.argtypes = [ctypes.c_int, ctypes.c_void_p] + [ctypes.c_double] * 3 + [ctypes.c_void_p]
+    L.shim_m2mT.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p] + [ctypes.c_double] * 3 + \
+        [ctypes.c_void_p]
     return L
 
 
@@ -125,3 +127,27 @@ def test_p2m_m2m_match_oracle(orc, shim, p):
         shim.shim_m2m(N, P(ref), *(c - parent), P(acc))
         gotp[off:off + len(acc)] = acc
     assert np.allclose(gotp, refp, rtol=1e-14, atol=1e-15 * np.abs(refp).max())
+
+
+@pytest.mark.parametrize("p", [0, 2, 5, 8])
+def test_m2m_transpose_is_the_adjoint_of_the_oracle_m2m(orc, shim, p):
+    """The generated transpose of the re-centring (the adjoint's downward
+    pass) satisfies <Mbar, m2m(M)> = <m2mT(Mbar), M> with the oracle's own
+    re-centring, for random moments and cotangents: it is the exact transpose
+    of the linear map, not only of the GPU's version of it."""
+    rng = np.random.default_rng(11 + p)
+    nm = orc.nm(p)
+    shift = np.array([0.13, -0.07, 0.21])
+    for _ in range(3):
+        M = rng.standard_normal(nm)
+        Mb = rng.standard_normal(nm)
+        lhs = float(np.dot(Mb, orc.m2m(p, M, shift)))
+        got = np.zeros(nm)
+        for N in range(p + 1):
+            off = N * (N + 1) * (N + 2) // 6
+            acc = np.zeros((N + 1) * (N + 2) // 2)
+            shim.shim_m2mT(p, N, P(Mb), *shift, P(acc))
+            got[off:off + len(acc)] = acc
+        rhs = float(np.dot(got, M))
+        scale = float(np.abs(Mb).sum() * np.abs(orc.m2m(p, np.abs(M), np.abs(shift))).max())
+        assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs, scale)
