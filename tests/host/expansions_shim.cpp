@@ -136,4 +136,17 @@ void shim_m2mT(int p, int N, const double* Mb, double dx, double dy, double dz, 
   if (p == 8 && N == 7) hot::m2mT_p8_order7(Mb, dx, dy, dz, acc);
   if (p == 8 && N == 8) hot::m2mT_p8_order8(Mb, dx, dy, dz, acc);
 }
+// moment cotangents to one unit-mass particle at offset d: g[0..2] the
+// position cotangent, g[3] the mass cotangent (accumulated into g)
+void shim_p2mT(int p, const double* Mb, double dx, double dy, double dz, double* g) {
+  if (p == 0) hot::p2mT_p0(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 1) hot::p2mT_p1(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 2) hot::p2mT_p2(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 3) hot::p2mT_p3(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 4) hot::p2mT_p4(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 5) hot::p2mT_p5(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 6) hot::p2mT_p6(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 7) hot::p2mT_p7(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+  if (p == 8) hot::p2mT_p8(Mb, dx, dy, dz, g[0], g[1], g[2], g[3]);
+}
 }

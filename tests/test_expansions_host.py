@@ -22,7 +22,8 @@ def shim(tmp_path_factory):
                     "-I", os.path.dirname(gen), os.path.join(ROOT, "tests", "host", "expansions_shim.cpp"),
                     "-o", out], check=True)
     L = ctypes.CDLL(out)
-    for f in ("shim_fwd", "shim_sink", "shim_cell", "shim_p2m", "shim_m2m", "shim_m2mT"):
+    for f in ("shim_fwd", "shim_sink", "shim_cell", "shim_p2m", "shim_m2m", "shim_m2mT",
+              "shim_p2mT"):
         getattr(L, f).restype = None
     i32 = ctypes.c_int
     L.shim_fwd.argtypes = [i32, i32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
@@ -32,6 +33,7 @@ def shim(tmp_path_factory):
     L.shim_m2m.argtypes = [ctypes.c_int, ctypes.c_void_p] + [ctypes.c_double] * 3 + [ctypes.c_void_p]
     L.shim_m2mT.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p] + [ctypes.c_double] * 3 + \
         [ctypes.c_void_p]
+    L.shim_p2mT.argtypes = [ctypes.c_int, ctypes.c_void_p] + [ctypes.c_double] * 3 + [ctypes.c_void_p]
     return L
 
 
@@ -151,3 +153,30 @@ def test_m2m_transpose_is_the_adjoint_of_the_oracle_m2m(orc, shim, p):
         rhs = float(np.dot(got, M))
         scale = float(np.abs(Mb).sum() * np.abs(orc.m2m(p, np.abs(M), np.abs(shift))).max())
         assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs, scale)
+
+
+@pytest.mark.parametrize("p", [0, 1, 4, 8])
+def test_p2m_transpose_is_the_gradient_of_the_oracle_p2m(orc, shim, p):
+    """The generated moment-to-particle transpose returns, for a unit mass at
+    offset d, the mass cotangent <Mbar, P2M(d)> and the position cotangent
+    grad_d <Mbar, P2M(d)>, both from the oracle's own P2M (the gradient by a
+    fourth-order central difference)."""
+    rng = np.random.default_rng(23 + p)
+    nm = orc.nm(p)
+    zero = np.zeros(3)
+    for _ in range(3):
+        Mb = rng.standard_normal(nm)
+        d = rng.uniform(-0.4, 0.4, 3)
+        g = np.zeros(4)
+        shim.shim_p2mT(p, P(Mb), *d, P(g))
+
+        def f(x):
+            return float(np.dot(Mb, orc.p2m(p, x[None, :], np.ones(1), zero)))
+
+        assert abs(g[3] - f(d)) <= 1e-14 * max(1.0, np.abs(Mb).sum())
+        h = 1e-3
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            fd = (8 * (f(d + e) - f(d - e)) - (f(d + 2 * e) - f(d - 2 * e))) / (12 * h)
+            assert abs(g[k] - fd) <= 1e-8 * max(1.0, np.abs(Mb).sum()), (k, g[k], fd)
